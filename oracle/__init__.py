@@ -1,0 +1,268 @@
+"""FP64 CPU oracle of one fast flow-based cartogram iteration.
+
+TEST INFRASTRUCTURE: only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package.  The product path
+(``paper_1802_07625_amd``) never imports it, and it imports nothing from the
+product path.  The arithmetic lives in ``ffb_oracle.c`` (plain loops, direct
+sums, no FFT); this module only marshals numpy arrays through ctypes and
+strings the steps of one round together in the paper's order:
+
+  areas -> densities -> raster -> Eq. 7 coefficients + blur -> flux sums ->
+  v = J / rho_t (Eq. 4-6) -> Dormand-Prince integration to t = 1 -> areas ->
+  relative area errors (stop below 1 %).
+
+Parity of the controller constants (tol, h0, safety, step-factor limits,
+h_min) and of the blur schedule is unpinned: the paper does not state them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ffb_oracle.c")
+_LIB = os.path.join(_HERE, "libffb_oracle.so")
+
+OK, E_INVALID, E_NOMEM, E_NONPOSITIVE, E_DOMAIN = 0, 1, 2, 4, 5
+E_STEP_UNDERFLOW, E_NONFINITE, E_MAX_ATTEMPTS = 6, 7, 9
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                        "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.ffbo_set_threads.argtypes = [ctypes.c_int]
+        L.ffbo_region_areas.argtypes = [i64, _d, i32, _i32, _i32, _i32, i32, _d]
+        L.ffbo_area_error.argtypes = [i32, _d, _d, _d, _d]
+        L.ffbo_density.argtypes = [i32, i32, i64, _d, i32, _i32, _i32, _i32, i32, _d, _d, _d, _d]
+        L.ffbo_dct2.argtypes = [i32, i32, _d, _d]
+        L.ffbo_flux.argtypes = [i32, i32, _d, dbl, _d, _d, _d, _d, _d]
+        L.ffbo_velocity.argtypes = [i32, i32, _d, _d, _d, dbl, dbl, i64, _d, _d]
+        L.ffbo_tableau.argtypes = [_d, _d, _d, _d]
+        L.ffbo_integrate.argtypes = [i32, i32, _d, _d, _d, dbl, i64, _d,
+                                     dbl, dbl, dbl, dbl, dbl, dbl, i32,
+                                     _d, i32, _i32, _i32, _d, i32]
+        _lib = L
+    return _lib
+
+
+def set_threads(n: int) -> int:
+    """Set the OpenMP thread count of the oracle; returns the count in use."""
+    return int(lib().ffbo_set_threads(int(n)))
+
+
+def _p(a, t=_d):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _check(code, what):
+    if code != OK:
+        raise OracleError(int(code), what)
+
+
+# ---------------------------------------------------------------- geometry
+def region_areas(m, xy=None) -> np.ndarray:
+    """Signed shoelace area of every region (sum over its rings)."""
+    xy = _f64(m.xy if xy is None else xy)
+    off, vid, reg = _i(m.ring_offsets), _i(m.ring_vidx), _i(m.ring_region)
+    out = np.zeros(m.n_regions)
+    _check(lib().ffbo_region_areas(xy.shape[0], _p(xy), reg.shape[0], _p(off, _i32),
+                                   _p(vid, _i32), _p(reg, _i32), m.n_regions, _p(out)),
+           "region_areas")
+    return out
+
+
+def area_error(value, area):
+    """(e_r, max |e_r|) with e_r = A_r / T_r - 1, T_r = value_r sum(A)/sum(value)."""
+    value, area = _f64(value), _f64(area)
+    err = np.zeros_like(area)
+    mx = np.zeros(1)
+    _check(lib().ffbo_area_error(area.shape[0], _p(value), _p(area), _p(err), _p(mx)),
+           "area_error")
+    return err, float(mx[0])
+
+
+def density(m, value, area, xy=None, lx=None, ly=None):
+    """Exact area-weighted cell densities rho0 [ly, lx] and rho_pad."""
+    lx = m.lx if lx is None else lx
+    ly = m.ly if ly is None else ly
+    xy = _f64(m.xy if xy is None else xy)
+    off, vid, reg = _i(m.ring_offsets), _i(m.ring_vidx), _i(m.ring_region)
+    value, area = _f64(value), _f64(area)
+    rho = np.zeros((ly, lx))
+    pad = np.zeros(1)
+    _check(lib().ffbo_density(lx, ly, xy.shape[0], _p(xy), reg.shape[0], _p(off, _i32),
+                              _p(vid, _i32), _p(reg, _i32), m.n_regions, _p(value),
+                              _p(area), _p(rho), _p(pad)), "density")
+    return rho, float(pad[0])
+
+
+# -------------------------------------------------------------- transforms
+def dct2(rho) -> np.ndarray:
+    """S[n, m] = sum_ij rho[j, i] cos(pi m (i+1/2)/lx) cos(pi n (j+1/2)/ly)."""
+    rho = _f64(rho)
+    ly, lx = rho.shape
+    S = np.zeros_like(rho)
+    _check(lib().ffbo_dct2(lx, ly, _p(rho), _p(S)), "dct2")
+    return S
+
+
+@dataclass
+class Fields:
+    lx: int
+    ly: int
+    rho_s: np.ndarray   # [ly, lx] blurred density on the nodes
+    jx: np.ndarray      # [ly, lx]
+    jy: np.ndarray      # [ly, lx]
+    rho_bar: float
+    coef: np.ndarray | None = None  # blurred Eq. 7 coefficients [n, m]
+
+    def rounded_f32(self) -> "Fields":
+        """The same fields rounded to FP32 (identical-input parity runs)."""
+        r = lambda a: a.astype(np.float32).astype(np.float64)
+        return Fields(self.lx, self.ly, r(self.rho_s), r(self.jx), r(self.jy),
+                      self.rho_bar, None)
+
+
+def flux(rho, sigma: float, keep_coef: bool = False) -> Fields:
+    rho = _f64(rho)
+    ly, lx = rho.shape
+    rs, jx, jy = np.zeros_like(rho), np.zeros_like(rho), np.zeros_like(rho)
+    rb = np.zeros(1)
+    coef = np.zeros_like(rho) if keep_coef else None
+    _check(lib().ffbo_flux(lx, ly, _p(rho), float(sigma), _p(rs), _p(jx), _p(jy),
+                           _p(rb), _p(coef) if keep_coef else None), "flux")
+    return Fields(lx, ly, rs, jx, jy, float(rb[0]), coef)
+
+
+def velocity(F: Fields, t: float, q) -> np.ndarray:
+    q = _f64(q).reshape(-1, 2)
+    v = np.zeros_like(q)
+    rs, jx, jy = _f64(F.rho_s), _f64(F.jx), _f64(F.jy)
+    _check(lib().ffbo_velocity(F.lx, F.ly, _p(rs), _p(jx), _p(jy), F.rho_bar, float(t),
+                               q.shape[0], _p(q), _p(v)), "velocity")
+    return v
+
+
+def tableau():
+    c, a, b, bs = np.zeros(7), np.zeros(42), np.zeros(7), np.zeros(7)
+    lib().ffbo_tableau(_p(c), _p(a), _p(b), _p(bs))
+    return c, a.reshape(7, 6), b, bs
+
+
+# -------------------------------------------------------------- integrator
+@dataclass
+class IntegrateOpts:
+    tol: float = 1e-3
+    h0: float = 1e-2
+    safety: float = 0.9
+    fac_min: float = 0.2
+    fac_max: float = 5.0
+    h_min: float = 1e-7
+    max_attempts: int = 10000
+
+
+@dataclass
+class IntegrateResult:
+    xy: np.ndarray
+    accepted: int
+    rejected: int
+    h: np.ndarray = field(repr=False)
+
+
+def integrate(F: Fields, pts, opts: IntegrateOpts | None = None,
+              replay_h=None) -> IntegrateResult:
+    """Advect points from t = 0 to t = 1 (adaptive, or replaying given steps)."""
+    opts = opts or IntegrateOpts()
+    xy = _f64(pts).reshape(-1, 2).copy()
+    rs, jx, jy = _f64(F.rho_s), _f64(F.jx), _f64(F.jy)
+    cap = opts.max_attempts + 1
+    hout = np.zeros(cap)
+    acc = np.zeros(1, np.int32)
+    rej = np.zeros(1, np.int32)
+    rh = None if replay_h is None else _f64(replay_h)
+    code = lib().ffbo_integrate(F.lx, F.ly, _p(rs), _p(jx), _p(jy), F.rho_bar,
+                                xy.shape[0], _p(xy), opts.tol, opts.h0, opts.safety,
+                                opts.fac_min, opts.fac_max, opts.h_min, opts.max_attempts,
+                                _p(rh) if rh is not None else None,
+                                0 if rh is None else rh.shape[0],
+                                _p(acc, _i32), _p(rej, _i32), _p(hout), cap)
+    _check(code, "integrate")
+    return IntegrateResult(xy, int(acc[0]), int(rej[0]), hout[:int(acc[0])].copy())
+
+
+# ------------------------------------------------------------------ rounds
+def default_sigma(k: int) -> float:
+    """Blur width of round k (0-based), in grid cells: 4 * 2^-k."""
+    return 4.0 * 2.0 ** (-k)
+
+
+@dataclass
+class RoundResult:
+    points: np.ndarray      # advected points [P, 2]
+    area_before: np.ndarray
+    area_after: np.ndarray
+    err_after: np.ndarray
+    max_err_after: float
+    rho: np.ndarray
+    rho_pad: float
+    fields: Fields
+    accepted: int
+    rejected: int
+    h: np.ndarray
+
+
+def iterate(m, value, points, n_vertices: int, sigma: float,
+            opts: IntegrateOpts | None = None, replay_h=None,
+            fields_override: Fields | None = None) -> RoundResult:
+    """One FFB iteration.  ``points[:n_vertices]`` are the polygon vertices
+    (indexed by the rings); further points (e.g. grid nodes) are advected
+    with them."""
+    pts = _f64(points).reshape(-1, 2)
+    verts = pts[:n_vertices]
+    a0 = region_areas(m, verts)
+    rho, pad = density(m, value, a0, xy=verts)
+    F = flux(rho, sigma) if fields_override is None else fields_override
+    res = integrate(F, pts, opts, replay_h)
+    a1 = region_areas(m, res.xy[:n_vertices])
+    e1, mx = area_error(value, a1)
+    return RoundResult(res.xy, a0, a1, e1, mx, rho, pad, F, res.accepted,
+                       res.rejected, res.h)

@@ -1,0 +1,623 @@
+/*
+ * ffb_oracle.c -- plain, slow, FP64 reference of one iteration of the fast
+ * flow-based cartogram method (Gastner, Seguy & More, "Fast flow-based
+ * algorithm for creating density-equalizing map projections").
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the HIP implementation, and the
+ * product path never calls it.
+ *
+ * Every step follows the paper's definitions written out directly:
+ *   - areas by the shoelace sum over polygon corners;
+ *   - cell densities by exact polygon/cell clipping (Sutherland-Hodgman);
+ *   - the cosine coefficients of Eq. 7 as direct separable sums (midpoint
+ *     rule on the cell centres), no FFT;
+ *   - the flux sums of the SI Appendix (section 2, the equations for J_x and
+ *     J_y of linear equalisation) as direct separable sums;
+ *   - the velocity v = J / rho_t with rho_t of Eq. 4, bilinear interpolation
+ *     between grid points, and Dormand-Prince 5(4) integration to t = 1.
+ * Readings of points where the paper is silent are stated at each function.
+ *
+ * Parity of the integrator controller constants (tolerance, initial step,
+ * safety factor, step-factor limits) is unpinned by the paper, which only
+ * says that a predictor-corrector method adapts the next step size and that
+ * a typical run takes about 100 steps.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* status codes (same numeric meaning as the library's, defined here on
+ * their own so that the two sides share no header) */
+#define O_OK 0
+#define O_E_INVALID 1
+#define O_E_NOMEM 2
+#define O_E_NONPOSITIVE 4
+#define O_E_DOMAIN 5
+#define O_E_STEP_UNDERFLOW 6
+#define O_E_NONFINITE 7
+#define O_E_MAX_ATTEMPTS 9
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+int ffbo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------
+ * Areas and area errors.
+ * A region's area is the sum over its rings of the shoelace sum
+ * 1/2 sum_k (x_k y_{k+1} - x_{k+1} y_k); counter-clockwise rings count
+ * positive, clockwise rings (holes) negative.  The relative area error of
+ * region r compares its current area A_r with its target share of the
+ * current total, T_r = value_r * sum(A) / sum(value): e_r = A_r / T_r - 1
+ * (main text, benchmarking section: the stopping rule of a maximum relative
+ * area error below 1 %).
+ * ---------------------------------------------------------------------- */
+static double ring_area(const double *xy, const int32_t *vidx, int32_t n)
+{
+    double s = 0.0;
+    for (int32_t k = 0; k < n; ++k) {
+        const double *p = xy + 2 * (int64_t)vidx[k];
+        const double *q = xy + 2 * (int64_t)vidx[(k + 1) % n];
+        s += p[0] * q[1] - q[0] * p[1];
+    }
+    return 0.5 * s;
+}
+
+static int check_geometry(int64_t nv, int32_t n_rings, const int32_t *ring_offsets,
+                          const int32_t *ring_vidx, const int32_t *ring_region,
+                          int32_t n_regions)
+{
+    if (nv < 0 || n_rings < 0 || n_regions <= 0) return O_E_INVALID;
+    if (ring_offsets[0] != 0) return O_E_INVALID;
+    for (int32_t r = 0; r < n_rings; ++r) {
+        if (ring_offsets[r + 1] - ring_offsets[r] < 3) return O_E_INVALID;
+        if (ring_region[r] < 0 || ring_region[r] >= n_regions) return O_E_INVALID;
+    }
+    int32_t ne = ring_offsets[n_rings];
+    for (int32_t k = 0; k < ne; ++k)
+        if (ring_vidx[k] < 0 || ring_vidx[k] >= nv) return O_E_INVALID;
+    return O_OK;
+}
+
+int ffbo_region_areas(int64_t nv, const double *xy, int32_t n_rings,
+                      const int32_t *ring_offsets, const int32_t *ring_vidx,
+                      const int32_t *ring_region, int32_t n_regions, double *area)
+{
+    int st = check_geometry(nv, n_rings, ring_offsets, ring_vidx, ring_region, n_regions);
+    if (st) return st;
+    for (int64_t k = 0; k < 2 * nv; ++k)
+        if (!isfinite(xy[k])) return O_E_NONFINITE;
+    for (int32_t r = 0; r < n_regions; ++r) area[r] = 0.0;
+    for (int32_t g = 0; g < n_rings; ++g) {
+        int32_t b = ring_offsets[g], e = ring_offsets[g + 1];
+        area[ring_region[g]] += ring_area(xy, ring_vidx + b, e - b);
+    }
+    return O_OK;
+}
+
+int ffbo_area_error(int32_t n_regions, const double *value, const double *area,
+                    double *err, double *max_abs_err)
+{
+    double sa = 0.0, sv = 0.0;
+    for (int32_t r = 0; r < n_regions; ++r) {
+        if (!(value[r] > 0.0)) return O_E_NONPOSITIVE;
+        sa += area[r];
+        sv += value[r];
+    }
+    double mx = 0.0;
+    for (int32_t r = 0; r < n_regions; ++r) {
+        double target = value[r] * sa / sv;
+        err[r] = area[r] / target - 1.0;
+        if (fabs(err[r]) > mx || isnan(err[r])) mx = fabs(err[r]);
+    }
+    *max_abs_err = mx;
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Rasterisation.  The density is piecewise constant per region, d_r =
+ * value_r / A_r (main text, section on previous all-coordinates methods),
+ * and the space between the map and the box edges holds the mean density
+ * (benchmarking section), read here as rho_pad = sum(value) / sum(A).  A
+ * grid cell [i, i+1] x [j, j+1] gets the exact area-weighted average:
+ *   rho0_ij = rho_pad + sum_r (d_r - rho_pad) * area(cell ∩ region_r).
+ * The intersection is computed by clipping each ring against the cell's
+ * four half-planes (first the row band, then the column) and taking the
+ * signed shoelace area of the clipped polygon.
+ * ---------------------------------------------------------------------- */
+typedef struct { double *x, *y; int32_t n, cap; } poly_t;
+
+static int poly_reserve(poly_t *p, int32_t cap)
+{
+    if (p->cap >= cap) return 0;
+    double *nx = (double *)realloc(p->x, sizeof(double) * cap);
+    if (!nx) return -1;
+    p->x = nx;
+    double *ny = (double *)realloc(p->y, sizeof(double) * cap);
+    if (!ny) return -1;
+    p->y = ny;
+    p->cap = cap;
+    return 0;
+}
+
+/* keep the part of `in` with s * (coord - c) <= 0, coord = x (axis 0) or y */
+static int clip_half(const poly_t *in, poly_t *out, int axis, double c, double s)
+{
+    out->n = 0;
+    if (poly_reserve(out, 2 * in->n + 4)) return -1;
+    for (int32_t k = 0; k < in->n; ++k) {
+        int32_t k1 = (k + 1) % in->n;
+        double px = in->x[k], py = in->y[k], qx = in->x[k1], qy = in->y[k1];
+        double fp = s * ((axis == 0 ? px : py) - c);
+        double fq = s * ((axis == 0 ? qx : qy) - c);
+        int pin = fp <= 0.0, qin = fq <= 0.0;
+        if (pin) { out->x[out->n] = px; out->y[out->n] = py; out->n++; }
+        if (pin != qin) {
+            double w = fp / (fp - fq);
+            double ix = px + w * (qx - px), iy = py + w * (qy - py);
+            if (axis == 0) ix = c; else iy = c;
+            out->x[out->n] = ix; out->y[out->n] = iy; out->n++;
+        }
+    }
+    return 0;
+}
+
+static double poly_area(const poly_t *p)
+{
+    double s = 0.0;
+    for (int32_t k = 0; k < p->n; ++k) {
+        int32_t k1 = (k + 1) % p->n;
+        s += p->x[k] * p->y[k1] - p->x[k1] * p->y[k];
+    }
+    return 0.5 * s;
+}
+
+int ffbo_density(int32_t lx, int32_t ly, int64_t nv, const double *xy, int32_t n_rings,
+                 const int32_t *ring_offsets, const int32_t *ring_vidx,
+                 const int32_t *ring_region, int32_t n_regions, const double *value,
+                 const double *area, double *rho, double *rho_pad_out)
+{
+    if (lx <= 0 || ly <= 0) return O_E_INVALID;
+    int st = check_geometry(nv, n_rings, ring_offsets, ring_vidx, ring_region, n_regions);
+    if (st) return st;
+    for (int64_t k = 0; k < nv; ++k) {
+        double x = xy[2 * k], y = xy[2 * k + 1];
+        if (!isfinite(x) || !isfinite(y)) return O_E_NONFINITE;
+        if (x < 0.0 || x > lx || y < 0.0 || y > ly) return O_E_DOMAIN;
+    }
+    double sa = 0.0, sv = 0.0;
+    for (int32_t r = 0; r < n_regions; ++r) {
+        if (!(value[r] > 0.0) || !(area[r] > 0.0)) return O_E_NONPOSITIVE;
+        sa += area[r];
+        sv += value[r];
+    }
+    const double rho_pad = sv / sa;
+    double *w = (double *)malloc(sizeof(double) * n_regions);
+    double *ymin = (double *)malloc(sizeof(double) * (n_rings + 1));
+    double *ymax = (double *)malloc(sizeof(double) * (n_rings + 1));
+    if (!w || !ymin || !ymax) { free(w); free(ymin); free(ymax); return O_E_NOMEM; }
+    for (int32_t r = 0; r < n_regions; ++r) w[r] = value[r] / area[r] - rho_pad;
+    for (int32_t g = 0; g < n_rings; ++g) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int32_t k = ring_offsets[g]; k < ring_offsets[g + 1]; ++k) {
+            double y = xy[2 * (int64_t)ring_vidx[k] + 1];
+            if (y < lo) lo = y;
+            if (y > hi) hi = y;
+        }
+        ymin[g] = lo; ymax[g] = hi;
+    }
+    for (int64_t c = 0; c < (int64_t)lx * ly; ++c) rho[c] = rho_pad;
+
+    int fail = 0;
+#pragma omp parallel
+    {
+        poly_t ring = {0}, t1 = {0}, band = {0}, t2 = {0}, cell = {0};
+#pragma omp for schedule(dynamic, 4)
+        for (int32_t j = 0; j < ly; ++j) {
+            for (int32_t g = 0; g < n_rings; ++g) {
+                if (ymax[g] <= j || ymin[g] >= j + 1) continue;
+                int32_t b = ring_offsets[g], n = ring_offsets[g + 1] - b;
+                if (poly_reserve(&ring, n)) { fail = 1; continue; }
+                for (int32_t k = 0; k < n; ++k) {
+                    ring.x[k] = xy[2 * (int64_t)ring_vidx[b + k]];
+                    ring.y[k] = xy[2 * (int64_t)ring_vidx[b + k] + 1];
+                }
+                ring.n = n;
+                if (clip_half(&ring, &t1, 1, (double)j, -1.0)) { fail = 1; continue; }
+                if (clip_half(&t1, &band, 1, (double)(j + 1), 1.0)) { fail = 1; continue; }
+                if (band.n < 3) continue;
+                double xlo = INFINITY, xhi = -INFINITY;
+                for (int32_t k = 0; k < band.n; ++k) {
+                    if (band.x[k] < xlo) xlo = band.x[k];
+                    if (band.x[k] > xhi) xhi = band.x[k];
+                }
+                int32_t i0 = (int32_t)floor(xlo), i1 = (int32_t)ceil(xhi);
+                if (i0 < 0) i0 = 0;
+                if (i1 > lx) i1 = lx;
+                for (int32_t i = i0; i < i1; ++i) {
+                    if (clip_half(&band, &t2, 0, (double)i, -1.0)) { fail = 1; break; }
+                    if (clip_half(&t2, &cell, 0, (double)(i + 1), 1.0)) { fail = 1; break; }
+                    if (cell.n < 3) continue;
+                    rho[(int64_t)j * lx + i] += w[ring_region[g]] * poly_area(&cell);
+                }
+            }
+        }
+        free(ring.x); free(ring.y); free(t1.x); free(t1.y); free(band.x); free(band.y);
+        free(t2.x); free(t2.y); free(cell.x); free(cell.y);
+    }
+    free(w); free(ymin); free(ymax);
+    if (fail) return O_E_NOMEM;
+    *rho_pad_out = rho_pad;
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Cosine/sine tables.  cos(pi * m * (2i + 1) / (2L)) for integers m, i is
+ * looked up as tab[(m * (2i + 1)) mod 4L] with tab[k] = cos(pi k / (2L)),
+ * and the matching sine as tab[(m * (2i + 1) - L) mod 4L].
+ * ---------------------------------------------------------------------- */
+static double *make_table(int32_t L)
+{
+    double *tab = (double *)malloc(sizeof(double) * 4 * (size_t)L);
+    if (!tab) return NULL;
+    for (int32_t k = 0; k < 4 * L; ++k) tab[k] = cos(PI * (double)k / (2.0 * L));
+    return tab;
+}
+
+static inline double tcos(const double *tab, int32_t L, int64_t m, int64_t i)
+{
+    int64_t k = (m * (2 * i + 1)) % (4 * (int64_t)L);
+    return tab[k];
+}
+
+static inline double tsin(const double *tab, int32_t L, int64_t m, int64_t i)
+{
+    int64_t k = (m * (2 * i + 1) - L) % (4 * (int64_t)L);
+    if (k < 0) k += 4 * (int64_t)L;
+    return tab[k];
+}
+
+/* S_mn = sum_{i<lx} sum_{j<ly} rho_ij cos(pi m (i+1/2)/lx) cos(pi n (j+1/2)/ly),
+ * stored as S[n * lx + m]: Eq. 7 with the integral taken by the midpoint
+ * rule on the cell centres, before the 4 / ((1 + delta_m0)(1 + delta_n0))
+ * factor.  Computed as two separable passes of direct sums. */
+int ffbo_dct2(int32_t lx, int32_t ly, const double *rho, double *S)
+{
+    if (lx <= 0 || ly <= 0) return O_E_INVALID;
+    double *tx = make_table(lx), *ty = make_table(ly);
+    double *T = (double *)malloc(sizeof(double) * (size_t)lx * ly);
+    if (!tx || !ty || !T) { free(tx); free(ty); free(T); return O_E_NOMEM; }
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t m = 0; m < lx; ++m) {
+            double s = 0.0;
+            for (int32_t i = 0; i < lx; ++i) s += rho[(int64_t)j * lx + i] * tcos(tx, lx, m, i);
+            T[(int64_t)j * lx + m] = s;
+        }
+#pragma omp parallel for schedule(static)
+    for (int32_t n = 0; n < ly; ++n)
+        for (int32_t m = 0; m < lx; ++m) {
+            double s = 0.0;
+            for (int32_t j = 0; j < ly; ++j) s += T[(int64_t)j * lx + m] * tcos(ty, ly, n, j);
+            S[(int64_t)n * lx + m] = s;
+        }
+    free(tx); free(ty); free(T);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Blur, flux and blurred density on the grid nodes (i + 1/2, j + 1/2).
+ *
+ *  rt_mn   = 4 S_mn / ((1 + delta_m0)(1 + delta_n0))                 (Eq. 7)
+ *  rts_mn  = rt_mn * exp(-pi^2 sigma^2 (m^2/lx^2 + n^2/ly^2) / 2)
+ *            (the Gaussian blur of the initial density, read as the heat
+ *            kernel with the box's reflecting edges, which is diagonal in
+ *            this cosine basis; sigma in grid units)
+ *  rho_bar = rts_00 / (lx ly)                  (rt_00 = rho_bar lx ly, SI)
+ *  rho_s   = (1/(lx ly)) sum_mn rts_mn cos cos        (SI backward series)
+ *  J_x     = (ly/pi) sum_{m>=1,n>=0} m/(m^2 ly^2 + n^2 lx^2) rts_mn sin cos
+ *  J_y     = (lx/pi) sum_{m>=0,n>=1} n/(m^2 ly^2 + n^2 lx^2) rts_mn cos sin
+ *
+ * Sign reading: the SI coefficients of the flux for linear equalisation are
+ * positive multiples of rt_mn, and inserting them into the SI sine/cosine
+ * series of J gives the "+" sign used here (the flux leaves dense regions,
+ * div J = rho_0 - rho_bar, as the continuity equation with Eq. 4 demands);
+ * the leading minus printed in Eq. 5-6 is taken as a typo.
+ * The series are truncated at m < lx, n < ly.
+ * ---------------------------------------------------------------------- */
+int ffbo_flux(int32_t lx, int32_t ly, const double *rho, double sigma,
+              double *rho_s, double *jx, double *jy, double *rho_bar_out, double *coef_out)
+{
+    if (lx <= 0 || ly <= 0 || !(sigma >= 0.0)) return O_E_INVALID;
+    const int64_t N = (int64_t)lx * ly;
+    for (int64_t c = 0; c < N; ++c)
+        if (!isfinite(rho[c])) return O_E_NONFINITE;
+    double *S = (double *)malloc(sizeof(double) * N);
+    double *A = (double *)malloc(sizeof(double) * N);
+    double *B = (double *)malloc(sizeof(double) * N);
+    double *C = (double *)malloc(sizeof(double) * N);
+    double *tx = make_table(lx), *ty = make_table(ly);
+    if (!S || !A || !B || !C || !tx || !ty) {
+        free(S); free(A); free(B); free(C); free(tx); free(ty);
+        return O_E_NOMEM;
+    }
+    int st = ffbo_dct2(lx, ly, rho, S);
+    if (st) { free(S); free(A); free(B); free(C); free(tx); free(ty); return st; }
+
+    for (int32_t n = 0; n < ly; ++n)
+        for (int32_t m = 0; m < lx; ++m) {
+            double f = 4.0 / ((m == 0 ? 2.0 : 1.0) * (n == 0 ? 2.0 : 1.0));
+            double k2 = (double)m * m / ((double)lx * lx) + (double)n * n / ((double)ly * ly);
+            S[(int64_t)n * lx + m] *= f * exp(-PI * PI * sigma * sigma * k2 / 2.0);
+        }
+    if (coef_out) memcpy(coef_out, S, sizeof(double) * N);
+    const double rho_bar = S[0] / (double)N;
+    const double LX = lx, LY = ly;
+
+    /* pass over n (y frequency) for each node row j and x frequency m */
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t m = 0; m < lx; ++m) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int32_t n = 0; n < ly; ++n) {
+                double r = S[(int64_t)n * lx + m];
+                double cy = tcos(ty, ly, n, j), sy = tsin(ty, ly, n, j);
+                double den = (double)m * m * LY * LY + (double)n * n * LX * LX;
+                a += r * cy;
+                if (m > 0) b += (LY / PI) * ((double)m / den) * r * cy;
+                if (n > 0) c += (LX / PI) * ((double)n / den) * r * sy;
+            }
+            A[(int64_t)j * lx + m] = a;
+            B[(int64_t)j * lx + m] = b;
+            C[(int64_t)j * lx + m] = c;
+        }
+    /* pass over m (x frequency) for each node (i, j) */
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t i = 0; i < lx; ++i) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int32_t m = 0; m < lx; ++m) {
+                double cx = tcos(tx, lx, m, i), sx = tsin(tx, lx, m, i);
+                a += A[(int64_t)j * lx + m] * cx;
+                b += B[(int64_t)j * lx + m] * sx;
+                c += C[(int64_t)j * lx + m] * cx;
+            }
+            rho_s[(int64_t)j * lx + i] = a / (double)N;
+            jx[(int64_t)j * lx + i] = b;
+            jy[(int64_t)j * lx + i] = c;
+        }
+    free(S); free(A); free(B); free(C); free(tx); free(ty);
+    *rho_bar_out = rho_bar;
+    double mn = INFINITY;
+    for (int64_t c = 0; c < N; ++c) if (rho_s[c] < mn) mn = rho_s[c];
+    if (!(mn > 0.0) || !(rho_bar > 0.0)) return O_E_NONPOSITIVE;
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Velocity at an arbitrary point (main text: v at each grid point by basic
+ * arithmetic, then interpolation between grid points).
+ * Node velocity: v_ij(t) = J_ij / ((1 - t) rho_s_ij + t rho_bar)   (Eq. 4-6).
+ * Lookup at q clamped to the box: u = q_x - 1/2, i0 = floor(u), alpha =
+ * u - i0 (same in y), bilinear in the four surrounding nodes.  Nodes outside
+ * the grid (index -1 or L) take the values the sine/cosine series have at
+ * the mirrored cell centres: v_x is odd and v_y even across the x edges,
+ * v_x even and v_y odd across the y edges, so v . n = 0 on the box.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t lx, ly;
+    const double *rho_s, *jx, *jy;
+    double rho_bar;
+} field_t;
+
+static void node_velocity(const field_t *F, double t, int32_t i, int32_t j,
+                          double *vx, double *vy)
+{
+    double sx = 1.0, sy = 1.0;
+    if (i < 0) { i = 0; sx = -sx; }
+    if (i >= F->lx) { i = F->lx - 1; sx = -sx; }
+    if (j < 0) { j = 0; sy = -sy; }
+    if (j >= F->ly) { j = F->ly - 1; sy = -sy; }
+    int64_t c = (int64_t)j * F->lx + i;
+    double rt = (1.0 - t) * F->rho_s[c] + t * F->rho_bar;
+    *vx = sx * F->jx[c] / rt;
+    *vy = sy * F->jy[c] / rt;
+}
+
+static void velocity_at(const field_t *F, double t, double qx, double qy,
+                        double *vx, double *vy)
+{
+    if (qx < 0.0) qx = 0.0;
+    if (qx > F->lx) qx = F->lx;
+    if (qy < 0.0) qy = 0.0;
+    if (qy > F->ly) qy = F->ly;
+    double u = qx - 0.5, w = qy - 0.5;
+    double fu = floor(u), fw = floor(w);
+    int32_t i0 = (int32_t)fu, j0 = (int32_t)fw;
+    double a = u - fu, b = w - fw;
+    double x00, y00, x10, y10, x01, y01, x11, y11;
+    node_velocity(F, t, i0, j0, &x00, &y00);
+    node_velocity(F, t, i0 + 1, j0, &x10, &y10);
+    node_velocity(F, t, i0, j0 + 1, &x01, &y01);
+    node_velocity(F, t, i0 + 1, j0 + 1, &x11, &y11);
+    /* interpolate along x on both node rows, then along y */
+    *vx = (1 - b) * ((1 - a) * x00 + a * x10) + b * ((1 - a) * x01 + a * x11);
+    *vy = (1 - b) * ((1 - a) * y00 + a * y10) + b * ((1 - a) * y01 + a * y11);
+}
+
+int ffbo_velocity(int32_t lx, int32_t ly, const double *rho_s, const double *jx,
+                  const double *jy, double rho_bar, double t, int64_t n,
+                  const double *q, double *v)
+{
+    if (lx <= 0 || ly <= 0 || n < 0) return O_E_INVALID;
+    field_t F = {lx, ly, rho_s, jx, jy, rho_bar};
+    for (int64_t p = 0; p < n; ++p)
+        velocity_at(&F, t, q[2 * p], q[2 * p + 1], &v[2 * p], &v[2 * p + 1]);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Time integration of dr/dt = v(r, t) from t = 0 to exactly t = 1 for all
+ * points together (main text: an adaptive predictor-corrector method, with
+ * the integrands of all grid points advanced in each step).  The method is
+ * the embedded Runge-Kutta pair of Dormand and Prince (1980), order 5 with
+ * an order-4 error estimate and first-same-as-last stages.  One step size
+ * serves all points.  Controller (constants are arguments):
+ *   err = max over points and both components of |h sum_s (b_s - b*_s) k_s|
+ *   accept iff err <= tol;
+ *   fac = safety * (err / tol)^(-1/5), limited to [fac_min, fac_max]
+ *         (fac_max when err = 0), and to at most 1 on the attempt that
+ *         follows a rejection;
+ *   the step is clipped so that the last one ends exactly at t = 1;
+ *   h < h_min before t = 1 is a step underflow.
+ * Replay mode takes a given sequence of accepted steps and skips control.
+ * ---------------------------------------------------------------------- */
+static const double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+static const double DP_B[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192,
+                               -2187.0 / 6784, 11.0 / 84, 0};
+static const double DP_BS[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640,
+                                -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+
+void ffbo_tableau(double *c, double *a, double *b, double *bs)
+{
+    for (int s = 0; s < 7; ++s) {
+        c[s] = DP_C[s];
+        b[s] = DP_B[s];
+        bs[s] = DP_BS[s];
+        for (int q = 0; q < 6; ++q) a[s * 6 + q] = DP_A[s][q];
+    }
+}
+
+/* One attempt of size h from (y, t) with k[0] = v(y, t) already known.
+ * Writes the order-5 solution to ynew, its velocity to k[6], returns err. */
+static double dp_attempt(const field_t *F, int64_t n, const double *y, double t, double h,
+                         double *k[7], double *ynew)
+{
+    for (int s = 1; s < 7; ++s) {
+        double ts = t + DP_C[s] * h;
+        double *dst = (s == 6) ? ynew : NULL;
+#pragma omp parallel for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            double qx = y[2 * p], qy = y[2 * p + 1];
+            for (int q = 0; q < s; ++q) {
+                qx += h * DP_A[s][q] * k[q][2 * p];
+                qy += h * DP_A[s][q] * k[q][2 * p + 1];
+            }
+            if (dst) { dst[2 * p] = qx; dst[2 * p + 1] = qy; }
+            velocity_at(F, ts, qx, qy, &k[s][2 * p], &k[s][2 * p + 1]);
+        }
+    }
+    double err = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : err)
+    for (int64_t p = 0; p < n; ++p) {
+        for (int d = 0; d < 2; ++d) {
+            double e = 0.0;
+            for (int s = 0; s < 7; ++s) e += (DP_B[s] - DP_BS[s]) * k[s][2 * p + d];
+            e = fabs(h * e);
+            if (!(e <= err)) err = isnan(e) ? INFINITY : e;
+        }
+    }
+    return err;
+}
+
+int ffbo_integrate(int32_t lx, int32_t ly, const double *rho_s, const double *jx,
+                   const double *jy, double rho_bar, int64_t n, double *xy,
+                   double tol, double h0, double safety, double fac_min, double fac_max,
+                   double h_min, int32_t max_attempts,
+                   const double *replay_h, int32_t n_replay,
+                   int32_t *accepted_out, int32_t *rejected_out,
+                   double *h_out, int32_t h_cap)
+{
+    if (lx <= 0 || ly <= 0 || n < 0 || !(rho_bar > 0.0)) return O_E_INVALID;
+    if (!replay_h && (!(tol > 0.0) || !(h0 > 0.0) || max_attempts <= 0)) return O_E_INVALID;
+    field_t F = {lx, ly, rho_s, jx, jy, rho_bar};
+    double *k[7];
+    double *ynew = (double *)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
+    int ok = ynew != NULL;
+    for (int s = 0; s < 7; ++s) {
+        k[s] = (double *)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
+        ok = ok && k[s];
+    }
+    int st = O_OK;
+    int32_t acc = 0, rej = 0;
+    if (!ok) { st = O_E_NOMEM; goto done; }
+
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p)
+        velocity_at(&F, 0.0, xy[2 * p], xy[2 * p + 1], &k[0][2 * p], &k[0][2 * p + 1]);
+
+    double t = 0.0;
+    if (replay_h) {
+        for (int32_t s = 0; s < n_replay; ++s) {
+            double h = replay_h[s];
+            double err = dp_attempt(&F, n, xy, t, h, k, ynew);
+            if (!isfinite(err)) { st = O_E_NONFINITE; break; }
+            memcpy(xy, ynew, sizeof(double) * 2 * (size_t)n);
+            double *tmp = k[0]; k[0] = k[6]; k[6] = tmp;
+            t = (s == n_replay - 1) ? 1.0 : t + h;
+            if (h_out && acc < h_cap) h_out[acc] = h;
+            acc++;
+        }
+        goto done;
+    }
+
+    double h = h0;
+    int last_rejected = 0;
+    int32_t attempts = 0;
+    while (t < 1.0) {
+        if (attempts >= max_attempts) { st = O_E_MAX_ATTEMPTS; break; }
+        int final_step = h >= 1.0 - t;
+        if (final_step) h = 1.0 - t;
+        double err = dp_attempt(&F, n, xy, t, h, k, ynew);
+        attempts++;
+        if (!isfinite(err)) { st = O_E_NONFINITE; break; }
+        if (err <= tol) {
+            memcpy(xy, ynew, sizeof(double) * 2 * (size_t)n);
+            double *tmp = k[0]; k[0] = k[6]; k[6] = tmp;
+            if (h_out && acc < h_cap) h_out[acc] = h;
+            acc++;
+            t = final_step ? 1.0 : t + h;
+            double fac = (err == 0.0) ? fac_max : safety * pow(err / tol, -0.2);
+            if (fac < fac_min) fac = fac_min;
+            if (fac > fac_max) fac = fac_max;
+            if (last_rejected && fac > 1.0) fac = 1.0;
+            h *= fac;
+            last_rejected = 0;
+        } else {
+            rej++;
+            double fac = safety * pow(err / tol, -0.2);
+            if (fac < fac_min) fac = fac_min;
+            h *= fac;
+            last_rejected = 1;
+        }
+        if (t < 1.0 && h < h_min) { st = O_E_STEP_UNDERFLOW; break; }
+    }
+done:
+    free(ynew);
+    for (int s = 0; s < 7; ++s) free(k[s]);
+    if (accepted_out) *accepted_out = acc;
+    if (rejected_out) *rejected_out = rej;
+    return st;
+}
