@@ -1,0 +1,196 @@
+"""Benchmark: milliseconds per fast flow-based cartogram iteration on one GPU.
+
+One step = one FFB iteration of the whole hot path on the L = 1024 workload
+(600-region seeded Voronoi map, Pareto(1.2) densities clipped at 1e3, 1.0 M
+polygon vertices plus all 1024^2 grid nodes advected): areas, density grid,
+blur + flux transforms, adaptive Dormand-Prince advection of every point to
+t = 1, areas and relative errors.  Each step starts from the same resident
+input map (a device-to-device copy of the points, inside the timed region),
+so every step does the same work.  Inputs are resident in HBM before timing.
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel
+(the advection launch, timed with events on its stream) and the FP64 oracle
+timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3_L1024")
+    ap.add_argument("--sigma", type=float, default=4.0)
+    ap.add_argument("--tol", type=float, default=1e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=64,
+                    help="the oracle advects 1/N of the points (other phases full size)")
+    ap.add_argument("--loop", action="store_true",
+                    help="also run the full loop to < 1%% error and report it")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_1802_07625_amd as ffb
+
+    if not os.path.exists(ffb.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    m = synth.workload(args.workload)
+    L = m.lx
+    pts_h = np.concatenate([m.xy, synth.grid_nodes(L, L)]).astype(np.float32)
+    P, V = pts_h.shape[0], m.n_vertices
+    print(f"# workload {args.workload}: L={L} regions={m.n_regions} V={V} P={P} E={m.n_entries}",
+          file=sys.stderr, flush=True)
+    pts0 = torch.as_tensor(pts_h, device=dev)
+    pts = pts0.clone()
+    geom = ffb.Geometry.from_map(m, xy=pts[:V])
+    value = torch.as_tensor(m.value, dtype=torch.float64, device=dev)
+    ctx = ffb.Context(L, L, max_points=P)
+    opts = ffb.IntegrateOpts(tol=args.tol)
+    stream = torch.cuda.current_stream()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    stats_all = torch.zeros((max(args.steps, 1), 4), dtype=torch.int32, device=dev)
+
+    def step(i=None):
+        pts.copy_(pts0)
+        area0, _, _ = ctx.area_error(geom, value)
+        rho, pad = ctx.density(geom, value, area0)
+        fields, rb = ctx.flux(rho, args.sigma)
+        st = stats_all[i] if i is not None else None
+        if i is not None:
+            ev[i][0].record(stream)
+        stats, _ = ctx.integrate(fields, rb, pts, opts, h_cap=0, stats=st)
+        if i is not None:
+            ev[i][1].record(stream)
+        area1, err1, mx = ctx.area_error(geom, value)
+        return stats, mx
+
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        stats, mx = step(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()
+    ms_step = 1e3 * wall / args.steps
+    adv_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    st = stats_all.cpu().numpy()
+    attempts = st[:, 2].astype(np.float64)
+    # algorithmic bytes of one advection launch: per RK attempt the point
+    # state is read and written once (16 B per point) and the packed fields
+    # are read once (16 B per node); S attempts per launch
+    bytes_per_attempt = 16.0 * P + 16.0 * L * L
+    achieved = float(np.mean(bytes_per_attempt * attempts / (adv_ms * 1e-3)) / 1e9)
+    # ALU view: ~6 stage evaluations per attempt, counted from the kernel's
+    # instruction mix -- reported for context only
+    result = {
+        "metric": "ms per FFB iteration at L=1024 (FP32 vs FP64 oracle); fwd+bwd/fwd time",
+        "value": round(ms_step, 4),
+        "unit": "ms/iteration",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "L": L, "regions": m.n_regions,
+                   "vertices": V, "points": P, "ring_entries": m.n_entries,
+                   "densities": "pareto(1.2) clipped 1e3" if args.workload == "c3_L1024" else "",
+                   "sigma": args.sigma, "tol": args.tol,
+                   "rk_attempts_mean": float(attempts.mean()),
+                   "rk_accepted_mean": float(st[:, 0].mean()),
+                   "advect_ms_mean": round(float(adv_ms.mean()), 4),
+                   "us_per_attempt": round(float((adv_ms / attempts).mean() * 1e3), 3),
+                   "final_max_area_error": float(mx)},
+        "roofline": {"kernel": "k_advect", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_attempt": bytes_per_attempt},
+    }
+
+    if args.loop:
+        pts.copy_(pts0)
+        rounds, mxv, t_loop = 0, None, time.perf_counter()
+        area = None
+        for k in range(30):
+            res = ffb.iterate(ctx, geom, value, pts, ffb.default_sigma(k), opts, area_before=area)
+            area = res.area_after
+            rounds += 1
+            mxv = float(res.max_err_after)     # sync point once per round
+            if mxv < 0.01:
+                break
+        torch.cuda.synchronize()
+        result["loop"] = {"rounds": rounds, "max_area_error": mxv,
+                          "total_ms": round(1e3 * (time.perf_counter() - t_loop), 2)}
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(m, pts_h, args)
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(m, pts_h, args):
+    """The FP64 oracle, untuned, on the host cores: every phase at full size
+    except the advection, which runs on a random 1/N of the points with the
+    oracle's own step control; its time is scaled by N."""
+    import oracle
+    cores = oracle.set_threads(0)
+    rng = np.random.default_rng(0)
+    N = args.cpu_sample
+    idx = rng.choice(pts_h.shape[0], pts_h.shape[0] // N, replace=False)
+    t = {}
+    t0 = time.perf_counter()
+    a = oracle.region_areas(m)
+    t["area"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rho, _ = oracle.density(m, m.value, a)
+    t["density"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F = oracle.flux(rho, args.sigma)
+    t["flux"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = oracle.integrate(F, pts_h[idx].astype(np.float64), oracle.IntegrateOpts(tol=args.tol))
+    t["advect_sample"] = time.perf_counter() - t0
+    est = 2 * t["area"] + t["density"] + t["flux"] + N * t["advect_sample"]
+    return {"value": round(1e3 * est, 1), "unit": "ms/iteration", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"areas, raster and direct-sum transforms at full size; advection of "
+                       f"{len(idx)} random points (1/{N}) with the oracle's own control "
+                       f"({r.accepted} accepted, {r.rejected} rejected), time x{N}"),
+            "phases_s": {k: round(v, 3) for k, v in t.items()}}
+
+
+if __name__ == "__main__":
+    main()

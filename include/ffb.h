@@ -1,0 +1,183 @@
+/*
+ * ffb.h -- C ABI of the MI355X (gfx950) implementation of one iteration of
+ * the fast flow-based cartogram method (Gastner, Seguy & More, "Fast
+ * flow-based algorithm for creating density-equalizing map projections").
+ *
+ * One iteration ("round") of the method:
+ *   1. ffb_area_error  -- region areas and relative area errors (the stopping
+ *                         rule of the benchmarking section: stop when the
+ *                         largest relative area error is below 1 %);
+ *   2. ffb_density     -- region densities value/area painted onto the
+ *                         lx x ly grid with exact cell coverage, the space
+ *                         outside the map at the mean density;
+ *   3. ffb_flux        -- Gaussian blur, the cosine coefficients of Eq. 7 and
+ *                         the flux series of the SI Appendix (section 2) for
+ *                         linear equalisation, evaluated on the grid nodes;
+ *   4. ffb_integrate   -- every point advected from t = 0 to t = 1 with
+ *                         v = J / rho_t (Eq. 4-6), bilinear interpolation
+ *                         between grid nodes and adaptive Dormand-Prince 5(4)
+ *                         steps shared by all points (main text, section
+ *                         "Flow-based cartogram with linear equalization");
+ *   5. ffb_area_error  -- again, on the advected polygons.
+ *
+ * Conventions shared by every call
+ *  - Pointers are DEVICE memory unless marked (host).  The caller owns every
+ *    buffer it passes and keeps it alive until the stream has passed the
+ *    work; the library never frees caller memory.
+ *  - Every call only enqueues work on the context's HIP stream and returns.
+ *    Host-detectable argument errors return a non-zero status before any
+ *    launch (ffb_last_error has the detail).  Errors found on the device
+ *    (non-finite or out-of-box coordinates, non-positive densities, step
+ *    underflow, malformed rings) set a sticky status word that ffb_sync
+ *    returns; later kernels of the same context see it and do nothing.
+ *  - Grids are row-major with x fastest: cell (i, j) = [i, i+1] x [j, j+1]
+ *    is element j * lx + i; its node (centre) is (i + 1/2, j + 1/2).
+ *  - lx and ly are powers of two in [8, 1024].  Coordinates live in the box
+ *    [0, lx] x [0, ly] whose edges reflect the flow.
+ *  - Precision: FP32 grids, fields and positions; FP64 for area sums, the
+ *    padding density, the mean density rho_bar and the step controller.
+ *  - One context per stream; a context is not thread-safe.
+ */
+#ifndef FFB_H
+#define FFB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffb_ctx ffb_ctx;
+
+enum {
+    FFB_OK = 0,
+    FFB_E_INVALID = 1,          /* bad argument, malformed rings            */
+    FFB_E_NOMEM = 2,            /* device allocation failed                 */
+    FFB_E_DEVICE = 3,           /* HIP runtime or launch failure            */
+    FFB_E_NONPOSITIVE = 4,      /* value, area or blurred density <= 0      */
+    FFB_E_DOMAIN = 5,           /* polygon vertex outside the box           */
+    FFB_E_STEP_UNDERFLOW = 6,   /* adaptive step fell below h_min           */
+    FFB_E_NONFINITE = 7,        /* NaN or Inf in coordinates or velocities  */
+    FFB_E_NO_TAPE = 8,          /* reserved                                 */
+    FFB_E_MAX_ATTEMPTS = 9      /* integration used up max_attempts         */
+};
+
+/* Polygon geometry in CSR-ring form over unique vertices (a region is one or
+ * more rings; counter-clockwise rings add area, clockwise rings are holes).
+ * The struct itself is host memory; its arrays are device memory. */
+typedef struct {
+    int64_t n_vertices;          /* V                                         */
+    const float *xy;             /* [V][2] vertex coordinates (box units)     */
+    int32_t n_rings;             /* G                                         */
+    const int32_t *ring_offsets; /* [G + 1], ring g is entries [off[g], off[g+1]) */
+    const int32_t *ring_vidx;    /* [E] vertex index of each ring entry       */
+    const int32_t *ring_region;  /* [G] region of each ring, in [0, R)        */
+    int32_t n_regions;           /* R                                         */
+    int64_t n_entries;           /* E = ring_offsets[G] (passed by the host)  */
+} ffb_geometry;
+
+/* Controller of the adaptive integration (host struct).  The paper only says
+ * that a predictor-corrector method adapts the next step; these constants
+ * are the caller's choice.  An attempt of size h has error estimate
+ * err = max over points and components |h sum_s (b_s - b*_s) k_s| (grid
+ * units); it is accepted iff err <= tol; then h *= clamp(safety *
+ * (err/tol)^(-1/5), fac_min, fac_max), with no growth right after a
+ * rejection; a rejection multiplies h by max(fac_min, safety *
+ * (err/tol)^(-1/5)).  The last step is clipped to end exactly at t = 1. */
+typedef struct {
+    double tol;            /* > 0, e.g. 1e-3                                   */
+    double h0;             /* first attempted step, e.g. 1e-2                  */
+    double safety;         /* e.g. 0.9                                         */
+    double fac_min;        /* e.g. 0.2                                         */
+    double fac_max;        /* e.g. 5                                           */
+    double h_min;          /* step underflow threshold, e.g. 1e-7              */
+    int32_t max_attempts;  /* attempts allowed before FFB_E_MAX_ATTEMPTS       */
+    int32_t n_replay;      /* > 0: take exactly these accepted steps (below)   */
+    const double *replay_h;/* device [n_replay] step sizes summing to 1, or NULL */
+} ffb_integrate_opts;
+
+/* Create a context bound to `hip_stream` (a hipStream_t, NULL = default
+ * stream) for an lx x ly grid.  `max_points` sizes the integrator's state
+ * buffers (they grow on demand later; growth allocates).  *out (host)
+ * receives the context.  Returns FFB_E_INVALID for bad sizes. */
+int ffb_create(ffb_ctx **out, int32_t lx, int32_t ly, int64_t max_points, void *hip_stream);
+
+/* Free the context and its device workspace (waits for its stream). */
+int ffb_destroy(ffb_ctx *ctx);
+
+/* Wait for the stream; return the sticky device status (FFB_OK if none). */
+int ffb_sync(ffb_ctx *ctx);
+
+/* Clear the sticky device status (enqueued on the stream). */
+int ffb_reset_status(ffb_ctx *ctx);
+
+/* Human-readable detail of the last host-side failure (host string owned by
+ * the context; valid until the next call on it). */
+const char *ffb_last_error(const ffb_ctx *ctx);
+
+/* Areas and relative area errors (benchmarking section, stopping rule).
+ *   area[r]  (out, [R]) = sum over the rings of region r of the shoelace sum
+ *            1/2 sum_k (x_k y_{k+1} - x_{k+1} y_k), FP64 sums of products of
+ *            the FP32 coordinates;
+ *   err[r]   (out, [R]) = area_r / T_r - 1 with T_r = value_r sum(area)/sum(value);
+ *   max_abs_err (out, [1]) = max_r |err[r]|.
+ * value[r] (in, [R]) is the region's statistic, > 0 (else FFB_E_NONPOSITIVE
+ * on the device).  Malformed rings (offsets out of range, fewer than three
+ * entries, vertex or region index out of range) give FFB_E_INVALID on the
+ * device; NaN/Inf coordinates give FFB_E_NONFINITE. */
+int ffb_area_error(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
+                   double *area, double *err, double *max_abs_err);
+
+/* Density grid (section on previous all-coordinates methods: region density
+ * = statistic / area; benchmarking section: the box around the map holds the
+ * mean density).  With d_r = value_r / area_r and
+ * rho_pad = sum(value) / sum(area),
+ *   rho[j][i] = rho_pad + sum_r (d_r - rho_pad) * |cell(i,j) ∩ region_r|
+ * (exact signed coverage of each cell).  area is ffb_area_error's output for
+ * the same vertices.  rho (out) is [ly][lx] FP32, rho_pad (out) [1] FP64.
+ * Vertices outside [0,lx] x [0,ly] give FFB_E_DOMAIN on the device. */
+int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
+                const double *area, float *rho, double *rho_pad);
+
+/* Blur and flux (Eq. 7; SI Appendix section 2, flux of linear equalisation).
+ * From rho [ly][lx] (in):
+ *   rt_mn  = 4 S_mn / ((1+delta_m0)(1+delta_n0)),
+ *            S_mn = sum_ij rho_ij cos(pi m (i+1/2)/lx) cos(pi n (j+1/2)/ly);
+ *   rts_mn = rt_mn exp(-pi^2 sigma^2 (m^2/lx^2 + n^2/ly^2) / 2)   (sigma >= 0,
+ *            grid cells: the Gaussian blur applied before integration);
+ *   rho_s  = (1/(lx ly)) sum_mn rts_mn cos cos;
+ *   J_x    = (ly/pi) sum_{m>=1} m/(m^2 ly^2 + n^2 lx^2) rts_mn sin cos;
+ *   J_y    = (lx/pi) sum_{n>=1} n/(m^2 ly^2 + n^2 lx^2) rts_mn cos sin;
+ * on the nodes, written as fields (out) = float4 [(ly+2)][(lx+2)] holding
+ * (J_x, J_y, rho_s, 0) with a one-node ghost border: node (i, j) is element
+ * (j+1)(lx+2) + (i+1); ghost nodes hold the series' values at the mirrored
+ * cell centres (J_x odd and J_y even across x edges, J_x even and J_y odd
+ * across y edges, rho_s even).  rho_bar (out, [1], FP64) = mean of rho.
+ * min rho_s <= 0 gives FFB_E_NONPOSITIVE on the device. */
+int ffb_flux(ffb_ctx *ctx, const float *rho, float sigma, float *fields, double *rho_bar);
+
+/* Pack node arrays jx, jy, rho_s ([ly][lx] each, in) into the ghosted
+ * float4 field layout of ffb_flux (out, [(ly+2)][(lx+2)][4]). */
+int ffb_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy, const float *rho_s,
+                    float *fields);
+
+/* Advect n points xy ([n][2], in/out, FP32) from t = 0 to t = 1 through
+ * v(r, t) = J(r) / ((1 - t) rho_s(r) + t rho_bar) (Eq. 4-6), with node
+ * velocities interpolated bilinearly (lookups clamped to the box, ghost
+ * nodes from `fields`) and Dormand-Prince 5(4) steps shared by all points.
+ * fields and rho_bar are ffb_flux outputs (or ffb_pack_fields + a caller
+ * value).  During the call positions are carried as compensated FP32 pairs;
+ * the result is rounded to FP32.  opts (host) is read at the call.
+ * stats (out, [4] int32): accepted, rejected, attempts, final status.
+ * h_out (out, [h_cap] FP64, may be NULL): the accepted step sizes in order.
+ * The whole integration is one persistent launch: step control happens on
+ * the device, with no host round trip per step. */
+int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
+                  int64_t n, const ffb_integrate_opts *opts, int32_t *stats,
+                  double *h_out, int32_t h_cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFB_H */

@@ -67,6 +67,8 @@ def lib():
         L.ffbo_density.argtypes = [i32, i32, i64, _d, i32, _i32, _i32, _i32, i32, _d, _d, _d, _d]
         L.ffbo_dct2.argtypes = [i32, i32, _d, _d]
         L.ffbo_flux.argtypes = [i32, i32, _d, dbl, _d, _d, _d, _d, _d]
+        L.ffbo_coefficients.argtypes = [i32, i32, _d, dbl, _d, _d]
+        L.ffbo_flux_nodes.argtypes = [i32, i32, _d, i64, _i32, _i32, _d]
         L.ffbo_velocity.argtypes = [i32, i32, _d, _d, _d, dbl, dbl, i64, _d, _d]
         L.ffbo_tableau.argtypes = [_d, _d, _d, _d]
         L.ffbo_integrate.argtypes = [i32, i32, _d, _d, _d, dbl, i64, _d,
@@ -171,6 +173,28 @@ def flux(rho, sigma: float, keep_coef: bool = False) -> Fields:
     _check(lib().ffbo_flux(lx, ly, _p(rho), float(sigma), _p(rs), _p(jx), _p(jy),
                            _p(rb), _p(coef) if keep_coef else None), "flux")
     return Fields(lx, ly, rs, jx, jy, float(rb[0]), coef)
+
+
+def coefficients(rho, sigma: float):
+    """Blurred Eq. 7 coefficients rts[n, m] and rho_bar (forward half only)."""
+    rho = _f64(rho)
+    ly, lx = rho.shape
+    coef = np.zeros_like(rho)
+    rb = np.zeros(1)
+    _check(lib().ffbo_coefficients(lx, ly, _p(rho), float(sigma), _p(coef), _p(rb)),
+           "coefficients")
+    return coef, float(rb[0])
+
+
+def flux_nodes(coef, ii, jj):
+    """(J_x, J_y, rho_s) at nodes (ii[k], jj[k]) by full double sums."""
+    coef = _f64(coef)
+    ly, lx = coef.shape
+    ii, jj = _i(ii), _i(jj)
+    out = np.zeros((ii.shape[0], 3))
+    _check(lib().ffbo_flux_nodes(lx, ly, _p(coef), ii.shape[0], _p(ii, _i32), _p(jj, _i32),
+                                 _p(out)), "flux_nodes")
+    return out
 
 
 def velocity(F: Fields, t: float, q) -> np.ndarray:

@@ -339,13 +339,63 @@ int ffbo_dct2(int32_t lx, int32_t ly, const double *rho, double *S)
  * the leading minus printed in Eq. 5-6 is taken as a typo.
  * The series are truncated at m < lx, n < ly.
  * ---------------------------------------------------------------------- */
-int ffbo_flux(int32_t lx, int32_t ly, const double *rho, double sigma,
-              double *rho_s, double *jx, double *jy, double *rho_bar_out, double *coef_out)
+/* Blurred coefficients rts[n][m] and rho_bar only (the forward half). */
+int ffbo_coefficients(int32_t lx, int32_t ly, const double *rho, double sigma, double *coef,
+                      double *rho_bar_out)
 {
     if (lx <= 0 || ly <= 0 || !(sigma >= 0.0)) return O_E_INVALID;
     const int64_t N = (int64_t)lx * ly;
     for (int64_t c = 0; c < N; ++c)
         if (!isfinite(rho[c])) return O_E_NONFINITE;
+    int st = ffbo_dct2(lx, ly, rho, coef);
+    if (st) return st;
+    for (int32_t n = 0; n < ly; ++n)
+        for (int32_t m = 0; m < lx; ++m) {
+            double f = 4.0 / ((m == 0 ? 2.0 : 1.0) * (n == 0 ? 2.0 : 1.0));
+            double k2 = (double)m * m / ((double)lx * lx) + (double)n * n / ((double)ly * ly);
+            coef[(int64_t)n * lx + m] *= f * exp(-PI * PI * sigma * sigma * k2 / 2.0);
+        }
+    *rho_bar_out = coef[0] / (double)N;
+    return O_OK;
+}
+
+/* The three series at selected nodes (i[k], j[k]) by full double sums over
+ * all coefficients: out[3k] = J_x, out[3k+1] = J_y, out[3k+2] = rho_s. */
+int ffbo_flux_nodes(int32_t lx, int32_t ly, const double *coef, int64_t k, const int32_t *ii,
+                    const int32_t *jj, double *out)
+{
+    if (lx <= 0 || ly <= 0 || k < 0) return O_E_INVALID;
+    double *tx = make_table(lx), *ty = make_table(ly);
+    if (!tx || !ty) { free(tx); free(ty); return O_E_NOMEM; }
+    const double LX = lx, LY = ly;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < k; ++q) {
+        const int32_t i = ii[q], j = jj[q];
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int32_t n = 0; n < ly; ++n) {
+            const double cy = tcos(ty, ly, n, j), sy = tsin(ty, ly, n, j);
+            for (int32_t m = 0; m < lx; ++m) {
+                const double r = coef[(int64_t)n * lx + m];
+                const double cx = tcos(tx, lx, m, i), sx = tsin(tx, lx, m, i);
+                const double den = (double)m * m * LY * LY + (double)n * n * LX * LX;
+                a += r * cx * cy;
+                if (m > 0) b += (LY / PI) * ((double)m / den) * r * sx * cy;
+                if (n > 0) c += (LX / PI) * ((double)n / den) * r * cx * sy;
+            }
+        }
+        out[3 * q] = b;
+        out[3 * q + 1] = c;
+        out[3 * q + 2] = a / (LX * LY);
+    }
+    free(tx); free(ty);
+    return O_OK;
+}
+
+int ffbo_flux(int32_t lx, int32_t ly, const double *rho, double sigma,
+              double *rho_s, double *jx, double *jy, double *rho_bar_out, double *coef_out)
+{
+    if (lx <= 0 || ly <= 0 || !(sigma >= 0.0)) return O_E_INVALID;
+    const int64_t N = (int64_t)lx * ly;
     double *S = (double *)malloc(sizeof(double) * N);
     double *A = (double *)malloc(sizeof(double) * N);
     double *B = (double *)malloc(sizeof(double) * N);
@@ -355,17 +405,10 @@ int ffbo_flux(int32_t lx, int32_t ly, const double *rho, double sigma,
         free(S); free(A); free(B); free(C); free(tx); free(ty);
         return O_E_NOMEM;
     }
-    int st = ffbo_dct2(lx, ly, rho, S);
+    double rho_bar = 0.0;
+    int st = ffbo_coefficients(lx, ly, rho, sigma, S, &rho_bar);
     if (st) { free(S); free(A); free(B); free(C); free(tx); free(ty); return st; }
-
-    for (int32_t n = 0; n < ly; ++n)
-        for (int32_t m = 0; m < lx; ++m) {
-            double f = 4.0 / ((m == 0 ? 2.0 : 1.0) * (n == 0 ? 2.0 : 1.0));
-            double k2 = (double)m * m / ((double)lx * lx) + (double)n * n / ((double)ly * ly);
-            S[(int64_t)n * lx + m] *= f * exp(-PI * PI * sigma * sigma * k2 / 2.0);
-        }
     if (coef_out) memcpy(coef_out, S, sizeof(double) * N);
-    const double rho_bar = S[0] / (double)N;
     const double LX = lx, LY = ly;
 
     /* pass over n (y frequency) for each node row j and x frequency m */
@@ -464,6 +507,8 @@ int ffbo_velocity(int32_t lx, int32_t ly, const double *rho_s, const double *jx,
                   const double *q, double *v)
 {
     if (lx <= 0 || ly <= 0 || n < 0) return O_E_INVALID;
+    for (int64_t k = 0; k < 2 * n; ++k)
+        if (!isfinite(q[k])) return O_E_NONFINITE;
     field_t F = {lx, ly, rho_s, jx, jy, rho_bar};
     for (int64_t p = 0; p < n; ++p)
         velocity_at(&F, t, q[2 * p], q[2 * p + 1], &v[2 * p], &v[2 * p + 1]);
@@ -552,6 +597,8 @@ int ffbo_integrate(int32_t lx, int32_t ly, const double *rho_s, const double *jx
 {
     if (lx <= 0 || ly <= 0 || n < 0 || !(rho_bar > 0.0)) return O_E_INVALID;
     if (!replay_h && (!(tol > 0.0) || !(h0 > 0.0) || max_attempts <= 0)) return O_E_INVALID;
+    for (int64_t k = 0; k < 2 * n; ++k)
+        if (!isfinite(xy[k])) return O_E_NONFINITE;
     field_t F = {lx, ly, rho_s, jx, jy, rho_bar};
     double *k[7];
     double *ynew = (double *)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));

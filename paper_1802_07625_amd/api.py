@@ -1,0 +1,322 @@
+"""Thin Python binding of the libffb C ABI (include/ffb.h).
+
+Only argument marshalling happens here: torch tensors supply device memory,
+``torch.cuda.current_stream()`` supplies the HIP stream, and every step of
+the method runs in the HIP kernels behind the C ABI.  There is no CPU
+fallback: if the library is not built, importing the binding fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libffb.so")
+
+FFB_OK = 0
+STATUS = {
+    0: "FFB_OK", 1: "FFB_E_INVALID", 2: "FFB_E_NOMEM", 3: "FFB_E_DEVICE",
+    4: "FFB_E_NONPOSITIVE", 5: "FFB_E_DOMAIN", 6: "FFB_E_STEP_UNDERFLOW",
+    7: "FFB_E_NONFINITE", 8: "FFB_E_NO_TAPE", 9: "FFB_E_MAX_ATTEMPTS",
+}
+globals().update({name: code for code, name in STATUS.items()})
+
+
+class FFBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class FFBGeometry(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("xy", ctypes.c_void_p),
+                ("n_rings", ctypes.c_int32), ("ring_offsets", ctypes.c_void_p),
+                ("ring_vidx", ctypes.c_void_p), ("ring_region", ctypes.c_void_p),
+                ("n_regions", ctypes.c_int32), ("n_entries", ctypes.c_int64)]
+
+
+class FFBIntegrateOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("h0", ctypes.c_double),
+                ("safety", ctypes.c_double), ("fac_min", ctypes.c_double),
+                ("fac_max", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("max_attempts", ctypes.c_int32), ("n_replay", ctypes.c_int32),
+                ("replay_h", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libffb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.ffb_create.argtypes = [ctypes.POINTER(vp), i32, i32, i64, vp]
+        L.ffb_destroy.argtypes = [vp]
+        L.ffb_sync.argtypes = [vp]
+        L.ffb_reset_status.argtypes = [vp]
+        L.ffb_last_error.argtypes = [vp]
+        L.ffb_last_error.restype = ctypes.c_char_p
+        G = ctypes.POINTER(FFBGeometry)
+        L.ffb_area_error.argtypes = [vp, G, vp, vp, vp, vp]
+        L.ffb_density.argtypes = [vp, G, vp, vp, vp, vp]
+        L.ffb_flux.argtypes = [vp, vp, ctypes.c_float, vp, vp]
+        L.ffb_pack_fields.argtypes = [vp, vp, vp, vp, vp]
+        L.ffb_integrate.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(FFBIntegrateOpts),
+                                    vp, vp, i32]
+        for f in ("ffb_create", "ffb_destroy", "ffb_sync", "ffb_reset_status", "ffb_area_error",
+                  "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------ marshalling
+def _ptr(t: torch.Tensor | None, dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(ctx, code: int, what: str):
+    if code != FFB_OK:
+        detail = lib().ffb_last_error(ctx).decode() if ctx else ""
+        raise FFBError(code, f"{what}: {detail}")
+
+
+@dataclass
+class Geometry:
+    """CSR rings over unique vertices, all device tensors."""
+    xy: torch.Tensor            # float32 [V, 2] (may be a view into a points tensor)
+    ring_offsets: torch.Tensor  # int32 [G + 1]
+    ring_vidx: torch.Tensor     # int32 [E]
+    ring_region: torch.Tensor   # int32 [G]
+    n_regions: int
+
+    @classmethod
+    def from_map(cls, m, xy: torch.Tensor | None = None, device="cuda"):
+        """From a synthetic map (host arrays) with vertices ``xy`` (device)."""
+        if xy is None:
+            xy = torch.as_tensor(m.xy, dtype=torch.float32, device=device)
+        t = lambda a: torch.as_tensor(a, dtype=torch.int32, device=device).contiguous()
+        return cls(xy, t(m.ring_offsets), t(m.ring_vidx), t(m.ring_region), int(m.n_regions))
+
+    def struct(self) -> FFBGeometry:
+        return FFBGeometry(
+            n_vertices=self.xy.shape[0], xy=_ptr(self.xy, torch.float32, name="xy"),
+            n_rings=self.ring_region.numel(),
+            ring_offsets=_ptr(self.ring_offsets, torch.int32, name="ring_offsets"),
+            ring_vidx=_ptr(self.ring_vidx, torch.int32, name="ring_vidx"),
+            ring_region=_ptr(self.ring_region, torch.int32, name="ring_region"),
+            n_regions=self.n_regions, n_entries=self.ring_vidx.numel())
+
+
+@dataclass
+class IntegrateOpts:
+    tol: float = 1e-3
+    h0: float = 1e-2
+    safety: float = 0.9
+    fac_min: float = 0.2
+    fac_max: float = 5.0
+    h_min: float = 1e-7
+    max_attempts: int = 4096
+
+    def struct(self, replay_h: torch.Tensor | None = None) -> FFBIntegrateOpts:
+        n = 0 if replay_h is None else replay_h.numel()
+        return FFBIntegrateOpts(self.tol, self.h0, self.safety, self.fac_min, self.fac_max,
+                                self.h_min, self.max_attempts, n,
+                                _ptr(replay_h, torch.float64, name="replay_h"))
+
+
+# ------------------------------------------------------- C-ABI functions
+def _stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def ffb_create(lx: int, ly: int, max_points: int = 0, stream=None):
+    ctx = ctypes.c_void_p()
+    code = lib().ffb_create(ctypes.byref(ctx), int(lx), int(ly), int(max_points),
+                            _stream_handle(stream))
+    if code != FFB_OK:
+        raise FFBError(code, f"ffb_create(lx={lx}, ly={ly}, max_points={max_points})")
+    return ctx
+
+
+def ffb_destroy(ctx) -> None:
+    _check(None, lib().ffb_destroy(ctx), "ffb_destroy")
+
+
+def ffb_sync(ctx) -> int:
+    return int(lib().ffb_sync(ctx))
+
+
+def ffb_reset_status(ctx) -> None:
+    _check(ctx, lib().ffb_reset_status(ctx), "ffb_reset_status")
+
+
+def ffb_last_error(ctx) -> str:
+    return lib().ffb_last_error(ctx).decode()
+
+
+def ffb_area_error(ctx, geom: Geometry, value, area, err, max_abs_err) -> None:
+    R = geom.n_regions
+    g = geom.struct()
+    _check(ctx, lib().ffb_area_error(ctx, ctypes.byref(g), _ptr(value, torch.float64, R, "value"),
+                                     _ptr(area, torch.float64, R, "area"),
+                                     _ptr(err, torch.float64, R, "err"),
+                                     _ptr(max_abs_err, torch.float64, 1, "max_abs_err")),
+           "ffb_area_error")
+
+
+def ffb_density(ctx, geom: Geometry, value, area, rho, rho_pad, lx: int, ly: int) -> None:
+    R = geom.n_regions
+    g = geom.struct()
+    _check(ctx, lib().ffb_density(ctx, ctypes.byref(g), _ptr(value, torch.float64, R, "value"),
+                                  _ptr(area, torch.float64, R, "area"),
+                                  _ptr(rho, torch.float32, lx * ly, "rho"),
+                                  _ptr(rho_pad, torch.float64, 1, "rho_pad")), "ffb_density")
+
+
+def ffb_flux(ctx, rho, sigma: float, fields, rho_bar, lx: int, ly: int) -> None:
+    _check(ctx, lib().ffb_flux(ctx, _ptr(rho, torch.float32, lx * ly, "rho"), float(sigma),
+                               _ptr(fields, torch.float32, 4 * (lx + 2) * (ly + 2), "fields"),
+                               _ptr(rho_bar, torch.float64, 1, "rho_bar")), "ffb_flux")
+
+
+def ffb_pack_fields(ctx, jx, jy, rho_s, fields, lx: int, ly: int) -> None:
+    n = lx * ly
+    _check(ctx, lib().ffb_pack_fields(ctx, _ptr(jx, torch.float32, n, "jx"),
+                                      _ptr(jy, torch.float32, n, "jy"),
+                                      _ptr(rho_s, torch.float32, n, "rho_s"),
+                                      _ptr(fields, torch.float32, 4 * (lx + 2) * (ly + 2),
+                                           "fields")), "ffb_pack_fields")
+
+
+def ffb_integrate(ctx, fields, rho_bar, xy, opts: IntegrateOpts, stats, h_out=None,
+                  replay_h=None) -> None:
+    n = xy.shape[0]
+    o = opts.struct(replay_h)
+    _check(ctx, lib().ffb_integrate(ctx, _ptr(fields, torch.float32, name="fields"),
+                                    _ptr(rho_bar, torch.float64, 1, "rho_bar"),
+                                    _ptr(xy, torch.float32, 2 * n, "xy"), n, ctypes.byref(o),
+                                    _ptr(stats, torch.int32, 4, "stats"),
+                                    _ptr(h_out, torch.float64, name="h_out"),
+                                    0 if h_out is None else h_out.numel()), "ffb_integrate")
+
+
+# ------------------------------------------------------------ convenience
+class Context:
+    """An ffb context bound to the current torch stream, with output
+    allocation helpers.  Every method only enqueues work."""
+
+    def __init__(self, lx: int, ly: int, max_points: int = 0, stream=None, device="cuda"):
+        self.lx, self.ly = int(lx), int(ly)
+        self.device = torch.device(device)
+        self.handle = ffb_create(lx, ly, max_points, stream)
+
+    def close(self):
+        if self.handle is not None:
+            ffb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self, check: bool = True) -> int:
+        code = ffb_sync(self.handle)
+        if check and code != FFB_OK:
+            raise FFBError(code, "device status after sync")
+        return code
+
+    def reset_status(self):
+        ffb_reset_status(self.handle)
+
+    def _f64(self, *shape):
+        return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    def area_error(self, geom: Geometry, value):
+        R = geom.n_regions
+        area, err, mx = self._f64(R), self._f64(R), self._f64(1)
+        ffb_area_error(self.handle, geom, value, area, err, mx)
+        return area, err, mx
+
+    def density(self, geom: Geometry, value, area):
+        rho = torch.empty((self.ly, self.lx), dtype=torch.float32, device=self.device)
+        pad = self._f64(1)
+        ffb_density(self.handle, geom, value, area, rho, pad, self.lx, self.ly)
+        return rho, pad
+
+    def new_fields(self):
+        return torch.empty((self.ly + 2, self.lx + 2, 4), dtype=torch.float32, device=self.device)
+
+    def flux(self, rho, sigma: float, fields=None, rho_bar=None):
+        fields = self.new_fields() if fields is None else fields
+        rho_bar = self._f64(1) if rho_bar is None else rho_bar
+        ffb_flux(self.handle, rho, sigma, fields, rho_bar, self.lx, self.ly)
+        return fields, rho_bar
+
+    def pack_fields(self, jx, jy, rho_s, fields=None):
+        fields = self.new_fields() if fields is None else fields
+        ffb_pack_fields(self.handle, jx, jy, rho_s, fields, self.lx, self.ly)
+        return fields
+
+    def integrate(self, fields, rho_bar, xy, opts: IntegrateOpts | None = None,
+                  replay_h=None, h_cap: int | None = None, stats=None, h_out=None):
+        opts = opts or IntegrateOpts()
+        stats = torch.empty(4, dtype=torch.int32, device=self.device) if stats is None else stats
+        if h_out is None and (h_cap is None or h_cap > 0):
+            h_out = self._f64(opts.max_attempts if h_cap is None else h_cap)
+        ffb_integrate(self.handle, fields, rho_bar, xy, opts, stats, h_out, replay_h)
+        return stats, h_out
+
+
+def default_sigma(k: int) -> float:
+    """Blur width of round k (0-based), in grid cells: 4 * 2^-k."""
+    return 4.0 * 2.0 ** (-k)
+
+
+@dataclass
+class IterationResult:
+    area_before: torch.Tensor
+    rho: torch.Tensor
+    rho_pad: torch.Tensor
+    fields: torch.Tensor
+    rho_bar: torch.Tensor
+    stats: torch.Tensor
+    h: torch.Tensor
+    area_after: torch.Tensor
+    err_after: torch.Tensor
+    max_err_after: torch.Tensor
+
+
+def iterate(ctx: Context, geom: Geometry, value, points, sigma: float,
+            opts: IntegrateOpts | None = None, area_before=None) -> IterationResult:
+    """One FFB iteration on the device: areas, density, flux, integration of
+    ``points`` (whose first rows are the polygon vertices ``geom.xy``), areas
+    and errors after.  Enqueue only; read results after ``ctx.sync()``."""
+    if area_before is None:
+        area_before, _, _ = ctx.area_error(geom, value)
+    rho, pad = ctx.density(geom, value, area_before)
+    fields, rho_bar = ctx.flux(rho, sigma)
+    stats, h = ctx.integrate(fields, rho_bar, points, opts)
+    area, err, mx = ctx.area_error(geom, value)
+    return IterationResult(area_before, rho, pad, fields, rho_bar, stats, h, area, err, mx)

@@ -1,0 +1,262 @@
+// C ABI of libffb: context management, host-side argument validation and
+// the entry points declared in include/ffb.h.  Kernels live in k_*.hip.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "ffb_internal.h"
+
+namespace {
+
+int fail(ffb_ctx *ctx, int code, const char *fmt, const char *detail = "")
+{
+    if (ctx) {
+        char buf[512];
+        snprintf(buf, sizeof buf, fmt, detail);
+        ctx->last_error = buf;
+    }
+    return code;
+}
+
+int hip_fail(ffb_ctx *ctx, hipError_t e, const char *where)
+{
+    if (ctx) {
+        ctx->last_error = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return e == hipErrorOutOfMemory ? FFB_E_NOMEM : FFB_E_DEVICE;
+}
+
+bool pow2_in_range(int32_t n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
+
+template <typename T>
+hipError_t grow(T **p, int64_t have, int64_t need)
+{
+    if (need <= have && *p) return hipSuccess;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        *p = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)(need > 0 ? need : 1));
+}
+
+// exp(-2 pi i k / N), k < N/2 and exp(-i pi m / (2N)), m < N, in FP64 then rounded.
+hipError_t upload_twiddles(float2 **tw, float2 **tq, int N)
+{
+    std::vector<float2> a(N / 2), b(N);
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < N / 2; ++k)
+        a[k] = make_float2((float)cos(2 * pi * k / N), (float)(-sin(2 * pi * k / N)));
+    for (int m = 0; m < N; ++m)
+        b[m] = make_float2((float)cos(pi * m / (2.0 * N)), (float)(-sin(pi * m / (2.0 * N))));
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(tw), sizeof(float2) * a.size());
+    if (e != hipSuccess) return e;
+    e = hipMalloc(reinterpret_cast<void **>(tq), sizeof(float2) * b.size());
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(*tw, a.data(), sizeof(float2) * a.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*tq, b.data(), sizeof(float2) * b.size(), hipMemcpyHostToDevice);
+}
+
+void free_all(ffb_ctx *c)
+{
+    void *ptrs[] = {c->d_status, c->tw_x, c->tq_x, c->tw_y, c->tq_y, c->t1, c->t2, c->pa,
+                    c->pb, c->pc, c->red, c->acc, c->w_region, c->st[0], c->st[1], c->kv[0],
+                    c->kv[1], c->errslot};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+int check_geometry(ffb_ctx *ctx, const ffb_geometry *g)
+{
+    if (!g) return fail(ctx, FFB_E_INVALID, "geometry is NULL%s");
+    if (g->n_vertices < 0 || g->n_rings < 0 || g->n_regions < 1 || g->n_entries < 0)
+        return fail(ctx, FFB_E_INVALID, "negative geometry size or no region%s");
+    if (g->n_rings == 0 && g->n_entries != 0)
+        return fail(ctx, FFB_E_INVALID, "ring entries without rings%s");
+    if (g->n_entries < 3 * (int64_t)g->n_rings)
+        return fail(ctx, FFB_E_INVALID, "fewer than three entries per ring%s");
+    if (g->n_entries > INT32_MAX) return fail(ctx, FFB_E_INVALID, "too many ring entries%s");
+    if ((g->n_vertices > 0 && !g->xy) || !g->ring_offsets ||
+        (g->n_entries > 0 && !g->ring_vidx) || (g->n_rings > 0 && !g->ring_region))
+        return fail(ctx, FFB_E_INVALID, "geometry array is NULL%s");
+    return FFB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffb_create(ffb_ctx **out, int32_t lx, int32_t ly, int64_t max_points, void *hip_stream)
+{
+    if (!out) return FFB_E_INVALID;
+    *out = nullptr;
+    if (!pow2_in_range(lx) || !pow2_in_range(ly) || max_points < 0) return FFB_E_INVALID;
+    ffb_ctx *c = new ffb_ctx();
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->lx = lx;
+    c->ly = ly;
+    hipError_t e = hipGetDevice(&c->device);
+    const int64_t plane = (int64_t)lx * ly;
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_status), sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int32_t));
+    if (e == hipSuccess) e = upload_twiddles(&c->tw_x, &c->tq_x, lx);
+    if (e == hipSuccess) e = upload_twiddles(&c->tw_y, &c->tq_y, ly);
+    float **planes[] = {&c->t1, &c->t2, &c->pa, &c->pb, &c->pc};
+    for (float **pl : planes)
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(pl), sizeof(float) * plane);
+    if (e == hipSuccess) e = grow(&c->red, 0, 1024);
+    c->red_cap = 1024;
+    if (e == hipSuccess) e = grow(&c->acc, 0, (int64_t)ly * (lx + 1));
+    if (e == hipSuccess) e = grow(&c->w_region, 0, 1024);
+    c->w_cap = 1024;
+    if (e == hipSuccess) e = grow(&c->errslot, 0, 4097);
+    c->err_cap = 4097;
+    if (e == hipSuccess && max_points > 0) {
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+            e = grow(&c->st[b], 0, max_points);
+            if (e == hipSuccess) e = grow(&c->kv[b], 0, max_points);
+        }
+        c->st_cap = max_points;
+    }
+    if (e == hipSuccess) {
+        int blocks = 0;
+        if (advect_max_blocks(&blocks) != 0 || blocks <= 0) e = hipErrorInvalidValue;
+        c->adv_blocks = blocks;
+    }
+    if (e != hipSuccess) {
+        free_all(c);
+        delete c;
+        return e == hipErrorOutOfMemory ? FFB_E_NOMEM : FFB_E_DEVICE;
+    }
+    *out = c;
+    return FFB_OK;
+}
+
+int ffb_destroy(ffb_ctx *ctx)
+{
+    if (!ctx) return FFB_E_INVALID;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return FFB_OK;
+}
+
+int ffb_sync(ffb_ctx *ctx)
+{
+    if (!ctx) return FFB_E_INVALID;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    int32_t st = 0;
+    e = hipMemcpy(&st, ctx->d_status, sizeof st, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "status read");
+    return st;
+}
+
+int ffb_reset_status(ffb_ctx *ctx)
+{
+    if (!ctx) return FFB_E_INVALID;
+    hipError_t e = launch_fill_i32(ctx->d_status, 1, 0, ctx->stream);
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "reset status");
+}
+
+const char *ffb_last_error(const ffb_ctx *ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "null context";
+}
+
+int ffb_area_error(ffb_ctx *ctx, const ffb_geometry *g, const double *value, double *area,
+                   double *err, double *max_abs_err)
+{
+    if (!ctx) return FFB_E_INVALID;
+    int st = check_geometry(ctx, g);
+    if (st) return st;
+    if (!value || !area || !err || !max_abs_err)
+        return fail(ctx, FFB_E_INVALID, "ffb_area_error: NULL output or value%s");
+    hipError_t e = launch_area(ctx, g, value, area, err, max_abs_err);
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_area_error launch");
+}
+
+int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const double *area,
+                float *rho, double *rho_pad)
+{
+    if (!ctx) return FFB_E_INVALID;
+    int st = check_geometry(ctx, g);
+    if (st) return st;
+    if (!value || !area || !rho || !rho_pad)
+        return fail(ctx, FFB_E_INVALID, "ffb_density: NULL argument%s");
+    if (g->n_regions > ctx->w_cap) {
+        hipError_t e = grow(&ctx->w_region, ctx->w_cap, g->n_regions);
+        if (e != hipSuccess) return hip_fail(ctx, e, "ffb_density workspace");
+        ctx->w_cap = g->n_regions;
+    }
+    hipError_t e = launch_density(ctx, g, value, area, rho, rho_pad);
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_density launch");
+}
+
+int ffb_flux(ffb_ctx *ctx, const float *rho, float sigma, float *fields, double *rho_bar)
+{
+    if (!ctx) return FFB_E_INVALID;
+    if (!rho || !fields || !rho_bar) return fail(ctx, FFB_E_INVALID, "ffb_flux: NULL argument%s");
+    if (!(sigma >= 0.0f) || !isfinite(sigma))
+        return fail(ctx, FFB_E_INVALID, "ffb_flux: sigma must be finite and >= 0%s");
+    hipError_t e = launch_flux(ctx, rho, sigma, reinterpret_cast<float4 *>(fields), rho_bar);
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_flux launch");
+}
+
+int ffb_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy, const float *rho_s,
+                    float *fields)
+{
+    if (!ctx) return FFB_E_INVALID;
+    if (!jx || !jy || !rho_s || !fields)
+        return fail(ctx, FFB_E_INVALID, "ffb_pack_fields: NULL argument%s");
+    hipError_t e = launch_pack_fields(ctx, jx, jy, rho_s, reinterpret_cast<float4 *>(fields));
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_pack_fields launch");
+}
+
+int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy, int64_t n,
+                  const ffb_integrate_opts *o, int32_t *stats, double *h_out, int32_t h_cap)
+{
+    if (!ctx) return FFB_E_INVALID;
+    if (!fields || !rho_bar || !o || !stats || (n > 0 && !xy))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: NULL argument%s");
+    if (n < 0) return fail(ctx, FFB_E_INVALID, "ffb_integrate: n < 0%s");
+    if (h_cap < 0 || (h_cap > 0 && !h_out))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad h_out/h_cap%s");
+    if (o->max_attempts <= 0 || o->max_attempts > (1 << 20))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: max_attempts out of range%s");
+    if (o->n_replay < 0 || (o->n_replay > 0 && !o->replay_h))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad replay schedule%s");
+    if (o->n_replay == 0) {
+        if (!(o->tol > 0.0) || !(o->h0 > 0.0) || !(o->safety > 0.0) || !(o->fac_min > 0.0) ||
+            !(o->fac_min <= 1.0) || !(o->fac_max >= 1.0) || !(o->h_min >= 0.0) ||
+            !isfinite(o->tol) || !isfinite(o->h0) || !isfinite(o->fac_max))
+            return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad controller constants%s");
+    }
+    if (n > ctx->st_cap) {
+        hipError_t e = hipSuccess;
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+            e = grow(&ctx->st[b], ctx->st_cap, n);
+            if (e == hipSuccess) e = grow(&ctx->kv[b], ctx->st_cap, n);
+        }
+        if (e != hipSuccess) {
+            ctx->st_cap = 0;
+            return hip_fail(ctx, e, "ffb_integrate state buffers");
+        }
+        ctx->st_cap = n;
+    }
+    if (o->max_attempts + 1 > ctx->err_cap) {
+        hipError_t e = grow(&ctx->errslot, ctx->err_cap, (int64_t)o->max_attempts + 1);
+        if (e != hipSuccess) return hip_fail(ctx, e, "ffb_integrate slots");
+        ctx->err_cap = o->max_attempts + 1;
+    }
+    hipError_t e = launch_fill_i32(stats, 4, 0, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_advect(ctx, reinterpret_cast<const float4 *>(fields), rho_bar,
+                          reinterpret_cast<float2 *>(xy), n, o, stats, h_out, h_cap);
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_integrate launch");
+}
+
+}  // extern "C"

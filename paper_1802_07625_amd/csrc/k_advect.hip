@@ -1,0 +1,400 @@
+// Advection of every point from t = 0 to t = 1 (main text, section
+// "Flow-based cartogram with linear equalization": velocities at grid points
+// by basic arithmetic, interpolation between grid points, an adaptive
+// predictor-corrector method whose steps advance all integrands together).
+//
+// Velocity: v(r, t) = J(r) / ((1 - t) rho_s(r) + t rho_bar)  (Eq. 4-6), formed
+// at the four grid nodes around r and interpolated bilinearly (first along x
+// on both node rows, then along y).  Lookups are clamped to the box; ghost
+// nodes come from the field layout, so v . n = 0 exactly on the box edges.
+//
+// Integrator: Dormand-Prince 5(4) with first-same-as-last stages, one step
+// size for all points.  The whole integration is ONE cooperative launch:
+//   * each lane owns a fixed set of points (grid-stride), so a point's state
+//     (compensated position hi + lo and its FSAL stage velocity) is private
+//     to one lane and lives in a double-buffered array;
+//   * per attempt every lane evaluates the six new stages of its points,
+//     writes the candidate state to the other buffer and takes the max error;
+//   * the workgroup max goes to a per-attempt slot with one atomic max and a
+//     grid barrier follows; every workgroup then reads the same maximum and
+//     takes the same accept/reject decision and step update in FP64, so no
+//     second barrier and no host round trip are needed;
+//   * the barrier has a bounded wait, so every wave exits even if something
+//     goes wrong (the status word then says FFB_E_DEVICE).
+//
+// Positions are compensated pairs: the candidate position is hi + (lo + d),
+// with d = h sum_s a_s k_s, updated with an error-free sum; lookups use
+// floor(hi - 1/2) plus a fraction computed from (hi - 1/2 - floor) + lo + d,
+// so the bilinear weights keep ~1e-7 cells of precision at L = 1024.
+#include "ffb_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Dormand & Prince (1980) tableau: nodes in FP64 for the stage times.
+__constant__ double kC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+// The same tableau in FP32 for the stage sums (used as instruction literals).
+constexpr float A21 = (float)(1.0 / 5);
+constexpr float A31 = (float)(3.0 / 40), A32 = (float)(9.0 / 40);
+constexpr float A41 = (float)(44.0 / 45), A42 = (float)(-56.0 / 15), A43 = (float)(32.0 / 9);
+constexpr float A51 = (float)(19372.0 / 6561), A52 = (float)(-25360.0 / 2187),
+                A53 = (float)(64448.0 / 6561), A54 = (float)(-212.0 / 729);
+constexpr float A61 = (float)(9017.0 / 3168), A62 = (float)(-355.0 / 33),
+                A63 = (float)(46732.0 / 5247), A64 = (float)(49.0 / 176),
+                A65 = (float)(-5103.0 / 18656);
+constexpr float B1 = (float)(35.0 / 384), B3 = (float)(500.0 / 1113), B4 = (float)(125.0 / 192),
+                B5 = (float)(-2187.0 / 6784), B6 = (float)(11.0 / 84);
+// b - b* (order-5 minus order-4 weights)
+constexpr float E1 = (float)(35.0 / 384 - 5179.0 / 57600),
+                E3 = (float)(500.0 / 1113 - 7571.0 / 16695),
+                E4 = (float)(125.0 / 192 - 393.0 / 640),
+                E5 = (float)(-2187.0 / 6784 + 92097.0 / 339200),
+                E6 = (float)(11.0 / 84 - 187.0 / 2100), E7 = (float)(-1.0 / 40);
+
+struct Params {
+    const float4 *fields;
+    int lx, ly, pitch;
+    const double *rho_bar;
+    float2 *xy;
+    int64_t n;
+    float4 *st0, *st1;
+    float2 *kv0, *kv1;
+    uint32_t *errslot;      // [max_attempts]
+    uint32_t *barrier;      // [1]
+    int32_t *status;
+    int32_t *stats;         // [4] accepted, rejected, attempts, status
+    double *h_out;
+    int32_t h_cap;
+    double tol, h0, safety, fac_min, fac_max, h_min;
+    int32_t max_attempts;
+    int32_t n_replay;
+    const double *replay_h;
+};
+
+struct Field {
+    const float4 *f;
+    int lx, ly, pitch;
+    float flx, fly;
+};
+
+// One coordinate of a lookup: cell index in [-1, L-1] and fraction in [0, 1].
+__device__ inline void locate(float hi, float d, float fL, int L, int &idx, float &frac)
+{
+    const float q = hi + d;                 // coarse position, for clamping only
+    const float u = hi - 0.5f;              // exact for |hi| < 2^22
+    const float fu = floorf(u);
+    float a = (u - fu) + d;                 // fraction relative to fu, precise
+    const float fa = floorf(a);
+    a -= fa;
+    int i = (int)fu + (int)fa;
+    // clamp to the box with selects (no branches); !(q > 0) also catches NaN
+    const bool below = !(q > 0.0f), above = q >= fL;
+    i = below ? -1 : (above ? L - 1 : i);
+    a = (below || above) ? 0.5f : a;
+    idx = min(max(i, -1), L - 1);
+    frac = a;
+}
+
+// Velocity at (hi + d) for time factors omt = 1 - t and tb = t * rho_bar.
+__device__ inline float2 velocity(const Field &F, float hx, float hy, float dx, float dy,
+                                  float omt, float tb)
+{
+    int i, j;
+    float a, b;
+    locate(hx, dx, F.flx, F.lx, i, a);
+    locate(hy, dy, F.fly, F.ly, j, b);
+    const int base = (j + 1) * F.pitch + (i + 1);     // < (L+2)^2 < 2^31
+    const float4 c00 = F.f[base];
+    const float4 c10 = F.f[base + 1];
+    const float4 c01 = F.f[base + F.pitch];
+    const float4 c11 = F.f[base + F.pitch + 1];
+    const float r00 = __builtin_amdgcn_rcpf(fmaf(c00.z, omt, tb));
+    const float r10 = __builtin_amdgcn_rcpf(fmaf(c10.z, omt, tb));
+    const float r01 = __builtin_amdgcn_rcpf(fmaf(c01.z, omt, tb));
+    const float r11 = __builtin_amdgcn_rcpf(fmaf(c11.z, omt, tb));
+    const float x00 = c00.x * r00, x10 = c10.x * r10, x01 = c01.x * r01, x11 = c11.x * r11;
+    const float y00 = c00.y * r00, y10 = c10.y * r10, y01 = c01.y * r01, y11 = c11.y * r11;
+    const float xr0 = fmaf(a, x10 - x00, x00), xr1 = fmaf(a, x11 - x01, x01);
+    const float yr0 = fmaf(a, y10 - y00, y00), yr1 = fmaf(a, y11 - y01, y01);
+    return make_float2(fmaf(b, xr1 - xr0, xr0), fmaf(b, yr1 - yr0, yr0));
+}
+
+// A wave-uniform float kept in a scalar register.
+__device__ inline float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Error-free sum: s + e == a + b exactly.
+__device__ inline void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ inline float wave_max(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Grid barrier on a monotonically increasing counter.  Returns false if the
+// bounded wait ran out (the caller then leaves its loop).
+__device__ bool grid_barrier(uint32_t *counter, uint32_t target, int32_t *status)
+{
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int good = 1;
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > kSpinLimit) {
+                good = 0;
+                set_status(status, FFB_E_DEVICE);
+                break;
+            }
+            if ((spins & 1023u) == 0 &&
+                __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                    FFB_E_DEVICE) {
+                good = 0;
+                break;
+            }
+        }
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_advect(Params p)
+{
+    __shared__ float s_err[kThreads / 64];
+    // a status set by an earlier call (e.g. non-positive density) stops the
+    // integration before any point is touched; the value is uniform.
+    if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+
+    const double rho_bar = *p.rho_bar;
+    const Field F{p.fields, p.lx, p.ly, p.pitch, (float)p.lx, (float)p.ly};
+    const int64_t G = (int64_t)gridDim.x * kThreads;
+    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool replay = p.n_replay > 0;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+
+    // initial state: hi = xy, lo = 0, FSAL velocity at t = 0
+    {
+        const float omt = 1.0f, tb = 0.0f;
+        for (int64_t i = gid; i < p.n; i += G) {
+            const float2 y = p.xy[i];
+            const float2 k1 = velocity(F, y.x, y.y, 0.f, 0.f, omt, tb);
+            p.st0[i] = make_float4(y.x, y.y, 0.f, 0.f);
+            p.kv0[i] = k1;
+        }
+    }
+
+    double t = 0.0, h = replay ? p.replay_h[0] : p.h0;
+    int last_rejected = 0, acc = 0, rej = 0, attempt = 0, cur = 0;
+    int32_t final_status = 0;
+
+    while (t < 1.0) {
+        if (attempt >= p.max_attempts || (replay && acc >= p.n_replay)) {
+            final_status = FFB_E_MAX_ATTEMPTS;
+            break;
+        }
+        bool final_step;
+        if (replay) {
+            h = p.replay_h[acc];
+            final_step = acc == p.n_replay - 1;
+        } else {
+            final_step = h >= 1.0 - t;
+            if (final_step) h = 1.0 - t;
+        }
+        // per-attempt uniforms: the step and the time factors of each stage;
+        // the tableau itself enters as instruction literals
+        const float hf = uniform((float)h);
+        float omt[7], tb[7];
+#pragma unroll
+        for (int s = 1; s < 7; ++s) {
+            const double ts = t + kC[s] * h;
+            omt[s] = uniform((float)(1.0 - ts));
+            tb[s] = uniform((float)(ts * rho_bar));
+        }
+        const float4 *stc = cur ? p.st1 : p.st0;
+        const float2 *kvc = cur ? p.kv1 : p.kv0;
+        float4 *stn = cur ? p.st0 : p.st1;
+        float2 *kvn = cur ? p.kv0 : p.kv1;
+
+        float emax = 0.0f;
+        for (int64_t i = gid; i < p.n; i += G) {
+            const float4 s0 = stc[i];
+            const float hx = s0.x, hy = s0.y, lx = s0.z, ly = s0.w;
+            // stage velocities scaled by the step: q_s = h k_s
+            const float2 k1 = kvc[i];
+            const float2 q1 = make_float2(hf * k1.x, hf * k1.y);
+            float dx, dy;
+            dx = A21 * q1.x;
+            dy = A21 * q1.y;
+            float2 q2 = velocity(F, hx, hy, lx + dx, ly + dy, omt[1], tb[1]);
+            q2 = make_float2(hf * q2.x, hf * q2.y);
+            dx = fmaf(A32, q2.x, A31 * q1.x);
+            dy = fmaf(A32, q2.y, A31 * q1.y);
+            float2 q3 = velocity(F, hx, hy, lx + dx, ly + dy, omt[2], tb[2]);
+            q3 = make_float2(hf * q3.x, hf * q3.y);
+            dx = fmaf(A43, q3.x, fmaf(A42, q2.x, A41 * q1.x));
+            dy = fmaf(A43, q3.y, fmaf(A42, q2.y, A41 * q1.y));
+            float2 q4 = velocity(F, hx, hy, lx + dx, ly + dy, omt[3], tb[3]);
+            q4 = make_float2(hf * q4.x, hf * q4.y);
+            dx = fmaf(A54, q4.x, fmaf(A53, q3.x, fmaf(A52, q2.x, A51 * q1.x)));
+            dy = fmaf(A54, q4.y, fmaf(A53, q3.y, fmaf(A52, q2.y, A51 * q1.y)));
+            float2 q5 = velocity(F, hx, hy, lx + dx, ly + dy, omt[4], tb[4]);
+            q5 = make_float2(hf * q5.x, hf * q5.y);
+            dx = fmaf(A65, q5.x, fmaf(A64, q4.x, fmaf(A63, q3.x, fmaf(A62, q2.x, A61 * q1.x))));
+            dy = fmaf(A65, q5.y, fmaf(A64, q4.y, fmaf(A63, q3.y, fmaf(A62, q2.y, A61 * q1.y))));
+            float2 q6 = velocity(F, hx, hy, lx + dx, ly + dy, omt[5], tb[5]);
+            q6 = make_float2(hf * q6.x, hf * q6.y);
+            // order-5 increment (weights of the last stage row; the k2 weight is 0)
+            const float ix = fmaf(B6, q6.x, fmaf(B5, q5.x, fmaf(B4, q4.x, fmaf(B3, q3.x, B1 * q1.x))));
+            const float iy = fmaf(B6, q6.y, fmaf(B5, q5.y, fmaf(B4, q4.y, fmaf(B3, q3.y, B1 * q1.y))));
+            const float2 k7 = velocity(F, hx, hy, lx + ix, ly + iy, omt[6], tb[6]);
+            const float ex = fmaf(E7 * hf, k7.x, fmaf(E6, q6.x, fmaf(E5, q5.x, fmaf(E4, q4.x,
+                                  fmaf(E3, q3.x, E1 * q1.x)))));
+            const float ey = fmaf(E7 * hf, k7.y, fmaf(E6, q6.y, fmaf(E5, q5.y, fmaf(E4, q4.y,
+                                  fmaf(E3, q3.y, E1 * q1.y)))));
+            // candidate state: (hi, lo) + increment, error-free
+            float sx, ex2, sy, ey2;
+            two_sum(hx, ix, sx, ex2);
+            two_sum(hy, iy, sy, ey2);
+            float nlx = lx + ex2, nly = ly + ey2;
+            const float rx = sx + nlx, ry = sy + nly;     // renormalise
+            nlx -= rx - sx;
+            nly -= ry - sy;
+            // a NaN or Inf in the error estimate or in the new position
+            // poisons the maximum (fmaxf alone would drop a NaN)
+            const float poison = (ex + ey) + (rx + ry);
+            const float e = (poison - poison == 0.0f) ? fmaxf(fabsf(ex), fabsf(ey))
+                                                      : __builtin_inff();
+            emax = fmaxf(emax, e);
+            stn[i] = make_float4(rx, ry, nlx, nly);
+            kvn[i] = k7;
+        }
+        // workgroup max -> per-attempt slot
+        emax = wave_max(emax);
+        if ((threadIdx.x & 63) == 0) s_err[threadIdx.x >> 6] = emax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = s_err[0];
+#pragma unroll
+            for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, s_err[w]);
+            __hip_atomic_fetch_max(&p.errslot[attempt], __float_as_uint(m), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!grid_barrier(p.barrier, (uint32_t)(attempt + 1) * gridDim.x, p.status)) {
+            final_status = FFB_E_DEVICE;
+            break;
+        }
+        const double err = (double)__uint_as_float(__hip_atomic_load(
+            &p.errslot[attempt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        ++attempt;
+        if (!(err < __builtin_huge_val())) {
+            final_status = FFB_E_NONFINITE;
+            break;
+        }
+        if (replay || err <= p.tol) {
+            cur ^= 1;
+            if (lead && acc < p.h_cap && p.h_out) p.h_out[acc] = h;
+            ++acc;
+            t = final_step ? 1.0 : t + h;
+            if (!replay) {
+                double fac = (err == 0.0) ? p.fac_max : p.safety * pow(err / p.tol, -0.2);
+                fac = fmin(fmax(fac, p.fac_min), p.fac_max);
+                if (last_rejected && fac > 1.0) fac = 1.0;
+                h *= fac;
+                last_rejected = 0;
+            }
+        } else {
+            ++rej;
+            h *= fmax(p.fac_min, p.safety * pow(err / p.tol, -0.2));
+            last_rejected = 1;
+        }
+        if (!replay && t < 1.0 && h < p.h_min) {
+            final_status = FFB_E_STEP_UNDERFLOW;
+            break;
+        }
+    }
+
+    if (final_status == 0) {
+        const float4 *stc = cur ? p.st1 : p.st0;
+        for (int64_t i = gid; i < p.n; i += G) {
+            const float4 s = stc[i];
+            p.xy[i] = make_float2(s.x + s.z, s.y + s.w);
+        }
+    }
+    if (lead) {
+        p.stats[0] = acc;
+        p.stats[1] = rej;
+        p.stats[2] = attempt;
+        p.stats[3] = final_status;
+        if (final_status) set_status(p.status, final_status);
+    }
+}
+
+}  // namespace
+
+int advect_max_blocks(int *out)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_advect, kThreads, 0) != hipSuccess)
+        return -1;
+    *out = cus * per;
+    return 0;
+}
+
+hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
+                         float2 *xy, int64_t n, const ffb_integrate_opts *o, int32_t *stats,
+                         double *h_out, int32_t h_cap)
+{
+    // slots for every attempt plus the barrier counter, cleared by a kernel
+    hipError_t e = launch_fill_u32(ctx->errslot, (int64_t)o->max_attempts + 1, 0u, ctx->stream);
+    if (e != hipSuccess) return e;
+    Params p;
+    p.fields = fields;
+    p.lx = ctx->lx;
+    p.ly = ctx->ly;
+    p.pitch = ctx->lx + 2;
+    p.rho_bar = rho_bar;
+    p.xy = xy;
+    p.n = n;
+    p.st0 = ctx->st[0];
+    p.st1 = ctx->st[1];
+    p.kv0 = ctx->kv[0];
+    p.kv1 = ctx->kv[1];
+    p.errslot = ctx->errslot;
+    p.barrier = ctx->errslot + o->max_attempts;
+    p.status = ctx->d_status;
+    p.stats = stats;
+    p.h_out = h_out;
+    p.h_cap = h_cap;
+    p.tol = o->tol;
+    p.h0 = o->h0;
+    p.safety = o->safety;
+    p.fac_min = o->fac_min;
+    p.fac_max = o->fac_max;
+    p.h_min = o->h_min;
+    p.max_attempts = o->max_attempts;
+    p.n_replay = o->n_replay;
+    p.replay_h = o->replay_h;
+    int64_t want = (n + kThreads - 1) / kThreads;
+    if (want < 1) want = 1;
+    int blocks = ctx->adv_blocks;
+    if (want < blocks) blocks = (int)want;
+    void *args[] = {&p};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_advect), dim3(blocks),
+                                      dim3(kThreads), args, 0, ctx->stream);
+}

@@ -1,0 +1,436 @@
+// Blur and flux on the grid nodes: the cosine coefficients of Eq. 7 (the
+// integral taken by the midpoint rule on cell centres, i.e. a 2D DCT-II),
+// a Gaussian blur (diagonal in this basis), and the sine/cosine flux series
+// of the SI Appendix (section 2) for linear equalisation, evaluated on the
+// nodes with DCT-III / DST-III transforms.
+//
+// Pipeline (lx x ly grid, x fastest):
+//   k_dct2_rows   rows j:      T1[j][m]  = sum_i rho[j][i] cos(pi m (i+1/2)/lx)
+//   k_transpose   T1 -> T2[m][j]
+//   k_col_pass    rows m:      S[m][n]   = sum_j T2[m][j] cos(pi n (j+1/2)/ly)
+//                              rts       = 4 S / ((1+d_m0)(1+d_n0)) * gauss(m, n)
+//                              a[m][j]   = sum_n rts cos(pi n (j+1/2)/ly)
+//                              b[m][j]   = sum_n wx(m,n) rts cos(...)
+//                              c[m][j]   = sum_n wy(m,n) rts sin(pi n (j+1/2)/ly)
+//   k_transpose   a, b, c -> [j][m]
+//   k_row_final   rows j:      rho_s = sum_m a cos / (lx ly), J_x = sum_m b sin,
+//                              J_y = sum_m c cos  -> ghosted float4 fields
+// with wx = (ly/pi) m/(m^2 ly^2 + n^2 lx^2), wy = (lx/pi) n/(...).
+//
+// Every 1D transform is a length-N complex FFT in LDS (radix-2 Stockham,
+// twiddles staged in LDS) serving two real rows at once (one as the real,
+// one as the imaginary part), with the even/odd reordering of Makhoul
+// (1980) turning the real DCT-II/DCT-III into a plain FFT; the DST-III is a
+// DCT-III of the index-reversed coefficients with alternating output signs.
+#include "ffb_internal.h"
+
+namespace {
+
+constexpr int kMaxN = 1024;
+
+__device__ inline float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ inline int ilog2(int n) { return 31 - __clz(n); }
+
+// Radix-2 Stockham FFT (unnormalised).  `a` holds the input; returns the
+// buffer holding the output (a or b).  `tw` (LDS) = exp(-2 pi i k / N),
+// k < N/2; the inverse uses the conjugates.
+__device__ float2 *fft_lds(float2 *a, float2 *b, int N, const float2 *tw, bool inverse)
+{
+    const int half = N >> 1;
+    const int lgN = ilog2(N);
+    for (int lgL = 0; lgL < lgN; ++lgL) {
+        const int Ls = 1 << lgL;
+        __syncthreads();
+        for (int bi = threadIdx.x; bi < half; bi += blockDim.x) {
+            const int j = bi & (Ls - 1);
+            const int k = bi >> lgL;
+            float2 w = tw[j << (lgN - 1 - lgL)];
+            if (inverse) w.y = -w.y;
+            const float2 u = a[bi];
+            const float2 v = cmul(a[bi + half], w);
+            const int o = (k << (lgL + 1)) + j;
+            b[o] = make_float2(u.x + v.x, u.y + v.y);
+            b[o + Ls] = make_float2(u.x - v.x, u.y - v.y);
+        }
+        float2 *t = a;
+        a = b;
+        b = t;
+    }
+    __syncthreads();
+    return a;
+}
+
+__device__ inline void load_twiddles(float2 *tw_lds, const float2 *__restrict__ tw, int N)
+{
+    for (int k = threadIdx.x; k < (N >> 1); k += blockDim.x) tw_lds[k] = tw[k];
+}
+
+// Makhoul reordering position of input element i: v[i/2] for even i,
+// v[N-1-(i-1)/2] for odd i.
+__device__ inline int mk_pos(int i, int N) { return (i & 1) ? (N - 1 - (i >> 1)) : (i >> 1); }
+
+// DCT-II of two rows held as (ra[i], rb[i]) pairs already placed in `a` in
+// Makhoul order; leaves X_a[m], X_b[m] (unnormalised: sum x_i cos(pi m (i+1/2)/N))
+// in `out` as float2 pairs.
+__device__ void dct2_pair(float2 *a, float2 *b, float2 *out, int N, const float2 *tw,
+                          const float2 *__restrict__ tq)
+{
+    float2 *Z = fft_lds(a, b, N, tw, false);
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        const float2 zm = Z[m];
+        const float2 zc = Z[(N - m) & (N - 1)];
+        // Va = (Zm + conj Zc)/2, Vb = (Zm - conj Zc)/(2i)
+        const float2 va = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
+        const float2 vb = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
+        const float2 q = tq[m];      // exp(-i pi m / (2N))
+        out[m] = make_float2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
+    }
+    __syncthreads();
+}
+
+// Build the inverse-transform input for a pair of DCT-III sums
+//   y_i = sum_{m<N} c_m cos(pi m (i+1/2)/N)
+// from coefficient pairs cpair(m) = (c_a[m], c_b[m]) into `a`:
+//   X_0 = c_0, X_m = c_m / 2, W_m = exp(i pi m/(2N)) (X_m - i X_{N-m}), X_N = 0,
+// and the pair is packed as W_a + i W_b.
+template <typename F>
+__device__ void dct3_input(float2 *a, int N, const float2 *__restrict__ tq, F cpair)
+{
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        float2 xm = cpair(m);
+        if (m) { xm.x *= 0.5f; xm.y *= 0.5f; }
+        float2 xr = make_float2(0.f, 0.f);
+        if (m) { xr = cpair(N - m); xr.x *= 0.5f; xr.y *= 0.5f; }
+        const float2 q = tq[m];
+        const float cr = q.x, ci = -q.y;          // exp(+i pi m/(2N))
+        // Wa = (cr + i ci)(xm.x - i xr.x), Wb likewise with .y
+        const float war = cr * xm.x + ci * xr.x, wai = ci * xm.x - cr * xr.x;
+        const float wbr = cr * xm.y + ci * xr.y, wbi = ci * xm.y - cr * xr.y;
+        a[m] = make_float2(war - wbi, wai + wbr);   // Wa + i Wb
+    }
+}
+
+// After the inverse FFT of dct3_input, output y[i] of the pair:
+// even i -> v[i/2], odd i -> v[N-1-(i-1)/2]; real part = row a, imag = row b.
+__device__ inline float2 dct3_output(const float2 *v, int i, int N) { return v[mk_pos(i, N)]; }
+
+// ------------------------------------------------------------------ kernels
+__global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
+                                                   float *__restrict__ out, int N,
+                                                   const float2 *__restrict__ tw,
+                                                   const float2 *__restrict__ tq)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    load_twiddles(stw, tw, N);
+    const int64_t r0 = 2 * (int64_t)blockIdx.x;
+    const float *ra = in + r0 * N, *rb = ra + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = make_float2(ra[i], rb[i]);
+    // result pairs land in sa or sb; reuse the other as output staging
+    float2 *Z = fft_lds(sa, sb, N, stw, false);
+    float2 *o = (Z == sa) ? sb : sa;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        const float2 zm = Z[m];
+        const float2 zc = Z[(N - m) & (N - 1)];
+        const float2 va = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
+        const float2 vb = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
+        const float2 q = tq[m];
+        o[m] = make_float2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
+    }
+    __syncthreads();
+    float *oa = out + r0 * N, *ob = oa + N;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        oa[m] = o[m].x;
+        ob[m] = o[m].y;
+    }
+}
+
+// 32 x 32 tiles through LDS; in [R][C] -> out [C][R]; z selects the plane.
+__global__ __launch_bounds__(256) void k_transpose(const float *__restrict__ in0,
+                                                   const float *__restrict__ in1,
+                                                   const float *__restrict__ in2,
+                                                   float *__restrict__ out0,
+                                                   float *__restrict__ out1,
+                                                   float *__restrict__ out2, int R, int C)
+{
+    __shared__ float tile[32][33];
+    const float *in = blockIdx.z == 0 ? in0 : (blockIdx.z == 1 ? in1 : in2);
+    float *out = blockIdx.z == 0 ? out0 : (blockIdx.z == 1 ? out1 : out2);
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, c = c0 + tx;
+        if (r < R && c < C) tile[k][tx] = in[(int64_t)r * C + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int c = c0 + k, r = r0 + tx;
+        if (r < R && c < C) out[(int64_t)c * R + r] = tile[tx][k];
+    }
+}
+
+// Column pass on rows m0 = 2 blockIdx.x, m1 = m0 + 1 of T2 [lx][ly].
+__global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, int lx, int ly,
+                                                  float sigma, const float2 *__restrict__ tw,
+                                                  const float2 *__restrict__ tq,
+                                                  float *__restrict__ pa, float *__restrict__ pb,
+                                                  float *__restrict__ pc)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
+    const int N = ly;
+    load_twiddles(stw, tw, N);
+    const int m0 = 2 * blockIdx.x;
+    const float *ra = t2 + (int64_t)m0 * N, *rb = ra + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = make_float2(ra[i], rb[i]);
+    dct2_pair(sa, sb, coef, N, stw, tq);   // coef[n] = (S[m0][n], S[m1][n])
+
+    // normalisation of Eq. 7 and the blur, separable in m and n
+    const float PI_F = 3.14159265358979f;
+    const float cgx = PI_F * PI_F * sigma * sigma / (2.0f * (float)lx * (float)lx);
+    const float cgy = PI_F * PI_F * sigma * sigma / (2.0f * (float)ly * (float)ly);
+    const float gx0 = expf(-cgx * (float)m0 * (float)m0) * (m0 == 0 ? 2.0f : 4.0f);
+    const float gx1 = expf(-cgx * (float)(m0 + 1) * (float)(m0 + 1)) * 4.0f;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const float gy = expf(-cgy * (float)n * (float)n) * (n == 0 ? 0.5f : 1.0f);
+        const float2 s = coef[n];
+        coef[n] = make_float2(s.x * gx0 * gy, s.y * gx1 * gy);
+    }
+    __syncthreads();
+
+    const float flx = (float)lx, fly = (float)ly;
+    const float inv_pi = 0.318309886183790672f;
+    const float ma = (float)m0, mb = (float)(m0 + 1);
+    // wx(m, n) and wy(m, n); zero where the numerator vanishes
+    auto wx = [&](float m, int n) {
+        if (m == 0.f) return 0.f;
+        const float den = (m * fly) * (m * fly) + ((float)n * flx) * ((float)n * flx);
+        return fly * inv_pi * m / den;
+    };
+    auto wy = [&](float m, int n) {
+        if (n == 0) return 0.f;
+        const float den = (m * fly) * (m * fly) + ((float)n * flx) * ((float)n * flx);
+        return flx * inv_pi * (float)n / den;
+    };
+
+    // a: plain DCT-III of the coefficients
+    dct3_input(sa, N, tq, [&](int n) { return coef[n]; });
+    float2 *v = fft_lds(sa, sb, N, stw, true);
+    float *oa0 = pa + (int64_t)m0 * N, *oa1 = oa0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        oa0[i] = y.x;
+        oa1[i] = y.y;
+    }
+    __syncthreads();
+    // b: DCT-III of wx * coefficients
+    dct3_input(sa, N, tq, [&](int n) {
+        const float2 c = coef[n];
+        return make_float2(wx(ma, n) * c.x, wx(mb, n) * c.y);
+    });
+    v = fft_lds(sa, sb, N, stw, true);
+    float *ob0 = pb + (int64_t)m0 * N, *ob1 = ob0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        ob0[i] = y.x;
+        ob1[i] = y.y;
+    }
+    __syncthreads();
+    // c: DST-III of wy * coefficients = (-1)^j DCT-III of the reversed sequence
+    dct3_input(sa, N, tq, [&](int mm) {
+        if (mm == 0) return make_float2(0.f, 0.f);
+        const int n = N - mm;
+        const float2 c = coef[n];
+        return make_float2(wy(ma, n) * c.x, wy(mb, n) * c.y);
+    });
+    v = fft_lds(sa, sb, N, stw, true);
+    float *oc0 = pc + (int64_t)m0 * N, *oc1 = oc0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        const float s = (i & 1) ? -1.0f : 1.0f;
+        oc0[i] = s * y.x;
+        oc1[i] = s * y.y;
+    }
+}
+
+// Row pass on rows j0 = 2 blockIdx.x, j1 = j0 + 1 of a, b, c [ly][lx]; writes
+// the ghosted float4 fields (J_x, J_y, rho_s, 0).
+__global__ __launch_bounds__(512) void k_row_final(const float *__restrict__ pa,
+                                                   const float *__restrict__ pb,
+                                                   const float *__restrict__ pc, int lx, int ly,
+                                                   const float2 *__restrict__ tw,
+                                                   const float2 *__restrict__ tq,
+                                                   float4 *__restrict__ fields, int32_t *status)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
+    const int N = lx;
+    load_twiddles(stw, tw, N);
+    const int j0 = 2 * blockIdx.x;
+    const float norm = 1.0f / ((float)lx * (float)ly);
+
+    const float *a0 = pa + (int64_t)j0 * N, *a1 = a0 + N;
+    dct3_input(sa, N, tq, [&](int m) { return make_float2(a0[m], a1[m]); });
+    float2 *v = fft_lds(sa, sb, N, stw, true);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        rs[i] = make_float2(y.x * norm, y.y * norm);
+    }
+    __syncthreads();
+    const float *b0 = pb + (int64_t)j0 * N, *b1 = b0 + N;
+    dct3_input(sa, N, tq, [&](int mm) {
+        if (mm == 0) return make_float2(0.f, 0.f);
+        return make_float2(b0[N - mm], b1[N - mm]);
+    });
+    v = fft_lds(sa, sb, N, stw, true);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        const float s = (i & 1) ? -1.0f : 1.0f;
+        jx[i] = make_float2(s * y.x, s * y.y);
+    }
+    __syncthreads();
+    const float *c0 = pc + (int64_t)j0 * N, *c1 = c0 + N;
+    dct3_input(sa, N, tq, [&](int m) { return make_float2(c0[m], c1[m]); });
+    v = fft_lds(sa, sb, N, stw, true);
+
+    const int P = lx + 2;
+    int bad = 0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 jy = dct3_output(v, i, N);
+        const float2 r = rs[i], x = jx[i];
+        bad |= !(r.x > 0.f) || !(r.y > 0.f);
+        const float4 f0 = make_float4(x.x, jy.x, r.x, 0.f);
+        const float4 f1 = make_float4(x.y, jy.y, r.y, 0.f);
+        float4 *row0 = fields + (int64_t)(j0 + 1) * P;
+        float4 *row1 = row0 + P;
+        row0[i + 1] = f0;
+        row1[i + 1] = f1;
+        // ghost columns: J_x odd across the x edges
+        if (i == 0 || i == N - 1) {
+            const int gi = (i == 0) ? 0 : N + 1;
+            row0[gi] = make_float4(-f0.x, f0.y, f0.z, 0.f);
+            row1[gi] = make_float4(-f1.x, f1.y, f1.z, 0.f);
+        }
+        // ghost rows: J_y odd across the y edges
+        if (j0 == 0) {
+            float4 *grow = fields;
+            grow[i + 1] = make_float4(f0.x, -f0.y, f0.z, 0.f);
+            if (i == 0 || i == N - 1) grow[(i == 0) ? 0 : N + 1] = make_float4(-f0.x, -f0.y, f0.z, 0.f);
+        }
+        if (j0 + 1 == ly - 1) {
+            float4 *grow = fields + (int64_t)(ly + 1) * P;
+            grow[i + 1] = make_float4(f1.x, -f1.y, f1.z, 0.f);
+            if (i == 0 || i == N - 1) grow[(i == 0) ? 0 : N + 1] = make_float4(-f1.x, -f1.y, f1.z, 0.f);
+        }
+    }
+    if (bad) set_status(status, FFB_E_NONPOSITIVE);
+}
+
+// Pack caller node arrays into the ghosted layout (same ghost rule).
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ jx,
+                                              const float *__restrict__ jy,
+                                              const float *__restrict__ rs, int lx, int ly,
+                                              float4 *__restrict__ fields)
+{
+    const int P = lx + 2;
+    const int64_t total = (int64_t)(lx + 2) * (ly + 2);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int pi = (int)(e % P), pj = (int)(e / P);
+        int i = pi - 1, j = pj - 1;
+        float sx = 1.f, sy = 1.f;
+        if (i < 0) { i = 0; sx = -1.f; }
+        if (i >= lx) { i = lx - 1; sx = -1.f; }
+        if (j < 0) { j = 0; sy = -1.f; }
+        if (j >= ly) { j = ly - 1; sy = -1.f; }
+        const int64_t c = (int64_t)j * lx + i;
+        fields[e] = make_float4(sx * jx[c], sy * jy[c], rs[c], 0.f);
+    }
+}
+
+// Fixed-order FP64 sum of a float array: per-block partials then one block.
+__global__ __launch_bounds__(256) void k_sum_partial(const float *__restrict__ x, int64_t n,
+                                                     double *__restrict__ part)
+{
+    __shared__ double lds[256];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        s += (double)x[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ part, int np,
+                                                   double scale, double *__restrict__ out,
+                                                   int32_t *status)
+{
+    __shared__ double lds[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = lds[0] * scale;
+        *out = m;
+        if (!(m > 0.0)) set_status(status, FFB_E_NONPOSITIVE);
+    }
+}
+
+inline int threads_for(int N)
+{
+    int t = N / 2;
+    if (t < 64) t = 64;
+    if (t > 512) t = 512;
+    return t;
+}
+
+}  // namespace
+
+hipError_t launch_flux(ffb_ctx *ctx, const float *rho, float sigma, float4 *fields,
+                       double *rho_bar)
+{
+    hipStream_t s = ctx->stream;
+    const int lx = ctx->lx, ly = ctx->ly;
+    const int64_t n = (int64_t)lx * ly;
+    constexpr int kParts = 256;
+    hipLaunchKernelGGL(k_sum_partial, dim3(kParts), dim3(256), 0, s, rho, n, ctx->red);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, ctx->red, kParts,
+                       1.0 / (double)n, rho_bar, ctx->d_status);
+    hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, ctx->t1, lx,
+                       ctx->tw_x, ctx->tq_x);
+    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
+                       ctx->t1, ctx->t1, ctx->t1, ctx->t2, ctx->t2, ctx->t2, ly, lx);
+    hipLaunchKernelGGL(k_col_pass, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t2, lx, ly,
+                       sigma, ctx->tw_y, ctx->tq_y, ctx->pa, ctx->pb, ctx->pc);
+    // [lx][ly] -> [ly][lx]: a, b, c into t1 and the two spare planes
+    float *qa = ctx->t1, *qb = ctx->t2, *qc = ctx->pa;
+    // pa is an input of this transpose: move planes through spare buffers
+    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 2), dim3(256), 0, s,
+                       ctx->pa, ctx->pb, ctx->pb, qa, qb, qb, lx, ly);
+    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 1), dim3(256), 0, s,
+                       ctx->pc, ctx->pc, ctx->pc, qc, qc, qc, lx, ly);
+    hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, qa, qb, qc, lx,
+                       ly, ctx->tw_x, ctx->tq_x, fields, ctx->d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy,
+                              const float *rho_s, float4 *fields)
+{
+    const int64_t total = (int64_t)(ctx->lx + 2) * (ctx->ly + 2);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, jx, jy, rho_s,
+                       ctx->lx, ctx->ly, fields);
+    return hipGetLastError();
+}

@@ -1,0 +1,47 @@
+"""Helpers for the GPU parity tests: move seeded inputs to the device, and
+pack oracle fields into the library's field layout through the C ABI."""
+import numpy as np
+import torch
+
+import paper_1802_07625_amd as ffb
+import synth
+
+DEV = "cuda"
+
+
+def dev_f64(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), device=DEV)
+
+
+def dev_f32(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32), device=DEV).contiguous()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def map_points(m, with_grid=True):
+    """Vertices first, then (optionally) every grid node; float32."""
+    parts = [m.xy.astype(np.float32)]
+    if with_grid:
+        parts.append(synth.grid_nodes(m.lx, m.ly))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def pack_oracle_fields(ctx, F):
+    """Oracle fields (FP64 node arrays) rounded to FP32 and packed into the
+    ghosted layout by the library's own pack entry point; returns
+    (fields tensor, rho_bar tensor, the FP32-rounded oracle Fields)."""
+    Fr = F.rounded_f32()
+    fields = ctx.pack_fields(dev_f32(Fr.jx), dev_f32(Fr.jy), dev_f32(Fr.rho_s))
+    return fields, dev_f64([F.rho_bar]), Fr
+
+
+def stats_of(stats):
+    s = to_np(stats)
+    return dict(accepted=int(s[0]), rejected=int(s[1]), attempts=int(s[2]), status=int(s[3]))
+
+
+def new_ctx(lx, ly=None, max_points=0):
+    return ffb.Context(lx, lx if ly is None else ly, max_points=max_points)

@@ -226,3 +226,12 @@ def test_c1_loop_converges_below_one_percent():
         if r.max_err_after < 0.01:
             break
     assert r.max_err_after < 0.01, (k, r.max_err_after)
+
+
+def test_nonfinite_points_are_an_error():
+    F, p0, _ = linear_case()
+    p = p0.copy()
+    p[3, 1] = np.nan
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.integrate(F, p)
+    assert ei.value.code == oracle.E_NONFINITE
