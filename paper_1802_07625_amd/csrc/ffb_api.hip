@@ -112,8 +112,8 @@ int ffb_create(ffb_ctx **out, int32_t lx, int32_t ly, int64_t max_points, void *
     if (e == hipSuccess) e = grow(&c->acc, 0, (int64_t)ly * (lx + 1));
     if (e == hipSuccess) e = grow(&c->w_region, 0, 1024);
     c->w_cap = 1024;
-    if (e == hipSuccess) e = grow(&c->errslot, 0, 4097);
-    c->err_cap = 4097;
+    if (e == hipSuccess) e = grow(&c->errslot, 0, 4096);   // advection sync words
+    c->err_cap = 4096;
     if (e == hipSuccess && max_points > 0) {
         for (int b = 0; b < 2 && e == hipSuccess; ++b) {
             e = grow(&c->st[b], 0, max_points);
@@ -246,11 +246,6 @@ int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, floa
             return hip_fail(ctx, e, "ffb_integrate state buffers");
         }
         ctx->st_cap = n;
-    }
-    if (o->max_attempts + 1 > ctx->err_cap) {
-        hipError_t e = grow(&ctx->errslot, ctx->err_cap, (int64_t)o->max_attempts + 1);
-        if (e != hipSuccess) return hip_fail(ctx, e, "ffb_integrate slots");
-        ctx->err_cap = o->max_attempts + 1;
     }
     hipError_t e = launch_fill_i32(stats, 4, 0, ctx->stream);
     if (e == hipSuccess)

@@ -34,7 +34,7 @@ struct ffb_ctx {
     float4 *st[2] = {nullptr, nullptr};        // (hi.x, hi.y, lo.x, lo.y) per point
     float2 *kv[2] = {nullptr, nullptr};        // first stage velocity (FSAL)
     int64_t st_cap = 0;
-    uint32_t *errslot = nullptr;               // one slot per attempt + barrier counter
+    uint32_t *errslot = nullptr;               // advection grid-sync words
     int32_t err_cap = 0;
     int adv_blocks = 0;                        // co-resident blocks of the advection kernel
 };

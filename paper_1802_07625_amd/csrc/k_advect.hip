@@ -30,8 +30,14 @@
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;          // one workgroup per CU
+constexpr int kXcds = 8;               // workgroups are dealt to 8 XCDs round-robin
+constexpr int kSegments = 2;           // contiguous point segments per XCD
 constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Synchronisation words, cleared before each launch: two banks (by attempt
+// parity) of one 64-bit slot per workgroup holding (attempt + 1) << 32 | the
+// workgroup's error maximum (FP32 bits).
 
 // Dormand & Prince (1980) tableau: nodes in FP64 for the stage times.
 __constant__ double kC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
@@ -61,8 +67,7 @@ struct Params {
     int64_t n;
     float4 *st0, *st1;
     float2 *kv0, *kv1;
-    uint32_t *errslot;      // [max_attempts]
-    uint32_t *barrier;      // [1]
+    uint64_t *sync;         // 2 banks x gridDim.x tagged slots
     int32_t *status;
     int32_t *stats;         // [4] accepted, rejected, attempts, status
     double *h_out;
@@ -97,25 +102,44 @@ __device__ inline void locate(float hi, float d, float fL, int L, int &idx, floa
     frac = a;
 }
 
+// The four field records around the last looked-up cell of one point.  The
+// stage positions of one attempt lie within a fraction of a cell of each
+// other, so most stage evaluations find their cell here and issue no gather.
+struct CellCache {
+    int key;                  // (j + 1) * pitch + (i + 1) of the cached cell, -1 = none
+    float3 c00, c10, c01, c11;
+};
+
+__device__ inline float3 ld3(const float4 *f, int idx)
+{
+    const float4 v = f[idx];
+    return make_float3(v.x, v.y, v.z);
+}
+
 // Velocity at (hi + d) for time factors omt = 1 - t and tb = t * rho_bar.
 __device__ inline float2 velocity(const Field &F, float hx, float hy, float dx, float dy,
-                                  float omt, float tb)
+                                  float omt, float tb, CellCache &cc)
 {
     int i, j;
     float a, b;
     locate(hx, dx, F.flx, F.lx, i, a);
     locate(hy, dy, F.fly, F.ly, j, b);
     const int base = (j + 1) * F.pitch + (i + 1);     // < (L+2)^2 < 2^31
-    const float4 c00 = F.f[base];
-    const float4 c10 = F.f[base + 1];
-    const float4 c01 = F.f[base + F.pitch];
-    const float4 c11 = F.f[base + F.pitch + 1];
-    const float r00 = __builtin_amdgcn_rcpf(fmaf(c00.z, omt, tb));
-    const float r10 = __builtin_amdgcn_rcpf(fmaf(c10.z, omt, tb));
-    const float r01 = __builtin_amdgcn_rcpf(fmaf(c01.z, omt, tb));
-    const float r11 = __builtin_amdgcn_rcpf(fmaf(c11.z, omt, tb));
-    const float x00 = c00.x * r00, x10 = c10.x * r10, x01 = c01.x * r01, x11 = c11.x * r11;
-    const float y00 = c00.y * r00, y10 = c10.y * r10, y01 = c01.y * r01, y11 = c11.y * r11;
+    if (base != cc.key) {
+        cc.key = base;
+        cc.c00 = ld3(F.f, base);
+        cc.c10 = ld3(F.f, base + 1);
+        cc.c01 = ld3(F.f, base + F.pitch);
+        cc.c11 = ld3(F.f, base + F.pitch + 1);
+    }
+    const float r00 = __builtin_amdgcn_rcpf(fmaf(cc.c00.z, omt, tb));
+    const float r10 = __builtin_amdgcn_rcpf(fmaf(cc.c10.z, omt, tb));
+    const float r01 = __builtin_amdgcn_rcpf(fmaf(cc.c01.z, omt, tb));
+    const float r11 = __builtin_amdgcn_rcpf(fmaf(cc.c11.z, omt, tb));
+    const float x00 = cc.c00.x * r00, x10 = cc.c10.x * r10;
+    const float x01 = cc.c01.x * r01, x11 = cc.c11.x * r11;
+    const float y00 = cc.c00.y * r00, y10 = cc.c10.y * r10;
+    const float y01 = cc.c01.y * r01, y11 = cc.c11.y * r11;
     const float xr0 = fmaf(a, x10 - x00, x00), xr1 = fmaf(a, x11 - x01, x01);
     const float yr0 = fmaf(a, y10 - y00, y00), yr1 = fmaf(a, y11 - y01, y01);
     return make_float2(fmaf(b, xr1 - xr0, xr0), fmaf(b, yr1 - yr0, yr0));
@@ -141,34 +165,107 @@ __device__ inline float wave_max(float v)
     return v;
 }
 
-// Grid barrier on a monotonically increasing counter.  Returns false if the
-// bounded wait ran out (the caller then leaves its loop).
-__device__ bool grid_barrier(uint32_t *counter, uint32_t target, int32_t *status)
+// Point ranges of a workgroup.  Points are cut into kXcds * kSegments equal
+// segments; segment s belongs to XCD s mod kXcds, so each XCD (whose L2 is
+// private) works on kSegments contiguous runs of points -- with the usual
+// [vertices | grid nodes] layout, one run of each, which also balances the
+// cheap vertex lookups against the wider grid-node lookups.  Within an XCD
+// the runs are concatenated and cut into one chunk per workgroup.
+struct Span {
+    int64_t seg;       // segment length
+    int64_t j0, j1;    // this workgroup's range in its XCD's concatenated runs
+    int xcd, nxcd;
+};
+
+__device__ inline Span span_of(int b, int nb, int64_t n)
+{
+    Span sp;
+    sp.nxcd = nb < kXcds ? nb : kXcds;
+    sp.xcd = b % sp.nxcd;
+    const int rank = b / sp.nxcd;
+    const int per = nb / sp.nxcd, extra = nb % sp.nxcd;
+    const int size = per + (sp.xcd < extra ? 1 : 0);        // workgroups on this XCD
+    const int64_t nseg = (int64_t)sp.nxcd * kSegments;
+    sp.seg = (n + nseg - 1) / nseg;
+    const int64_t total = sp.seg * kSegments;                // this XCD's share
+    const int64_t chunk = (total + size - 1) / size;
+    sp.j0 = min(total, (int64_t)rank * chunk);
+    sp.j1 = min(total, sp.j0 + chunk);
+    return sp;
+}
+
+// Point index of position j in the XCD's concatenated runs.
+__device__ inline int64_t point_of(const Span &sp, int64_t j)
+{
+    const int64_t r = j / sp.seg;
+    return (r * sp.nxcd + sp.xcd) * sp.seg + (j - r * sp.seg);
+}
+
+// Grid-wide maximum of the workgroups' values for attempt n; it doubles as
+// the grid barrier of the attempt.  Each workgroup stores one tagged 64-bit
+// slot; wave 0 of every workgroup then scans all slots of the attempt's bank
+// (one relaxed load per lane per 64 workgroups) until every tag is current.
+// No read-modify-write atomic and no cache-maintaining fence is involved, so
+// the cost does not grow with contention on one address.  Banks alternate
+// by attempt parity: a workgroup can only overwrite a bank two attempts
+// later, after every workgroup has stored the slot of the attempt between,
+// i.e. after every workgroup has finished scanning this one.  Returns false
+// if the bounded wait ran out.
+__device__ bool grid_max(uint64_t *sync, int n, float m, int32_t *status, float &out)
 {
     __shared__ int ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    __shared__ float res;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int nb = gridDim.x;
+        uint64_t *bank = sync + (size_t)(n & 1) * nb;
+        const uint32_t tag = (uint32_t)(n + 1);
+        if (lane == 0)
+            __hip_atomic_store(&bank[blockIdx.x], ((uint64_t)tag << 32) | __float_as_uint(m),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0, mx = 0;
         int good = 1;
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) {
-                good = 0;
-                set_status(status, FFB_E_DEVICE);
+        for (;;) {
+            bool done = true;
+            uint32_t v = 0;
+            for (int r = lane; r < nb; r += 64) {
+                const uint64_t w = __hip_atomic_load(&bank[r], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if ((uint32_t)(w >> 32) != tag) done = false;
+                const uint32_t x = (uint32_t)w;
+                v = v > x ? v : x;
+            }
+            if (__all(done)) {
+                for (int o = 32; o > 0; o >>= 1) {
+                    const uint32_t x = __shfl_xor(v, o, 64);
+                    v = v > x ? v : x;
+                }
+                mx = v;
                 break;
             }
-            if ((spins & 1023u) == 0 &&
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                good = 0;
+                if (lane == 0) set_status(status, FFB_E_DEVICE);
+                break;
+            }
+            if ((spins & 255u) == 0 &&
                 __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
                     FFB_E_DEVICE) {
                 good = 0;
                 break;
             }
         }
-        ok = good;
+        if (lane == 0) {
+            res = __uint_as_float(mx);
+            ok = good;
+        }
     }
     __syncthreads();
-    return ok != 0;
+    out = res;
+    const bool r = ok != 0;
+    __syncthreads();
+    return r;
 }
 
 __global__ __launch_bounds__(kThreads) void k_advect(Params p)
@@ -180,17 +277,23 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
 
     const double rho_bar = *p.rho_bar;
     const Field F{p.fields, p.lx, p.ly, p.pitch, (float)p.lx, (float)p.ly};
-    const int64_t G = (int64_t)gridDim.x * kThreads;
-    const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    // XCD-aware contiguous chunks: the workgroups of one XCD share one
+    // contiguous run of points (spatially coherent in the usual layouts),
+    // so that XCD's L2 holds a compact part of the fields
+    const Span sp = span_of(blockIdx.x, gridDim.x, p.n);
     const bool replay = p.n_replay > 0;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
 
     // initial state: hi = xy, lo = 0, FSAL velocity at t = 0
     {
         const float omt = 1.0f, tb = 0.0f;
-        for (int64_t i = gid; i < p.n; i += G) {
+        for (int64_t j = sp.j0 + threadIdx.x; j < sp.j1; j += kThreads) {
+            const int64_t i = point_of(sp, j);
+            if (i >= p.n) continue;
             const float2 y = p.xy[i];
-            const float2 k1 = velocity(F, y.x, y.y, 0.f, 0.f, omt, tb);
+            CellCache cc;
+            cc.key = -1;
+            const float2 k1 = velocity(F, y.x, y.y, 0.f, 0.f, omt, tb, cc);
             p.st0[i] = make_float4(y.x, y.y, 0.f, 0.f);
             p.kv0[i] = k1;
         }
@@ -229,37 +332,41 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         float2 *kvn = cur ? p.kv0 : p.kv1;
 
         float emax = 0.0f;
-        for (int64_t i = gid; i < p.n; i += G) {
+        for (int64_t j = sp.j0 + threadIdx.x; j < sp.j1; j += kThreads) {
+            const int64_t i = point_of(sp, j);
+            if (i >= p.n) continue;
             const float4 s0 = stc[i];
             const float hx = s0.x, hy = s0.y, lx = s0.z, ly = s0.w;
             // stage velocities scaled by the step: q_s = h k_s
             const float2 k1 = kvc[i];
+            CellCache cc;
+            cc.key = -1;
             const float2 q1 = make_float2(hf * k1.x, hf * k1.y);
             float dx, dy;
             dx = A21 * q1.x;
             dy = A21 * q1.y;
-            float2 q2 = velocity(F, hx, hy, lx + dx, ly + dy, omt[1], tb[1]);
+            float2 q2 = velocity(F, hx, hy, lx + dx, ly + dy, omt[1], tb[1], cc);
             q2 = make_float2(hf * q2.x, hf * q2.y);
             dx = fmaf(A32, q2.x, A31 * q1.x);
             dy = fmaf(A32, q2.y, A31 * q1.y);
-            float2 q3 = velocity(F, hx, hy, lx + dx, ly + dy, omt[2], tb[2]);
+            float2 q3 = velocity(F, hx, hy, lx + dx, ly + dy, omt[2], tb[2], cc);
             q3 = make_float2(hf * q3.x, hf * q3.y);
             dx = fmaf(A43, q3.x, fmaf(A42, q2.x, A41 * q1.x));
             dy = fmaf(A43, q3.y, fmaf(A42, q2.y, A41 * q1.y));
-            float2 q4 = velocity(F, hx, hy, lx + dx, ly + dy, omt[3], tb[3]);
+            float2 q4 = velocity(F, hx, hy, lx + dx, ly + dy, omt[3], tb[3], cc);
             q4 = make_float2(hf * q4.x, hf * q4.y);
             dx = fmaf(A54, q4.x, fmaf(A53, q3.x, fmaf(A52, q2.x, A51 * q1.x)));
             dy = fmaf(A54, q4.y, fmaf(A53, q3.y, fmaf(A52, q2.y, A51 * q1.y)));
-            float2 q5 = velocity(F, hx, hy, lx + dx, ly + dy, omt[4], tb[4]);
+            float2 q5 = velocity(F, hx, hy, lx + dx, ly + dy, omt[4], tb[4], cc);
             q5 = make_float2(hf * q5.x, hf * q5.y);
             dx = fmaf(A65, q5.x, fmaf(A64, q4.x, fmaf(A63, q3.x, fmaf(A62, q2.x, A61 * q1.x))));
             dy = fmaf(A65, q5.y, fmaf(A64, q4.y, fmaf(A63, q3.y, fmaf(A62, q2.y, A61 * q1.y))));
-            float2 q6 = velocity(F, hx, hy, lx + dx, ly + dy, omt[5], tb[5]);
+            float2 q6 = velocity(F, hx, hy, lx + dx, ly + dy, omt[5], tb[5], cc);
             q6 = make_float2(hf * q6.x, hf * q6.y);
             // order-5 increment (weights of the last stage row; the k2 weight is 0)
             const float ix = fmaf(B6, q6.x, fmaf(B5, q5.x, fmaf(B4, q4.x, fmaf(B3, q3.x, B1 * q1.x))));
             const float iy = fmaf(B6, q6.y, fmaf(B5, q5.y, fmaf(B4, q4.y, fmaf(B3, q3.y, B1 * q1.y))));
-            const float2 k7 = velocity(F, hx, hy, lx + ix, ly + iy, omt[6], tb[6]);
+            const float2 k7 = velocity(F, hx, hy, lx + ix, ly + iy, omt[6], tb[6], cc);
             const float ex = fmaf(E7 * hf, k7.x, fmaf(E6, q6.x, fmaf(E5, q5.x, fmaf(E4, q4.x,
                                   fmaf(E3, q3.x, E1 * q1.x)))));
             const float ey = fmaf(E7 * hf, k7.y, fmaf(E6, q6.y, fmaf(E5, q5.y, fmaf(E4, q4.y,
@@ -281,23 +388,19 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             stn[i] = make_float4(rx, ry, nlx, nly);
             kvn[i] = k7;
         }
-        // workgroup max -> per-attempt slot
+        // workgroup max, then the grid-wide max (one barrier per attempt)
         emax = wave_max(emax);
         if ((threadIdx.x & 63) == 0) s_err[threadIdx.x >> 6] = emax;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            float m = s_err[0];
+        float m = s_err[0];
 #pragma unroll
-            for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, s_err[w]);
-            __hip_atomic_fetch_max(&p.errslot[attempt], __float_as_uint(m), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (!grid_barrier(p.barrier, (uint32_t)(attempt + 1) * gridDim.x, p.status)) {
+        for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, s_err[w]);
+        float gmax;
+        if (!grid_max(p.sync, attempt, m, p.status, gmax)) {
             final_status = FFB_E_DEVICE;
             break;
         }
-        const double err = (double)__uint_as_float(__hip_atomic_load(
-            &p.errslot[attempt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const double err = (double)gmax;
         ++attempt;
         if (!(err < __builtin_huge_val())) {
             final_status = FFB_E_NONFINITE;
@@ -328,7 +431,9 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
 
     if (final_status == 0) {
         const float4 *stc = cur ? p.st1 : p.st0;
-        for (int64_t i = gid; i < p.n; i += G) {
+        for (int64_t j = sp.j0 + threadIdx.x; j < sp.j1; j += kThreads) {
+            const int64_t i = point_of(sp, j);
+            if (i >= p.n) continue;
             const float4 s = stc[i];
             p.xy[i] = make_float2(s.x + s.z, s.y + s.w);
         }
@@ -360,8 +465,13 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
                          float2 *xy, int64_t n, const ffb_integrate_opts *o, int32_t *stats,
                          double *h_out, int32_t h_cap)
 {
-    // slots for every attempt plus the barrier counter, cleared by a kernel
-    hipError_t e = launch_fill_u32(ctx->errslot, (int64_t)o->max_attempts + 1, 0u, ctx->stream);
+    int64_t want = (n + kThreads - 1) / kThreads;
+    if (want < 1) want = 1;
+    int blocks = ctx->adv_blocks;
+    if (want < blocks) blocks = (int)want;
+    if (4 * blocks > ctx->err_cap) return hipErrorInvalidValue;
+    // synchronisation slots, cleared by a kernel (graph-capture safe)
+    hipError_t e = launch_fill_u32(ctx->errslot, 4 * (int64_t)blocks, 0u, ctx->stream);
     if (e != hipSuccess) return e;
     Params p;
     p.fields = fields;
@@ -375,8 +485,7 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     p.st1 = ctx->st[1];
     p.kv0 = ctx->kv[0];
     p.kv1 = ctx->kv[1];
-    p.errslot = ctx->errslot;
-    p.barrier = ctx->errslot + o->max_attempts;
+    p.sync = reinterpret_cast<uint64_t *>(ctx->errslot);
     p.status = ctx->d_status;
     p.stats = stats;
     p.h_out = h_out;
@@ -390,10 +499,6 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     p.max_attempts = o->max_attempts;
     p.n_replay = o->n_replay;
     p.replay_h = o->replay_h;
-    int64_t want = (n + kThreads - 1) / kThreads;
-    if (want < 1) want = 1;
-    int blocks = ctx->adv_blocks;
-    if (want < blocks) blocks = (int)want;
     void *args[] = {&p};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_advect), dim3(blocks),
                                       dim3(kThreads), args, 0, ctx->stream);
