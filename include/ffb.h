@@ -115,6 +115,21 @@ int ffb_reset_status(ffb_ctx *ctx);
  * the context; valid until the next call on it). */
 const char *ffb_last_error(const ffb_ctx *ctx);
 
+/* Implementation options of a context (host call, takes effect for later
+ * calls).  They change where work happens, never what is computed beyond
+ * FP32 rounding.
+ *   FFB_OPT_ADVECT_STATE: where ffb_integrate keeps each point's state
+ *     0 = device memory (any number of points);
+ *     1 = LDS, first-stage velocity carried between steps (default);
+ *     2 = LDS, first-stage velocity recomputed each step.
+ *     Modes 1 and 2 apply when one workgroup's share of points fits in LDS
+ *     (about 2.5 M points on 256 CUs); otherwise mode 0 runs.
+ *   FFB_OPT_ADVECT_BLOCKS: cap on the persistent workgroups of
+ *     ffb_integrate (0 = one per CU, the default).
+ * Returns FFB_E_INVALID for an unknown option or value. */
+enum { FFB_OPT_ADVECT_STATE = 1, FFB_OPT_ADVECT_BLOCKS = 2 };
+int ffb_set_option(ffb_ctx *ctx, int32_t option, int32_t value);
+
 /* Areas and relative area errors (benchmarking section, stopping rule).
  *   area[r]  (out, [R]) = sum over the rings of region r of the shoelace sum
  *            1/2 sum_k (x_k y_{k+1} - x_{k+1} y_k), FP64 sums of products of

@@ -9,4 +9,5 @@ from .api import (  # noqa: F401
     default_sigma, iterate, lib, LIB_PATH,
     ffb_create, ffb_destroy, ffb_sync, ffb_reset_status, ffb_last_error,
     ffb_area_error, ffb_density, ffb_flux, ffb_pack_fields, ffb_integrate,
+    ffb_set_option, OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS,
 )

@@ -71,8 +71,9 @@ def lib():
         L.ffb_pack_fields.argtypes = [vp, vp, vp, vp, vp]
         L.ffb_integrate.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(FFBIntegrateOpts),
                                     vp, vp, i32]
+        L.ffb_set_option.argtypes = [vp, i32, i32]
         for f in ("ffb_create", "ffb_destroy", "ffb_sync", "ffb_reset_status", "ffb_area_error",
-                  "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate"):
+                  "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -174,6 +175,13 @@ def ffb_last_error(ctx) -> str:
     return lib().ffb_last_error(ctx).decode()
 
 
+OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS = 1, 2
+
+
+def ffb_set_option(ctx, option: int, value: int) -> None:
+    _check(ctx, lib().ffb_set_option(ctx, int(option), int(value)), "ffb_set_option")
+
+
 def ffb_area_error(ctx, geom: Geometry, value, area, err, max_abs_err) -> None:
     R = geom.n_regions
     g = geom.struct()
@@ -249,6 +257,9 @@ class Context:
 
     def reset_status(self):
         ffb_reset_status(self.handle)
+
+    def set_option(self, option: int, value: int):
+        ffb_set_option(self.handle, option, value)
 
     def _f64(self, *shape):
         return torch.empty(shape, dtype=torch.float64, device=self.device)

@@ -167,6 +167,22 @@ const char *ffb_last_error(const ffb_ctx *ctx)
     return ctx ? ctx->last_error.c_str() : "null context";
 }
 
+int ffb_set_option(ffb_ctx *ctx, int32_t option, int32_t value)
+{
+    if (!ctx) return FFB_E_INVALID;
+    if (option == FFB_OPT_ADVECT_STATE) {
+        if (value < 0 || value > 2) return fail(ctx, FFB_E_INVALID, "advect state mode out of range%s");
+        ctx->adv_mode = value;
+        return FFB_OK;
+    }
+    if (option == FFB_OPT_ADVECT_BLOCKS) {
+        if (value < 0) return fail(ctx, FFB_E_INVALID, "negative workgroup cap%s");
+        ctx->adv_cap = value;
+        return FFB_OK;
+    }
+    return fail(ctx, FFB_E_INVALID, "unknown option%s");
+}
+
 int ffb_area_error(ffb_ctx *ctx, const ffb_geometry *g, const double *value, double *area,
                    double *err, double *max_abs_err)
 {
@@ -222,7 +238,8 @@ int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, floa
     if (!ctx) return FFB_E_INVALID;
     if (!fields || !rho_bar || !o || !stats || (n > 0 && !xy))
         return fail(ctx, FFB_E_INVALID, "ffb_integrate: NULL argument%s");
-    if (n < 0) return fail(ctx, FFB_E_INVALID, "ffb_integrate: n < 0%s");
+    if (n < 0 || n > INT32_MAX - 4096)
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: n out of range%s");
     if (h_cap < 0 || (h_cap > 0 && !h_out))
         return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad h_out/h_cap%s");
     if (o->max_attempts <= 0 || o->max_attempts > (1 << 20))

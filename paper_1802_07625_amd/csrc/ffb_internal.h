@@ -37,6 +37,8 @@ struct ffb_ctx {
     uint32_t *errslot = nullptr;               // advection grid-sync words
     int32_t err_cap = 0;
     int adv_blocks = 0;                        // co-resident blocks of the advection kernel
+    int adv_mode = 1;                          // advection state placement (FFB_OPT_ADVECT_STATE)
+    int adv_cap = 0;                           // cap on advection workgroups, 0 = none
 };
 
 // ---------------------------------------------------------------- launches

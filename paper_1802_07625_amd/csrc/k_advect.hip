@@ -22,10 +22,11 @@
 //   * the barrier has a bounded wait, so every wave exits even if something
 //     goes wrong (the status word then says FFB_E_DEVICE).
 //
-// Positions are compensated pairs: the candidate position is hi + (lo + d),
-// with d = h sum_s a_s k_s, updated with an error-free sum; lookups use
-// floor(hi - 1/2) plus a fraction computed from (hi - 1/2 - floor) + lo + d,
-// so the bilinear weights keep ~1e-7 cells of precision at L = 1024.
+// Positions are compensated pairs hi + lo (an error-free sum adds each
+// accepted increment).  A lookup at hi + lo + d splits off the integer part
+// of hi - 1/2 once per point and attempt and forms the fraction from
+// (hi - 1/2 - floor) + lo + d, so the bilinear weights keep ~1e-7 cells of
+// precision at L = 1024; clamping to the box is one med3 on that fraction.
 #include "ffb_internal.h"
 
 namespace {
@@ -64,7 +65,7 @@ struct Params {
     int lx, ly, pitch;
     const double *rho_bar;
     float2 *xy;
-    int64_t n;
+    int n;                  // < 2^31 (checked by the caller)
     float4 *st0, *st1;
     float2 *kv0, *kv1;
     uint64_t *sync;         // 2 banks x gridDim.x tagged slots
@@ -81,25 +82,38 @@ struct Params {
 struct Field {
     const float4 *f;
     int lx, ly, pitch;
-    float flx, fly;
 };
 
-// One coordinate of a lookup: cell index in [-1, L-1] and fraction in [0, 1].
-__device__ inline void locate(float hi, float d, float fL, int L, int &idx, float &frac)
+// One coordinate of a point, prepared once per point and attempt:
+// hi - 1/2 = ifl + fr with ifl integral, frl = fr + lo, and the bounds of the
+// box in the same frame ([-1/2, L - 1/2] relative to ifl).
+struct Axis {
+    int ifl;
+    float frl, lo_t, hi_t;
+};
+
+__device__ inline Axis make_axis(float hi, float lo, int L)
 {
-    const float q = hi + d;                 // coarse position, for clamping only
-    const float u = hi - 0.5f;              // exact for |hi| < 2^22
+    Axis a;
+    const float u = hi - 0.5f;          // exact for |hi| < 2^22
     const float fu = floorf(u);
-    float a = (u - fu) + d;                 // fraction relative to fu, precise
-    const float fa = floorf(a);
-    a -= fa;
-    int i = (int)fu + (int)fa;
-    // clamp to the box with selects (no branches); !(q > 0) also catches NaN
-    const bool below = !(q > 0.0f), above = q >= fL;
-    i = below ? -1 : (above ? L - 1 : i);
-    a = (below || above) ? 0.5f : a;
-    idx = min(max(i, -1), L - 1);
-    frac = a;
+    a.ifl = (int)fu;
+    a.frl = (u - fu) + lo;
+    a.lo_t = -0.5f - fu;                // exact: fu is integral
+    a.hi_t = ((float)L - 0.5f) - fu;
+    return a;
+}
+
+// Cell index in [-1, L-1] and fraction of the lookup at hi + lo + d, clamped
+// to the box.  The integer med3 keeps the index in range for any input
+// (NaN or Inf positions included).
+__device__ inline void locate(const Axis &a, float d, int L, int &idx, float &frac)
+{
+    float t = a.frl + d;
+    t = __builtin_amdgcn_fmed3f(t, a.lo_t, a.hi_t);
+    const float ft = floorf(t);
+    idx = min(max(a.ifl + (int)ft, -1), L - 1);
+    frac = t - ft;
 }
 
 // The four field records around the last looked-up cell of one point.  The
@@ -116,15 +130,16 @@ __device__ inline float3 ld3(const float4 *f, int idx)
     return make_float3(v.x, v.y, v.z);
 }
 
-// Velocity at (hi + d) for time factors omt = 1 - t and tb = t * rho_bar.
-__device__ inline float2 velocity(const Field &F, float hx, float hy, float dx, float dy,
-                                  float omt, float tb, CellCache &cc)
+// h * v at hi + lo + d, for the stage factors omh = (1 - t) / h and
+// tbh = t rho_bar / h:  h v = J / ((1 - t) rho_s + t rho_bar) * h.
+__device__ inline float2 velocity(const Field &F, const Axis &ax, const Axis &ay, float dx,
+                                  float dy, float omh, float tbh, CellCache &cc)
 {
     int i, j;
     float a, b;
-    locate(hx, dx, F.flx, F.lx, i, a);
-    locate(hy, dy, F.fly, F.ly, j, b);
-    const int base = (j + 1) * F.pitch + (i + 1);     // < (L+2)^2 < 2^31
+    locate(ax, dx, F.lx, i, a);
+    locate(ay, dy, F.ly, j, b);
+    const int base = __umul24(j + 1, F.pitch) + (i + 1);     // < (L+2)^2
     if (base != cc.key) {
         cc.key = base;
         cc.c00 = ld3(F.f, base);
@@ -132,14 +147,15 @@ __device__ inline float2 velocity(const Field &F, float hx, float hy, float dx, 
         cc.c01 = ld3(F.f, base + F.pitch);
         cc.c11 = ld3(F.f, base + F.pitch + 1);
     }
-    const float r00 = __builtin_amdgcn_rcpf(fmaf(cc.c00.z, omt, tb));
-    const float r10 = __builtin_amdgcn_rcpf(fmaf(cc.c10.z, omt, tb));
-    const float r01 = __builtin_amdgcn_rcpf(fmaf(cc.c01.z, omt, tb));
-    const float r11 = __builtin_amdgcn_rcpf(fmaf(cc.c11.z, omt, tb));
+    const float r00 = __builtin_amdgcn_rcpf(fmaf(cc.c00.z, omh, tbh));
+    const float r10 = __builtin_amdgcn_rcpf(fmaf(cc.c10.z, omh, tbh));
+    const float r01 = __builtin_amdgcn_rcpf(fmaf(cc.c01.z, omh, tbh));
+    const float r11 = __builtin_amdgcn_rcpf(fmaf(cc.c11.z, omh, tbh));
     const float x00 = cc.c00.x * r00, x10 = cc.c10.x * r10;
     const float x01 = cc.c01.x * r01, x11 = cc.c11.x * r11;
     const float y00 = cc.c00.y * r00, y10 = cc.c10.y * r10;
     const float y01 = cc.c01.y * r01, y11 = cc.c11.y * r11;
+    // along x on both node rows, then along y (exact zeros on the box edges)
     const float xr0 = fmaf(a, x10 - x00, x00), xr1 = fmaf(a, x11 - x01, x01);
     const float yr0 = fmaf(a, y10 - y00, y00), yr1 = fmaf(a, y11 - y01, y01);
     return make_float2(fmaf(b, xr1 - xr0, xr0), fmaf(b, yr1 - yr0, yr0));
@@ -170,35 +186,31 @@ __device__ inline float wave_max(float v)
 // private) works on kSegments contiguous runs of points -- with the usual
 // [vertices | grid nodes] layout, one run of each, which also balances the
 // cheap vertex lookups against the wider grid-node lookups.  Within an XCD
-// the runs are concatenated and cut into one chunk per workgroup.
+// the two runs are concatenated and cut into one chunk per workgroup, which
+// is at most two contiguous point ranges [a0, a0 + la) and [b0, b0 + lb).
 struct Span {
-    int64_t seg;       // segment length
-    int64_t j0, j1;    // this workgroup's range in its XCD's concatenated runs
-    int xcd, nxcd;
+    int a0, la, b0, lb;
 };
 
-__device__ inline Span span_of(int b, int nb, int64_t n)
+__device__ inline Span span_of(int b, int nb, int n)
 {
+    const int nx = nb < kXcds ? nb : kXcds;
+    const int x = b % nx, rank = b / nx;
+    const int size = nb / nx + (x < nb % nx ? 1 : 0);       // workgroups on this XCD
+    const int seg = (n + nx * kSegments - 1) / (nx * kSegments);
+    const int total = seg * kSegments;                       // this XCD's share
+    const int chunk = (total + size - 1) / size;
+    const int j0 = min(total, rank * chunk), j1 = min(total, j0 + chunk);
     Span sp;
-    sp.nxcd = nb < kXcds ? nb : kXcds;
-    sp.xcd = b % sp.nxcd;
-    const int rank = b / sp.nxcd;
-    const int per = nb / sp.nxcd, extra = nb % sp.nxcd;
-    const int size = per + (sp.xcd < extra ? 1 : 0);        // workgroups on this XCD
-    const int64_t nseg = (int64_t)sp.nxcd * kSegments;
-    sp.seg = (n + nseg - 1) / nseg;
-    const int64_t total = sp.seg * kSegments;                // this XCD's share
-    const int64_t chunk = (total + size - 1) / size;
-    sp.j0 = min(total, (int64_t)rank * chunk);
-    sp.j1 = min(total, sp.j0 + chunk);
+    // run 0: points x * seg + j for j in [0, seg)
+    const int ja = j0, jb = min(j1, seg);
+    sp.a0 = x * seg + ja;
+    sp.la = max(0, min(n, x * seg + jb) - sp.a0);
+    // run 1: points (nx + x) * seg + (j - seg) for j in [seg, 2 seg)
+    const int jc = max(j0, seg) - seg, jd = j1 - seg;
+    sp.b0 = (nx + x) * seg + jc;
+    sp.lb = max(0, min(n, (nx + x) * seg + max(jd, jc)) - sp.b0);
     return sp;
-}
-
-// Point index of position j in the XCD's concatenated runs.
-__device__ inline int64_t point_of(const Span &sp, int64_t j)
-{
-    const int64_t r = j / sp.seg;
-    return (r * sp.nxcd + sp.xcd) * sp.seg + (j - r * sp.seg);
 }
 
 // Grid-wide maximum of the workgroups' values for attempt n; it doubles as
@@ -268,34 +280,72 @@ __device__ bool grid_max(uint64_t *sync, int n, float m, int32_t *status, float 
     return r;
 }
 
+// Where a point's state lives during one launch.
+enum StateMode {
+    kGlobalState = 0,   // (hi, lo) and the FSAL velocity double-buffered in HBM
+    kLdsState = 1,      // (hi, lo) in LDS, FSAL velocity double-buffered in HBM
+    kLdsRecompute = 2,  // (hi, lo) in LDS, first-stage velocity recomputed
+};
+
+// The six new stages of one attempt for one point, from q1 = h k1.  Returns
+// the order-5 increment (ix, iy), q7 = h k7 and the error estimate (ex, ey).
+__device__ inline void dp_stages(const Field &F, const Axis &ax, const Axis &ay, float2 q1,
+                                 const float *omh, const float *tbh, CellCache &cc, float &ix,
+                                 float &iy, float2 &q7, float &ex, float &ey)
+{
+    float dx, dy;
+    dx = A21 * q1.x;
+    dy = A21 * q1.y;
+    const float2 q2 = velocity(F, ax, ay, dx, dy, omh[1], tbh[1], cc);
+    dx = fmaf(A32, q2.x, A31 * q1.x);
+    dy = fmaf(A32, q2.y, A31 * q1.y);
+    const float2 q3 = velocity(F, ax, ay, dx, dy, omh[2], tbh[2], cc);
+    dx = fmaf(A43, q3.x, fmaf(A42, q2.x, A41 * q1.x));
+    dy = fmaf(A43, q3.y, fmaf(A42, q2.y, A41 * q1.y));
+    const float2 q4 = velocity(F, ax, ay, dx, dy, omh[3], tbh[3], cc);
+    dx = fmaf(A54, q4.x, fmaf(A53, q3.x, fmaf(A52, q2.x, A51 * q1.x)));
+    dy = fmaf(A54, q4.y, fmaf(A53, q3.y, fmaf(A52, q2.y, A51 * q1.y)));
+    const float2 q5 = velocity(F, ax, ay, dx, dy, omh[4], tbh[4], cc);
+    dx = fmaf(A65, q5.x, fmaf(A64, q4.x, fmaf(A63, q3.x, fmaf(A62, q2.x, A61 * q1.x))));
+    dy = fmaf(A65, q5.y, fmaf(A64, q4.y, fmaf(A63, q3.y, fmaf(A62, q2.y, A61 * q1.y))));
+    const float2 q6 = velocity(F, ax, ay, dx, dy, omh[5], tbh[5], cc);
+    // order-5 increment (weights of the last stage row; the k2 weight is 0)
+    ix = fmaf(B6, q6.x, fmaf(B5, q5.x, fmaf(B4, q4.x, fmaf(B3, q3.x, B1 * q1.x))));
+    iy = fmaf(B6, q6.y, fmaf(B5, q5.y, fmaf(B4, q4.y, fmaf(B3, q3.y, B1 * q1.y))));
+    q7 = velocity(F, ax, ay, ix, iy, omh[6], tbh[6], cc);
+    ex = fmaf(E7, q7.x, fmaf(E6, q6.x, fmaf(E5, q5.x, fmaf(E4, q4.x, fmaf(E3, q3.x, E1 * q1.x)))));
+    ey = fmaf(E7, q7.y, fmaf(E6, q6.y, fmaf(E5, q5.y, fmaf(E4, q4.y, fmaf(E3, q3.y, E1 * q1.y)))));
+}
+
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_advect(Params p)
 {
+    extern __shared__ float4 lds_state[];      // LDS modes: one slot per owned point
     __shared__ float s_err[kThreads / 64];
     // a status set by an earlier call (e.g. non-positive density) stops the
     // integration before any point is touched; the value is uniform.
     if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
 
     const double rho_bar = *p.rho_bar;
-    const Field F{p.fields, p.lx, p.ly, p.pitch, (float)p.lx, (float)p.ly};
-    // XCD-aware contiguous chunks: the workgroups of one XCD share one
-    // contiguous run of points (spatially coherent in the usual layouts),
-    // so that XCD's L2 holds a compact part of the fields
+    const Field F{p.fields, p.lx, p.ly, p.pitch};
     const Span sp = span_of(blockIdx.x, gridDim.x, p.n);
+    const int npts = sp.la + sp.lb;
     const bool replay = p.n_replay > 0;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    float4 *bak = p.st0;                       // LDS modes: state before the attempt
 
-    // initial state: hi = xy, lo = 0, FSAL velocity at t = 0
-    {
-        const float omt = 1.0f, tb = 0.0f;
-        for (int64_t j = sp.j0 + threadIdx.x; j < sp.j1; j += kThreads) {
-            const int64_t i = point_of(sp, j);
-            if (i >= p.n) continue;
-            const float2 y = p.xy[i];
+    // initial state: hi = xy, lo = 0 (and the FSAL velocity at t = 0)
+    for (int k = threadIdx.x; k < npts; k += kThreads) {
+        const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+        const float2 y = p.xy[i];
+        const float4 s0 = make_float4(y.x, y.y, 0.f, 0.f);
+        if (MODE == kGlobalState) p.st0[i] = s0;
+        else lds_state[k] = s0;
+        if (MODE != kLdsRecompute) {
             CellCache cc;
             cc.key = -1;
-            const float2 k1 = velocity(F, y.x, y.y, 0.f, 0.f, omt, tb, cc);
-            p.st0[i] = make_float4(y.x, y.y, 0.f, 0.f);
-            p.kv0[i] = k1;
+            const Axis ax = make_axis(y.x, 0.f, p.lx), ay = make_axis(y.y, 0.f, p.ly);
+            p.kv0[i] = velocity(F, ax, ay, 0.f, 0.f, 1.0f, 0.0f, cc);
         }
     }
 
@@ -316,15 +366,17 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             final_step = h >= 1.0 - t;
             if (final_step) h = 1.0 - t;
         }
-        // per-attempt uniforms: the step and the time factors of each stage;
-        // the tableau itself enters as instruction literals
-        const float hf = uniform((float)h);
-        float omt[7], tb[7];
+        // per-attempt uniforms: the step, its inverse and the time factors of
+        // each stage divided by h (so lookups return h * v); the tableau
+        // itself enters as instruction literals
+        const double rh = 1.0 / h;
+        const float hf = uniform((float)h), rhf = uniform((float)rh);
+        float omh[7], tbh[7];
 #pragma unroll
-        for (int s = 1; s < 7; ++s) {
+        for (int s = 0; s < 7; ++s) {
             const double ts = t + kC[s] * h;
-            omt[s] = uniform((float)(1.0 - ts));
-            tb[s] = uniform((float)(ts * rho_bar));
+            omh[s] = uniform((float)((1.0 - ts) * rh));
+            tbh[s] = uniform((float)(ts * rho_bar * rh));
         }
         const float4 *stc = cur ? p.st1 : p.st0;
         const float2 *kvc = cur ? p.kv1 : p.kv0;
@@ -332,61 +384,43 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         float2 *kvn = cur ? p.kv0 : p.kv1;
 
         float emax = 0.0f;
-        for (int64_t j = sp.j0 + threadIdx.x; j < sp.j1; j += kThreads) {
-            const int64_t i = point_of(sp, j);
-            if (i >= p.n) continue;
-            const float4 s0 = stc[i];
+        for (int k = threadIdx.x; k < npts; k += kThreads) {
+            const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+            const float4 s0 = MODE == kGlobalState ? stc[i] : lds_state[k];
             const float hx = s0.x, hy = s0.y, lx = s0.z, ly = s0.w;
-            // stage velocities scaled by the step: q_s = h k_s
-            const float2 k1 = kvc[i];
+            const Axis ax = make_axis(hx, lx, p.lx), ay = make_axis(hy, ly, p.ly);
             CellCache cc;
             cc.key = -1;
-            const float2 q1 = make_float2(hf * k1.x, hf * k1.y);
-            float dx, dy;
-            dx = A21 * q1.x;
-            dy = A21 * q1.y;
-            float2 q2 = velocity(F, hx, hy, lx + dx, ly + dy, omt[1], tb[1], cc);
-            q2 = make_float2(hf * q2.x, hf * q2.y);
-            dx = fmaf(A32, q2.x, A31 * q1.x);
-            dy = fmaf(A32, q2.y, A31 * q1.y);
-            float2 q3 = velocity(F, hx, hy, lx + dx, ly + dy, omt[2], tb[2], cc);
-            q3 = make_float2(hf * q3.x, hf * q3.y);
-            dx = fmaf(A43, q3.x, fmaf(A42, q2.x, A41 * q1.x));
-            dy = fmaf(A43, q3.y, fmaf(A42, q2.y, A41 * q1.y));
-            float2 q4 = velocity(F, hx, hy, lx + dx, ly + dy, omt[3], tb[3], cc);
-            q4 = make_float2(hf * q4.x, hf * q4.y);
-            dx = fmaf(A54, q4.x, fmaf(A53, q3.x, fmaf(A52, q2.x, A51 * q1.x)));
-            dy = fmaf(A54, q4.y, fmaf(A53, q3.y, fmaf(A52, q2.y, A51 * q1.y)));
-            float2 q5 = velocity(F, hx, hy, lx + dx, ly + dy, omt[4], tb[4], cc);
-            q5 = make_float2(hf * q5.x, hf * q5.y);
-            dx = fmaf(A65, q5.x, fmaf(A64, q4.x, fmaf(A63, q3.x, fmaf(A62, q2.x, A61 * q1.x))));
-            dy = fmaf(A65, q5.y, fmaf(A64, q4.y, fmaf(A63, q3.y, fmaf(A62, q2.y, A61 * q1.y))));
-            float2 q6 = velocity(F, hx, hy, lx + dx, ly + dy, omt[5], tb[5], cc);
-            q6 = make_float2(hf * q6.x, hf * q6.y);
-            // order-5 increment (weights of the last stage row; the k2 weight is 0)
-            const float ix = fmaf(B6, q6.x, fmaf(B5, q5.x, fmaf(B4, q4.x, fmaf(B3, q3.x, B1 * q1.x))));
-            const float iy = fmaf(B6, q6.y, fmaf(B5, q5.y, fmaf(B4, q4.y, fmaf(B3, q3.y, B1 * q1.y))));
-            const float2 k7 = velocity(F, hx, hy, lx + ix, ly + iy, omt[6], tb[6], cc);
-            const float ex = fmaf(E7 * hf, k7.x, fmaf(E6, q6.x, fmaf(E5, q5.x, fmaf(E4, q4.x,
-                                  fmaf(E3, q3.x, E1 * q1.x)))));
-            const float ey = fmaf(E7 * hf, k7.y, fmaf(E6, q6.y, fmaf(E5, q5.y, fmaf(E4, q4.y,
-                                  fmaf(E3, q3.y, E1 * q1.y)))));
-            // candidate state: (hi, lo) + increment, error-free
+            // stage velocities scaled by the step: q_s = h k_s
+            float2 q1;
+            if (MODE == kLdsRecompute) {
+                q1 = velocity(F, ax, ay, 0.f, 0.f, omh[0], tbh[0], cc);
+            } else {
+                const float2 k1 = kvc[i];
+                q1 = make_float2(hf * k1.x, hf * k1.y);
+            }
+            float ix, iy, ex, ey;
+            float2 q7;
+            dp_stages(F, ax, ay, q1, omh, tbh, cc, ix, iy, q7, ex, ey);
+            // candidate state: hi + increment split error-free, the rounding
+            // error added to lo (whose own rounding stays ~1e-12 cells)
             float sx, ex2, sy, ey2;
             two_sum(hx, ix, sx, ex2);
             two_sum(hy, iy, sy, ey2);
-            float nlx = lx + ex2, nly = ly + ey2;
-            const float rx = sx + nlx, ry = sy + nly;     // renormalise
-            nlx -= rx - sx;
-            nly -= ry - sy;
+            const float4 cand = make_float4(sx, sy, lx + ex2, ly + ey2);
             // a NaN or Inf in the error estimate or in the new position
             // poisons the maximum (fmaxf alone would drop a NaN)
-            const float poison = (ex + ey) + (rx + ry);
+            const float poison = (ex + ey) + (sx + sy);
             const float e = (poison - poison == 0.0f) ? fmaxf(fabsf(ex), fabsf(ey))
                                                       : __builtin_inff();
             emax = fmaxf(emax, e);
-            stn[i] = make_float4(rx, ry, nlx, nly);
-            kvn[i] = k7;
+            if (MODE == kGlobalState) {
+                stn[i] = cand;
+            } else {
+                bak[i] = s0;
+                lds_state[k] = cand;
+            }
+            if (MODE != kLdsRecompute) kvn[i] = make_float2(q7.x * rhf, q7.y * rhf);
         }
         // workgroup max, then the grid-wide max (one barrier per attempt)
         emax = wave_max(emax);
@@ -422,6 +456,13 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             ++rej;
             h *= fmax(p.fac_min, p.safety * pow(err / p.tol, -0.2));
             last_rejected = 1;
+            if (MODE != kGlobalState) {
+                // undo the attempt: every lane restores its own points
+                for (int k = threadIdx.x; k < npts; k += kThreads) {
+                    const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+                    lds_state[k] = bak[i];
+                }
+            }
         }
         if (!replay && t < 1.0 && h < p.h_min) {
             final_status = FFB_E_STEP_UNDERFLOW;
@@ -431,10 +472,9 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
 
     if (final_status == 0) {
         const float4 *stc = cur ? p.st1 : p.st0;
-        for (int64_t j = sp.j0 + threadIdx.x; j < sp.j1; j += kThreads) {
-            const int64_t i = point_of(sp, j);
-            if (i >= p.n) continue;
-            const float4 s = stc[i];
+        for (int k = threadIdx.x; k < npts; k += kThreads) {
+            const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+            const float4 s = MODE == kGlobalState ? stc[i] : lds_state[k];
             p.xy[i] = make_float2(s.x + s.z, s.y + s.w);
         }
     }
@@ -447,6 +487,18 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
     }
 }
 
+// LDS bytes a workgroup needs for its point slots (the largest chunk of the
+// span mapping), or -1 if they exceed the per-workgroup LDS.
+inline int64_t lds_bytes_for(int nb, int64_t n)
+{
+    const int64_t nx = nb < kXcds ? nb : kXcds;
+    const int64_t seg = (n + nx * kSegments - 1) / (nx * kSegments);
+    const int64_t total = seg * kSegments;
+    const int64_t size_min = nb / nx;
+    const int64_t chunk = (total + size_min - 1) / size_min;
+    return chunk * (int64_t)sizeof(float4);
+}
+
 }  // namespace
 
 int advect_max_blocks(int *out)
@@ -455,7 +507,8 @@ int advect_max_blocks(int *out)
     if (hipGetDevice(&dev) != hipSuccess) return -1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return -1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_advect, kThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_advect<kGlobalState>, kThreads, 0) !=
+        hipSuccess)
         return -1;
     *out = cus * per;
     return 0;
@@ -468,6 +521,7 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     int64_t want = (n + kThreads - 1) / kThreads;
     if (want < 1) want = 1;
     int blocks = ctx->adv_blocks;
+    if (ctx->adv_cap > 0 && ctx->adv_cap < blocks) blocks = ctx->adv_cap;
     if (want < blocks) blocks = (int)want;
     if (4 * blocks > ctx->err_cap) return hipErrorInvalidValue;
     // synchronisation slots, cleared by a kernel (graph-capture safe)
@@ -480,7 +534,7 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     p.pitch = ctx->lx + 2;
     p.rho_bar = rho_bar;
     p.xy = xy;
-    p.n = n;
+    p.n = (int)n;
     p.st0 = ctx->st[0];
     p.st1 = ctx->st[1];
     p.kv0 = ctx->kv[0];
@@ -500,6 +554,21 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     p.n_replay = o->n_replay;
     p.replay_h = o->replay_h;
     void *args[] = {&p};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_advect), dim3(blocks),
-                                      dim3(kThreads), args, 0, ctx->stream);
+    // keep the point state in LDS when one workgroup's share fits (one
+    // workgroup per CU, 160 KB of LDS each on gfx950)
+    const int64_t lds = lds_bytes_for(blocks, n);
+    int dev = 0, lds_max = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t reserve = 1024;              // static LDS of the kernel
+    if (ctx->adv_mode != kGlobalState && blocks <= cus && lds + reserve <= lds_max) {
+        const void *k = ctx->adv_mode == kLdsState
+                            ? reinterpret_cast<const void *>(k_advect<kLdsState>)
+                            : reinterpret_cast<const void *>(k_advect<kLdsRecompute>);
+        return hipLaunchCooperativeKernel(k, dim3(blocks), dim3(kThreads), args, (size_t)lds,
+                                          ctx->stream);
+    }
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_advect<kGlobalState>),
+                                      dim3(blocks), dim3(kThreads), args, 0, ctx->stream);
 }

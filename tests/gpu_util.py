@@ -43,5 +43,8 @@ def stats_of(stats):
     return dict(accepted=int(s[0]), rejected=int(s[1]), attempts=int(s[2]), status=int(s[3]))
 
 
-def new_ctx(lx, ly=None, max_points=0):
-    return ffb.Context(lx, lx if ly is None else ly, max_points=max_points)
+def new_ctx(lx, ly=None, max_points=0, mode=None):
+    ctx = ffb.Context(lx, lx if ly is None else ly, max_points=max_points)
+    if mode is not None:
+        ctx.set_option(ffb.OPT_ADVECT_STATE, mode)
+    return ctx

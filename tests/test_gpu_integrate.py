@@ -38,13 +38,19 @@ def _gpu_integrate(ctx, fields, rb, pts, opts=None, replay=None):
     return to_np(xy).astype(np.float64), st, hh, code
 
 
+# where the integrator keeps the point state: 0 device memory, 1 LDS with
+# the first-stage velocity carried, 2 LDS with it recomputed
+MODES = [0, 1, 2]
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name", ["c1_L64", "c4_0", "c2_L512"])
-def test_replayed_schedule_parity(name):
+def test_replayed_schedule_parity(name, mode):
     from gpu_util import map_points, new_ctx, pack_oracle_fields
     m = synth.workload(name)
     pts = map_points(m)
-    print(f"[integrate] {name} P={pts.shape[0]}", flush=True)
-    ctx = new_ctx(m.lx, m.ly, pts.shape[0])
+    print(f"[integrate] {name} mode={mode} P={pts.shape[0]}", flush=True)
+    ctx = new_ctx(m.lx, m.ly, pts.shape[0], mode=mode)
     F = _oracle_fields(m, 4.0)
     fields, rb, Fr = pack_oracle_fields(ctx, F)
     ref = oracle.integrate(Fr, pts.astype(np.float64))        # oracle's own control
@@ -52,7 +58,7 @@ def test_replayed_schedule_parity(name):
     assert code == 0 and st["accepted"] == ref.accepted and st["rejected"] == 0
     np.testing.assert_array_equal(h, ref.h)
     d = np.abs(got - ref.xy).max()
-    print(f"[integrate] {name} steps={ref.accepted} max|dx|={d:.3e}", flush=True)
+    print(f"[integrate] {name} mode={mode} steps={ref.accepted} max|dx|={d:.3e}", flush=True)
     assert d < TOL_POS
 
 
@@ -69,8 +75,11 @@ def test_adaptive_run_outcome(name):
     assert code == 0
     assert abs(st["accepted"] - ref.accepted) <= 1
     assert h.sum() == pytest.approx(1.0, abs=1e-12)
-    # the first steps see the same error estimate up to FP32 rounding
-    np.testing.assert_allclose(h[:3], ref.h[:3], rtol=1e-4)
+    # h0 is exact; later steps follow err^(-1/5) of an error estimate that is
+    # a difference of nearly equal sums (err ~ 2e-6 against terms ~ 1e-1 at
+    # C2), whose FP32 rounding is ~1e-3 relative, i.e. ~2e-4 on the step
+    assert h[0] == ref.h[0]
+    np.testing.assert_allclose(h[1:3], ref.h[1:3], rtol=2e-3)
     # each run's local errors are <= tol per accepted step, so two runs with
     # different schedules differ by at most about steps * tol in total
     d = np.abs(got - ref.xy)
@@ -81,16 +90,19 @@ def test_adaptive_run_outcome(name):
     assert np.percentile(d, 99) < 1e-3
 
 
-def test_replay_equals_adaptive_bitwise():
+@pytest.mark.parametrize("mode", MODES)
+def test_replay_equals_adaptive_bitwise(mode):
+    """Rejected attempts (forced by a large first step) leave no trace: the
+    adaptive run equals a replay of its accepted steps bit for bit."""
     from gpu_util import map_points, new_ctx, pack_oracle_fields
     m = synth.workload("c1_L64")
     pts = map_points(m)
-    ctx = new_ctx(m.lx, m.ly, pts.shape[0])
+    ctx = new_ctx(m.lx, m.ly, pts.shape[0], mode=mode)
     fields, rb, _ = pack_oracle_fields(ctx, _oracle_fields(m, 4.0))
     import paper_1802_07625_amd as ffb
-    a, sa, ha, _ = _gpu_integrate(ctx, fields, rb, pts, ffb.IntegrateOpts(tol=1e-4))
+    a, sa, ha, _ = _gpu_integrate(ctx, fields, rb, pts, ffb.IntegrateOpts(tol=1e-4, h0=0.5))
     b, sb, hb, _ = _gpu_integrate(ctx, fields, rb, pts, replay=ha)
-    assert sa["rejected"] >= 0 and sb["accepted"] == sa["accepted"]
+    assert sa["rejected"] > 0 and sb["accepted"] == sa["accepted"]
     np.testing.assert_array_equal(a, b)
 
 
@@ -192,15 +204,16 @@ def test_points_outside_box_and_errors():
     np.testing.assert_array_equal(got, q.astype(np.float64))
 
 
-def test_full_size_sampled_points():
+@pytest.mark.parametrize("mode", MODES)
+def test_full_size_sampled_points(mode):
     """C3 (L = 1024, 1.0 M vertices + 1024^2 grid nodes) in one launch with a
     fixed schedule of 32 equal steps; 3000 sampled points against the
     oracle integrating only those points."""
     from gpu_util import map_points, new_ctx, pack_oracle_fields
     m = synth.workload("c3_L1024")
     pts = map_points(m)
-    print(f"[integrate] c3_L1024 P={pts.shape[0]}", flush=True)
-    ctx = new_ctx(m.lx, m.ly, pts.shape[0])
+    print(f"[integrate] c3_L1024 mode={mode} P={pts.shape[0]}", flush=True)
+    ctx = new_ctx(m.lx, m.ly, pts.shape[0], mode=mode)
     F = _oracle_fields(m, 4.0)
     fields, rb, Fr = pack_oracle_fields(ctx, F)
     sched = np.full(32, 1.0 / 32)
