@@ -37,6 +37,11 @@
  *  - Precision: FP32 grids, fields and positions; FP64 for area sums, the
  *    padding density, the mean density rho_bar and the step controller.
  *  - One context per stream; a context is not thread-safe.
+ *
+ * Gradients (not part of the paper's method): the adjoint calls at the end
+ * of this header differentiate the rounds above in reverse mode, for a
+ * scalar loss of the final region areas, with the integration's accepted
+ * step sizes frozen.
  */
 #ifndef FFB_H
 #define FFB_H
@@ -58,7 +63,7 @@ enum {
     FFB_E_DOMAIN = 5,           /* polygon vertex outside the box           */
     FFB_E_STEP_UNDERFLOW = 6,   /* adaptive step fell below h_min           */
     FFB_E_NONFINITE = 7,        /* NaN or Inf in coordinates or velocities  */
-    FFB_E_NO_TAPE = 8,          /* reserved                                 */
+    FFB_E_NO_TAPE = 8,          /* backward without a complete record       */
     FFB_E_MAX_ATTEMPTS = 9      /* integration used up max_attempts         */
 };
 
@@ -190,6 +195,94 @@ int ffb_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy, const float 
 int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
                   int64_t n, const ffb_integrate_opts *opts, int32_t *stats,
                   double *h_out, int32_t h_cap);
+
+/* ------------------------------------------------------------------ adjoints
+ * Reverse-mode derivatives of the calls above, for a scalar L of the final
+ * region areas.  The accepted step sizes of each integration are frozen at
+ * the forward pass's values (the step-size controller is not
+ * differentiated); otherwise each adjoint is the exact transpose of its
+ * forward map up to FP32 rounding (bilinear lookups and cell coverage are
+ * piecewise smooth; the derivative taken is the one of the piece the
+ * forward pass evaluated).  Arguments marked (+=) accumulate into the
+ * caller's buffer; (out) ones are overwritten.  Enqueue-only, like the
+ * forward calls; the same status rules apply. */
+
+/* Adjoint of the areas of ffb_area_error: with lam_area (in, [R] FP64),
+ * lam_xy (+=, [V][2] FP64) += sum_r lam_area_r d area_r / d xy, where over
+ * the ring entries k of region r d area_r/d x_k = (y_{k+1} - y_{k-1}) / 2 and
+ * d area_r/d y_k = (x_{k-1} - x_{k+1}) / 2. */
+int ffb_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *lam_area, double *lam_xy);
+
+/* Adjoint of ffb_density for lam_rho = dL/drho (in, [ly][lx] FP32), at the
+ * same g, value and area as the forward call:
+ *   lam_value (+=, [R] FP64), lam_area (+=, [R] FP64) through d_r and
+ *   rho_pad, and lam_xy (+=, [V][2] FP64): moving a ring edge p0 -> p1 (a
+ *   counter-clockwise ring) changes the coverage integral of lam_rho over
+ *   its region by the edge integral of lam_rho times the normal speed, so
+ *   d/dp0 = (d_r - rho_pad) (dy, -dx) int lam (1 - s) ds and
+ *   d/dp1 = (d_r - rho_pad) (dy, -dx) int lam s ds, s in [0, 1]. */
+int ffb_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
+                    const double *area, const float *lam_rho, double *lam_value,
+                    double *lam_area, double *lam_xy);
+
+/* Adjoint of ffb_flux (linear in rho): lam_fields (in) has the ghosted
+ * layout of ffb_flux's fields and holds dL/dJ_x, dL/dJ_y, dL/drho_s (the
+ * fourth component is ignored; ghost entries count for the node they mirror,
+ * with the parity sign of the component); lam_rho_bar (in, [1] FP64) is
+ * dL/drho_bar.  lam_rho (out, [ly][lx] FP32) = dL/drho: the transposed
+ * sine/cosine transforms, the same blur and Eq. 7 factors, and the 2D
+ * DCT-III. */
+int ffb_flux_adj(ffb_ctx *ctx, float sigma, const float *lam_fields, const double *lam_rho_bar,
+                 float *lam_rho);
+
+/* ffb_integrate that also records what ffb_integrate_adj needs: before
+ * each accepted step, the state of the first tape_n points (tape_n <= n) as
+ * (hi.x, hi.y, lo.x, lo.y) compensated FP32 pairs, tape_states (out,
+ * [tape_cap][tape_n][4] FP32), and the step, tape_h (out, [tape_cap] FP64).
+ * stats[0] (the accepted steps) sizes the record; more than tape_cap
+ * accepted steps make ffb_integrate_adj fail with FFB_E_NO_TAPE. */
+int ffb_integrate_record(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
+                         int64_t n, const ffb_integrate_opts *opts, int32_t *stats,
+                         float *tape_states, int64_t tape_n, int32_t tape_cap, double *tape_h);
+
+/* Adjoint of a recorded integration (steps frozen).  fields, rho_bar, stats
+ * and the tape are those of the ffb_integrate_record call.  lam_xy (in/out,
+ * [tape_n][2] FP64): dL/d(positions at t = 1) on entry, dL/d(positions at
+ * t = 0) after.  lam_fields (+=, ghosted field layout, FP32: J_x, J_y,
+ * rho_s, unused) and lam_rho_bar (+=, [1] FP64) receive the field
+ * adjoints.  Each step's six stages are recomputed from its record. */
+int ffb_integrate_adj(ffb_ctx *ctx, const float *fields, const double *rho_bar,
+                      const int32_t *stats, const float *tape_states, int64_t tape_n,
+                      int32_t tape_cap, const double *tape_h, double *lam_xy, float *lam_fields,
+                      double *lam_rho_bar);
+
+/* Context tape (host calls).  ffb_tape_begin clears any previous record
+ * (waiting for the stream) and starts recording: every later ffb_area_error,
+ * ffb_density, ffb_flux and ffb_integrate call appends what its adjoint
+ * needs to the context (device copies of its vertices, values, areas,
+ * fields and rho_bar, made on the stream, so callers may reuse those
+ * buffers; the geometry's ring arrays are referenced and must stay alive).
+ * ffb_integrate records the state of the first V points (the recorded
+ * geometry's vertices, which must come first in its xy) before each
+ * accepted step, for at most max_steps steps per call.  Memory per round:
+ * about 16 max_steps V + 16 (lx+2)(ly+2) + 40 V bytes.
+ * ffb_tape_end stops recording (the record stays); ffb_tape_clear frees it. */
+int ffb_tape_begin(ffb_ctx *ctx, int32_t max_steps);
+int ffb_tape_end(ffb_ctx *ctx);
+int ffb_tape_clear(ffb_ctx *ctx);
+
+/* Reverse pass over the context's record, which must read
+ *   area+ (density flux integrate area+)*
+ * (one or more ffb_area_error calls, then rounds on the same vertices and
+ * regions; each density call uses the areas of the area call before it).
+ * dL_darea (in, [R] FP64): dL/d(areas of the last recorded ffb_area_error).
+ * dL_dvalue (out, [R] FP64): dL/dvalue through the densities of every
+ * recorded round (a direct dependence of L on value is the caller's to add).
+ * dL_dxy0 (out, [V][2] FP64, may be NULL): dL/d(vertices of the first
+ * record).  Stops recording.  A malformed record gives FFB_E_NO_TAPE; a
+ * round with more accepted steps than max_steps gives FFB_E_NO_TAPE on the
+ * device. */
+int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double *dL_dxy0);
 
 #ifdef __cplusplus
 }

@@ -290,3 +290,56 @@ def iterate(m, value, points, n_vertices: int, sigma: float,
     e1, mx = area_error(value, a1)
     return RoundResult(res.xy, a0, a1, e1, mx, rho, pad, F, res.accepted,
                        res.rejected, res.h)
+
+
+# ------------------------------------------------------- loss and gradient
+def area_loss(value, area):
+    """L = sum_r (A_r / T_r - 1)^2 with T_r = value_r sum(A) / sum(value): the
+    squared relative area errors of the stopping rule."""
+    e, _ = area_error(value, area)
+    return float(np.sum(e * e))
+
+
+@dataclass
+class RoundsResult:
+    loss: float
+    points: np.ndarray
+    schedules: list
+    areas: list           # area of every region at the start of each round, and at the end
+
+
+def rounds(m, density, sigmas, points=None, opts: IntegrateOpts | None = None,
+           schedules=None) -> RoundsResult:
+    """K = len(sigmas) FFB iterations from the map's initial vertices with
+    region densities ``density`` (statistic value_r = d_r * A_r at the start),
+    then the area loss.  ``schedules`` (one accepted-step list per round)
+    replays fixed steps; otherwise the adaptive controller chooses them."""
+    pts = _f64(m.xy if points is None else points).reshape(-1, 2)
+    V = m.n_vertices
+    a0 = region_areas(m, pts[:V])
+    value = np.asarray(density, dtype=np.float64) * a0
+    scheds, areas = [], []
+    for k, s in enumerate(sigmas):
+        rr = iterate(m, value, pts, V, s, opts,
+                     replay_h=None if schedules is None else schedules[k])
+        pts = rr.points
+        scheds.append(rr.h)
+        areas.append(rr.area_before)
+    a_end = region_areas(m, pts[:V])
+    areas.append(a_end)
+    return RoundsResult(area_loss(value, a_end), pts, scheds, areas)
+
+
+def fd_gradient(m, density, sigmas, schedules, step=1e-4, points=None):
+    """Central differences of the K-round loss with respect to every region
+    density (absolute step on d_r), with the step schedules frozen."""
+    d = np.asarray(density, dtype=np.float64)
+    g = np.zeros_like(d)
+    for r in range(d.shape[0]):
+        dp, dm = d.copy(), d.copy()
+        dp[r] += step
+        dm[r] -= step
+        lp = rounds(m, dp, sigmas, points, schedules=schedules).loss
+        lm = rounds(m, dm, sigmas, points, schedules=schedules).loss
+        g[r] = (lp - lm) / (2.0 * step)
+    return g

@@ -72,8 +72,21 @@ def lib():
         L.ffb_integrate.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(FFBIntegrateOpts),
                                     vp, vp, i32]
         L.ffb_set_option.argtypes = [vp, i32, i32]
+        L.ffb_area_adj.argtypes = [vp, G, vp, vp]
+        L.ffb_density_adj.argtypes = [vp, G, vp, vp, vp, vp, vp, vp]
+        L.ffb_flux_adj.argtypes = [vp, ctypes.c_float, vp, vp, vp]
+        L.ffb_integrate_record.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(FFBIntegrateOpts),
+                                           vp, vp, i64, i32, vp]
+        L.ffb_integrate_adj.argtypes = [vp, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
+        L.ffb_tape_begin.argtypes = [vp, i32]
+        L.ffb_tape_end.argtypes = [vp]
+        L.ffb_tape_clear.argtypes = [vp]
+        L.ffb_backward.argtypes = [vp, vp, vp, vp]
         for f in ("ffb_create", "ffb_destroy", "ffb_sync", "ffb_reset_status", "ffb_area_error",
-                  "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option"):
+                  "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option",
+                  "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
+                  "ffb_integrate_adj", "ffb_tape_begin", "ffb_tape_end", "ffb_tape_clear",
+                  "ffb_backward"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -228,6 +241,78 @@ def ffb_integrate(ctx, fields, rho_bar, xy, opts: IntegrateOpts, stats, h_out=No
                                     0 if h_out is None else h_out.numel()), "ffb_integrate")
 
 
+def ffb_area_adj(ctx, geom: Geometry, lam_area, lam_xy) -> None:
+    g = geom.struct()
+    _check(ctx, lib().ffb_area_adj(ctx, ctypes.byref(g),
+                                   _ptr(lam_area, torch.float64, geom.n_regions, "lam_area"),
+                                   _ptr(lam_xy, torch.float64, 2 * g.n_vertices, "lam_xy")),
+           "ffb_area_adj")
+
+
+def ffb_density_adj(ctx, geom: Geometry, value, area, lam_rho, lam_value, lam_area, lam_xy,
+                    lx: int, ly: int) -> None:
+    R = geom.n_regions
+    g = geom.struct()
+    _check(ctx, lib().ffb_density_adj(
+        ctx, ctypes.byref(g), _ptr(value, torch.float64, R, "value"),
+        _ptr(area, torch.float64, R, "area"), _ptr(lam_rho, torch.float32, lx * ly, "lam_rho"),
+        _ptr(lam_value, torch.float64, R, "lam_value"),
+        _ptr(lam_area, torch.float64, R, "lam_area"),
+        _ptr(lam_xy, torch.float64, 2 * g.n_vertices, "lam_xy")), "ffb_density_adj")
+
+
+def ffb_flux_adj(ctx, sigma: float, lam_fields, lam_rho_bar, lam_rho, lx: int, ly: int) -> None:
+    _check(ctx, lib().ffb_flux_adj(
+        ctx, float(sigma), _ptr(lam_fields, torch.float32, 4 * (lx + 2) * (ly + 2), "lam_fields"),
+        _ptr(lam_rho_bar, torch.float64, 1, "lam_rho_bar"),
+        _ptr(lam_rho, torch.float32, lx * ly, "lam_rho")), "ffb_flux_adj")
+
+
+def ffb_integrate_record(ctx, fields, rho_bar, xy, opts: IntegrateOpts, stats, tape_states,
+                         tape_h, tape_n: int, replay_h=None) -> None:
+    n = xy.shape[0]
+    cap = tape_h.numel()
+    o = opts.struct(replay_h)
+    _check(ctx, lib().ffb_integrate_record(
+        ctx, _ptr(fields, torch.float32, name="fields"), _ptr(rho_bar, torch.float64, 1, "rho_bar"),
+        _ptr(xy, torch.float32, 2 * n, "xy"), n, ctypes.byref(o),
+        _ptr(stats, torch.int32, 4, "stats"),
+        _ptr(tape_states, torch.float32, 4 * cap * tape_n, "tape_states"), int(tape_n), cap,
+        _ptr(tape_h, torch.float64, cap, "tape_h")), "ffb_integrate_record")
+
+
+def ffb_integrate_adj(ctx, fields, rho_bar, stats, tape_states, tape_h, tape_n: int, lam_xy,
+                      lam_fields, lam_rho_bar) -> None:
+    cap = tape_h.numel()
+    _check(ctx, lib().ffb_integrate_adj(
+        ctx, _ptr(fields, torch.float32, name="fields"), _ptr(rho_bar, torch.float64, 1, "rho_bar"),
+        _ptr(stats, torch.int32, 4, "stats"),
+        _ptr(tape_states, torch.float32, 4 * cap * tape_n, "tape_states"), int(tape_n), cap,
+        _ptr(tape_h, torch.float64, cap, "tape_h"),
+        _ptr(lam_xy, torch.float64, 2 * tape_n, "lam_xy"),
+        _ptr(lam_fields, torch.float32, name="lam_fields"),
+        _ptr(lam_rho_bar, torch.float64, 1, "lam_rho_bar")), "ffb_integrate_adj")
+
+
+def ffb_tape_begin(ctx, max_steps: int) -> None:
+    _check(ctx, lib().ffb_tape_begin(ctx, int(max_steps)), "ffb_tape_begin")
+
+
+def ffb_tape_end(ctx) -> None:
+    _check(ctx, lib().ffb_tape_end(ctx), "ffb_tape_end")
+
+
+def ffb_tape_clear(ctx) -> None:
+    _check(ctx, lib().ffb_tape_clear(ctx), "ffb_tape_clear")
+
+
+def ffb_backward(ctx, dL_darea, dL_dvalue, dL_dxy0=None) -> None:
+    R = dL_darea.numel()
+    _check(ctx, lib().ffb_backward(ctx, _ptr(dL_darea, torch.float64, R, "dL_darea"),
+                                   _ptr(dL_dvalue, torch.float64, R, "dL_dvalue"),
+                                   _ptr(dL_dxy0, torch.float64, name="dL_dxy0")), "ffb_backward")
+
+
 # ------------------------------------------------------------ convenience
 class Context:
     """An ffb context bound to the current torch stream, with output
@@ -299,6 +384,23 @@ class Context:
         ffb_integrate(self.handle, fields, rho_bar, xy, opts, stats, h_out, replay_h)
         return stats, h_out
 
+    # adjoints
+    def tape_begin(self, max_steps: int = 512):
+        ffb_tape_begin(self.handle, max_steps)
+
+    def tape_end(self):
+        ffb_tape_end(self.handle)
+
+    def tape_clear(self):
+        ffb_tape_clear(self.handle)
+
+    def backward(self, dL_darea, n_vertices: int | None = None):
+        """Reverse pass over the recorded rounds: (dL/dvalue, dL/dxy0 or None)."""
+        dval = torch.empty_like(dL_darea)
+        dxy = None if n_vertices is None else self._f64(n_vertices, 2)
+        ffb_backward(self.handle, dL_darea.contiguous(), dval, dxy)
+        return dval, dxy
+
 
 def default_sigma(k: int) -> float:
     """Blur width of round k (0-based), in grid cells: 4 * 2^-k."""
@@ -331,3 +433,36 @@ def iterate(ctx: Context, geom: Geometry, value, points, sigma: float,
     stats, h = ctx.integrate(fields, rho_bar, points, opts)
     area, err, mx = ctx.area_error(geom, value)
     return IterationResult(area_before, rho, pad, fields, rho_bar, stats, h, area, err, mx)
+
+
+class FFBFunction(torch.autograd.Function):
+    """K FFB rounds as a differentiable map value -> final region areas.
+
+    forward(value, ctx, geom, points, sigmas, opts, max_steps, replay):
+      on the device, recorded on the context's tape: one area call, then per
+      sigma a round (density, flux, integration of ``points`` -- whose first
+      rows are the vertices ``geom.xy``, advected in place -- and the areas
+      after); returns the final areas [R] FP64.  ``replay`` (one FP64 device
+      tensor of step sizes per round, or None) freezes the step schedules;
+      otherwise the adaptive controller chooses them.
+    backward: dL/dvalue by ffb_backward, with the forward's steps frozen."""
+
+    @staticmethod
+    def forward(fctx, value, ctx, geom, points, sigmas, opts=None, max_steps=512, replay=None):
+        value = value.detach().contiguous()
+        ctx.tape_begin(max_steps)
+        area, _, _ = ctx.area_error(geom, value)
+        for k, sigma in enumerate(sigmas):
+            rho, _ = ctx.density(geom, value, area)
+            fields, rho_bar = ctx.flux(rho, sigma)
+            ctx.integrate(fields, rho_bar, points, opts, h_cap=0,
+                          replay_h=None if replay is None else replay[k])
+            area, _, _ = ctx.area_error(geom, value)
+        ctx.tape_end()
+        fctx.ffb = ctx
+        return area
+
+    @staticmethod
+    def backward(fctx, g_area):
+        dval, _ = fctx.ffb.backward(g_area.detach().to(torch.float64).contiguous())
+        return dval, None, None, None, None, None, None, None

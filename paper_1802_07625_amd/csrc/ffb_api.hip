@@ -8,9 +8,9 @@
 
 #include "ffb_internal.h"
 
-namespace {
+namespace ffbi {
 
-int fail(ffb_ctx *ctx, int code, const char *fmt, const char *detail = "")
+int fail(ffb_ctx *ctx, int code, const char *fmt, const char *detail)
 {
     if (ctx) {
         char buf[512];
@@ -28,10 +28,7 @@ int hip_fail(ffb_ctx *ctx, hipError_t e, const char *where)
     return e == hipErrorOutOfMemory ? FFB_E_NOMEM : FFB_E_DEVICE;
 }
 
-bool pow2_in_range(int32_t n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
-
-template <typename T>
-hipError_t grow(T **p, int64_t have, int64_t need)
+hipError_t grow_bytes(void **p, int64_t have, int64_t need)
 {
     if (need <= have && *p) return hipSuccess;
     if (*p) {
@@ -39,8 +36,42 @@ hipError_t grow(T **p, int64_t have, int64_t need)
         *p = nullptr;
         if (e != hipSuccess) return e;
     }
-    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)(need > 0 ? need : 1));
+    return hipMalloc(p, (size_t)(need > 0 ? need : 1));
 }
+
+int check_geometry(ffb_ctx *ctx, const ffb_geometry *g)
+{
+    if (!g) return fail(ctx, FFB_E_INVALID, "geometry is NULL%s");
+    if (g->n_vertices < 0 || g->n_rings < 0 || g->n_regions < 1 || g->n_entries < 0)
+        return fail(ctx, FFB_E_INVALID, "negative geometry size or no region%s");
+    if (g->n_rings == 0 && g->n_entries != 0)
+        return fail(ctx, FFB_E_INVALID, "ring entries without rings%s");
+    if (g->n_entries < 3 * (int64_t)g->n_rings)
+        return fail(ctx, FFB_E_INVALID, "fewer than three entries per ring%s");
+    if (g->n_entries > INT32_MAX) return fail(ctx, FFB_E_INVALID, "too many ring entries%s");
+    if (g->n_vertices > INT32_MAX) return fail(ctx, FFB_E_INVALID, "too many vertices%s");
+    if ((g->n_vertices > 0 && !g->xy) || !g->ring_offsets ||
+        (g->n_entries > 0 && !g->ring_vidx) || (g->n_rings > 0 && !g->ring_region))
+        return fail(ctx, FFB_E_INVALID, "geometry array is NULL%s");
+    return FFB_OK;
+}
+
+hipError_t ensure_region_capacity(ffb_ctx *ctx, int32_t R)
+{
+    if (R <= ctx->w_cap) return hipSuccess;
+    hipError_t e = grow(&ctx->w_region, ctx->w_cap, R);
+    if (e == hipSuccess) e = grow(&ctx->lam_w, ctx->w_cap, R);
+    ctx->w_cap = e == hipSuccess ? R : 0;
+    return e;
+}
+
+}  // namespace ffbi
+
+using namespace ffbi;
+
+namespace {
+
+bool pow2_in_range(int32_t n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
 
 // exp(-2 pi i k / N), k < N/2 and exp(-i pi m / (2N)), m < N, in FP64 then rounded.
 hipError_t upload_twiddles(float2 **tw, float2 **tq, int N)
@@ -64,25 +95,58 @@ void free_all(ffb_ctx *c)
 {
     void *ptrs[] = {c->d_status, c->tw_x, c->tq_x, c->tw_y, c->tq_y, c->t1, c->t2, c->pa,
                     c->pb, c->pc, c->red, c->acc, c->w_region, c->st[0], c->st[1], c->kv[0],
-                    c->kv[1], c->errslot};
+                    c->kv[1], c->errslot, c->lam_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    tape_free(c);
 }
 
-int check_geometry(ffb_ctx *ctx, const ffb_geometry *g)
+int check_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
+                    int64_t n, const ffb_integrate_opts *o, int32_t *stats, double *h_out,
+                    int32_t h_cap)
 {
-    if (!g) return fail(ctx, FFB_E_INVALID, "geometry is NULL%s");
-    if (g->n_vertices < 0 || g->n_rings < 0 || g->n_regions < 1 || g->n_entries < 0)
-        return fail(ctx, FFB_E_INVALID, "negative geometry size or no region%s");
-    if (g->n_rings == 0 && g->n_entries != 0)
-        return fail(ctx, FFB_E_INVALID, "ring entries without rings%s");
-    if (g->n_entries < 3 * (int64_t)g->n_rings)
-        return fail(ctx, FFB_E_INVALID, "fewer than three entries per ring%s");
-    if (g->n_entries > INT32_MAX) return fail(ctx, FFB_E_INVALID, "too many ring entries%s");
-    if ((g->n_vertices > 0 && !g->xy) || !g->ring_offsets ||
-        (g->n_entries > 0 && !g->ring_vidx) || (g->n_rings > 0 && !g->ring_region))
-        return fail(ctx, FFB_E_INVALID, "geometry array is NULL%s");
+    if (!ctx) return FFB_E_INVALID;
+    if (!fields || !rho_bar || !o || !stats || (n > 0 && !xy))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: NULL argument%s");
+    if (n < 0 || n > INT32_MAX - 4096)
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: n out of range%s");
+    if (h_cap < 0 || (h_cap > 0 && !h_out))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad h_out/h_cap%s");
+    if (o->max_attempts <= 0 || o->max_attempts > (1 << 20))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: max_attempts out of range%s");
+    if (o->n_replay < 0 || (o->n_replay > 0 && !o->replay_h))
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad replay schedule%s");
+    if (o->n_replay == 0) {
+        if (!(o->tol > 0.0) || !(o->h0 > 0.0) || !(o->safety > 0.0) || !(o->fac_min > 0.0) ||
+            !(o->fac_min <= 1.0) || !(o->fac_max >= 1.0) || !(o->h_min >= 0.0) ||
+            !isfinite(o->tol) || !isfinite(o->h0) || !isfinite(o->fac_max))
+            return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad controller constants%s");
+    }
     return FFB_OK;
+}
+
+int run_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy, int64_t n,
+                  const ffb_integrate_opts *o, int32_t *stats, double *h_out, int32_t h_cap,
+                  const advect_tape *rec)
+{
+    if (n > ctx->st_cap) {
+        hipError_t e = hipSuccess;
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+            e = grow(&ctx->st[b], ctx->st_cap, n);
+            if (e == hipSuccess) e = grow(&ctx->kv[b], ctx->st_cap, n);
+        }
+        if (e != hipSuccess) {
+            ctx->st_cap = 0;
+            return hip_fail(ctx, e, "ffb_integrate state buffers");
+        }
+        ctx->st_cap = n;
+    }
+    hipError_t e = launch_fill_i32(stats, 4, 0, ctx->stream);
+    if (e == hipSuccess && rec && rec->count) e = launch_fill_i32(rec->count, 1, 0, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_advect(ctx, reinterpret_cast<const float4 *>(fields), rho_bar,
+                          reinterpret_cast<float2 *>(xy), n, o, stats, h_out, h_cap, rec);
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_integrate launch");
 }
 
 }  // namespace
@@ -111,6 +175,7 @@ int ffb_create(ffb_ctx **out, int32_t lx, int32_t ly, int64_t max_points, void *
     c->red_cap = 1024;
     if (e == hipSuccess) e = grow(&c->acc, 0, (int64_t)ly * (lx + 1));
     if (e == hipSuccess) e = grow(&c->w_region, 0, 1024);
+    if (e == hipSuccess) e = grow(&c->lam_w, 0, 1024);
     c->w_cap = 1024;
     if (e == hipSuccess) e = grow(&c->errslot, 0, 4096);   // advection sync words
     c->err_cap = 4096;
@@ -191,6 +256,8 @@ int ffb_area_error(ffb_ctx *ctx, const ffb_geometry *g, const double *value, dou
     if (st) return st;
     if (!value || !area || !err || !max_abs_err)
         return fail(ctx, FFB_E_INVALID, "ffb_area_error: NULL output or value%s");
+    st = tape_on_area(ctx, g);
+    if (st) return st;
     hipError_t e = launch_area(ctx, g, value, area, err, max_abs_err);
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_area_error launch");
 }
@@ -203,12 +270,11 @@ int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const 
     if (st) return st;
     if (!value || !area || !rho || !rho_pad)
         return fail(ctx, FFB_E_INVALID, "ffb_density: NULL argument%s");
-    if (g->n_regions > ctx->w_cap) {
-        hipError_t e = grow(&ctx->w_region, ctx->w_cap, g->n_regions);
-        if (e != hipSuccess) return hip_fail(ctx, e, "ffb_density workspace");
-        ctx->w_cap = g->n_regions;
-    }
-    hipError_t e = launch_density(ctx, g, value, area, rho, rho_pad);
+    hipError_t e = ensure_region_capacity(ctx, g->n_regions);
+    if (e != hipSuccess) return hip_fail(ctx, e, "ffb_density workspace");
+    st = tape_on_density(ctx, g, value, area);
+    if (st) return st;
+    e = launch_density(ctx, g, value, area, rho, rho_pad);
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_density launch");
 }
 
@@ -218,6 +284,8 @@ int ffb_flux(ffb_ctx *ctx, const float *rho, float sigma, float *fields, double 
     if (!rho || !fields || !rho_bar) return fail(ctx, FFB_E_INVALID, "ffb_flux: NULL argument%s");
     if (!(sigma >= 0.0f) || !isfinite(sigma))
         return fail(ctx, FFB_E_INVALID, "ffb_flux: sigma must be finite and >= 0%s");
+    int st = tape_on_flux(ctx, sigma);
+    if (st) return st;
     hipError_t e = launch_flux(ctx, rho, sigma, reinterpret_cast<float4 *>(fields), rho_bar);
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_flux launch");
 }
@@ -235,40 +303,27 @@ int ffb_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy, const float 
 int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy, int64_t n,
                   const ffb_integrate_opts *o, int32_t *stats, double *h_out, int32_t h_cap)
 {
-    if (!ctx) return FFB_E_INVALID;
-    if (!fields || !rho_bar || !o || !stats || (n > 0 && !xy))
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: NULL argument%s");
-    if (n < 0 || n > INT32_MAX - 4096)
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: n out of range%s");
-    if (h_cap < 0 || (h_cap > 0 && !h_out))
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad h_out/h_cap%s");
-    if (o->max_attempts <= 0 || o->max_attempts > (1 << 20))
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: max_attempts out of range%s");
-    if (o->n_replay < 0 || (o->n_replay > 0 && !o->replay_h))
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad replay schedule%s");
-    if (o->n_replay == 0) {
-        if (!(o->tol > 0.0) || !(o->h0 > 0.0) || !(o->safety > 0.0) || !(o->fac_min > 0.0) ||
-            !(o->fac_min <= 1.0) || !(o->fac_max >= 1.0) || !(o->h_min >= 0.0) ||
-            !isfinite(o->tol) || !isfinite(o->h0) || !isfinite(o->fac_max))
-            return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad controller constants%s");
-    }
-    if (n > ctx->st_cap) {
-        hipError_t e = hipSuccess;
-        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-            e = grow(&ctx->st[b], ctx->st_cap, n);
-            if (e == hipSuccess) e = grow(&ctx->kv[b], ctx->st_cap, n);
-        }
-        if (e != hipSuccess) {
-            ctx->st_cap = 0;
-            return hip_fail(ctx, e, "ffb_integrate state buffers");
-        }
-        ctx->st_cap = n;
-    }
-    hipError_t e = launch_fill_i32(stats, 4, 0, ctx->stream);
-    if (e == hipSuccess)
-        e = launch_advect(ctx, reinterpret_cast<const float4 *>(fields), rho_bar,
-                          reinterpret_cast<float2 *>(xy), n, o, stats, h_out, h_cap);
-    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_integrate launch");
+    int st = check_integrate(ctx, fields, rho_bar, xy, n, o, stats, h_out, h_cap);
+    if (st) return st;
+    advect_tape rec{};
+    bool record = false;
+    st = tape_on_integrate(ctx, n, reinterpret_cast<const float4 *>(fields), rho_bar, &rec,
+                           &record);
+    if (st) return st;
+    return run_integrate(ctx, fields, rho_bar, xy, n, o, stats, h_out, h_cap,
+                         record ? &rec : nullptr);
+}
+
+int ffb_integrate_record(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
+                         int64_t n, const ffb_integrate_opts *o, int32_t *stats,
+                         float *tape_states, int64_t tape_n, int32_t tape_cap, double *tape_h)
+{
+    int st = check_integrate(ctx, fields, rho_bar, xy, n, o, stats, nullptr, 0);
+    if (st) return st;
+    if (tape_n < 0 || tape_n > n || tape_cap < 1 || !tape_states || !tape_h)
+        return fail(ctx, FFB_E_INVALID, "ffb_integrate_record: bad tape arguments%s");
+    advect_tape rec{reinterpret_cast<float4 *>(tape_states), tape_n, tape_cap, tape_h, nullptr};
+    return run_integrate(ctx, fields, rho_bar, xy, n, o, stats, nullptr, 0, &rec);
 }
 
 }  // extern "C"

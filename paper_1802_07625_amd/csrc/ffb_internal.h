@@ -28,6 +28,7 @@ struct ffb_ctx {
     // raster workspace
     double *acc = nullptr;                     // [ly][lx+1] coverage deltas
     double *w_region = nullptr;                // [cap] d_r - rho_pad
+    double *lam_w = nullptr;                   // [cap] adjoint of w_r
     int32_t w_cap = 0;
 
     // integrator workspace
@@ -39,13 +40,47 @@ struct ffb_ctx {
     int adv_blocks = 0;                        // co-resident blocks of the advection kernel
     int adv_mode = 1;                          // advection state placement (FFB_OPT_ADVECT_STATE)
     int adv_cap = 0;                           // cap on advection workgroups, 0 = none
+
+    struct ffb_tape *tape = nullptr;           // recording for ffb_backward
 };
+
+// ------------------------------------------------------------ host helpers
+namespace ffbi {
+// Record `fmt` (with one %s for detail) as the context's last error; returns code.
+int fail(ffb_ctx *ctx, int code, const char *fmt, const char *detail = "");
+// Record a HIP failure; returns FFB_E_NOMEM or FFB_E_DEVICE.
+int hip_fail(ffb_ctx *ctx, hipError_t e, const char *where);
+// Host-side checks of a geometry struct (sizes and NULL arrays).
+int check_geometry(ffb_ctx *ctx, const ffb_geometry *g);
+// Reallocate *p to at least `need` bytes (contents not kept) if `have` is short.
+hipError_t grow_bytes(void **p, int64_t have, int64_t need);
+template <typename T>
+hipError_t grow(T **p, int64_t have, int64_t need)
+{
+    return grow_bytes(reinterpret_cast<void **>(p), have * (int64_t)sizeof(T),
+                      need * (int64_t)sizeof(T));
+}
+// Per-region workspace (w_region, lam_w) for at least R regions.
+hipError_t ensure_region_capacity(ffb_ctx *ctx, int32_t R);
+}  // namespace ffbi
+
+// Context tape (recording for ffb_backward).  Each hook returns FFB_OK when
+// the context is not recording.
+int tape_on_area(ffb_ctx *ctx, const ffb_geometry *g);
+int tape_on_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
+                    const double *area);
+int tape_on_flux(ffb_ctx *ctx, float sigma);
+// Sets *record and fills *out with the record's buffers when recording.
+int tape_on_integrate(ffb_ctx *ctx, int64_t n, const float4 *fields, const double *rho_bar,
+                      struct advect_tape *out, bool *record);
+void tape_free(ffb_ctx *ctx);
 
 // ---------------------------------------------------------------- launches
 // Every launcher enqueues on ctx->stream and returns hipSuccess or the
 // launch error.  Arguments are validated by the C-ABI layer beforehand.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 
 hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *value,
@@ -59,10 +94,35 @@ hipError_t launch_flux(ffb_ctx *ctx, const float *rho, float sigma, float4 *fiel
 hipError_t launch_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy,
                               const float *rho_s, float4 *fields);
 
+hipError_t launch_density_weights(ffb_ctx *ctx, int32_t R, const double *value,
+                                  const double *area, double *rho_pad);
+
+// Where ffb_integrate records what its adjoint needs (all device memory).
+struct advect_tape {
+    float4 *states;       // [cap][n] (hi.x, hi.y, lo.x, lo.y) before each accepted step
+    int64_t n;            // recorded points: the first n of the integration
+    int32_t cap;          // steps the record holds
+    double *h;            // [cap] accepted step sizes
+    int32_t *count;       // [1] accepted steps of the integration
+};
+
 int advect_max_blocks(int *out);
 hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                          float2 *xy, int64_t n, const ffb_integrate_opts *o,
-                         int32_t *stats, double *h_out, int32_t h_cap);
+                         int32_t *stats, double *h_out, int32_t h_cap, const advect_tape *tape);
+
+// Adjoints.  lam_fields has the ghosted layout of the fields, [(ly+2)(lx+2)]
+// float4 (J_x, J_y, rho_s, unused); lam_xy is [n][2] FP64.
+hipError_t launch_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *lam_area,
+                           double *lam_xy);
+hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
+                              const double *area, const float *lam_rho, double *lam_value,
+                              double *lam_area, double *lam_xy);
+hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
+                           const double *lam_rho_bar, float *lam_rho);
+hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
+                             const advect_tape *tape, double *lam_xy, float4 *lam_fields,
+                             double *lam_rho_bar);
 
 // ---------------------------------------------------------------- device
 // Record the first error code in the sticky status word.

@@ -77,6 +77,13 @@ struct Params {
     int32_t max_attempts;
     int32_t n_replay;
     const double *replay_h;
+    // optional record for the adjoint: the state of the first tape_n points
+    // before every accepted step, [tape_cap][tape_n], the accepted steps and
+    // their count
+    float4 *tape;
+    int tape_n, tape_cap;
+    double *tape_h;
+    int32_t *tape_count;
 };
 
 struct Field {
@@ -384,9 +391,13 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         float2 *kvn = cur ? p.kv0 : p.kv1;
 
         float emax = 0.0f;
+        // a rejected attempt leaves the state unchanged, so the retry writes
+        // the same record again
+        float4 *rec = (p.tape && acc < p.tape_cap) ? p.tape + (int64_t)acc * p.tape_n : nullptr;
         for (int k = threadIdx.x; k < npts; k += kThreads) {
             const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
             const float4 s0 = MODE == kGlobalState ? stc[i] : lds_state[k];
+            if (rec && i < p.tape_n) rec[i] = s0;
             const float hx = s0.x, hy = s0.y, lx = s0.z, ly = s0.w;
             const Axis ax = make_axis(hx, lx, p.lx), ay = make_axis(hy, ly, p.ly);
             CellCache cc;
@@ -443,6 +454,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         if (replay || err <= p.tol) {
             cur ^= 1;
             if (lead && acc < p.h_cap && p.h_out) p.h_out[acc] = h;
+            if (lead && acc < p.tape_cap && p.tape_h) p.tape_h[acc] = h;
             ++acc;
             t = final_step ? 1.0 : t + h;
             if (!replay) {
@@ -483,6 +495,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         p.stats[1] = rej;
         p.stats[2] = attempt;
         p.stats[3] = final_status;
+        if (p.tape_count) *p.tape_count = acc;
         if (final_status) set_status(p.status, final_status);
     }
 }
@@ -516,7 +529,7 @@ int advect_max_blocks(int *out)
 
 hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                          float2 *xy, int64_t n, const ffb_integrate_opts *o, int32_t *stats,
-                         double *h_out, int32_t h_cap)
+                         double *h_out, int32_t h_cap, const advect_tape *tape)
 {
     int64_t want = (n + kThreads - 1) / kThreads;
     if (want < 1) want = 1;
@@ -553,6 +566,11 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     p.max_attempts = o->max_attempts;
     p.n_replay = o->n_replay;
     p.replay_h = o->replay_h;
+    p.tape = tape ? tape->states : nullptr;
+    p.tape_n = tape ? (int)tape->n : 0;
+    p.tape_cap = tape ? tape->cap : 0;
+    p.tape_h = tape ? tape->h : nullptr;
+    p.tape_count = tape ? tape->count : nullptr;
     void *args[] = {&p};
     // keep the point state in LDS when one workgroup's share fits (one
     // workgroup per CU, 160 KB of LDS each on gfx950)

@@ -28,6 +28,12 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
+__global__ void k_fill_f32(float *p, int64_t n, float v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
 __global__ void k_fill_f64(double *p, int64_t n, double v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -154,6 +160,10 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
 {
     return fill<uint32_t>(k_fill_u32, p, n, v, s);
+}
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s)
+{
+    return fill<float>(k_fill_f32, p, n, v, s);
 }
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
 {

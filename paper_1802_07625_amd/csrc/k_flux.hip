@@ -386,6 +386,186 @@ __global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ pa
     }
 }
 
+// ------------------------------------------------------------ adjoint
+// The flux is linear in rho.  With S = C_y C_x rho (DCT-II sums), R = G o S
+// (G: Eq. 7 factors times the blur), the forward gives
+//   rho_s = C_x^T C_y^T R / (lx ly),  J_x = S_x^T C_y^T (W_x o R),
+//   J_y = C_x^T S_y^T (W_y o R),      rho_bar = S_00 / (lx ly),
+// so for adjoints (lr, lx_, ly_) of (rho_s, J_x, J_y) and lb of rho_bar
+//   Rbar = C_y C_x lr / (lx ly) + W_x o (C_y S_x lx_) + W_y o (S_y C_x ly_),
+//   Sbar = G o Rbar,  Sbar_00 += lb / (lx ly),  lam_rho = C_x^T C_y^T Sbar,
+// where S_x lam = sum_i lam_i sin(pi m (i + 1/2) / lx) (a DST-II) is the
+// DCT-II of (-1)^i lam_i read at index lx - m.
+
+// DCT-II (rows a, b) of a pair of rows placed by `val(i)` in Makhoul order.
+template <typename F>
+__device__ void dct2_rows_pair(float2 *sa, float2 *sb, float2 *out, int N, const float2 *stw,
+                               const float2 *__restrict__ tq, F val)
+{
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = val(i);
+    dct2_pair(sa, sb, out, N, stw, tq);
+}
+
+// Transpose of the ghost fill: every ghost entry of lam_fields is added to
+// the node it mirrors, with the parity sign of its component (J_x odd across
+// x edges, J_y odd across y edges, rho_s even).  Writes the node adjoints as
+// planes [ly][lx]: rho_s -> prs, J_x -> pjx, J_y -> pjy.
+__global__ __launch_bounds__(256) void k_adj_fold(const float4 *__restrict__ lam, int lx, int ly,
+                                                  float *__restrict__ prs, float *__restrict__ pjx,
+                                                  float *__restrict__ pjy)
+{
+    const int64_t c = blockIdx.x * 256ll + threadIdx.x;
+    if (c >= (int64_t)lx * ly) return;
+    const int i = (int)(c % lx), j = (int)(c / lx);
+    const int pitch = lx + 2;
+    int ii[2] = {i, 0}, jj[2] = {j, 0};
+    float sxs[2] = {1.f, -1.f}, sys[2] = {1.f, -1.f};
+    int ni = 1, nj = 1;
+    if (i == 0) ii[ni++] = -1;
+    else if (i == lx - 1) ii[ni++] = lx;
+    if (j == 0) jj[nj++] = -1;
+    else if (j == ly - 1) jj[nj++] = ly;
+    float ax = 0.f, ay = 0.f, ar = 0.f;
+    for (int q = 0; q < nj; ++q)
+        for (int r = 0; r < ni; ++r) {
+            const float4 v = lam[(int64_t)(jj[q] + 1) * pitch + (ii[r] + 1)];
+            ax += sxs[r] * v.x;
+            ay += sys[q] * v.y;
+            ar += v.z;
+        }
+    prs[c] = ar;
+    pjx[c] = ax;
+    pjy[c] = ay;
+}
+
+// Row pass along x of the three adjoint planes, in place (each workgroup
+// owns rows j0, j0 + 1): rho_s -> DCT-II, J_x -> DST-II, J_y -> DCT-II.
+__global__ __launch_bounds__(512) void k_adj_rows(int lx, const float2 *__restrict__ tw,
+                                                  const float2 *__restrict__ tq,
+                                                  float *__restrict__ pa, float *__restrict__ pb,
+                                                  float *__restrict__ pc)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], o[kMaxN], stw[kMaxN / 2];
+    const int N = lx;
+    load_twiddles(stw, tw, N);
+    const int64_t j0 = 2 * (int64_t)blockIdx.x;
+    float *a0 = pa + j0 * N, *a1 = a0 + N;
+    float *b0 = pb + j0 * N, *b1 = b0 + N;
+    float *c0 = pc + j0 * N, *c1 = c0 + N;
+    dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) { return make_float2(a0[i], a1[i]); });
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        a0[m] = o[m].x;
+        a1[m] = o[m].y;
+    }
+    dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) {
+        const float sg = (i & 1) ? -1.f : 1.f;
+        return make_float2(sg * b0[i], sg * b1[i]);
+    });
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        const float2 v = m ? o[N - m] : make_float2(0.f, 0.f);
+        b0[m] = v.x;
+        b1[m] = v.y;
+    }
+    dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) { return make_float2(c0[i], c1[i]); });
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        c0[m] = o[m].x;
+        c1[m] = o[m].y;
+    }
+}
+
+// Column pass on rows m0, m0 + 1 of the transposed planes [lx][ly]: the
+// transforms along y, the spectral weights, then the DCT-III along y.
+__global__ __launch_bounds__(512) void k_adj_cols(const float *__restrict__ ta,
+                                                  const float *__restrict__ tb,
+                                                  const float *__restrict__ tc, int lx, int ly,
+                                                  float sigma, const double *__restrict__ lam_rb,
+                                                  const float2 *__restrict__ tw,
+                                                  const float2 *__restrict__ tq,
+                                                  float *__restrict__ out)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], A[kMaxN], B[kMaxN], stw[kMaxN / 2];
+    const int N = ly;
+    load_twiddles(stw, tw, N);
+    const int m0 = 2 * blockIdx.x;
+    const float *a0 = ta + (int64_t)m0 * N, *a1 = a0 + N;
+    const float *b0 = tb + (int64_t)m0 * N, *b1 = b0 + N;
+    const float *c0 = tc + (int64_t)m0 * N, *c1 = c0 + N;
+    dct2_rows_pair(sa, sb, A, N, stw, tq, [&](int i) { return make_float2(a0[i], a1[i]); });
+    dct2_rows_pair(sa, sb, B, N, stw, tq, [&](int i) { return make_float2(b0[i], b1[i]); });
+    // C: DST-II along y, kept in the FFT scratch for the combination below
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float sg = (i & 1) ? -1.f : 1.f;
+        sa[mk_pos(i, N)] = make_float2(sg * c0[i], sg * c1[i]);
+    }
+    float2 *Z = fft_lds(sa, sb, N, stw, false);
+    float2 *C = (Z == sa) ? sb : sa;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        const float2 zm = Z[m];
+        const float2 zc = Z[(N - m) & (N - 1)];
+        const float2 va = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
+        const float2 vb = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
+        const float2 q = tq[m];
+        C[m] = make_float2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
+    }
+    __syncthreads();
+    // combine: Sbar = G o (A / (lx ly) + W_x B + W_y C), C read at index N - n
+    const float PI_F = 3.14159265358979f;
+    const float inv_pi = 0.318309886183790672f;
+    const float flx = (float)lx, fly = (float)ly, norm = 1.0f / (flx * fly);
+    const float cgx = PI_F * PI_F * sigma * sigma / (2.0f * flx * flx);
+    const float cgy = PI_F * PI_F * sigma * sigma / (2.0f * fly * fly);
+    const float gx0 = expf(-cgx * (float)m0 * (float)m0) * (m0 == 0 ? 2.0f : 4.0f);
+    const float gx1 = expf(-cgx * (float)(m0 + 1) * (float)(m0 + 1)) * 4.0f;
+    const float ma = (float)m0, mb = (float)(m0 + 1);
+    const float lb = (float)(*lam_rb * (double)norm);
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const float gy = expf(-cgy * (float)n * (float)n) * (n == 0 ? 0.5f : 1.0f);
+        const float fn = (float)n;
+        const float2 cv = n ? C[N - n] : make_float2(0.f, 0.f);
+        const float da = (ma * fly) * (ma * fly) + (fn * flx) * (fn * flx);
+        const float db = (mb * fly) * (mb * fly) + (fn * flx) * (fn * flx);
+        const float wxa = m0 == 0 ? 0.f : fly * inv_pi * ma / da, wxb = fly * inv_pi * mb / db;
+        const float wya = n == 0 ? 0.f : flx * inv_pi * fn / da;
+        const float wyb = n == 0 ? 0.f : flx * inv_pi * fn / db;
+        float ra = A[n].x * norm + wxa * B[n].x + wya * cv.x;
+        float rb = A[n].y * norm + wxb * B[n].y + wyb * cv.y;
+        ra *= gx0 * gy;
+        rb *= gx1 * gy;
+        if (m0 == 0 && n == 0) ra += lb;
+        B[n] = make_float2(ra, rb);       // B is free now
+    }
+    __syncthreads();
+    dct3_input(sa, N, tq, [&](int n) { return B[n]; });
+    float2 *v = fft_lds(sa, sb, N, stw, true);
+    float *o0 = out + (int64_t)m0 * N, *o1 = o0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        o0[i] = y.x;
+        o1[i] = y.y;
+    }
+}
+
+// Final row pass: DCT-III along x of the [ly][lx] plane.
+__global__ __launch_bounds__(512) void k_adj_rows_final(const float *__restrict__ in, int lx,
+                                                        const float2 *__restrict__ tw,
+                                                        const float2 *__restrict__ tq,
+                                                        float *__restrict__ lam_rho)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    const int N = lx;
+    load_twiddles(stw, tw, N);
+    const int64_t j0 = 2 * (int64_t)blockIdx.x;
+    const float *r0 = in + j0 * N, *r1 = r0 + N;
+    dct3_input(sa, N, tq, [&](int m) { return make_float2(r0[m], r1[m]); });
+    float2 *v = fft_lds(sa, sb, N, stw, true);
+    float *o0 = lam_rho + j0 * N, *o1 = o0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        o0[i] = y.x;
+        o1[i] = y.y;
+    }
+}
+
 inline int threads_for(int N)
 {
     int t = N / 2;
@@ -432,5 +612,30 @@ hipError_t launch_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy,
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, jx, jy, rho_s,
                        ctx->lx, ctx->ly, fields);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
+                           const double *lam_rho_bar, float *lam_rho)
+{
+    hipStream_t s = ctx->stream;
+    const int lx = ctx->lx, ly = ctx->ly;
+    const int64_t cells = (int64_t)lx * ly;
+    hipLaunchKernelGGL(k_adj_fold, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s,
+                       lam_fields, lx, ly, ctx->pa, ctx->pb, ctx->pc);
+    hipLaunchKernelGGL(k_adj_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, lx, ctx->tw_x,
+                       ctx->tq_x, ctx->pa, ctx->pb, ctx->pc);
+    // [ly][lx] -> [lx][ly]
+    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 2), dim3(256), 0, s,
+                       ctx->pa, ctx->pb, ctx->pb, ctx->t1, ctx->t2, ctx->t2, ly, lx);
+    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
+                       ctx->pc, ctx->pc, ctx->pc, ctx->pa, ctx->pa, ctx->pa, ly, lx);
+    hipLaunchKernelGGL(k_adj_cols, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t1, ctx->t2,
+                       ctx->pa, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->pb);
+    // [lx][ly] -> [ly][lx]
+    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 1), dim3(256), 0, s,
+                       ctx->pb, ctx->pb, ctx->pb, ctx->pc, ctx->pc, ctx->pc, lx, ly);
+    hipLaunchKernelGGL(k_adj_rows_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->pc, lx,
+                       ctx->tw_x, ctx->tq_x, lam_rho);
     return hipGetLastError();
 }

@@ -210,6 +210,14 @@ __global__ __launch_bounds__(kScanThreads) void k_raster_scan(
 
 }  // namespace
 
+hipError_t launch_density_weights(ffb_ctx *ctx, int32_t R, const double *value,
+                                  const double *area, double *rho_pad)
+{
+    hipLaunchKernelGGL(k_density_prep, dim3(1), dim3(kPrepThreads), 0, ctx->stream, value, area,
+                       R, ctx->w_region, rho_pad, ctx->d_status);
+    return hipGetLastError();
+}
+
 hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                           const double *area, float *rho, double *rho_pad)
 {

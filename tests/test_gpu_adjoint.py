@@ -1,0 +1,351 @@
+"""GPU adjoints (steps frozen) against the FP64 oracle.
+
+Each adjoint call is checked by directional derivatives: for random
+directions, <lam_out, delta_in> from the HIP adjoint must match the central
+difference of <lam_in, oracle forward> along delta_in.  The oracle forward is
+FP64 and smooth along the directions taken, so the differences carry only
+O(eps^2) truncation; the bars come from the FP32 arithmetic of the adjoint.
+The flux adjoint is also checked as the transpose of the HIP flux itself
+(<F rho, lam> = <rho, F^T lam>), and the composed backward against the
+oracle's central-difference gradient with the oracle's step schedules
+replayed on the device.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1802_07625_amd as ffb
+import synth
+from gpu_util import dev_f32, dev_f64, new_ctx, pack_oracle_fields, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _geom(m, xy=None):
+    xy_t = dev_f32(m.xy if xy is None else xy).reshape(-1, 2)
+    return ffb.Geometry.from_map(m, xy_t)
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(a), abs(b), 1e-300)
+
+
+# ------------------------------------------------------------------ flux
+@pytest.mark.parametrize("lx,ly,sigma", [(64, 64, 0.0), (64, 64, 2.5), (128, 32, 4.0),
+                                         (16, 256, 1.0)])
+def test_flux_adj_is_transpose(lx, ly, sigma):
+    """<flux(rho), lam> + rho_bar lam_rb == <rho, flux_adj(lam, lam_rb)> over
+    every entry of the ghosted field layout (ghosts included)."""
+    rng = np.random.default_rng(11 + lx + ly)
+    ctx = new_ctx(lx, ly)
+    rho = dev_f32(1.0 + 0.5 * rng.random((ly, lx)))
+    fields, rho_bar = ctx.flux(rho, sigma)
+    lam = dev_f32(rng.standard_normal((ly + 2, lx + 2, 4)))
+    lrb = dev_f64([rng.standard_normal()])
+    lam_rho = torch.empty((ly, lx), dtype=torch.float32, device="cuda")
+    ffb.ffb_flux_adj(ctx.handle, sigma, lam, lrb, lam_rho, lx, ly)
+    assert ctx.sync(check=False) == 0
+    F, L = to_np(fields).astype(np.float64), to_np(lam).astype(np.float64)
+    lhs = float(np.sum(F[..., :3] * L[..., :3])) + float(to_np(rho_bar)[0] * to_np(lrb)[0])
+    rhs = float(np.sum(to_np(rho).astype(np.float64) * to_np(lam_rho)))
+    # both sides are sums of ~4 L^2 FP32 terms of size |F||lam|: the bar is a
+    # few FP32 ulps of the sum of absolute terms
+    scale = float(np.sum(np.abs(F[..., :3] * L[..., :3])))
+    assert abs(lhs - rhs) <= 1e-5 * scale, (lhs, rhs, scale)
+
+
+def test_flux_adj_matches_oracle_direction():
+    """d/deps <lam, oracle flux(rho + eps delta)> (exact: the flux is linear)
+    equals <flux_adj(lam), delta>."""
+    m = synth.workload("c1_L64")
+    lx = ly = m.lx
+    rng = np.random.default_rng(5)
+    rho = 1.0 + rng.random((ly, lx))
+    delta = 0.5 + rng.random((ly, lx))              # positive: the oracle flux checks rho_s > 0
+    sigma = 3.0
+    lam_nodes = rng.standard_normal((3, ly, lx))     # J_x, J_y, rho_s adjoints on nodes
+    lrb = rng.standard_normal()
+    ctx = new_ctx(lx, ly)
+    # node adjoints placed on the real nodes of the ghosted layout, ghosts zero
+    lam = np.zeros((ly + 2, lx + 2, 4), np.float32)
+    lam[1:-1, 1:-1, 0] = lam_nodes[0]
+    lam[1:-1, 1:-1, 1] = lam_nodes[1]
+    lam[1:-1, 1:-1, 2] = lam_nodes[2]
+    lam_rho = torch.empty((ly, lx), dtype=torch.float32, device="cuda")
+    ffb.ffb_flux_adj(ctx.handle, sigma, dev_f32(lam), dev_f64([lrb]), lam_rho, lx, ly)
+    assert ctx.sync(check=False) == 0
+    Fd = oracle.flux(delta, sigma)                   # linear: F(rho+eps d) - F(rho) = eps F(d)
+    want = (np.sum(lam_nodes[0] * Fd.jx) + np.sum(lam_nodes[1] * Fd.jy)
+            + np.sum(lam_nodes[2] * Fd.rho_s) + lrb * Fd.rho_bar)
+    got = float(np.sum(to_np(lam_rho).astype(np.float64) * delta))
+    scale = float(np.sum(np.abs(to_np(lam_rho)) * np.abs(delta)))
+    assert abs(got - want) <= 1e-5 * scale, (got, want)
+
+
+# ------------------------------------------------------------------ area
+def test_area_adj_matches_oracle_direction():
+    m = synth.workload("c1_L64")
+    rng = np.random.default_rng(7)
+    lam_area = rng.standard_normal(m.n_regions)
+    delta = rng.standard_normal(m.xy.shape)
+    ctx = new_ctx(m.lx)
+    g = _geom(m)
+    lam_xy = torch.zeros((m.n_vertices, 2), dtype=torch.float64, device="cuda")
+    ffb.ffb_area_adj(ctx.handle, g, dev_f64(lam_area), lam_xy)
+    assert ctx.sync(check=False) == 0
+    xy = to_np(g.xy).astype(np.float64)
+    # areas are quadratic in the coordinates, so central differences are exact
+    # for any step; a large one keeps the FP64 rounding of the shoelace sums
+    # (~1e-16 of sum |x y| ~ 1e-9 here) far below the bar after division
+    eps = 0.5
+    fp = oracle.region_areas(m, xy + eps * delta) @ lam_area
+    fm = oracle.region_areas(m, xy - eps * delta) @ lam_area
+    want = (fp - fm) / (2 * eps)
+    got = float(np.sum(to_np(lam_xy) * delta))
+    assert _rel(got, want) < 1e-10, (got, want)
+
+
+# --------------------------------------------------------------- density
+def test_density_adj_matches_oracle_directions():
+    """value, area and vertex directions; lam_rho random on the grid.
+
+    The coverage integral is not differentiable where an edge lies on a grid
+    line (moving it out of or into a cell differs), which is where the
+    synthetic map's outer boundary starts, and it curves sharply where an
+    edge is nearly parallel to a grid line close to it (the crossing point
+    slides fast), which spoils central differences.  Vertices are jittered by
+    up to 0.02 cells so that every edge is in general position, as after any
+    round; the differences then agree with the boundary integral to ~1e-8."""
+    m = synth.workload("c1_L64")
+    rng = np.random.default_rng(8)
+    lx = ly = m.lx
+    xy = (m.xy + rng.uniform(-2e-2, 2e-2, m.xy.shape)).astype(np.float32).astype(np.float64)
+    area = oracle.region_areas(m, xy)
+    value = m.density * area
+    lam_rho = rng.standard_normal((ly, lx)).astype(np.float32).astype(np.float64)
+    ctx = new_ctx(lx)
+    g = _geom(m, xy)
+    R, V = m.n_regions, m.n_vertices
+    lv = torch.zeros(R, dtype=torch.float64, device="cuda")
+    la = torch.zeros(R, dtype=torch.float64, device="cuda")
+    lxy = torch.zeros((V, 2), dtype=torch.float64, device="cuda")
+    ffb.ffb_density_adj(ctx.handle, g, dev_f64(value), dev_f64(area), dev_f32(lam_rho), lv, la,
+                        lxy, lx, ly)
+    assert ctx.sync(check=False) == 0
+
+    def L(v, a, p):
+        rho, _ = oracle.density(m, v, a, xy=p)
+        return float(np.sum(lam_rho * rho))
+
+    # value and area: smooth rational functions, central FD with relative step
+    for which, lam_t in (("value", lv), ("area", la)):
+        d = rng.standard_normal(R)
+        base = value if which == "value" else area
+        eps = 1e-6 * float(np.max(np.abs(base)))
+        args_p = (value + eps * d, area) if which == "value" else (value, area + eps * d)
+        args_m = (value - eps * d, area) if which == "value" else (value, area - eps * d)
+        want = (L(*args_p, xy) - L(*args_m, xy)) / (2 * eps)
+        got = float(np.sum(to_np(lam_t) * d))
+        assert _rel(got, want) < 1e-6, (which, got, want)
+    # vertices: the coverage integral is piecewise quadratic in the vertex
+    # positions; a small step keeps every edge within its cells
+    d = rng.standard_normal((V, 2))
+    eps = 1e-6
+    want = (L(value, area, xy + eps * d) - L(value, area, xy - eps * d)) / (2 * eps)
+    got = float(np.sum(to_np(lxy) * d))
+    # the adjoint is FP64 arithmetic on FP32-exact inputs; the bar covers the
+    # truncation of the differences
+    scale = float(np.sum(np.abs(to_np(lxy) * d)))
+    assert abs(got - want) <= 1e-6 * scale, (got, want, scale)
+
+
+# ----------------------------------------------------------- integration
+def _c1_fields(sigma=4.0):
+    m = synth.workload("c1_L64")
+    xy = m.xy.astype(np.float32).astype(np.float64)
+    area = oracle.region_areas(m, xy)
+    rho, _ = oracle.density(m, m.density * area, area, xy=xy)
+    return m, xy, oracle.flux(rho, sigma)
+
+
+def test_integrate_adj_matches_oracle_directions():
+    """Directional derivatives of <lam, X(t=1)> along the start positions, the
+    node fields and rho_bar, with the oracle's schedule frozen on both sides."""
+    m, xy, F = _c1_fields()
+    Fr = F.rounded_f32()
+    sched = oracle.integrate(Fr, xy).h
+    rng = np.random.default_rng(9)
+    V = xy.shape[0]
+    lam_end = rng.standard_normal((V, 2))
+    ctx = new_ctx(m.lx, max_points=V)
+    fields, rho_bar, _ = pack_oracle_fields(ctx, F)
+    pts = dev_f32(xy)
+    S = len(sched)
+    cap = S + 4
+    stats = torch.empty(4, dtype=torch.int32, device="cuda")
+    tape = torch.empty((cap, V, 4), dtype=torch.float32, device="cuda")
+    tape_h = torch.empty(cap, dtype=torch.float64, device="cuda")
+    ffb.ffb_integrate_record(ctx.handle, fields, rho_bar, pts, ffb.IntegrateOpts(), stats, tape,
+                             tape_h, V, replay_h=dev_f64(sched))
+    lam_xy = dev_f64(lam_end).contiguous()
+    lam_f = torch.zeros((m.ly + 2, m.lx + 2, 4), dtype=torch.float32, device="cuda")
+    lam_rb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ffb.ffb_integrate_adj(ctx.handle, fields, rho_bar, stats, tape, tape_h, V, lam_xy, lam_f,
+                          lam_rb)
+    assert ctx.sync(check=False) == 0
+    assert int(to_np(stats)[0]) == S
+
+    def L(F_, p):
+        return float(np.sum(lam_end * oracle.integrate(F_, p, replay_h=sched).xy))
+
+    def shifted(F_, djx, djy, drs, drb, eps):
+        return oracle.Fields(F_.lx, F_.ly, F_.rho_s + eps * drs, F_.jx + eps * djx,
+                             F_.jy + eps * djy, F_.rho_bar + eps * drb)
+
+    # start positions
+    d = rng.standard_normal((V, 2))
+    eps = 1e-5
+    want = (L(Fr, xy + eps * d) - L(Fr, xy - eps * d)) / (2 * eps)
+    got = float(np.sum(to_np(lam_xy) * d))
+    assert _rel(got, want) < 2e-4, ("xy", got, want)
+    # fields: the node perturbation is packed (ghosts included) by the
+    # library's pack call, so <lam_f, pack(delta)> is the directional derivative
+    djx, djy, drs = (rng.standard_normal((m.ly, m.lx)) for _ in range(3))
+    drb = rng.standard_normal()
+    scale_f = float(np.max(np.abs(Fr.jx)))
+    eps = 1e-6 * scale_f
+    want = (L(shifted(Fr, djx, djy, drs, drb, eps), xy)
+            - L(shifted(Fr, djx, djy, drs, drb, -eps), xy)) / (2 * eps)
+    dpack = ctx.pack_fields(dev_f32(djx), dev_f32(djy), dev_f32(drs))
+    got = float(np.sum(to_np(lam_f)[..., :3].astype(np.float64)
+                       * to_np(dpack)[..., :3].astype(np.float64))
+                + to_np(lam_rb)[0] * drb)
+    assert _rel(got, want) < 2e-4, ("fields", got, want)
+
+
+def test_integrate_adj_tape_overflow_sets_status():
+    m, xy, F = _c1_fields()
+    sched = oracle.integrate(F.rounded_f32(), xy).h
+    V = xy.shape[0]
+    ctx = new_ctx(m.lx, max_points=V)
+    fields, rho_bar, _ = pack_oracle_fields(ctx, F)
+    cap = len(sched) - 1                             # one step short
+    stats = torch.empty(4, dtype=torch.int32, device="cuda")
+    tape = torch.empty((cap, V, 4), dtype=torch.float32, device="cuda")
+    tape_h = torch.empty(cap, dtype=torch.float64, device="cuda")
+    ffb.ffb_integrate_record(ctx.handle, fields, rho_bar, dev_f32(xy), ffb.IntegrateOpts(),
+                             stats, tape, tape_h, V, replay_h=dev_f64(sched))
+    assert ctx.sync(check=False) == 0
+    lam_xy = torch.zeros((V, 2), dtype=torch.float64, device="cuda")
+    lam_f = torch.zeros((m.ly + 2, m.lx + 2, 4), dtype=torch.float32, device="cuda")
+    lam_rb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ffb.ffb_integrate_adj(ctx.handle, fields, rho_bar, stats, tape, tape_h, V, lam_xy, lam_f,
+                          lam_rb)
+    assert ctx.sync(check=False) == ffb.FFB_E_NO_TAPE
+
+
+# -------------------------------------------------------------- backward
+SIGMAS = [oracle.default_sigma(k) for k in range(3)]
+
+
+def _gpu_gradient(m, density, sigmas, schedules=None, with_grid=False, max_steps=512):
+    """dL/dd on the device through FFBFunction and torch autograd."""
+    V = m.n_vertices
+    pts_np = m.xy.astype(np.float32)
+    if with_grid:
+        pts_np = np.concatenate([pts_np, synth.grid_nodes(m.lx, m.ly)])
+    pts = dev_f32(pts_np).reshape(-1, 2)
+    ctx = new_ctx(m.lx, max_points=pts.shape[0])
+    geom = ffb.Geometry.from_map(m, pts[:V])
+    a0, _, _ = ctx.area_error(geom, dev_f64(np.ones(m.n_regions)))
+    d = dev_f64(density).requires_grad_(True)
+    value = d * a0
+    replay = None if schedules is None else [dev_f64(s) for s in schedules]
+    area = ffb.FFBFunction.apply(value, ctx, geom, pts, sigmas, None, max_steps, replay)
+    T = value * area.sum() / value.sum()
+    e = area / T - 1.0
+    loss = (e * e).sum()
+    loss.backward()
+    assert ctx.sync(check=False) == 0
+    return float(loss.detach()), to_np(d.grad)
+
+
+def test_backward_matches_oracle_fd_c1():
+    """Gradient of the 3-round area loss w.r.t. the region densities vs the
+    oracle's central differences (h = 1e-4), schedules frozen at the
+    oracle's adaptive ones."""
+    m = synth.workload("c1_L64")
+    ref = oracle.rounds(m, m.density, SIGMAS)
+    g_fd = oracle.fd_gradient(m, m.density, SIGMAS, ref.schedules, step=1e-4)
+    loss, g = _gpu_gradient(m, m.density, SIGMAS, ref.schedules)
+    assert _rel(loss, ref.loss) < 1e-3
+    err = np.max(np.abs(g - g_fd)) / np.max(np.abs(g_fd))
+    assert err < 1e-3, (err, g, g_fd)
+
+
+def test_backward_scale_invariance():
+    """The loss is invariant under d -> c d (velocities and targets do not
+    change), so sum_r d_r dL/dd_r = 0; holds at any size and schedule."""
+    m = synth.workload("c1_L64")
+    _, g = _gpu_gradient(m, m.density, SIGMAS)
+    s = float(np.dot(m.density, g))
+    assert abs(s) < 1e-3 * float(np.sum(np.abs(m.density * g))), s
+
+
+def test_backward_uniform_density_is_minimum():
+    """Uniform densities: no flow, zero loss, zero gradient."""
+    m = synth.workload("c1_L64")
+    d = np.full(m.n_regions, 1.7)
+    loss, g = _gpu_gradient(m, d, SIGMAS)
+    # FP32 transforms of a constant leave ~1e-7 relative residue in the
+    # higher modes, so the flow and the loss are zero only to that level
+    assert loss < 1e-12
+    assert np.max(np.abs(g)) < 1e-5
+
+
+def test_backward_grid_points_do_not_change_gradient():
+    """Advecting the grid nodes with the vertices (as a full cartogram does)
+    leaves the area gradient unchanged up to FP32 rounding."""
+    m = synth.workload("c1_L64")
+    ref = oracle.rounds(m, m.density, SIGMAS)
+    _, g0 = _gpu_gradient(m, m.density, SIGMAS, ref.schedules)
+    _, g1 = _gpu_gradient(m, m.density, SIGMAS, ref.schedules, with_grid=True)
+    assert np.max(np.abs(g0 - g1)) <= 1e-5 * np.max(np.abs(g0))
+
+
+def test_backward_requires_complete_tape():
+    m = synth.workload("c1_L64")
+    ctx = new_ctx(m.lx, max_points=m.n_vertices)
+    dl = dev_f64(np.ones(m.n_regions))
+    dv = torch.empty_like(dl)
+    with pytest.raises(ffb.FFBError) as ei:
+        ffb.ffb_backward(ctx.handle, dl, dv)
+    assert ei.value.code == ffb.FFB_E_NO_TAPE
+    # a round without its closing area call
+    pts = dev_f32(m.xy).reshape(-1, 2)
+    geom = ffb.Geometry.from_map(m, pts)
+    value = dev_f64(m.density * oracle.region_areas(m))
+    ctx.tape_begin(64)
+    area, _, _ = ctx.area_error(geom, value)
+    rho, _ = ctx.density(geom, value, area)
+    fields, rb = ctx.flux(rho, 4.0)
+    ctx.integrate(fields, rb, pts, h_cap=0)
+    with pytest.raises(ffb.FFBError) as ei:
+        ffb.ffb_backward(ctx.handle, dl, dv)
+    assert ei.value.code == ffb.FFB_E_NO_TAPE
+    assert ctx.sync(check=False) == 0
+
+
+def test_backward_max_steps_too_small_sets_status():
+    m = synth.workload("c1_L64")
+    ref = oracle.rounds(m, m.density, SIGMAS[:1])
+    S = len(ref.schedules[0])
+    pts = dev_f32(m.xy).reshape(-1, 2)
+    ctx = new_ctx(m.lx, max_points=m.n_vertices)
+    geom = ffb.Geometry.from_map(m, pts)
+    value = dev_f64(m.density * oracle.region_areas(m))
+    area = ffb.FFBFunction.apply(value, ctx, geom, pts, SIGMAS[:1], None, S - 1,
+                                 [dev_f64(ref.schedules[0])])
+    dv, _ = ctx.backward(torch.ones_like(area))
+    assert ctx.sync(check=False) == ffb.FFB_E_NO_TAPE
