@@ -65,6 +65,21 @@ hipError_t ensure_region_capacity(ffb_ctx *ctx, int32_t R)
     return e;
 }
 
+hipError_t ensure_adjoint_capacity(ffb_ctx *ctx, int32_t cap, int64_t n)
+{
+    hipError_t e = hipSuccess;
+    if (cap > ctx->adj_t_cap) {
+        e = grow(&ctx->adj_t, ctx->adj_t_cap, cap);
+        ctx->adj_t_cap = e == hipSuccess ? cap : 0;
+    }
+    const int64_t need = (int64_t)cap * (n > 0 ? n : 1);
+    if (e == hipSuccess && need > ctx->adj_jac_cap) {
+        e = grow(&ctx->adj_jac, ctx->adj_jac_cap, need);
+        ctx->adj_jac_cap = e == hipSuccess ? need : 0;
+    }
+    return e;
+}
+
 }  // namespace ffbi
 
 using namespace ffbi;
@@ -95,7 +110,7 @@ void free_all(ffb_ctx *c)
 {
     void *ptrs[] = {c->d_status, c->tw_x, c->tq_x, c->tw_y, c->tq_y, c->t1, c->t2, c->pa,
                     c->pb, c->pc, c->red, c->acc, c->w_region, c->st[0], c->st[1], c->kv[0],
-                    c->kv[1], c->errslot, c->lam_w};
+                    c->kv[1], c->errslot, c->lam_w, c->adj_t, c->adj_jac};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     tape_free(c);

@@ -33,12 +33,15 @@ struct tape_rec {
     float4 *fields = nullptr;      // I
     double *rho_bar = nullptr;     // I
     advect_tape at{};              // I: states, h, count owned by the record
+    // allocated sizes (elements), so a later recording can reuse the buffers
+    int64_t xy_cap = 0, r_cap = 0, st_cap = 0, h_cap = 0;
 };
 
 struct ffb_tape {
     bool recording = false;
     int32_t max_steps = 0;
-    std::vector<tape_rec> recs;
+    std::vector<tape_rec> recs;    // recs[0, used) is the current record
+    size_t used = 0;
     // backward workspace
     double *lam_xy = nullptr;
     int64_t lam_xy_cap = 0;
@@ -63,37 +66,57 @@ void clear_records(ffb_tape *t)
 {
     for (tape_rec &r : t->recs) free_rec(r);
     t->recs.clear();
+    t->used = 0;
 }
 
 bool recording(ffb_ctx *ctx) { return ctx->tape && ctx->tape->recording; }
 
-template <typename T>
-hipError_t alloc_copy(T **dst, const T *src, int64_t n, hipStream_t s)
+// The next record slot: buffers of an earlier recording at the same position
+// are kept (queued work that still reads them precedes, on the same stream,
+// whatever overwrites them).
+tape_rec &next_slot(ffb_tape *t, char kind)
 {
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), sizeof(T) * (size_t)(n > 0 ? n : 1));
+    if (t->used == t->recs.size()) t->recs.emplace_back();
+    tape_rec &r = t->recs[t->used];
+    r.kind = kind;
+    return r;
+}
+
+template <typename T>
+hipError_t ensure(T **p, int64_t *cap, int64_t need)
+{
+    if (need <= *cap && *p) return hipSuccess;
+    hipError_t e = grow(p, *cap, need);
+    *cap = e == hipSuccess ? need : 0;
+    return e;
+}
+
+template <typename T>
+hipError_t copy_in(T **dst, int64_t *cap, const T *src, int64_t n, hipStream_t s)
+{
+    hipError_t e = ensure(dst, cap, n);
     if (e != hipSuccess || n == 0) return e;
     return hipMemcpyAsync(*dst, src, sizeof(T) * (size_t)n, hipMemcpyDeviceToDevice, s);
 }
 
-int push(ffb_ctx *ctx, tape_rec &r, hipError_t e, const char *what)
+int commit(ffb_ctx *ctx, hipError_t e, const char *what)
 {
-    if (e != hipSuccess) {
-        free_rec(r);
-        return hip_fail(ctx, e, what);
-    }
-    ctx->tape->recs.push_back(r);
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    ++ctx->tape->used;
     return FFB_OK;
 }
 
 // Number of vertices and regions of the recorded rounds (from the first record).
 bool tape_sizes(const ffb_tape *t, int64_t *V, int32_t *R)
 {
-    for (const tape_rec &r : t->recs)
+    for (size_t k = 0; k < t->used; ++k) {
+        const tape_rec &r = t->recs[k];
         if (r.kind == 'A' || r.kind == 'D') {
             *V = r.g.n_vertices;
             *R = r.g.n_regions;
             return true;
         }
+    }
     return false;
 }
 
@@ -102,36 +125,40 @@ bool tape_sizes(const ffb_tape *t, int64_t *V, int32_t *R)
 int tape_on_area(ffb_ctx *ctx, const ffb_geometry *g)
 {
     if (!recording(ctx)) return FFB_OK;
-    tape_rec r;
-    r.kind = 'A';
+    tape_rec &r = next_slot(ctx->tape, 'A');
     r.g = *g;
-    hipError_t e = alloc_copy(&r.xy, reinterpret_cast<const float2 *>(g->xy), g->n_vertices,
-                              ctx->stream);
+    hipError_t e = copy_in(&r.xy, &r.xy_cap, reinterpret_cast<const float2 *>(g->xy),
+                           g->n_vertices, ctx->stream);
     r.g.xy = reinterpret_cast<const float *>(r.xy);
-    return push(ctx, r, e, "tape (area)");
+    return commit(ctx, e, "tape (area)");
 }
 
 int tape_on_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const double *area)
 {
     if (!recording(ctx)) return FFB_OK;
-    tape_rec r;
-    r.kind = 'D';
+    tape_rec &r = next_slot(ctx->tape, 'D');
     r.g = *g;
-    hipError_t e = alloc_copy(&r.xy, reinterpret_cast<const float2 *>(g->xy), g->n_vertices,
-                              ctx->stream);
+    hipError_t e = copy_in(&r.xy, &r.xy_cap, reinterpret_cast<const float2 *>(g->xy),
+                           g->n_vertices, ctx->stream);
     r.g.xy = reinterpret_cast<const float *>(r.xy);
-    if (e == hipSuccess) e = alloc_copy(&r.value, value, g->n_regions, ctx->stream);
-    if (e == hipSuccess) e = alloc_copy(&r.area, area, g->n_regions, ctx->stream);
-    return push(ctx, r, e, "tape (density)");
+    if (e == hipSuccess) {
+        int64_t rc = r.r_cap;       // value and area share one capacity
+        e = copy_in(&r.value, &rc, value, g->n_regions, ctx->stream);
+        if (e == hipSuccess) {
+            rc = r.r_cap;
+            e = copy_in(&r.area, &rc, area, g->n_regions, ctx->stream);
+        }
+        r.r_cap = e == hipSuccess ? rc : 0;
+    }
+    return commit(ctx, e, "tape (density)");
 }
 
 int tape_on_flux(ffb_ctx *ctx, float sigma)
 {
     if (!recording(ctx)) return FFB_OK;
-    tape_rec r;
-    r.kind = 'F';
+    tape_rec &r = next_slot(ctx->tape, 'F');
     r.sigma = sigma;
-    return push(ctx, r, hipSuccess, "tape (flux)");
+    return commit(ctx, hipSuccess, "tape (flux)");
 }
 
 int tape_on_integrate(ffb_ctx *ctx, int64_t n, const float4 *fields, const double *rho_bar,
@@ -146,20 +173,17 @@ int tape_on_integrate(ffb_ctx *ctx, int64_t n, const float4 *fields, const doubl
         return fail(ctx, FFB_E_INVALID, "tape: ffb_integrate recorded before any area or density call%s");
     if (n < V)
         return fail(ctx, FFB_E_INVALID, "tape: ffb_integrate must advect the recorded vertices first%s");
-    tape_rec r;
-    r.kind = 'I';
+    tape_rec &r = next_slot(t, 'I');
     const int64_t nf = (int64_t)(ctx->lx + 2) * (ctx->ly + 2);
-    hipError_t e = alloc_copy(&r.fields, fields, nf, ctx->stream);
-    if (e == hipSuccess) e = alloc_copy(&r.rho_bar, rho_bar, 1, ctx->stream);
+    int64_t fcap = r.fields ? nf : 0, one = r.rho_bar ? 1 : 0, cnt = r.at.count ? 1 : 0;
+    hipError_t e = copy_in(&r.fields, &fcap, fields, nf, ctx->stream);
+    if (e == hipSuccess) e = copy_in(&r.rho_bar, &one, rho_bar, 1, ctx->stream);
+    if (e == hipSuccess) e = ensure(&r.at.states, &r.st_cap, (V > 0 ? V : 1) * (int64_t)t->max_steps);
+    if (e == hipSuccess) e = ensure(&r.at.h, &r.h_cap, (int64_t)t->max_steps);
+    if (e == hipSuccess) e = ensure(&r.at.count, &cnt, 1);
     r.at.n = V;
     r.at.cap = t->max_steps;
-    if (e == hipSuccess)
-        e = hipMalloc(reinterpret_cast<void **>(&r.at.states),
-                      sizeof(float4) * (size_t)(V > 0 ? V : 1) * (size_t)t->max_steps);
-    if (e == hipSuccess)
-        e = hipMalloc(reinterpret_cast<void **>(&r.at.h), sizeof(double) * (size_t)t->max_steps);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&r.at.count), sizeof(int32_t));
-    const int st = push(ctx, r, e, "tape (integrate)");
+    const int st = commit(ctx, e, "tape (integrate)");
     if (st == FFB_OK) {
         *out = r.at;
         *record = true;
@@ -232,7 +256,9 @@ int ffb_integrate_adj(ffb_ctx *ctx, const float *fields, const double *rho_bar,
         return fail(ctx, FFB_E_INVALID, "ffb_integrate_adj: bad tape size%s");
     advect_tape t{const_cast<float4 *>(reinterpret_cast<const float4 *>(tape_states)), tape_n,
                   tape_cap, const_cast<double *>(tape_h), const_cast<int32_t *>(stats)};
-    hipError_t e = launch_advect_adj(ctx, reinterpret_cast<const float4 *>(fields), rho_bar, &t,
+    hipError_t e = ensure_adjoint_capacity(ctx, tape_cap, tape_n);
+    if (e != hipSuccess) return hip_fail(ctx, e, "ffb_integrate_adj workspace");
+    e = launch_advect_adj(ctx, reinterpret_cast<const float4 *>(fields), rho_bar, &t,
                                      lam_xy, reinterpret_cast<float4 *>(lam_fields), lam_rho_bar);
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_integrate_adj launch");
 }
@@ -243,10 +269,7 @@ int ffb_tape_begin(ffb_ctx *ctx, int32_t max_steps)
     if (max_steps < 1 || max_steps > (1 << 20))
         return fail(ctx, FFB_E_INVALID, "ffb_tape_begin: max_steps out of range%s");
     if (!ctx->tape) ctx->tape = new ffb_tape();
-    // records may still be read by queued work
-    hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "ffb_tape_begin");
-    clear_records(ctx->tape);
+    ctx->tape->used = 0;          // buffers are kept for reuse
     ctx->tape->recording = true;
     ctx->tape->max_steps = max_steps;
     return FFB_OK;
@@ -273,13 +296,14 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
     if (!ctx) return FFB_E_INVALID;
     if (!dL_darea || !dL_dvalue) return fail(ctx, FFB_E_INVALID, "ffb_backward: NULL argument%s");
     ffb_tape *t = ctx->tape;
-    if (!t || t->recs.empty())
+    if (!t || t->used == 0)
         return fail(ctx, FFB_E_NO_TAPE, "ffb_backward: nothing recorded (call ffb_tape_begin)%s");
     t->recording = false;
     std::vector<tape_rec> &recs = t->recs;
+    const int64_t used = (int64_t)t->used;
     // the record sequence must be A+ (D F I A+)*
     std::string seq;
-    for (const tape_rec &r : recs) seq += r.kind;
+    for (int64_t k = 0; k < used; ++k) seq += recs[k].kind;
     {
         size_t k = 0;
         bool ok = k < seq.size() && seq[k] == 'A';
@@ -298,7 +322,8 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
     int64_t V = 0;
     int32_t R = 0;
     tape_sizes(t, &V, &R);
-    for (const tape_rec &r : recs) {
+    for (int64_t k = 0; k < used; ++k) {
+        const tape_rec &r = recs[k];
         if ((r.kind == 'A' || r.kind == 'D') && (r.g.n_vertices != V || r.g.n_regions != R))
             return fail(ctx, FFB_E_INVALID, "ffb_backward: rounds differ in vertices or regions%s");
     }
@@ -322,13 +347,14 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
         t->lam_area_cap = e == hipSuccess ? R : 0;
     }
     if (e == hipSuccess) e = ensure_region_capacity(ctx, R);
+    if (e == hipSuccess) e = ensure_adjoint_capacity(ctx, t->max_steps, V);
     if (e != hipSuccess) return hip_fail(ctx, e, "ffb_backward workspace");
 
     e = launch_fill_f64(t->lam_xy, 2 * V, 0.0, s);
     if (e == hipSuccess) e = launch_fill_f64(dL_dvalue, R, 0.0, s);
-    if (e == hipSuccess) e = launch_area_adj(ctx, &recs.back().g, dL_darea, t->lam_xy);
+    if (e == hipSuccess) e = launch_area_adj(ctx, &recs[used - 1].g, dL_darea, t->lam_xy);
     bool pending = false;           // an area adjoint from a density record waits
-    for (int64_t k = (int64_t)recs.size() - 2; k >= 0 && e == hipSuccess; --k) {
+    for (int64_t k = used - 2; k >= 0 && e == hipSuccess; --k) {
         tape_rec &r = recs[k];
         switch (r.kind) {
         case 'I':

@@ -42,6 +42,10 @@ struct ffb_ctx {
     int adv_cap = 0;                           // cap on advection workgroups, 0 = none
 
     struct ffb_tape *tape = nullptr;           // recording for ffb_backward
+    double *adj_t = nullptr;                   // [cap] step start times (adjoint)
+    int64_t adj_t_cap = 0;
+    float4 *adj_jac = nullptr;                 // [cap][n] step Jacobians (adjoint)
+    int64_t adj_jac_cap = 0;
 };
 
 // ------------------------------------------------------------ host helpers
@@ -62,6 +66,8 @@ hipError_t grow(T **p, int64_t have, int64_t need)
 }
 // Per-region workspace (w_region, lam_w) for at least R regions.
 hipError_t ensure_region_capacity(ffb_ctx *ctx, int32_t R);
+// Integration adjoint workspace for `cap` steps of n points.
+hipError_t ensure_adjoint_capacity(ffb_ctx *ctx, int32_t cap, int64_t n);
 }  // namespace ffbi
 
 // Context tape (recording for ffb_backward).  Each hook returns FFB_OK when

@@ -20,6 +20,14 @@
 //            lam = lam' + sum_s Ybar_s,
 //            and each stage adds (df/dfields)^T kbar_s to the field adjoints.
 //            Stages are recomputed from the checkpointed state of the step.
+//            The position adjoint is only 2D per point, so the steps are
+//            split into three passes that each run over all (point, step)
+//            pairs or all points: the 2 x 2 Jacobian of every step (forward
+//            mode), a cheap per-point scan lam_k = M_k^T lam_{k+1}, and the
+//            field adjoints of every step given lam_{k+1} -- parallel over
+//            steps, instead of one long dependent chain per point.
+#include <algorithm>
+
 #include "ffb_internal.h"
 
 namespace {
@@ -112,9 +120,18 @@ __device__ inline int32_t lines_between(double a, double b, double *first, doubl
     return 0;
 }
 
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // One edge: its contribution to sum_c lam_c cov_r(c) (through the coverage
 // deltas of the forward raster and the row suffix sums) and the geometric
-// derivatives of that sum with respect to both endpoints.
+// derivatives of that sum with respect to both endpoints.  A wavefront
+// usually covers 64 entries of one ring, i.e. one region: then its coverage
+// sums are reduced in registers and added with one atomic (thousands of
+// edges share each region's word).  Every lane stays active to the end.
 __global__ __launch_bounds__(kThreads) void k_raster_adj(
     const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
     const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t G,
@@ -123,76 +140,96 @@ __global__ __launch_bounds__(kThreads) void k_raster_adj(
     double *__restrict__ lam_xy, int32_t *status)
 {
     const int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    if (k >= E) return;
-    int32_t lo = 0, hi = G;
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= k) lo = mid; else hi = mid;
-    }
-    const int64_t b = off[lo], e = off[lo + 1];
-    if (!(b <= k && k < e) || e - b < 3 || e > E) { set_status(status, FFB_E_INVALID); return; }
-    const int32_t r = region[lo];
-    const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
-    if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
-        set_status(status, FFB_E_INVALID);
-        return;
-    }
-    const float2 p = xy[i0], q = xy[i1];
-    const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
-    if (!(x0 >= 0.0 && x0 <= lx && y0 >= 0.0 && y0 <= ly && x1 >= 0.0 && x1 <= lx &&
-          y1 >= 0.0 && y1 <= ly)) {
-        set_status(status, FFB_E_DOMAIN);
-        return;
-    }
-    const double dx = x1 - x0, dy = y1 - y0;
-    double fx, sx, fy, sy;
-    const int32_t nx = lines_between(x0, x1, &fx, &sx);
-    const int32_t ny = lines_between(y0, y1, &fy, &sy);
-    int32_t ix = 0, iy = 0;
-    double sa = 0.0, xa = x0, ya = y0;
-    double cov = 0.0, I0 = 0.0, I1 = 0.0;
-    for (;;) {
-        double sb, xb, yb;
-        const bool last = !(ix < nx || iy < ny);
-        if (last) {
-            sb = 1.0;
-            xb = x1;
-            yb = y1;
+    int32_t r = -1, i0 = 0, i1 = 0;
+    double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
+    if (k < E) {
+        int32_t lo = 0, hi = G;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (off[mid] <= k) lo = mid; else hi = mid;
+        }
+        const int64_t b = off[lo], e = off[lo + 1];
+        if (!(b <= k && k < e) || e - b < 3 || e > E) {
+            set_status(status, FFB_E_INVALID);
         } else {
-            const double X = fx + sx * ix, Y = fy + sy * iy;
-            const double tx = (ix < nx) ? (X - x0) / dx : 2.0;
-            const double ty = (iy < ny) ? (Y - y0) / dy : 2.0;
-            if (tx < ty) {
-                sb = tx; xb = X; yb = y0 + tx * dy; ++ix;
-            } else if (ty < tx) {
-                sb = ty; xb = x0 + ty * dx; yb = Y; ++iy;
+            const int32_t rr = region[lo];
+            i0 = vidx[k];
+            i1 = vidx[(k + 1 == e) ? b : k + 1];
+            if (rr < 0 || rr >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
+                set_status(status, FFB_E_INVALID);
             } else {
-                sb = tx; xb = X; yb = Y; ++ix; ++iy;
+                const float2 p = xy[i0], q = xy[i1];
+                x0 = p.x; y0 = p.y; x1 = q.x; y1 = q.y;
+                if (!(x0 >= 0.0 && x0 <= lx && y0 >= 0.0 && y0 <= ly && x1 >= 0.0 && x1 <= lx &&
+                      y1 >= 0.0 && y1 <= ly))
+                    set_status(status, FFB_E_DOMAIN);
+                else
+                    r = rr;
             }
         }
-        // the piece [sa, sb] lies in cell (kc, jc)
-        const double xm = 0.5 * (xa + xb);
-        int32_t kc = (int32_t)floor(xm), jc = (int32_t)floor(0.5 * (ya + yb));
-        kc = min(max(kc, 0), lx - 1);
-        jc = min(max(jc, 0), ly - 1);
-        const double D = ya - yb;
-        if (D != 0.0) {
-            const double *srow = suf + (int64_t)jc * (lx + 1);
-            cov += D * ((double)(kc + 1) - xm) * srow[kc] + D * (xm - (double)kc) * srow[kc + 1];
-        }
-        const double lc = lam[(int64_t)jc * lx + kc];
-        I0 += lc * ((sb - sa) - 0.5 * (sb * sb - sa * sa));
-        I1 += lc * 0.5 * (sb * sb - sa * sa);
-        sa = sb; xa = xb; ya = yb;
-        if (last) break;
     }
-    const double wr = w[r];
-    unsafeAtomicAdd(&lam_w[r], cov);
-    // outward normal times length of a counter-clockwise edge: (dy, -dx)
-    unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0], wr * dy * I0);
-    unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0 + 1], -wr * dx * I0);
-    unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1], wr * dy * I1);
-    unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1 + 1], -wr * dx * I1);
+    double cov = 0.0, I0 = 0.0, I1 = 0.0;
+    const double dx = x1 - x0, dy = y1 - y0;
+    if (r >= 0) {
+        double fx, sx, fy, sy;
+        const int32_t nx = lines_between(x0, x1, &fx, &sx);
+        const int32_t ny = lines_between(y0, y1, &fy, &sy);
+        int32_t ix = 0, iy = 0;
+        double sa = 0.0, xa = x0, ya = y0;
+        for (;;) {
+            double sb, xb, yb;
+            const bool last = !(ix < nx || iy < ny);
+            if (last) {
+                sb = 1.0;
+                xb = x1;
+                yb = y1;
+            } else {
+                const double X = fx + sx * ix, Y = fy + sy * iy;
+                const double tx = (ix < nx) ? (X - x0) / dx : 2.0;
+                const double ty = (iy < ny) ? (Y - y0) / dy : 2.0;
+                if (tx < ty) {
+                    sb = tx; xb = X; yb = y0 + tx * dy; ++ix;
+                } else if (ty < tx) {
+                    sb = ty; xb = x0 + ty * dx; yb = Y; ++iy;
+                } else {
+                    sb = tx; xb = X; yb = Y; ++ix; ++iy;
+                }
+            }
+            // the piece [sa, sb] lies in cell (kc, jc)
+            const double xm = 0.5 * (xa + xb);
+            int32_t kc = (int32_t)floor(xm), jc = (int32_t)floor(0.5 * (ya + yb));
+            kc = min(max(kc, 0), lx - 1);
+            jc = min(max(jc, 0), ly - 1);
+            const double D = ya - yb;
+            if (D != 0.0) {
+                const double *srow = suf + (int64_t)jc * (lx + 1);
+                cov += D * ((double)(kc + 1) - xm) * srow[kc] + D * (xm - (double)kc) * srow[kc + 1];
+            }
+            const double lc = lam[(int64_t)jc * lx + kc];
+            I0 += lc * ((sb - sa) - 0.5 * (sb * sb - sa * sa));
+            I1 += lc * 0.5 * (sb * sb - sa * sa);
+            sa = sb; xa = xb; ya = yb;
+            if (last) break;
+        }
+        const double wr = w[r];
+        // outward normal times length of a counter-clockwise edge: (dy, -dx)
+        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0], wr * dy * I0);
+        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0 + 1], -wr * dx * I0);
+        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1], wr * dy * I1);
+        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1 + 1], -wr * dx * I1);
+    }
+    // region sums of the coverage term
+    int32_t rlo = r >= 0 ? r : INT32_MAX, rhi = r;
+    for (int o = 32; o > 0; o >>= 1) {
+        rlo = min(rlo, __shfl_xor(rlo, o, 64));
+        rhi = max(rhi, __shfl_xor(rhi, o, 64));
+    }
+    if (rlo == rhi) {
+        const double s = wave_sum(cov);
+        if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(&lam_w[rhi], s);
+    } else if (r >= 0) {
+        unsafeAtomicAdd(&lam_w[r], cov);
+    }
 }
 
 // Per region: w_r = value_r / A_r - rho_pad, rho_pad = sum(value) / sum(A).
@@ -243,17 +280,19 @@ __constant__ float kA[6][5] = {
 __constant__ float kB[6] = {(float)(35.0 / 384), 0.f, (float)(500.0 / 1113),
                             (float)(125.0 / 192), (float)(-2187.0 / 6784), (float)(11.0 / 84)};
 
+constexpr int kChunk = 8;          // consecutive steps of one point per work item
+
 // Lookup of one stage position: the cell of the ghosted field layout (key =
 // (j + 1) pitch + (i + 1) of its lower-left node), the bilinear fractions,
 // and whether the position lies strictly inside the box along x / y (where
 // the clamped lookup has a derivative).
 struct Stage {
-    int key;
+    int ci, cj;           // lower-left node of the cell in the ghosted frame (i + 1, j + 1)
     float a, b;
     bool fx, fy;
 };
 
-__device__ inline Stage lookup(float qx, float qy, int lx, int ly, int pitch)
+__device__ inline Stage lookup(float qx, float qy, int lx, int ly)
 {
     Stage L;
     L.fx = qx > 0.f && qx < (float)lx;
@@ -265,7 +304,8 @@ __device__ inline Stage lookup(float qx, float qy, int lx, int ly, int pitch)
     const int j = min(max((int)floorf(v), -1), ly - 1);
     L.a = u - (float)i;
     L.b = v - (float)j;
-    L.key = (j + 1) * pitch + (i + 1);
+    L.ci = i + 1;
+    L.cj = j + 1;
     return L;
 }
 
@@ -287,24 +327,87 @@ __device__ inline void load_cell(const float4 *__restrict__ f, int pitch, int ke
     }
 }
 
-// Field adjoints of one cell, summed over consecutive stage evaluations that
-// use it and scattered with atomics when the cell changes.
+// Node velocities of the cached cell at one stage time and their reciprocal
+// densities; the bilinear value and its derivatives in the cell fractions.
+struct Local {
+    float vx[4], vy[4], r[4];
+    float kx, ky;                      // v at (a, b)
+    float xa, xb, ya, yb;              // dvx/da, dvx/db, dvy/da, dvy/db
+};
+
+__device__ inline void local_velocity(const Cell &cc, float omt, float tb, float a, float b,
+                                      Local &o)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        o.r[q] = __builtin_amdgcn_rcpf(fmaf(cc.c[q].z, omt, tb));
+        o.vx[q] = cc.c[q].x * o.r[q];
+        o.vy[q] = cc.c[q].y * o.r[q];
+    }
+    const float x0 = fmaf(a, o.vx[1] - o.vx[0], o.vx[0]), x1 = fmaf(a, o.vx[3] - o.vx[2], o.vx[2]);
+    const float y0 = fmaf(a, o.vy[1] - o.vy[0], o.vy[0]), y1 = fmaf(a, o.vy[3] - o.vy[2], o.vy[2]);
+    o.kx = fmaf(b, x1 - x0, x0);
+    o.ky = fmaf(b, y1 - y0, y0);
+    o.xa = (1.f - b) * (o.vx[1] - o.vx[0]) + b * (o.vx[3] - o.vx[2]);
+    o.ya = (1.f - b) * (o.vy[1] - o.vy[0]) + b * (o.vy[3] - o.vy[2]);
+    o.xb = x1 - x0;
+    o.yb = y1 - y0;
+}
+
+// Field adjoints are summed in three levels.  (1) Each lane keeps two cell
+// accumulators in registers (the stages of a point walk through few cells,
+// and near a cell boundary they alternate between two); a third cell pushes
+// the older accumulator out.  (2) Pushed sums go with LDS atomics to a
+// window of kWin x kWin nodes (ghosted frame) private to the wavefront and
+// placed around the cells of its 64 consecutive vertices; the window has
+// kCopies copies, lane l using copy l mod kCopies, so that neighbouring
+// vertices (which share nodes) do not collide on one LDS address.  (3) At
+// the end of a tile the copies are summed and every touched node is added to
+// the global adjoint with one atomic.  Cells outside the window go to the
+// global adjoint directly.
+constexpr int kWin = 18;
+constexpr int kCopies = 4;
+constexpr int kWinFloats = 3 * kWin * kWin;
+constexpr int kWaveFloats = kCopies * kWinFloats;
+
+// The wavefront's accepted node region, in window coordinates
+// [x0, x1) x [y0, y1) (inside the window); the end-of-tile pass visits
+// exactly this region.
+struct Region {
+    int wx0, wy0;         // window origin in the ghosted node frame
+    int x0, x1, y0, y1;
+};
+
 struct CellAcc {
-    int key;
+    int ci, cj;           // lower-left node (ghosted frame), ci < 0 = empty
     float3 g[4];
 };
 
-__device__ inline void flush(float4 *__restrict__ lam, int pitch, CellAcc &ac)
+__device__ inline void push(float4 *__restrict__ lam, int pitch, float *cw, const Region &R,
+                            const CellAcc &ac)
 {
-    if (ac.key < 0) return;
-    const int idx[4] = {ac.key, ac.key + 1, ac.key + pitch, ac.key + pitch + 1};
+    if (ac.ci < 0) return;
+    const int wx = ac.ci - R.wx0, wy = ac.cj - R.wy0;
+    if (wx >= R.x0 && wy >= R.y0 && wx + 1 < R.x1 && wy + 1 < R.y1) {
+        const int b = wy * kWin + wx;
+        const int idx[4] = {b, b + 1, b + kWin, b + kWin + 1};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        float *d = reinterpret_cast<float *>(lam + idx[q]);
-        unsafeAtomicAdd(d, ac.g[q].x);
-        unsafeAtomicAdd(d + 1, ac.g[q].y);
-        unsafeAtomicAdd(d + 2, ac.g[q].z);
-        ac.g[q] = make_float3(0.f, 0.f, 0.f);
+        for (int q = 0; q < 4; ++q) {
+            float *d = cw + 3 * idx[q];
+            atomicAdd(d, ac.g[q].x);
+            atomicAdd(d + 1, ac.g[q].y);
+            atomicAdd(d + 2, ac.g[q].z);
+        }
+    } else {
+        const int key = ac.cj * pitch + ac.ci;
+        const int idx[4] = {key, key + 1, key + pitch, key + pitch + 1};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float *d = reinterpret_cast<float *>(lam + idx[q]);
+            unsafeAtomicAdd(d, ac.g[q].x);
+            unsafeAtomicAdd(d + 1, ac.g[q].y);
+            unsafeAtomicAdd(d + 2, ac.g[q].z);
+        }
     }
 }
 
@@ -317,136 +420,324 @@ struct AdjParams {
     const double *h;           // [cap]
     const int32_t *count;      // accepted steps
     int cap;
+    double *tstart;            // [cap] start time of each step (workspace)
+    float4 *jac;               // [cap][n] step Jacobians, then lam after each step (workspace)
     double *lam_xy;            // [n][2] in: dL/dX(t=1), out: dL/dX(t=0)
     float4 *lam_f;             // ghosted field adjoints (accumulated)
     double *lam_rb;            // rho_bar adjoint (accumulated)
     int32_t *status;
 };
 
-// One lane per recorded point, steps in reverse.  Per step the six stages are
-// recomputed from the recorded state (lookups only), then swept in reverse:
-// kbar_s, the position adjoint of the stage and the field adjoints at its
-// four nodes (v = J / rt with rt = (1 - t) rho_s + t rho_bar, so
-// dv/dJ = 1/rt, dv/drho_s = -(1 - t) J/rt^2, dv/drho_bar = -t J/rt^2).
-__global__ __launch_bounds__(kThreads) void k_advect_adj(AdjParams p)
+__device__ inline bool adj_ok(const AdjParams &p, int &S)
 {
-    __shared__ double s_rb[kThreads / 64];
-    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    S = *p.count;
+    return S >= 0 && S <= p.cap;
+}
+
+// Start times of the steps, summed in the order the integration summed them,
+// and the record check.
+__global__ void k_adj_times(AdjParams p)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     const int S = *p.count;
-    if (S > p.cap || S < 0) {
-        if (i == 0) set_status(p.status, FFB_E_NO_TAPE);
+    if (S < 0 || S > p.cap) {
+        set_status(p.status, FFB_E_NO_TAPE);
         return;
     }
-    const double rho_bar = *p.rho_bar;
-    const bool live = i < p.n;
-    float lx_ = 0.f, ly_ = 0.f;
-    if (live) {
-        lx_ = (float)p.lam_xy[2 * (int64_t)i];
-        ly_ = (float)p.lam_xy[2 * (int64_t)i + 1];
+    double t = 0.0;
+    for (int k = 0; k < S; ++k) {
+        p.tstart[k] = t;
+        t += p.h[k];
     }
+}
+
+// Work tiles: kChunk consecutive steps of kThreads consecutive points.
+// `spread` deals the tile's points to the wavefronts round-robin, so that
+// the lanes of one wavefront hold every (kThreads/64)-th vertex of a chain:
+// fewer lanes of one atomic instruction then share a grid node.
+__device__ inline void tile_of(int tile, int n_pt_tiles, int &step0, int &i, bool spread)
+{
+    const int st = tile / n_pt_tiles;
+    step0 = st * kChunk;
+    const int t = (int)threadIdx.x;
+    const int r = spread ? (t & 63) * (kThreads / 64) + (t >> 6) : t;
+    i = (tile - st * n_pt_tiles) * kThreads + r;
+}
+
+// The six stages of step k of a point: lookups, velocities K_s and their
+// derivatives in the position (Jv_s, masked where the lookup is clamped).
+// Forward mode gives the step's Jacobian M = dX_{k+1}/dX_k:
+//   T_s = I + h sum_{q<s} a_sq dK_q,  dK_s = Jv_s T_s,  M = I + h sum_s b_s dK_s.
+__global__ __launch_bounds__(kThreads) void k_adj_jacobian(AdjParams p)
+{
+    int S;
+    if (!adj_ok(p, S)) return;
+    const double rho_bar = *p.rho_bar;
+    const int n_pt_tiles = (p.n + kThreads - 1) / kThreads;
+    const int n_tiles = ((S + kChunk - 1) / kChunk) * n_pt_tiles;
+    Cell cc;
+    cc.key = -1;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        int step0, i;
+        tile_of(tile, n_pt_tiles, step0, i, false);
+        if (i >= p.n) continue;
+        const int step1 = min(S, step0 + kChunk);
+        for (int k = step0; k < step1; ++k) {
+            const double h = p.h[k], t0 = p.tstart[k];
+            const float hf = (float)h;
+            const float4 st = p.tape[(int64_t)k * p.n + i];
+            float Kx[6], Ky[6];
+            float D[6][4];                     // dK_s, row-major 2 x 2
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                float dx = 0.f, dy = 0.f;
+                float T0 = 1.f, T1 = 0.f, T2 = 0.f, T3 = 1.f;
+#pragma unroll
+                for (int q = 0; q < s; ++q) {
+                    const float c = hf * kA[s][q];
+                    dx = fmaf(c, Kx[q], dx);
+                    dy = fmaf(c, Ky[q], dy);
+                    T0 = fmaf(c, D[q][0], T0);
+                    T1 = fmaf(c, D[q][1], T1);
+                    T2 = fmaf(c, D[q][2], T2);
+                    T3 = fmaf(c, D[q][3], T3);
+                }
+                const Stage L = lookup(st.x + (st.z + dx), st.y + (st.w + dy), p.lx, p.ly);
+                load_cell(p.fields, p.pitch, L.cj * p.pitch + L.ci, cc);
+                const double ts = t0 + kC[s] * h;
+                Local o;
+                local_velocity(cc, (float)(1.0 - ts), (float)(ts * rho_bar), L.a, L.b, o);
+                Kx[s] = o.kx;
+                Ky[s] = o.ky;
+                const float j00 = L.fx ? o.xa : 0.f, j01 = L.fy ? o.xb : 0.f;
+                const float j10 = L.fx ? o.ya : 0.f, j11 = L.fy ? o.yb : 0.f;
+                D[s][0] = j00 * T0 + j01 * T2;
+                D[s][1] = j00 * T1 + j01 * T3;
+                D[s][2] = j10 * T0 + j11 * T2;
+                D[s][3] = j10 * T1 + j11 * T3;
+            }
+            float M0 = 1.f, M1 = 0.f, M2 = 0.f, M3 = 1.f;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const float c = hf * kB[s];
+                M0 = fmaf(c, D[s][0], M0);
+                M1 = fmaf(c, D[s][1], M1);
+                M2 = fmaf(c, D[s][2], M2);
+                M3 = fmaf(c, D[s][3], M3);
+            }
+            p.jac[(int64_t)k * p.n + i] = make_float4(M0, M1, M2, M3);
+        }
+    }
+}
+
+// Position adjoints through the steps, per point: lam_k = M_k^T lam_{k+1};
+// lam_{k+1} is stored over M_k for the field pass.
+__global__ __launch_bounds__(kThreads) void k_adj_scan(AdjParams p)
+{
+    int S;
+    if (!adj_ok(p, S)) return;
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= p.n) return;
+    float lx_ = (float)p.lam_xy[2 * (int64_t)i], ly_ = (float)p.lam_xy[2 * (int64_t)i + 1];
+    int k = S - 1;
+    // groups of four steps: the four loads do not depend on lam
+    for (; k >= 3; k -= 4) {
+        float4 M[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) M[u] = p.jac[(int64_t)(k - u) * p.n + i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            p.jac[(int64_t)(k - u) * p.n + i] = make_float4(lx_, ly_, 0.f, 0.f);
+            const float nx = fmaf(M[u].x, lx_, M[u].z * ly_);
+            const float ny = fmaf(M[u].y, lx_, M[u].w * ly_);
+            lx_ = nx;
+            ly_ = ny;
+        }
+    }
+    for (; k >= 0; --k) {
+        const float4 M = p.jac[(int64_t)k * p.n + i];
+        p.jac[(int64_t)k * p.n + i] = make_float4(lx_, ly_, 0.f, 0.f);
+        const float nx = fmaf(M.x, lx_, M.z * ly_);
+        const float ny = fmaf(M.y, lx_, M.w * ly_);
+        lx_ = nx;
+        ly_ = ny;
+    }
+    p.lam_xy[2 * (int64_t)i] = lx_;
+    p.lam_xy[2 * (int64_t)i + 1] = ly_;
+}
+
+// Field adjoints of every (point, step): with lam' = dL/dX_{k+1}, the reverse
+// sweep over the recomputed stages gives
+//   kbar_s = h b_s lam' + h sum_{j > s} a_js Ybar_j,  Ybar_s = Jv_s^T kbar_s,
+// and (v = J / rt, rt = (1 - t) rho_s + t rho_bar) each stage adds, at its
+// four nodes with bilinear weight w, w kbar / rt to the J adjoints,
+// -w (1 - t) (kbar . J) / rt^2 to rho_s and -w t (kbar . J) / rt^2 to rho_bar.
+// The steps of a tile are taken last to first, so that each point's stages
+// run monotonically backwards in time and its cell changes only where its
+// path crosses a cell edge.
+__global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
+{
+    __shared__ double s_rb[kThreads / 64];
+    __shared__ float win[(kThreads / 64) * kWaveFloats];
+    int S;
+    if (!adj_ok(p, S)) return;
+    const double rho_bar = *p.rho_bar;
+    const int n_pt_tiles = (p.n + kThreads - 1) / kThreads;
+    const int n_tiles = ((S + kChunk - 1) / kChunk) * n_pt_tiles;
+    const int lane = threadIdx.x & 63;
+    float *wwin = win + (threadIdx.x >> 6) * kWaveFloats;      // this wavefront's copies
+    float *cw = wwin + (lane % kCopies) * kWinFloats;           // this lane's copy
     double lrb = 0.0;
     Cell cc;
     cc.key = -1;
-    CellAcc ac;
-    ac.key = -1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) ac.g[q] = make_float3(0.f, 0.f, 0.f);
-    // start time of the last step; earlier ones by subtracting the steps
-    double tn = 0.0;
-    for (int s = 0; s < S - 1; ++s) tn += p.h[s];
-    for (int n = S - 1; n >= 0 && live; --n) {
-        const double h = p.h[n];
-        if (n < S - 1) tn -= h;
-        const float4 st = p.tape[(int64_t)n * p.n + i];
-        const float hf = (float)h;
-        float omt[6], tb[6];
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            const double ts = tn + kC[s] * h;
-            omt[s] = (float)(1.0 - ts);
-            tb[s] = (float)(ts * rho_bar);
+    for (int k = lane; k < kWaveFloats; k += 64) wwin[k] = 0.f;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        int step0, i;
+        tile_of(tile, n_pt_tiles, step0, i, false);
+        const bool live = i < p.n;
+        const int step1 = min(S, step0 + kChunk);
+        // window: the box of the cells of the wavefront's recorded states
+        int bx0 = INT32_MAX, by0 = INT32_MAX, bx1 = INT32_MIN, by1 = INT32_MIN;
+        for (int k = step0; k < step1 && live; ++k) {
+            const float4 st = p.tape[(int64_t)k * p.n + i];
+            const int cx = (int)fminf(fmaxf(st.x + 0.5f, 0.f), (float)(p.lx + 1));
+            const int cy = (int)fminf(fmaxf(st.y + 0.5f, 0.f), (float)(p.ly + 1));
+            bx0 = min(bx0, cx);
+            bx1 = max(bx1, cx);
+            by0 = min(by0, cy);
+            by1 = max(by1, cy);
         }
-        // forward: the stage lookups and velocities
-        Stage L[6];
-        float Kx[6], Ky[6];
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            float dx = 0.f, dy = 0.f;
-#pragma unroll
-            for (int q = 0; q < s; ++q) {
-                dx = fmaf(hf * kA[s][q], Kx[q], dx);
-                dy = fmaf(hf * kA[s][q], Ky[q], dy);
-            }
-            L[s] = lookup(st.x + (st.z + dx), st.y + (st.w + dy), p.lx, p.ly, p.pitch);
-            load_cell(p.fields, p.pitch, L[s].key, cc);
-            float vx[4], vy[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float r = 1.f / fmaf(cc.c[q].z, omt[s], tb[s]);
-                vx[q] = cc.c[q].x * r;
-                vy[q] = cc.c[q].y * r;
-            }
-            const float a = L[s].a, b = L[s].b;
-            const float x0 = fmaf(a, vx[1] - vx[0], vx[0]), x1 = fmaf(a, vx[3] - vx[2], vx[2]);
-            const float y0 = fmaf(a, vy[1] - vy[0], vy[0]), y1 = fmaf(a, vy[3] - vy[2], vy[2]);
-            Kx[s] = fmaf(b, x1 - x0, x0);
-            Ky[s] = fmaf(b, y1 - y0, y0);
+        for (int o = 32; o > 0; o >>= 1) {
+            bx0 = min(bx0, __shfl_xor(bx0, o, 64));
+            by0 = min(by0, __shfl_xor(by0, o, 64));
+            bx1 = max(bx1, __shfl_xor(bx1, o, 64));
+            by1 = max(by1, __shfl_xor(by1, o, 64));
         }
-        // reverse sweep
-        float Ybx[6], Yby[6];
-        float sumx = 0.f, sumy = 0.f;
+        if (bx0 > bx1 || by0 > by1) bx0 = bx1 = by0 = by1 = 0;
+        Region R;
+        R.wx0 = bx0 - 1;
+        R.wy0 = by0 - 1;
+        if (bx1 - bx0 + 3 > kWin) R.wx0 = (bx0 + bx1) / 2 - kWin / 2;
+        if (by1 - by0 + 3 > kWin) R.wy0 = (by0 + by1) / 2 - kWin / 2;
+        R.wx0 = max(0, min(R.wx0, p.lx + 2 - kWin));
+        R.wy0 = max(0, min(R.wy0, p.ly + 2 - kWin));
+        R.x0 = 0;
+        R.y0 = 0;
+        R.x1 = min(kWin, p.lx + 2 - R.wx0);
+        R.y1 = min(kWin, p.ly + 2 - R.wy0);
+
+        CellAcc A, B;
+        A.ci = B.ci = -1;
+        A.cj = B.cj = 0;
 #pragma unroll
-        for (int s = 5; s >= 0; --s) {
-            float kbx = hf * kB[s] * lx_, kby = hf * kB[s] * ly_;
+        for (int q = 0; q < 4; ++q) A.g[q] = B.g[q] = make_float3(0.f, 0.f, 0.f);
+        for (int k = step1 - 1; k >= step0 && live; --k) {
+            const double h = p.h[k], t0 = p.tstart[k];
+            const float hf = (float)h;
+            const float4 st = p.tape[(int64_t)k * p.n + i];
+            const float4 lam = p.jac[(int64_t)k * p.n + i];
+            float omt[6], tb[6];
 #pragma unroll
-            for (int j = s + 1; j < 6; ++j) {
-                kbx = fmaf(hf * kA[j][s], Ybx[j], kbx);
-                kby = fmaf(hf * kA[j][s], Yby[j], kby);
+            for (int s = 0; s < 6; ++s) {
+                const double ts = t0 + kC[s] * h;
+                omt[s] = (float)(1.0 - ts);
+                tb[s] = (float)(ts * rho_bar);
             }
-            const Stage &Ls = L[s];
-            load_cell(p.fields, p.pitch, Ls.key, cc);
-            float vx[4], vy[4], r[4];
+            Stage L[6];
+            float Kx[6], Ky[6];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                r[q] = 1.f / fmaf(cc.c[q].z, omt[s], tb[s]);
-                vx[q] = cc.c[q].x * r[q];
-                vy[q] = cc.c[q].y * r[q];
-            }
-            const float a = Ls.a, b = Ls.b;
-            const float dvx_da = (1.f - b) * (vx[1] - vx[0]) + b * (vx[3] - vx[2]);
-            const float dvy_da = (1.f - b) * (vy[1] - vy[0]) + b * (vy[3] - vy[2]);
-            const float dvx_db = (1.f - a) * (vx[2] - vx[0]) + a * (vx[3] - vx[1]);
-            const float dvy_db = (1.f - a) * (vy[2] - vy[0]) + a * (vy[3] - vy[1]);
-            Ybx[s] = Ls.fx ? kbx * dvx_da + kby * dvy_da : 0.f;
-            Yby[s] = Ls.fy ? kbx * dvx_db + kby * dvy_db : 0.f;
-            sumx += Ybx[s];
-            sumy += Yby[s];
-            if (Ls.key != ac.key) {
-                flush(p.lam_f, p.pitch, ac);
-                ac.key = Ls.key;
-            }
-            const float w[4] = {(1.f - a) * (1.f - b), a * (1.f - b), (1.f - a) * b, a * b};
-            const double ts = tn + kC[s] * h;
-            float rb = 0.f;
+            for (int s = 0; s < 6; ++s) {
+                float dx = 0.f, dy = 0.f;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float g = w[q] * r[q];
-                const float dot = kbx * vx[q] + kby * vy[q];     // (kbar . J) / rt
-                ac.g[q].x = fmaf(kbx, g, ac.g[q].x);
-                ac.g[q].y = fmaf(kby, g, ac.g[q].y);
-                ac.g[q].z = fmaf(-dot * g, omt[s], ac.g[q].z);
-                rb = fmaf(-dot, g, rb);
+                for (int q = 0; q < s; ++q) {
+                    dx = fmaf(hf * kA[s][q], Kx[q], dx);
+                    dy = fmaf(hf * kA[s][q], Ky[q], dy);
+                }
+                L[s] = lookup(st.x + (st.z + dx), st.y + (st.w + dy), p.lx, p.ly);
+                load_cell(p.fields, p.pitch, L[s].cj * p.pitch + L[s].ci, cc);
+                Local o;
+                local_velocity(cc, omt[s], tb[s], L[s].a, L[s].b, o);
+                Kx[s] = o.kx;
+                Ky[s] = o.ky;
             }
-            lrb += (double)rb * ts;
+            float Ybx[6], Yby[6];
+#pragma unroll
+            for (int s = 5; s >= 0; --s) {
+                float kbx = hf * kB[s] * lam.x, kby = hf * kB[s] * lam.y;
+#pragma unroll
+                for (int j = s + 1; j < 6; ++j) {
+                    kbx = fmaf(hf * kA[j][s], Ybx[j], kbx);
+                    kby = fmaf(hf * kA[j][s], Yby[j], kby);
+                }
+                const Stage &Ls = L[s];
+                load_cell(p.fields, p.pitch, Ls.cj * p.pitch + Ls.ci, cc);
+                Local o;
+                local_velocity(cc, omt[s], tb[s], Ls.a, Ls.b, o);
+                Ybx[s] = Ls.fx ? kbx * o.xa + kby * o.ya : 0.f;
+                Yby[s] = Ls.fy ? kbx * o.xb + kby * o.yb : 0.f;
+                const bool inA = Ls.ci == A.ci && Ls.cj == A.cj;
+                const bool inB = Ls.ci == B.ci && Ls.cj == B.cj;
+                if (!inA && !inB) {
+                    // a third cell: push the older sum, A becomes B
+                    push(p.lam_f, p.pitch, cw, R, B);
+                    B = A;
+                    A.ci = Ls.ci;
+                    A.cj = Ls.cj;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) A.g[q] = make_float3(0.f, 0.f, 0.f);
+                }
+                const float ma = (inA || !inB) ? 1.f : 0.f, mb = 1.f - ma;
+                const float a = Ls.a, b = Ls.b;
+                const float w[4] = {(1.f - a) * (1.f - b), a * (1.f - b), (1.f - a) * b, a * b};
+                float rb = 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float gq = w[q] * o.r[q];
+                    const float dot = kbx * o.vx[q] + kby * o.vy[q];     // (kbar . J) / rt
+                    const float gx = kbx * gq, gy = kby * gq, gz = -dot * gq * omt[s];
+                    A.g[q].x = fmaf(ma, gx, A.g[q].x);
+                    A.g[q].y = fmaf(ma, gy, A.g[q].y);
+                    A.g[q].z = fmaf(ma, gz, A.g[q].z);
+                    B.g[q].x = fmaf(mb, gx, B.g[q].x);
+                    B.g[q].y = fmaf(mb, gy, B.g[q].y);
+                    B.g[q].z = fmaf(mb, gz, B.g[q].z);
+                    rb = fmaf(-dot, gq, rb);
+                }
+                lrb += (double)rb * (t0 + kC[s] * h);
+            }
         }
-        lx_ += sumx;
-        ly_ += sumy;
-    }
-    if (live) {
-        flush(p.lam_f, p.pitch, ac);
-        p.lam_xy[2 * (int64_t)i] = lx_;
-        p.lam_xy[2 * (int64_t)i + 1] = ly_;
+        if (live) {
+            push(p.lam_f, p.pitch, cw, R, A);
+            push(p.lam_f, p.pitch, cw, R, B);
+        }
+        __syncthreads();
+        // the wavefront's window: sum the copies, add each touched node once,
+        // clear for the next tile
+        const int uw = R.x1 - R.x0, uh = R.y1 - R.y0;
+        for (int k = lane; k < uw * uh; k += 64) {
+            const int ry = k / uw;
+            const int wy = R.y0 + ry, wx = R.x0 + (k - ry * uw);
+            const int e = 3 * (wy * kWin + wx);
+            float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+            for (int c = 0; c < kCopies; ++c) {
+                float *w = wwin + c * kWinFloats + e;
+                gx += w[0];
+                gy += w[1];
+                gz += w[2];
+                w[0] = 0.f;
+                w[1] = 0.f;
+                w[2] = 0.f;
+            }
+            if (gx == 0.f && gy == 0.f && gz == 0.f) continue;
+            float *d = reinterpret_cast<float *>(p.lam_f + (int64_t)(R.wy0 + wy) * p.pitch + (R.wx0 + wx));
+            unsafeAtomicAdd(d, gx);
+            unsafeAtomicAdd(d + 1, gy);
+            unsafeAtomicAdd(d + 2, gz);
+        }
+        __syncthreads();
     }
     // workgroup sum of the rho_bar adjoint, one atomic per workgroup
     for (int o = 32; o > 0; o >>= 1) lrb += __shfl_xor(lrb, o, 64);
@@ -506,6 +797,8 @@ hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *r
                              double *lam_rho_bar)
 {
     if (tape->n == 0) return hipSuccess;
+    if (ctx->adj_t_cap < tape->cap || ctx->adj_jac_cap < (int64_t)tape->cap * tape->n)
+        return hipErrorInvalidValue;
     AdjParams p;
     p.fields = fields;
     p.lx = ctx->lx;
@@ -517,11 +810,22 @@ hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *r
     p.h = tape->h;
     p.count = tape->count;
     p.cap = tape->cap;
+    p.tstart = ctx->adj_t;
+    p.jac = ctx->adj_jac;
     p.lam_xy = lam_xy;
     p.lam_f = lam_fields;
     p.lam_rb = lam_rho_bar;
     p.status = ctx->d_status;
-    const int64_t blocks = (tape->n + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_advect_adj, dim3((unsigned)blocks), dim3(kThreads), 0, ctx->stream, p);
+    hipStream_t s = ctx->stream;
+    const int64_t pt_tiles = (tape->n + kThreads - 1) / kThreads;
+    const int64_t max_tiles = ((tape->cap + kChunk - 1) / kChunk) * pt_tiles;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(max_tiles, 8 * (int64_t)cus));
+    hipLaunchKernelGGL(k_adj_times, dim3(1), dim3(64), 0, s, p);
+    hipLaunchKernelGGL(k_adj_jacobian, dim3((unsigned)grid), dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL(k_adj_scan, dim3((unsigned)pt_tiles), dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL(k_adj_fields, dim3((unsigned)grid), dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
