@@ -8,6 +8,12 @@ t = 1, areas and relative errors.  Each step starts from the same resident
 input map (a device-to-device copy of the points, inside the timed region),
 so every step does the same work.  Inputs are resident in HBM before timing.
 
+Second part of the metric (fwd+bwd / fwd): on the L = 512, 50-region map,
+three rounds (blur widths 4, 2, 1) of the full cartogram (100 k vertices and
+all 512^2 grid nodes) without recording, against the same three rounds
+recorded plus the reverse pass that yields the gradient of the area loss
+with respect to the 50 region statistics.
+
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (the advection launch, timed with events on its stream) and the FP64 oracle
 timed on the host cores on a bounded sample.
@@ -27,6 +33,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per RK attempt of the advection launch on the L = 1024 workload,
+# from FETCH_SIZE and WRITE_SIZE counter runs calibrated on a copy of known
+# size, for the kernel source with this sha256 prefix; reported only while the
+# source is unchanged.
+ADVECT_TRAFFIC = {"bytes_per_attempt": 2.4114e10 / 274, "workload": "c3_L1024",
+                  "source_sha256": "bc23c1829c0fab44"}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -37,10 +50,13 @@ def parse():
     ap.add_argument("--sigma", type=float, default=4.0)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=64,
-                    help="the oracle advects 1/N of the points (other phases full size)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="time whole oracle iterations until this much work is timed")
     ap.add_argument("--loop", action="store_true",
                     help="also run the full loop to < 1%% error and report it")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the fwd+bwd / fwd measurement")
+    ap.add_argument("--grad-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -110,6 +126,10 @@ def main():
     # are read once (16 B per node); S attempts per launch
     bytes_per_attempt = 16.0 * P + 16.0 * L * L
     achieved = float(np.mean(bytes_per_attempt * attempts / (adv_ms * 1e-3)) / 1e9)
+    traffic = None
+    if args.workload == ADVECT_TRAFFIC["workload"] and _advect_sha() == ADVECT_TRAFFIC["source_sha256"]:
+        traffic = round(float(np.mean(ADVECT_TRAFFIC["bytes_per_attempt"] * attempts
+                                      / (adv_ms * 1e-3)) / 1e9), 1)
     # ALU view: ~6 stage evaluations per attempt, counted from the kernel's
     # instruction mix -- reported for context only
     result = {
@@ -136,7 +156,7 @@ def main():
                    "final_max_area_error": float(mx)},
         "roofline": {"kernel": "k_advect", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_attempt": bytes_per_attempt},
     }
 
@@ -155,40 +175,111 @@ def main():
         result["loop"] = {"rounds": rounds, "max_area_error": mxv,
                           "total_ms": round(1e3 * (time.perf_counter() - t_loop), 2)}
 
+    ctx.close()
+    if not args.no_grad:
+        result["grad"] = grad_leg(args, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(m, pts_h, args)
-    ctx.close()
     print(json.dumps(result), flush=True)
 
 
+def _advect_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1802_07625_amd", "csrc", "k_advect.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def grad_leg(args, dev, workload="c5_L512", rounds=3, max_steps=256):
+    """fwd = `rounds` FFB rounds (areas, density, flux, integration, areas);
+    fwd+bwd = the same rounds recorded on the tape plus ffb_backward for
+    dL/d(value) of a loss of the final areas.  Both start from the same
+    resident map; times are per whole run, averaged over --grad-steps."""
+    import torch
+    import synth
+    import paper_1802_07625_amd as ffb
+
+    m = synth.workload(workload)
+    L, V = m.lx, m.n_vertices
+    sigmas = [ffb.default_sigma(k) for k in range(rounds)]
+    out = {"workload": workload, "rounds": rounds, "sigmas": sigmas, "regions": m.n_regions,
+           "vertices": V}
+    for label, with_grid in (("", True), ("_vertices_only", False)):
+        parts = [m.xy.astype(np.float32)]
+        if with_grid:
+            parts.append(synth.grid_nodes(L, L))
+        pts0 = torch.as_tensor(np.concatenate(parts), device=dev)
+        pts = pts0.clone()
+        ctx = ffb.Context(L, L, max_points=pts.shape[0])
+        geom = ffb.Geometry.from_map(m, xy=pts[:V])
+        value = torch.as_tensor(m.value, dtype=torch.float64, device=dev)
+        g_area = torch.ones(m.n_regions, dtype=torch.float64, device=dev)
+
+        def fwd():
+            pts.copy_(pts0)
+            area, _, _ = ctx.area_error(geom, value)
+            for s in sigmas:
+                rho, _ = ctx.density(geom, value, area)
+                f, rb = ctx.flux(rho, s)
+                ctx.integrate(f, rb, pts, h_cap=0)
+                area, _, _ = ctx.area_error(geom, value)
+
+        def fwd_bwd():
+            pts.copy_(pts0)
+            ffb.FFBFunction.apply(value, ctx, geom, pts, sigmas, None, max_steps, None)
+            ctx.backward(g_area)
+
+        times = {}
+        for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd)):
+            for _ in range(2):
+                fn()
+            ctx.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.grad_steps):
+                fn()
+            torch.cuda.synchronize()
+            times[name] = 1e3 * (time.perf_counter() - t0) / args.grad_steps
+        ctx.sync()
+        ctx.close()
+        if with_grid:
+            out["points"] = int(pts0.shape[0])
+        out["fwd_ms" + label] = round(times["fwd"], 4)
+        out["fwd_bwd_ms" + label] = round(times["fwd_bwd"], 4)
+        out["ratio" + label] = round(times["fwd_bwd"] / times["fwd"], 3)
+    return out
+
+
 def cpu_baseline(m, pts_h, args):
-    """The FP64 oracle, untuned, on the host cores: every phase at full size
-    except the advection, which runs on a random 1/N of the points with the
-    oracle's own step control; its time is scaled by N."""
+    """The FP64 oracle, untuned, on the host cores: whole iterations of the
+    same workload (areas, raster, direct-sum transforms, advection of every
+    vertex and grid node with the oracle's own step control, areas), repeated
+    until about ten seconds of work have been timed."""
     import oracle
     cores = oracle.set_threads(0)
-    rng = np.random.default_rng(0)
-    N = args.cpu_sample
-    idx = rng.choice(pts_h.shape[0], pts_h.shape[0] // N, replace=False)
-    t = {}
-    t0 = time.perf_counter()
-    a = oracle.region_areas(m)
-    t["area"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rho, _ = oracle.density(m, m.value, a)
-    t["density"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    F = oracle.flux(rho, args.sigma)
-    t["flux"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r = oracle.integrate(F, pts_h[idx].astype(np.float64), oracle.IntegrateOpts(tol=args.tol))
-    t["advect_sample"] = time.perf_counter() - t0
-    est = 2 * t["area"] + t["density"] + t["flux"] + N * t["advect_sample"]
-    return {"value": round(1e3 * est, 1), "unit": "ms/iteration", "cores": cores,
-            "kind": "oracle",
-            "sample": (f"areas, raster and direct-sum transforms at full size; advection of "
-                       f"{len(idx)} random points (1/{N}) with the oracle's own control "
-                       f"({r.accepted} accepted, {r.rejected} rejected), time x{N}"),
+    runs, t = [], {}
+    while sum(runs) < args.cpu_seconds or not runs:
+        t0 = time.perf_counter()
+        a = oracle.region_areas(m)
+        t["area"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rho, _ = oracle.density(m, m.value, a)
+        t["density"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        F = oracle.flux(rho, args.sigma)
+        t["flux"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = oracle.integrate(F, pts_h.astype(np.float64), oracle.IntegrateOpts(tol=args.tol))
+        t["advect"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.region_areas(m, r.xy[:m.n_vertices])
+        t["area_after"] = time.perf_counter() - t0
+        runs.append(sum(t.values()))
+    return {"value": round(1e3 * float(np.mean(runs)), 1), "unit": "ms/iteration",
+            "cores": cores, "kind": "oracle",
+            "sample": (f"{len(runs)} whole iterations of the same workload at full size "
+                       f"({pts_h.shape[0]} points; the oracle's own step control took "
+                       f"{r.accepted} accepted and {r.rejected} rejected steps)"),
             "phases_s": {k: round(v, 3) for k, v in t.items()}}
 
 
