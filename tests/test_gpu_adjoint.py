@@ -349,3 +349,39 @@ def test_backward_max_steps_too_small_sets_status():
                                  [dev_f64(ref.schedules[0])])
     dv, _ = ctx.backward(torch.ones_like(area))
     assert ctx.sync(check=False) == ffb.FFB_E_NO_TAPE
+
+
+def _golden_c5():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_c5_L512.txt")
+    loss, sched, grad = None, {}, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            t = line.split()
+            if t[0] == "loss":
+                loss = float(t[1])
+            elif t[0] == "schedule":
+                sched[int(t[1])] = np.array([float(x) for x in t[2:]])
+            elif t[0] == "gradient":
+                grad = np.array([float(x) for x in t[1:]])
+    return loss, [sched[k] for k in sorted(sched)], grad
+
+
+@pytest.mark.parametrize("with_grid", [False, True])
+def test_backward_matches_oracle_golden_c5_full_size(with_grid):
+    """L = 512, 50 regions, 100 k vertices (and the 512^2 grid nodes): the
+    3-round loss gradient against the oracle's central differences stored in
+    tests/golden/grad_c5_L512.txt (written by make_grad_c5.py from the oracle
+    alone), the oracle's schedules replayed on the device."""
+    m = synth.workload("c5_L512")
+    loss_ref, sched, g_fd = _golden_c5()
+    loss, g = _gpu_gradient(m, m.density, SIGMAS, sched, with_grid=with_grid)
+    assert _rel(loss, loss_ref) < 1e-4
+    err = np.max(np.abs(g - g_fd)) / np.max(np.abs(g_fd))
+    print(f"[grad] c5 grid={with_grid} loss={loss:.9e} ref={loss_ref:.9e} max rel err={err:.3e}",
+          flush=True)
+    assert err < 1e-3
+    # scale invariance at full size
+    assert abs(np.dot(m.density, g)) < 1e-3 * np.sum(np.abs(m.density * g))
