@@ -284,6 +284,84 @@ int ffb_tape_clear(ffb_ctx *ctx);
  * device. */
 int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double *dL_dxy0);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent maps -- each with its own box and grid (lx[m] x ly[m]),
+ * vertices, rings, regions and statistics -- iterated together: every round
+ * of every map (areas, density, flux, integration, areas and errors, as
+ * above) runs inside one pass of batched launches, and each map keeps its
+ * own round counter (blur sigma0 * 2^-k in round k), its own adaptive step
+ * control and its own stopping rule (max |e_r| < stop_err, or max_rounds).
+ * Host-side descriptors are copied at creation; device arrays are
+ * referenced and must stay alive.  The batch runs on a stream of its own,
+ * ordered after the caller's stream at each call and before it at each
+ * return.  Device-side errors set the batch's sticky status. */
+typedef struct ffb_batch ffb_batch;
+
+typedef struct {
+    int32_t n_maps;
+    const int32_t *lx, *ly;           /* (host) [n_maps] grid sizes, powers of two in [8, 1024];
+                                         at most 8 distinct lx in one batch */
+    const int64_t *point_offsets;     /* (host) [n_maps + 1]: map m advects points
+                                         [point_offsets[m], point_offsets[m+1])           */
+    const int64_t *n_vertices;        /* (host) [n_maps]: the first n_vertices[m] of them
+                                         are its polygon vertices                           */
+    const int32_t *ring_offsets_map;  /* (host) [n_maps + 1]: map m owns rings [.., ..)    */
+    const int32_t *region_offsets;    /* (host) [n_maps + 1]: map m owns regions [.., ..)  */
+    ffb_geometry geometry;            /* all maps: n_vertices = total points, ring_vidx are
+                                         global point indices (into the owning map's range),
+                                         ring_region global region ids; xy is ignored      */
+    float *points;                    /* device [total points][2], in/out, advected in place */
+    const double *value;              /* device [total regions] statistics, > 0             */
+} ffb_batch_desc;
+
+typedef struct {
+    double stop_err;                  /* stop a map once max |e_r| < stop_err (e.g. 0.01) */
+    int32_t max_rounds;               /* ... or after this many rounds                     */
+    double sigma0;                    /* blur of round k = sigma0 * 2^-k cells (e.g. 4)    */
+    ffb_integrate_opts integrate;     /* step controller of every integration (its
+                                         n_replay / replay_h are ignored)                  */
+    int32_t use_graph;                /* 1: capture one iteration in a HIP graph and replay it */
+} ffb_batch_opts;
+
+/* Create a batch (allocates its workspace; computes the initial areas and
+ * sets every map active at round 0).  hip_stream is the caller's stream. */
+int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream);
+int ffb_batch_destroy(ffb_batch *b);
+const char *ffb_batch_last_error(const ffb_batch *b);
+
+/* Launch shapes: the workgroup size of the transform passes (64, 128, 256
+ * or 512; 0 = keep) for every grid-size class and of the integration (256,
+ * 512 or 1024; 0 = keep).  Results do not depend on them. */
+int ffb_batch_set_shapes(ffb_batch *b, int32_t fft_threads, int32_t advect_threads);
+/* (host outs) number of grid-size classes, their widths, transform
+ * workgroup size per class, integration workgroup size. */
+int ffb_batch_get_shapes(const ffb_batch *b, int32_t *n_classes, int32_t *widths,
+                         int32_t *fft_threads, int32_t *advect_threads);
+/* Time the candidate shapes on this batch (round-0 inputs, points left
+ * unchanged) and keep the fastest: per class for the transforms, one for
+ * the integration.  Waits for the device; resets the loop state. */
+int ffb_batch_autotune(ffb_batch *b, const ffb_batch_opts *opts);
+
+/* Every map active at round 0; areas from the current points (enqueued). */
+int ffb_batch_reset(ffb_batch *b);
+/* One round of every active map (enqueued).  replay_offsets (device
+ * [n_maps + 1]) and replay_h (device) optionally give each map's accepted
+ * steps, map m using replay_h[replay_offsets[m] .. replay_offsets[m+1]);
+ * with them the step is issued directly, without the graph. */
+int ffb_batch_step(ffb_batch *b, const ffb_batch_opts *opts, const int32_t *replay_offsets,
+                   const double *replay_h);
+/* Reset, then rounds until no map is active (one 4-byte device read per
+ * round); *iterations (host) receives the rounds issued.  Waits; returns the
+ * sticky status. */
+int ffb_batch_run(ffb_batch *b, const ffb_batch_opts *opts, int32_t *iterations);
+/* Waits, then copies per-map results: rounds (host [n_maps]) taken when the
+ * map stopped (0 while still active), max_err (host [n_maps]) after its
+ * last round, stats (host [n_maps][4]) of its last integration, area
+ * (device [total regions]) the last areas; any may be NULL.  Returns the
+ * sticky status. */
+int ffb_batch_results(ffb_batch *b, int32_t *rounds, double *max_err, int32_t *stats,
+                      double *area);
+
 #ifdef __cplusplus
 }
 #endif

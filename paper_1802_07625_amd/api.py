@@ -46,6 +46,19 @@ class FFBIntegrateOpts(ctypes.Structure):
                 ("replay_h", ctypes.c_void_p)]
 
 
+class FFBBatchDesc(ctypes.Structure):
+    _fields_ = [("n_maps", ctypes.c_int32), ("lx", ctypes.c_void_p), ("ly", ctypes.c_void_p),
+                ("point_offsets", ctypes.c_void_p), ("n_vertices", ctypes.c_void_p),
+                ("ring_offsets_map", ctypes.c_void_p), ("region_offsets", ctypes.c_void_p),
+                ("geometry", FFBGeometry), ("points", ctypes.c_void_p), ("value", ctypes.c_void_p)]
+
+
+class FFBBatchOpts(ctypes.Structure):
+    _fields_ = [("stop_err", ctypes.c_double), ("max_rounds", ctypes.c_int32),
+                ("sigma0", ctypes.c_double), ("integrate", FFBIntegrateOpts),
+                ("use_graph", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -82,11 +95,25 @@ def lib():
         L.ffb_tape_end.argtypes = [vp]
         L.ffb_tape_clear.argtypes = [vp]
         L.ffb_backward.argtypes = [vp, vp, vp, vp]
+        B, BO = ctypes.POINTER(FFBBatchDesc), ctypes.POINTER(FFBBatchOpts)
+        L.ffb_batch_create.argtypes = [ctypes.POINTER(vp), B, vp]
+        L.ffb_batch_destroy.argtypes = [vp]
+        L.ffb_batch_last_error.argtypes = [vp]
+        L.ffb_batch_last_error.restype = ctypes.c_char_p
+        L.ffb_batch_set_shapes.argtypes = [vp, i32, i32]
+        L.ffb_batch_get_shapes.argtypes = [vp, vp, vp, vp, vp]
+        L.ffb_batch_autotune.argtypes = [vp, BO]
+        L.ffb_batch_reset.argtypes = [vp]
+        L.ffb_batch_step.argtypes = [vp, BO, vp, vp]
+        L.ffb_batch_run.argtypes = [vp, BO, vp]
+        L.ffb_batch_results.argtypes = [vp, vp, vp, vp, vp]
         for f in ("ffb_create", "ffb_destroy", "ffb_sync", "ffb_reset_status", "ffb_area_error",
                   "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option",
                   "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
                   "ffb_integrate_adj", "ffb_tape_begin", "ffb_tape_end", "ffb_tape_clear",
-                  "ffb_backward"):
+                  "ffb_backward", "ffb_batch_create", "ffb_batch_destroy", "ffb_batch_set_shapes",
+                  "ffb_batch_get_shapes", "ffb_batch_autotune", "ffb_batch_reset",
+                  "ffb_batch_step", "ffb_batch_run", "ffb_batch_results"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -466,3 +493,152 @@ class FFBFunction(torch.autograd.Function):
     def backward(fctx, g_area):
         dval, _ = fctx.ffb.backward(g_area.detach().to(torch.float64).contiguous())
         return dval, None, None, None, None, None, None, None
+
+
+# ---------------------------------------------------------------- batches
+@dataclass
+class BatchOpts:
+    stop_err: float = 0.01
+    max_rounds: int = 30
+    sigma0: float = 4.0
+    integrate: IntegrateOpts | None = None
+    use_graph: bool = True
+
+    def struct(self) -> FFBBatchOpts:
+        io = (self.integrate or IntegrateOpts()).struct()
+        return FFBBatchOpts(self.stop_err, self.max_rounds, self.sigma0, io, int(self.use_graph))
+
+
+class Batch:
+    """Many maps iterated together on the device (ffb_batch_*).
+
+    ``maps`` are objects with lx, ly, xy [V, 2], ring_offsets, ring_vidx,
+    ring_region (per-map indices), n_regions and value; ``extra_points``
+    optionally gives further points per map (e.g. its grid nodes), advected
+    after its vertices.  The packed points live in ``self.points``."""
+
+    def __init__(self, maps, extra_points=None, device="cuda", stream=None):
+        import numpy as np
+        M = len(maps)
+        dev = torch.device(device)
+        pts, voff, nvert, roff, goff = [], [0], [], [0], [0]
+        offs, vidx, reg, vals = [0], [], [], []
+        for k, m in enumerate(maps):
+            p = np.asarray(m.xy, dtype=np.float32).reshape(-1, 2)
+            extra = None if extra_points is None else extra_points[k]
+            if extra is not None:
+                p = np.concatenate([p, np.asarray(extra, dtype=np.float32).reshape(-1, 2)])
+            base = voff[-1]
+            pts.append(p)
+            nvert.append(int(np.asarray(m.xy).reshape(-1, 2).shape[0]))
+            o = np.asarray(m.ring_offsets, dtype=np.int64)
+            offs.extend((o[1:] + offs[-1]).tolist())
+            vidx.append(np.asarray(m.ring_vidx, dtype=np.int64) + base)
+            reg.append(np.asarray(m.ring_region, dtype=np.int64) + roff[-1])
+            vals.append(np.asarray(m.value, dtype=np.float64))
+            voff.append(base + p.shape[0])
+            roff.append(roff[-1] + int(m.n_regions))
+            goff.append(goff[-1] + len(o) - 1)
+        self.n_maps = M
+        self.point_offsets = np.array(voff, dtype=np.int64)
+        self.region_offsets = np.array(roff, dtype=np.int32)
+        self.ring_offsets_map = np.array(goff, dtype=np.int32)
+        self.n_vertices = np.array(nvert, dtype=np.int64)
+        self.lx = np.array([m.lx for m in maps], dtype=np.int32)
+        self.ly = np.array([m.ly for m in maps], dtype=np.int32)
+        t32 = lambda a: torch.as_tensor(np.asarray(a, dtype=np.int32), device=dev).contiguous()
+        self.points = torch.as_tensor(np.concatenate(pts), device=dev).contiguous()
+        self.ring_offsets = t32(offs)
+        self.ring_vidx = t32(np.concatenate(vidx))
+        self.ring_region = t32(np.concatenate(reg))
+        self.value = torch.as_tensor(np.concatenate(vals), device=dev).contiguous()
+        self.n_regions = int(roff[-1])
+        g = FFBGeometry(n_vertices=int(voff[-1]), xy=None, n_rings=int(goff[-1]),
+                        ring_offsets=_ptr(self.ring_offsets, torch.int32),
+                        ring_vidx=_ptr(self.ring_vidx, torch.int32),
+                        ring_region=_ptr(self.ring_region, torch.int32),
+                        n_regions=self.n_regions, n_entries=self.ring_vidx.numel())
+        hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._host = (self.lx, self.ly, self.point_offsets, self.n_vertices,
+                      self.ring_offsets_map, self.region_offsets)
+        d = FFBBatchDesc(M, hp(self.lx), hp(self.ly), hp(self.point_offsets), hp(self.n_vertices),
+                         hp(self.ring_offsets_map), hp(self.region_offsets), g,
+                         _ptr(self.points, torch.float32), _ptr(self.value, torch.float64))
+        h = ctypes.c_void_p()
+        code = lib().ffb_batch_create(ctypes.byref(h), ctypes.byref(d), _stream_handle(stream))
+        if code != FFB_OK:
+            raise FFBError(code, "ffb_batch_create")
+        self.handle = h
+
+    def _check(self, code, what):
+        if code != FFB_OK:
+            raise FFBError(code, f"{what}: {lib().ffb_batch_last_error(self.handle).decode()}")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib().ffb_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_shapes(self, fft_threads: int = 0, advect_threads: int = 0):
+        self._check(lib().ffb_batch_set_shapes(self.handle, fft_threads, advect_threads),
+                    "ffb_batch_set_shapes")
+
+    def shapes(self):
+        import numpy as np
+        n = ctypes.c_int32()
+        w = np.zeros(8, np.int32)
+        f = np.zeros(8, np.int32)
+        a = ctypes.c_int32()
+        self._check(lib().ffb_batch_get_shapes(self.handle, ctypes.byref(n),
+                                               w.ctypes.data_as(ctypes.c_void_p),
+                                               f.ctypes.data_as(ctypes.c_void_p), ctypes.byref(a)),
+                    "ffb_batch_get_shapes")
+        return {"widths": w[:n.value].tolist(), "fft_threads": f[:n.value].tolist(),
+                "advect_threads": a.value}
+
+    def autotune(self, opts: BatchOpts | None = None):
+        o = (opts or BatchOpts()).struct()
+        self._check(lib().ffb_batch_autotune(self.handle, ctypes.byref(o)), "ffb_batch_autotune")
+        return self.shapes()
+
+    def reset(self):
+        self._check(lib().ffb_batch_reset(self.handle), "ffb_batch_reset")
+
+    def step(self, opts: BatchOpts | None = None, replay=None):
+        """One round of every active map; ``replay`` = (offsets [M+1] int32,
+        steps float64) device tensors of per-map accepted steps."""
+        o = (opts or BatchOpts()).struct()
+        ro, rh = (None, None) if replay is None else replay
+        self._check(lib().ffb_batch_step(self.handle, ctypes.byref(o),
+                                         _ptr(ro, torch.int32, name="replay_offsets"),
+                                         _ptr(rh, torch.float64, name="replay_h")),
+                    "ffb_batch_step")
+
+    def run(self, opts: BatchOpts | None = None) -> int:
+        o = (opts or BatchOpts()).struct()
+        it = ctypes.c_int32()
+        self._check(lib().ffb_batch_run(self.handle, ctypes.byref(o), ctypes.byref(it)),
+                    "ffb_batch_run")
+        return it.value
+
+    def results(self):
+        import numpy as np
+        M = self.n_maps
+        rounds = np.zeros(M, np.int32)
+        mx = np.zeros(M, np.float64)
+        stats = np.zeros((M, 4), np.int32)
+        area = torch.empty(self.n_regions, dtype=torch.float64, device=self.points.device)
+        self._check(lib().ffb_batch_results(self.handle, rounds.ctypes.data_as(ctypes.c_void_p),
+                                            mx.ctypes.data_as(ctypes.c_void_p),
+                                            stats.ctypes.data_as(ctypes.c_void_p),
+                                            _ptr(area, torch.float64)), "ffb_batch_results")
+        return rounds, mx, stats, area
+
+    def map_points(self, m: int) -> torch.Tensor:
+        return self.points[int(self.point_offsets[m]):int(self.point_offsets[m + 1])]

@@ -130,6 +130,77 @@ hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *r
                              const advect_tape *tape, double *lam_xy, float4 *lam_fields,
                              double *lam_rho_bar);
 
+// ---------------------------------------------------------------- batches
+// Device view of a batch of maps, passed by value to the batched kernels.
+// Map m owns grid planes at plane_off[m] ([ly][lx] floats), fields at
+// field_off[m] ([(ly+2)][(lx+2)] float4), coverage deltas at acc_off[m]
+// ([ly][lx+1] doubles), points [point_off[m], point_off[m+1]) of which the
+// first n_vert[m] are its vertices, and regions [region_off[m],
+// region_off[m+1]).  Rings and regions use global indices.
+struct batch_view {
+    int32_t n_maps;
+    const int32_t *lx, *ly;
+    const int64_t *plane_off, *field_off, *acc_off, *point_off, *n_vert;
+    const int32_t *region_off;
+    const int32_t *ring_map;       // [G] map of each ring
+    int32_t *active;               // [M] 1 while the map iterates
+    int32_t *round;                // [M] 0-based round index of the next iteration
+    int32_t *rounds_done;          // [M] rounds taken when the map stopped
+    double *max_err;               // [M] max |e_r| after the last iteration
+    double sigma0;                 // blur of round k = sigma0 * 2^-k
+    double stop_err;               // stop when max |e_r| < stop_err
+    int32_t max_rounds;
+};
+
+// Launch tables: entry k of a table names (map, index) for block k.
+struct batch_tables {
+    const int2 *rows;              // (map, j0) for every even row j0 of every map
+    const int2 *cols;              // (map, m0) for every even column m0
+    const int4 *tiles_a;           // (map, c0, r0, -) tiles of [ly][lx] -> [lx][ly]
+    const int4 *tiles_b;           // (map, c0, r0, -) tiles of [lx][ly] -> [ly][lx]
+    int32_t n_rows, n_cols, n_tiles_a, n_tiles_b, n_scan_rows;
+    const int2 *scan_rows;         // (map, j) for every row
+};
+
+// Batched launchers (k_area.hip, k_raster.hip, k_flux.hip, k_advect.hip).
+hipError_t launch_ring_areas(hipStream_t s, const ffb_geometry *g, double *area, int32_t *status);
+hipError_t launch_batch_finalize(hipStream_t s, const batch_view &bv, const double *value,
+                                 const double *area, double *err, int32_t *n_active,
+                                 int32_t *status);
+hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch_tables &bt,
+                                const ffb_geometry *g, const double *value, const double *area,
+                                double *w_region, double *rho_pad, double *acc, int64_t acc_total,
+                                float *rho, int32_t *status);
+// Row and column tables are sorted by grid width; class c owns entries
+// [row_beg[c], row_beg[c+1]) and [col_beg[c], col_beg[c+1]) and its passes
+// run with threads[c] lanes per workgroup.
+constexpr int kBatchMaxClasses = 8;
+struct batch_fft_plan {
+    int n_classes;
+    int32_t row_beg[kBatchMaxClasses + 1], col_beg[kBatchMaxClasses + 1];
+    int threads[kBatchMaxClasses];
+};
+hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
+                             const batch_fft_plan &plan, const float2 *tw1024,
+                             const float2 *tq1024, float *rho, float *t1, float *t2, float *pa,
+                             float *pb, float *pc, float4 *fields, double *rho_bar,
+                             int32_t *status);
+struct batch_advect_args {
+    const float4 *fields;
+    const double *rho_bar;         // [M]
+    float2 *xy;
+    float4 *st0, *st1;
+    float2 *kv0, *kv1;
+    int32_t *stats;                // [M][4]
+    const int32_t *order;          // [M] map of block b (largest first)
+    const int32_t *replay_off;     // [M + 1] or NULL
+    const double *replay_h;
+    double tol, h0, safety, fac_min, fac_max, h_min;
+    int32_t max_attempts;
+};
+hipError_t launch_batch_advect(hipStream_t s, const batch_view &bv, const batch_advect_args &a,
+                               int threads, int32_t *status);
+
 // ---------------------------------------------------------------- device
 // Record the first error code in the sticky status word.
 __device__ inline void set_status(int32_t *status, int32_t code)

@@ -512,6 +512,142 @@ inline int64_t lds_bytes_for(int nb, int64_t n)
     return chunk * (int64_t)sizeof(float4);
 }
 
+// ------------------------------------------------------------- batched
+// Many maps, one workgroup per map (largest maps first): the same stages,
+// controller and compensated state as k_advect, with the error maximum
+// reduced over the workgroup only.  No workgroup waits for another, so the
+// launch needs no co-residency and can be captured in a graph.  State and
+// first-stage velocities live in HBM, double-buffered per point.
+template <int NT>
+__global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args a,
+                                                int32_t *status)
+{
+    __shared__ float s_err[NT / 64];
+    const int m = a.order[blockIdx.x];
+    if (!bv.active[m]) return;
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    const double rho_bar = a.rho_bar[m];
+    const int lx = bv.lx[m], ly = bv.ly[m];
+    const Field F{a.fields + bv.field_off[m], lx, ly, lx + 2};
+    const int64_t p0 = bv.point_off[m];
+    const int npts = (int)(bv.point_off[m + 1] - p0);
+    const int n_replay = a.replay_off ? a.replay_off[m + 1] - a.replay_off[m] : 0;
+    const double *replay_h = a.replay_off ? a.replay_h + a.replay_off[m] : nullptr;
+    const bool replay = n_replay > 0;
+    float4 *st0 = a.st0 + p0, *st1 = a.st1 + p0;
+    float2 *kv0 = a.kv0 + p0, *kv1 = a.kv1 + p0;
+    float2 *xy = a.xy + p0;
+
+    for (int k = threadIdx.x; k < npts; k += NT) {
+        const float2 y = xy[k];
+        st0[k] = make_float4(y.x, y.y, 0.f, 0.f);
+        CellCache cc;
+        cc.key = -1;
+        const Axis ax = make_axis(y.x, 0.f, lx), ay = make_axis(y.y, 0.f, ly);
+        kv0[k] = velocity(F, ax, ay, 0.f, 0.f, 1.0f, 0.0f, cc);
+    }
+
+    double t = 0.0, h = replay ? replay_h[0] : a.h0;
+    int last_rejected = 0, acc = 0, rej = 0, attempt = 0, cur = 0;
+    int32_t final_status = 0;
+    while (t < 1.0) {
+        if (attempt >= a.max_attempts || (replay && acc >= n_replay)) {
+            final_status = FFB_E_MAX_ATTEMPTS;
+            break;
+        }
+        bool final_step;
+        if (replay) {
+            h = replay_h[acc];
+            final_step = acc == n_replay - 1;
+        } else {
+            final_step = h >= 1.0 - t;
+            if (final_step) h = 1.0 - t;
+        }
+        const double rh = 1.0 / h;
+        const float hf = uniform((float)h), rhf = uniform((float)rh);
+        float omh[7], tbh[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double ts = t + kC[q] * h;
+            omh[q] = uniform((float)((1.0 - ts) * rh));
+            tbh[q] = uniform((float)(ts * rho_bar * rh));
+        }
+        const float4 *stc = cur ? st1 : st0;
+        const float2 *kvc = cur ? kv1 : kv0;
+        float4 *stn = cur ? st0 : st1;
+        float2 *kvn = cur ? kv0 : kv1;
+        float emax = 0.0f;
+        for (int k = threadIdx.x; k < npts; k += NT) {
+            const float4 s0 = stc[k];
+            const Axis ax = make_axis(s0.x, s0.z, lx), ay = make_axis(s0.y, s0.w, ly);
+            CellCache cc;
+            cc.key = -1;
+            const float2 k1 = kvc[k];
+            const float2 q1 = make_float2(hf * k1.x, hf * k1.y);
+            float ix, iy, ex, ey;
+            float2 q7;
+            dp_stages(F, ax, ay, q1, omh, tbh, cc, ix, iy, q7, ex, ey);
+            float sx, ex2, sy, ey2;
+            two_sum(s0.x, ix, sx, ex2);
+            two_sum(s0.y, iy, sy, ey2);
+            stn[k] = make_float4(sx, sy, s0.z + ex2, s0.w + ey2);
+            const float poison = (ex + ey) + (sx + sy);
+            const float e = (poison - poison == 0.0f) ? fmaxf(fabsf(ex), fabsf(ey))
+                                                      : __builtin_inff();
+            emax = fmaxf(emax, e);
+            kvn[k] = make_float2(q7.x * rhf, q7.y * rhf);
+        }
+        emax = wave_max(emax);
+        if ((threadIdx.x & 63) == 0) s_err[threadIdx.x >> 6] = emax;
+        __syncthreads();
+        float gmax = s_err[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) gmax = fmaxf(gmax, s_err[w]);
+        __syncthreads();
+        const double err = (double)gmax;
+        ++attempt;
+        if (!(err < __builtin_huge_val())) {
+            final_status = FFB_E_NONFINITE;
+            break;
+        }
+        if (replay || err <= a.tol) {
+            cur ^= 1;
+            ++acc;
+            t = final_step ? 1.0 : t + h;
+            if (!replay) {
+                double fac = (err == 0.0) ? a.fac_max : a.safety * pow(err / a.tol, -0.2);
+                fac = fmin(fmax(fac, a.fac_min), a.fac_max);
+                if (last_rejected && fac > 1.0) fac = 1.0;
+                h *= fac;
+                last_rejected = 0;
+            }
+        } else {
+            ++rej;
+            h *= fmax(a.fac_min, a.safety * pow(err / a.tol, -0.2));
+            last_rejected = 1;
+        }
+        if (!replay && t < 1.0 && h < a.h_min) {
+            final_status = FFB_E_STEP_UNDERFLOW;
+            break;
+        }
+    }
+    if (final_status == 0) {
+        const float4 *stc = cur ? st1 : st0;
+        for (int k = threadIdx.x; k < npts; k += NT) {
+            const float4 q = stc[k];
+            xy[k] = make_float2(q.x + q.z, q.y + q.w);
+        }
+    }
+    if (threadIdx.x == 0) {
+        int32_t *st = a.stats + 4 * (int64_t)m;
+        st[0] = acc;
+        st[1] = rej;
+        st[2] = attempt;
+        st[3] = final_status;
+        if (final_status) set_status(status, final_status);
+    }
+}
+
 }  // namespace
 
 int advect_max_blocks(int *out)
@@ -589,4 +725,24 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     }
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_advect<kGlobalState>),
                                       dim3(blocks), dim3(kThreads), args, 0, ctx->stream);
+}
+
+hipError_t launch_batch_advect(hipStream_t s, const batch_view &bv, const batch_advect_args &a,
+                               int threads, int32_t *status)
+{
+    const dim3 grid(bv.n_maps);
+    switch (threads) {
+    case 256:
+        hipLaunchKernelGGL(kb_advect<256>, grid, dim3(256), 0, s, bv, a, status);
+        break;
+    case 512:
+        hipLaunchKernelGGL(kb_advect<512>, grid, dim3(512), 0, s, bv, a, status);
+        break;
+    case 1024:
+        hipLaunchKernelGGL(kb_advect<1024>, grid, dim3(1024), 0, s, bv, a, status);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }

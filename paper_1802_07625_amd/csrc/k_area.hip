@@ -151,6 +151,83 @@ __global__ __launch_bounds__(kFinThreads) void k_area_finalize(
     }
 }
 
+// Batched end of an iteration, one workgroup per map: sums over the map's
+// regions, e_r = A_r / T_r - 1, max |e_r|, and the map's loop state (stop
+// below the threshold or at the round cap, else one more round).  Maps that
+// already stopped keep their state.
+__global__ __launch_bounds__(kFinThreads) void kb_finalize(batch_view bv,
+                                                           const double *__restrict__ value,
+                                                           const double *__restrict__ area,
+                                                           double *__restrict__ err,
+                                                           int32_t *status)
+{
+    __shared__ double lds[kFinThreads / 64 + 1];
+    const int m = blockIdx.x;
+    const int32_t r0 = bv.region_off[m], r1 = bv.region_off[m + 1];
+    const bool was_active = bv.active[m] != 0;
+    double sa = 0.0, sv = 0.0;
+    for (int32_t r = r0 + threadIdx.x; r < r1; r += kFinThreads) {
+        sa += area[r];
+        sv += value[r];
+    }
+    sa = block_sum<kFinThreads>(sa, lds);
+    sv = block_sum<kFinThreads>(sv, lds);
+    const double scale = sa / sv;
+    double mxd = 0.0;
+    int nan = 0;
+    for (int32_t r = r0 + threadIdx.x; r < r1; r += kFinThreads) {
+        const double e = area[r] / (value[r] * scale) - 1.0;
+        err[r] = e;
+        const double a = fabs(e);
+        if (isnan(a)) nan = 1;
+        else if (a > mxd) mxd = a;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mxd = fmax(mxd, __shfl_xor(mxd, o, 64));
+        nan |= __shfl_xor(nan, o, 64);
+    }
+    __shared__ double m_lds[kFinThreads / 64];
+    __shared__ int n_lds[kFinThreads / 64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) { m_lds[w] = mxd; n_lds[w] = nan; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = 0.0;
+        int anynan = 0;
+        for (int i = 0; i < kFinThreads / 64; ++i) { mx = fmax(mx, m_lds[i]); anynan |= n_lds[i]; }
+        if (anynan) {
+            mx = (double)NAN;
+            set_status(status, FFB_E_NONFINITE);
+        }
+        if (was_active) {
+            bv.max_err[m] = mx;
+            const int32_t k = bv.round[m] + 1;           // rounds taken so far
+            if (mx < bv.stop_err || k >= bv.max_rounds || anynan) {
+                bv.active[m] = 0;
+                bv.rounds_done[m] = k;
+            } else {
+                bv.round[m] = k;
+            }
+        }
+    }
+}
+
+// Number of maps still iterating.
+__global__ __launch_bounds__(256) void kb_count_active(const int32_t *__restrict__ active, int n,
+                                                       int32_t *__restrict__ out)
+{
+    __shared__ int lds[256];
+    int c = 0;
+    for (int i = threadIdx.x; i < n; i += 256) c += active[i] != 0;
+    lds[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lds[0];
+}
+
 }  // namespace
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
@@ -185,5 +262,26 @@ hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *
     }
     hipLaunchKernelGGL(k_area_finalize, dim3(1), dim3(kFinThreads), 0, ctx->stream, value,
                        area, g->n_regions, err, max_abs_err, ctx->d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_areas(hipStream_t s, const ffb_geometry *g, double *area, int32_t *status)
+{
+    hipError_t e = launch_fill_f64(area, g->n_regions, 0.0, s);
+    if (e != hipSuccess || g->n_rings == 0) return e;
+    hipLaunchKernelGGL(k_ring_area, dim3(g->n_rings), dim3(kAreaThreads), 0, s,
+                       reinterpret_cast<const float2 *>(g->xy), g->n_vertices, g->ring_offsets,
+                       g->ring_vidx, g->ring_region, g->n_rings, g->n_regions, g->n_entries, area,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(hipStream_t s, const batch_view &bv, const double *value,
+                                 const double *area, double *err, int32_t *n_active,
+                                 int32_t *status)
+{
+    hipLaunchKernelGGL(kb_finalize, dim3(bv.n_maps), dim3(kFinThreads), 0, s, bv, value, area,
+                       err, status);
+    hipLaunchKernelGGL(kb_count_active, dim3(1), dim3(256), 0, s, bv.active, bv.n_maps, n_active);
     return hipGetLastError();
 }

@@ -64,9 +64,12 @@ __device__ float2 *fft_lds(float2 *a, float2 *b, int N, const float2 *tw, bool i
     return a;
 }
 
-__device__ inline void load_twiddles(float2 *tw_lds, const float2 *__restrict__ tw, int N)
+// `s`: stride into a table built for a longer transform (tables for length
+// 1024 serve every power of two N <= 1024 with s = 1024 / N).
+__device__ inline void load_twiddles(float2 *tw_lds, const float2 *__restrict__ tw, int N,
+                                     int s = 1)
 {
-    for (int k = threadIdx.x; k < (N >> 1); k += blockDim.x) tw_lds[k] = tw[k];
+    for (int k = threadIdx.x; k < (N >> 1); k += blockDim.x) tw_lds[k] = tw[k * s];
 }
 
 // Makhoul reordering position of input element i: v[i/2] for even i,
@@ -77,7 +80,7 @@ __device__ inline int mk_pos(int i, int N) { return (i & 1) ? (N - 1 - (i >> 1))
 // Makhoul order; leaves X_a[m], X_b[m] (unnormalised: sum x_i cos(pi m (i+1/2)/N))
 // in `out` as float2 pairs.
 __device__ void dct2_pair(float2 *a, float2 *b, float2 *out, int N, const float2 *tw,
-                          const float2 *__restrict__ tq)
+                          const float2 *__restrict__ tq, int qs = 1)
 {
     float2 *Z = fft_lds(a, b, N, tw, false);
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
@@ -86,7 +89,7 @@ __device__ void dct2_pair(float2 *a, float2 *b, float2 *out, int N, const float2
         // Va = (Zm + conj Zc)/2, Vb = (Zm - conj Zc)/(2i)
         const float2 va = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
         const float2 vb = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
-        const float2 q = tq[m];      // exp(-i pi m / (2N))
+        const float2 q = tq[m * qs];      // exp(-i pi m / (2N))
         out[m] = make_float2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
     }
     __syncthreads();
@@ -98,14 +101,14 @@ __device__ void dct2_pair(float2 *a, float2 *b, float2 *out, int N, const float2
 //   X_0 = c_0, X_m = c_m / 2, W_m = exp(i pi m/(2N)) (X_m - i X_{N-m}), X_N = 0,
 // and the pair is packed as W_a + i W_b.
 template <typename F>
-__device__ void dct3_input(float2 *a, int N, const float2 *__restrict__ tq, F cpair)
+__device__ void dct3_input(float2 *a, int N, const float2 *__restrict__ tq, F cpair, int qs = 1)
 {
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
         float2 xm = cpair(m);
         if (m) { xm.x *= 0.5f; xm.y *= 0.5f; }
         float2 xr = make_float2(0.f, 0.f);
         if (m) { xr = cpair(N - m); xr.x *= 0.5f; xr.y *= 0.5f; }
-        const float2 q = tq[m];
+        const float2 q = tq[m * qs];
         const float cr = q.x, ci = -q.y;          // exp(+i pi m/(2N))
         // Wa = (cr + i ci)(xm.x - i xr.x), Wb likewise with .y
         const float war = cr * xm.x + ci * xr.x, wai = ci * xm.x - cr * xr.x;
@@ -119,14 +122,13 @@ __device__ void dct3_input(float2 *a, int N, const float2 *__restrict__ tq, F cp
 __device__ inline float2 dct3_output(const float2 *v, int i, int N) { return v[mk_pos(i, N)]; }
 
 // ------------------------------------------------------------------ kernels
-__global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
-                                                   float *__restrict__ out, int N,
-                                                   const float2 *__restrict__ tw,
-                                                   const float2 *__restrict__ tq)
+// DCT-II of rows r0, r0 + 1 of `in` [rows][N] into `out` (LDS: sa, sb of
+// kMaxN and stw of kMaxN / 2 float2).
+__device__ void dct2_rows_body(const float *__restrict__ in, float *__restrict__ out, int64_t r0,
+                               int N, const float2 *__restrict__ tw, const float2 *__restrict__ tq,
+                               int qs, float2 *sa, float2 *sb, float2 *stw)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
-    load_twiddles(stw, tw, N);
-    const int64_t r0 = 2 * (int64_t)blockIdx.x;
+    load_twiddles(stw, tw, N, qs);
     const float *ra = in + r0 * N, *rb = ra + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = make_float2(ra[i], rb[i]);
     // result pairs land in sa or sb; reuse the other as output staging
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
         const float2 zc = Z[(N - m) & (N - 1)];
         const float2 va = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
         const float2 vb = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
-        const float2 q = tq[m];
+        const float2 q = tq[m * qs];
         o[m] = make_float2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
     }
     __syncthreads();
@@ -145,6 +147,32 @@ __global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
         oa[m] = o[m].x;
         ob[m] = o[m].y;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
+                                                   float *__restrict__ out, int N,
+                                                   const float2 *__restrict__ tw,
+                                                   const float2 *__restrict__ tq)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    dct2_rows_body(in, out, 2 * (int64_t)blockIdx.x, N, tw, tq, 1, sa, sb, stw);
+}
+
+// One 32 x 32 tile (columns c0.., rows r0..) of in [R][C] -> out [C][R],
+// through LDS; 256 threads.
+__device__ void transpose_tile(const float *__restrict__ in, float *__restrict__ out, int R, int C,
+                               int c0, int r0, float (*tile)[33])
+{
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, c = c0 + tx;
+        if (r < R && c < C) tile[k][tx] = in[(int64_t)r * C + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int c = c0 + k, r = r0 + tx;
+        if (r < R && c < C) out[(int64_t)c * R + r] = tile[tx][k];
     }
 }
 
@@ -159,33 +187,22 @@ __global__ __launch_bounds__(256) void k_transpose(const float *__restrict__ in0
     __shared__ float tile[32][33];
     const float *in = blockIdx.z == 0 ? in0 : (blockIdx.z == 1 ? in1 : in2);
     float *out = blockIdx.z == 0 ? out0 : (blockIdx.z == 1 ? out1 : out2);
-    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    for (int k = ty; k < 32; k += 8) {
-        const int r = r0 + k, c = c0 + tx;
-        if (r < R && c < C) tile[k][tx] = in[(int64_t)r * C + c];
-    }
-    __syncthreads();
-    for (int k = ty; k < 32; k += 8) {
-        const int c = c0 + k, r = r0 + tx;
-        if (r < R && c < C) out[(int64_t)c * R + r] = tile[tx][k];
-    }
+    transpose_tile(in, out, R, C, blockIdx.x * 32, blockIdx.y * 32, tile);
 }
 
-// Column pass on rows m0 = 2 blockIdx.x, m1 = m0 + 1 of T2 [lx][ly].
-__global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, int lx, int ly,
-                                                  float sigma, const float2 *__restrict__ tw,
-                                                  const float2 *__restrict__ tq,
-                                                  float *__restrict__ pa, float *__restrict__ pb,
-                                                  float *__restrict__ pc)
+// Column pass on rows m0, m1 = m0 + 1 of T2 [lx][ly] (LDS: sa, sb, coef of
+// kMaxN and stw of kMaxN / 2 float2).
+__device__ void col_pass_body(const float *__restrict__ t2, int m0, int lx, int ly, float sigma,
+                              const float2 *__restrict__ tw, const float2 *__restrict__ tq, int qs,
+                              float *__restrict__ pa, float *__restrict__ pb,
+                              float *__restrict__ pc, float2 *sa, float2 *sb, float2 *coef,
+                              float2 *stw)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
     const int N = ly;
-    load_twiddles(stw, tw, N);
-    const int m0 = 2 * blockIdx.x;
+    load_twiddles(stw, tw, N, qs);
     const float *ra = t2 + (int64_t)m0 * N, *rb = ra + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = make_float2(ra[i], rb[i]);
-    dct2_pair(sa, sb, coef, N, stw, tq);   // coef[n] = (S[m0][n], S[m1][n])
+    dct2_pair(sa, sb, coef, N, stw, tq, qs);   // coef[n] = (S[m0][n], S[m1][n])
 
     // normalisation of Eq. 7 and the blur, separable in m and n
     const float PI_F = 3.14159265358979f;
@@ -216,7 +233,7 @@ __global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, 
     };
 
     // a: plain DCT-III of the coefficients
-    dct3_input(sa, N, tq, [&](int n) { return coef[n]; });
+    dct3_input(sa, N, tq, [&](int n) { return coef[n]; }, qs);
     float2 *v = fft_lds(sa, sb, N, stw, true);
     float *oa0 = pa + (int64_t)m0 * N, *oa1 = oa0 + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -229,7 +246,7 @@ __global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, 
     dct3_input(sa, N, tq, [&](int n) {
         const float2 c = coef[n];
         return make_float2(wx(ma, n) * c.x, wx(mb, n) * c.y);
-    });
+    }, qs);
     v = fft_lds(sa, sb, N, stw, true);
     float *ob0 = pb + (int64_t)m0 * N, *ob1 = ob0 + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -244,7 +261,7 @@ __global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, 
         const int n = N - mm;
         const float2 c = coef[n];
         return make_float2(wy(ma, n) * c.x, wy(mb, n) * c.y);
-    });
+    }, qs);
     v = fft_lds(sa, sb, N, stw, true);
     float *oc0 = pc + (int64_t)m0 * N, *oc1 = oc0 + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -255,23 +272,31 @@ __global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, 
     }
 }
 
-// Row pass on rows j0 = 2 blockIdx.x, j1 = j0 + 1 of a, b, c [ly][lx]; writes
-// the ghosted float4 fields (J_x, J_y, rho_s, 0).
-__global__ __launch_bounds__(512) void k_row_final(const float *__restrict__ pa,
-                                                   const float *__restrict__ pb,
-                                                   const float *__restrict__ pc, int lx, int ly,
-                                                   const float2 *__restrict__ tw,
-                                                   const float2 *__restrict__ tq,
-                                                   float4 *__restrict__ fields, int32_t *status)
+__global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, int lx, int ly,
+                                                  float sigma, const float2 *__restrict__ tw,
+                                                  const float2 *__restrict__ tq,
+                                                  float *__restrict__ pa, float *__restrict__ pb,
+                                                  float *__restrict__ pc)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
+    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
+    col_pass_body(t2, 2 * blockIdx.x, lx, ly, sigma, tw, tq, 1, pa, pb, pc, sa, sb, coef, stw);
+}
+
+// Row pass on rows j0, j1 = j0 + 1 of a, b, c [ly][lx]; writes the ghosted
+// float4 fields (J_x, J_y, rho_s, 0) (LDS: sa, sb, rs, jx of kMaxN and stw of
+// kMaxN / 2 float2).
+__device__ void row_final_body(const float *__restrict__ pa, const float *__restrict__ pb,
+                               const float *__restrict__ pc, int j0, int lx, int ly,
+                               const float2 *__restrict__ tw, const float2 *__restrict__ tq,
+                               int qs, float4 *__restrict__ fields, int32_t *status, float2 *sa,
+                               float2 *sb, float2 *rs, float2 *jx, float2 *stw)
+{
     const int N = lx;
-    load_twiddles(stw, tw, N);
-    const int j0 = 2 * blockIdx.x;
+    load_twiddles(stw, tw, N, qs);
     const float norm = 1.0f / ((float)lx * (float)ly);
 
     const float *a0 = pa + (int64_t)j0 * N, *a1 = a0 + N;
-    dct3_input(sa, N, tq, [&](int m) { return make_float2(a0[m], a1[m]); });
+    dct3_input(sa, N, tq, [&](int m) { return make_float2(a0[m], a1[m]); }, qs);
     float2 *v = fft_lds(sa, sb, N, stw, true);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const float2 y = dct3_output(v, i, N);
@@ -282,7 +307,7 @@ __global__ __launch_bounds__(512) void k_row_final(const float *__restrict__ pa,
     dct3_input(sa, N, tq, [&](int mm) {
         if (mm == 0) return make_float2(0.f, 0.f);
         return make_float2(b0[N - mm], b1[N - mm]);
-    });
+    }, qs);
     v = fft_lds(sa, sb, N, stw, true);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const float2 y = dct3_output(v, i, N);
@@ -291,7 +316,7 @@ __global__ __launch_bounds__(512) void k_row_final(const float *__restrict__ pa,
     }
     __syncthreads();
     const float *c0 = pc + (int64_t)j0 * N, *c1 = c0 + N;
-    dct3_input(sa, N, tq, [&](int m) { return make_float2(c0[m], c1[m]); });
+    dct3_input(sa, N, tq, [&](int m) { return make_float2(c0[m], c1[m]); }, qs);
     v = fft_lds(sa, sb, N, stw, true);
 
     const int P = lx + 2;
@@ -325,6 +350,18 @@ __global__ __launch_bounds__(512) void k_row_final(const float *__restrict__ pa,
         }
     }
     if (bad) set_status(status, FFB_E_NONPOSITIVE);
+}
+
+__global__ __launch_bounds__(512) void k_row_final(const float *__restrict__ pa,
+                                                   const float *__restrict__ pb,
+                                                   const float *__restrict__ pc, int lx, int ly,
+                                                   const float2 *__restrict__ tw,
+                                                   const float2 *__restrict__ tq,
+                                                   float4 *__restrict__ fields, int32_t *status)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
+    row_final_body(pa, pb, pc, 2 * blockIdx.x, lx, ly, tw, tq, 1, fields, status, sa, sb, rs, jx,
+                   stw);
 }
 
 // Pack caller node arrays into the ghosted layout (same ghost rule).
@@ -566,6 +603,103 @@ __global__ __launch_bounds__(512) void k_adj_rows_final(const float *__restrict_
     }
 }
 
+// ------------------------------------------------------------- batched
+// Transforms of many maps of different sizes: every workgroup reads its
+// (map, index) from a launch table, offsets its planes, and runs the same
+// bodies as the single-map kernels with the length-1024 twiddle tables read
+// at stride 1024 / N.  Maps that stopped iterating are skipped.
+
+__global__ __launch_bounds__(1024) void kb_mean(batch_view bv, const float *__restrict__ rho,
+                                                double *__restrict__ rho_bar, int32_t *status)
+{
+    __shared__ double lds[1024];
+    const int m = blockIdx.x;
+    if (!bv.active[m]) return;
+    const int64_t n = (int64_t)bv.lx[m] * bv.ly[m];
+    const float *x = rho + bv.plane_off[m];
+    double sum = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) sum += (double)x[i];
+    lds[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mean = lds[0] / (double)n;
+        rho_bar[m] = mean;
+        if (!(mean > 0.0)) set_status(status, FFB_E_NONPOSITIVE);
+    }
+}
+
+__global__ __launch_bounds__(512) void kb_dct2_rows(batch_view bv, const int2 *__restrict__ rows,
+                                                    const float *__restrict__ in,
+                                                    float *__restrict__ out,
+                                                    const float2 *__restrict__ tw,
+                                                    const float2 *__restrict__ tq)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    const int2 e = rows[blockIdx.x];
+    const int m = e.x;
+    if (!bv.active[m]) return;
+    const int N = bv.lx[m];
+    const int64_t o = bv.plane_off[m];
+    dct2_rows_body(in + o, out + o, e.y, N, tw, tq, kMaxN / N, sa, sb, stw);
+}
+
+// blockIdx.y selects the plane pair (in_k -> out_k).
+__global__ __launch_bounds__(256) void kb_transpose(batch_view bv, const int4 *__restrict__ tiles,
+                                                    bool rows_are_y, const float *in0,
+                                                    const float *in1, float *out0, float *out1)
+{
+    __shared__ float tile[32][33];
+    const int4 t = tiles[blockIdx.x];
+    const int m = t.x;
+    if (!bv.active[m]) return;
+    const int R = rows_are_y ? bv.ly[m] : bv.lx[m];
+    const int C = rows_are_y ? bv.lx[m] : bv.ly[m];
+    const int64_t o = bv.plane_off[m];
+    const float *in = (blockIdx.y == 0 ? in0 : in1) + o;
+    float *out = (blockIdx.y == 0 ? out0 : out1) + o;
+    transpose_tile(in, out, R, C, t.y, t.z, tile);
+}
+
+__global__ __launch_bounds__(512) void kb_col_pass(batch_view bv, const int2 *__restrict__ cols,
+                                                   const float *__restrict__ t2,
+                                                   const float2 *__restrict__ tw,
+                                                   const float2 *__restrict__ tq,
+                                                   float *__restrict__ pa, float *__restrict__ pb,
+                                                   float *__restrict__ pc)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
+    const int2 e = cols[blockIdx.x];
+    const int m = e.x;
+    if (!bv.active[m]) return;
+    const int lx = bv.lx[m], ly = bv.ly[m];
+    const int64_t o = bv.plane_off[m];
+    const float sigma = (float)ldexp(bv.sigma0, -bv.round[m]);
+    col_pass_body(t2 + o, e.y, lx, ly, sigma, tw, tq, kMaxN / ly, pa + o, pb + o, pc + o, sa, sb,
+                  coef, stw);
+}
+
+__global__ __launch_bounds__(512) void kb_row_final(batch_view bv, const int2 *__restrict__ rows,
+                                                    const float *__restrict__ pa,
+                                                    const float *__restrict__ pb,
+                                                    const float *__restrict__ pc,
+                                                    const float2 *__restrict__ tw,
+                                                    const float2 *__restrict__ tq,
+                                                    float4 *__restrict__ fields, int32_t *status)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
+    const int2 e = rows[blockIdx.x];
+    const int m = e.x;
+    if (!bv.active[m]) return;
+    const int lx = bv.lx[m], ly = bv.ly[m];
+    const int64_t o = bv.plane_off[m];
+    row_final_body(pa + o, pb + o, pc + o, e.y, lx, ly, tw, tq, kMaxN / lx,
+                   fields + bv.field_off[m], status, sa, sb, rs, jx, stw);
+}
+
 inline int threads_for(int N)
 {
     int t = N / 2;
@@ -637,5 +771,42 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
                        ctx->pb, ctx->pb, ctx->pb, ctx->pc, ctx->pc, ctx->pc, lx, ly);
     hipLaunchKernelGGL(k_adj_rows_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->pc, lx,
                        ctx->tw_x, ctx->tq_x, lam_rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
+                             const batch_fft_plan &plan, const float2 *tw1024,
+                             const float2 *tq1024, float *rho, float *t1, float *t2, float *pa,
+                             float *pb, float *pc, float4 *fields, double *rho_bar,
+                             int32_t *status)
+{
+    hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(1024), 0, s, bv, rho, rho_bar, status);
+    for (int c = 0; c < plan.n_classes; ++c) {
+        const int n = plan.row_beg[c + 1] - plan.row_beg[c];
+        if (n > 0)
+            hipLaunchKernelGGL(kb_dct2_rows, dim3(n), dim3(plan.threads[c]), 0, s, bv,
+                               bt.rows + plan.row_beg[c], rho, t1, tw1024, tq1024);
+    }
+    // [ly][lx] -> [lx][ly]
+    hipLaunchKernelGGL(kb_transpose, dim3(bt.n_tiles_a, 1), dim3(256), 0, s, bv, bt.tiles_a, true,
+                       t1, t1, t2, t2);
+    for (int c = 0; c < plan.n_classes; ++c) {
+        const int n = plan.col_beg[c + 1] - plan.col_beg[c];
+        if (n > 0)
+            hipLaunchKernelGGL(kb_col_pass, dim3(n), dim3(plan.threads[c]), 0, s, bv,
+                               bt.cols + plan.col_beg[c], t2, tw1024, tq1024, pa, pb, pc);
+    }
+    // [lx][ly] -> [ly][lx]: a, b into t1, t2 and c into pa (read after the first launch)
+    hipLaunchKernelGGL(kb_transpose, dim3(bt.n_tiles_b, 2), dim3(256), 0, s, bv, bt.tiles_b,
+                       false, pa, pb, t1, t2);
+    hipLaunchKernelGGL(kb_transpose, dim3(bt.n_tiles_b, 1), dim3(256), 0, s, bv, bt.tiles_b,
+                       false, pc, pc, pa, pa);
+    for (int c = 0; c < plan.n_classes; ++c) {
+        const int n = plan.row_beg[c + 1] - plan.row_beg[c];
+        if (n > 0)
+            hipLaunchKernelGGL(kb_row_final, dim3(n), dim3(plan.threads[c]), 0, s, bv,
+                               bt.rows + plan.row_beg[c], t1, t2, pa, tw1024, tq1024, fields,
+                               status);
+    }
     return hipGetLastError();
 }

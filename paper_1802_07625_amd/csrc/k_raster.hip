@@ -208,6 +208,130 @@ __global__ __launch_bounds__(kScanThreads) void k_raster_scan(
     }
 }
 
+// ------------------------------------------------------------- batched
+// One workgroup per map: its rho_pad and w_r (maps that stopped are skipped).
+__global__ __launch_bounds__(kPrepThreads) void kb_density_prep(
+    batch_view bv, const double *__restrict__ value, const double *__restrict__ area,
+    double *__restrict__ w, double *__restrict__ rho_pad, int32_t *status)
+{
+    __shared__ double lds[kPrepThreads / 64 + 1];
+    const int m = blockIdx.x;
+    if (!bv.active[m]) return;
+    const int32_t r0 = bv.region_off[m], r1 = bv.region_off[m + 1];
+    double sa = 0.0, sv = 0.0;
+    int bad = 0;
+    for (int32_t r = r0 + threadIdx.x; r < r1; r += kPrepThreads) {
+        const double a = area[r], v = value[r];
+        bad |= !(a > 0.0) || !(v > 0.0);
+        sa += a;
+        sv += v;
+    }
+    sa = block_sum<kPrepThreads>(sa, lds);
+    sv = block_sum<kPrepThreads>(sv, lds);
+    const double pad = sv / sa;
+    for (int32_t r = r0 + threadIdx.x; r < r1; r += kPrepThreads) w[r] = value[r] / area[r] - pad;
+    if (bad) set_status(status, FFB_E_NONPOSITIVE);
+    if (threadIdx.x == 0) rho_pad[m] = pad;
+}
+
+// One lane per ring entry of every map (global ring and vertex indices); the
+// deltas go to the map's coverage grid.
+__global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
+    batch_view bv, const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
+    const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t G, int32_t R,
+    int64_t E, const double *__restrict__ w, double *__restrict__ acc, int32_t *status)
+{
+    const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
+    if (k >= E) return;
+    int32_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    const int32_t g = lo;
+    const int64_t b = off[g], e = off[g + 1];
+    if (!(b <= k && k < e) || e - b < 3 || e > E) { set_status(status, FFB_E_INVALID); return; }
+    const int32_t m = bv.ring_map[g];
+    if (m < 0 || m >= bv.n_maps) { set_status(status, FFB_E_INVALID); return; }
+    if (!bv.active[m]) return;
+    const int32_t lx = bv.lx[m], ly = bv.ly[m];
+    const int32_t r = region[g];
+    const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
+    if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
+        set_status(status, FFB_E_INVALID);
+        return;
+    }
+    const float2 p = xy[i0], q = xy[i1];
+    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
+        set_status(status, FFB_E_NONFINITE);
+        return;
+    }
+    const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
+    if (x0 < 0.0 || x0 > lx || y0 < 0.0 || y0 > ly || x1 < 0.0 || x1 > lx || y1 < 0.0 ||
+        y1 > ly) {
+        set_status(status, FFB_E_DOMAIN);
+        return;
+    }
+    if (y0 == y1) return;
+    double *macc = acc + bv.acc_off[m];
+    const double wt = w[r];
+    const double dx = x1 - x0, dy = y1 - y0;
+    double fx, sx, fy, sy;
+    const int32_t nx = lines_between(x0, x1, &fx, &sx);
+    const int32_t ny = lines_between(y0, y1, &fy, &sy);
+    int32_t ix = 0, iy = 0;
+    double xa = x0, ya = y0;
+    while (ix < nx || iy < ny) {
+        const double X = fx + sx * ix, Y = fy + sy * iy;
+        const double tx = (ix < nx) ? (X - x0) / dx : 2.0;
+        const double ty = (iy < ny) ? (Y - y0) / dy : 2.0;
+        double xb, yb;
+        if (tx < ty) {
+            xb = X; yb = y0 + tx * dy; ++ix;
+        } else if (ty < tx) {
+            xb = x0 + ty * dx; yb = Y; ++iy;
+        } else {
+            xb = X; yb = Y; ++ix; ++iy;
+        }
+        deposit(macc, lx, ly, wt, xa, ya, xb, yb);
+        xa = xb;
+        ya = yb;
+    }
+    deposit(macc, lx, ly, wt, xa, ya, x1, y1);
+}
+
+// Row prefix sums of every active map, one workgroup per (map, row).
+__global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
+    batch_view bv, const int2 *__restrict__ rows, const double *__restrict__ acc,
+    const double *__restrict__ rho_pad, float *__restrict__ rho)
+{
+    __shared__ double part[kScanThreads];
+    const int2 e = rows[blockIdx.x];
+    const int m = e.x, j = e.y;
+    if (!bv.active[m]) return;
+    const int32_t lx = bv.lx[m];
+    const double *row = acc + bv.acc_off[m] + (int64_t)j * (lx + 1);
+    const int32_t chunk = (lx + kScanThreads - 1) / kScanThreads;
+    const int32_t beg = threadIdx.x * chunk;
+    const int32_t end = min(beg + chunk, lx);
+    double s = 0.0;
+    for (int32_t i = beg; i < end; ++i) s += row[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        const double v = (threadIdx.x >= (unsigned)o) ? part[threadIdx.x - o] : 0.0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    double run = part[threadIdx.x] - s + rho_pad[m];
+    float *out = rho + bv.plane_off[m] + (int64_t)j * lx;
+    for (int32_t i = beg; i < end; ++i) {
+        run += row[i];
+        out[i] = (float)run;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_density_weights(ffb_ctx *ctx, int32_t R, const double *value,
@@ -240,5 +364,26 @@ hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *val
     }
     hipLaunchKernelGGL(k_raster_scan, dim3(ctx->ly), dim3(kScanThreads), 0, s, ctx->acc,
                        ctx->lx, rho_pad, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch_tables &bt,
+                                const ffb_geometry *g, const double *value, const double *area,
+                                double *w_region, double *rho_pad, double *acc, int64_t acc_total,
+                                float *rho, int32_t *status)
+{
+    hipLaunchKernelGGL(kb_density_prep, dim3(bv.n_maps), dim3(kPrepThreads), 0, s, bv, value,
+                       area, w_region, rho_pad, status);
+    hipError_t e = launch_fill_f64(acc, acc_total, 0.0, s);
+    if (e != hipSuccess) return e;
+    if (g->n_entries > 0) {
+        const int64_t blocks = (g->n_entries + kEdgeThreads - 1) / kEdgeThreads;
+        hipLaunchKernelGGL(kb_raster_edges, dim3((unsigned)blocks), dim3(kEdgeThreads), 0, s, bv,
+                           reinterpret_cast<const float2 *>(g->xy), g->n_vertices,
+                           g->ring_offsets, g->ring_vidx, g->ring_region, g->n_rings,
+                           g->n_regions, g->n_entries, w_region, acc, status);
+    }
+    hipLaunchKernelGGL(kb_raster_scan, dim3(bt.n_scan_rows), dim3(kScanThreads), 0, s, bv,
+                       bt.scan_rows, acc, rho_pad, rho);
     return hipGetLastError();
 }

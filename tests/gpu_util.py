@@ -48,3 +48,22 @@ def new_ctx(lx, ly=None, max_points=0, mode=None):
     if mode is not None:
         ctx.set_option(ffb.OPT_ADVECT_STATE, mode)
     return ctx
+
+
+def l1_perimeters(m, xy):
+    """Per-region sum over its ring edges of |dx| + |dy| (FP64)."""
+    xy = np.asarray(xy, dtype=np.float64).reshape(-1, 2)
+    per = np.zeros(m.n_regions)
+    for g in range(len(m.ring_region)):
+        idx = m.ring_vidx[m.ring_offsets[g]:m.ring_offsets[g + 1]]
+        p = xy[idx]
+        per[m.ring_region[g]] += np.abs(np.roll(p, -1, axis=0) - p).sum()
+    return per
+
+
+def area_bound(m, xy_ref, dx):
+    """Largest |A_r - A_r(ref)| when every vertex is within dx (max norm) of
+    the reference: the shoelace sum changes at first order by at most
+    dx * sum over edges (|dx_e| + |dy_e|); 1 % covers the second order, and
+    1e-12 relative the FP64 sums."""
+    return 1.01 * dx * l1_perimeters(m, xy_ref)

@@ -53,6 +53,12 @@ int main(void) {{
          offsetof(ffb_geometry, n_entries));
   printf("%zu %zu %zu %zu\\n", sizeof(ffb_integrate_opts), offsetof(ffb_integrate_opts, max_attempts),
          offsetof(ffb_integrate_opts, n_replay), offsetof(ffb_integrate_opts, replay_h));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(ffb_batch_desc), offsetof(ffb_batch_desc, lx),
+         offsetof(ffb_batch_desc, geometry), offsetof(ffb_batch_desc, points),
+         offsetof(ffb_batch_desc, value));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(ffb_batch_opts), offsetof(ffb_batch_opts, max_rounds),
+         offsetof(ffb_batch_opts, sigma0), offsetof(ffb_batch_opts, integrate),
+         offsetof(ffb_batch_opts, use_graph));
   return 0;
 }}''')
     exe = tmp_path / "layout"
@@ -64,6 +70,12 @@ int main(void) {{
     assert g == [ctypes.sizeof(G), G.n_rings.offset, G.ring_region.offset, G.n_regions.offset,
                  G.n_entries.offset]
     assert o == [ctypes.sizeof(O), O.max_attempts.offset, O.n_replay.offset, O.replay_h.offset]
+    bd = [int(v) for v in lines[2].split()]
+    bo = [int(v) for v in lines[3].split()]
+    D, BO = api.FFBBatchDesc, api.FFBBatchOpts
+    assert bd == [ctypes.sizeof(D), D.lx.offset, D.geometry.offset, D.points.offset, D.value.offset]
+    assert bo == [ctypes.sizeof(BO), BO.max_rounds.offset, BO.sigma0.offset, BO.integrate.offset,
+                  BO.use_graph.offset]
 
 
 def test_status_codes_match_header():
@@ -87,6 +99,14 @@ def test_host_validation_without_gpu(lib):
     assert lib.ffb_integrate(None, None, None, None, 0, None, None, None, 0) == 1
     assert lib.ffb_destroy(None) == 1
     assert lib.ffb_last_error(None) == b"null context"
+    # batches: descriptions are checked before any device work
+    import paper_1802_07625_amd.api as api
+    b = ctypes.c_void_p()
+    assert lib.ffb_batch_create(ctypes.byref(b), None, None) == 1
+    assert lib.ffb_batch_create(ctypes.byref(b), ctypes.byref(api.FFBBatchDesc()), None) == 1
+    assert lib.ffb_batch_destroy(None) == 1
+    assert lib.ffb_batch_run(None, None, None) == 1
+    assert lib.ffb_batch_last_error(None) == b"null batch"
 
 
 def test_product_and_oracle_are_independent():
