@@ -86,10 +86,30 @@ struct Params {
     int32_t *tape_count;
 };
 
+// The packed fields as a buffer resource: gathers take a 32-bit byte offset
+// (no 64-bit address arithmetic per load), the row step rides in the scalar
+// offset, and the hardware returns zeros for any offset past the end.
 struct Field {
-    const float4 *f;
+    __amdgpu_buffer_rsrc_t rs;
     int lx, ly, pitch;
+    uint32_t max_base;       // largest lower-left node index of a cell
+    int row_bytes;           // 16 * pitch
 };
+
+__device__ inline Field make_field(const float4 *f, int lx, int ly)
+{
+    Field F;
+    const int pitch = lx + 2;
+    const uint32_t bytes = 16u * (uint32_t)pitch * (uint32_t)(ly + 2);
+    // third dword 0x00020000: raw 32-bit dword access on gfx9-family chips
+    F.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float4 *>(f), 0, (int)bytes, 0x00020000);
+    F.lx = lx;
+    F.ly = ly;
+    F.pitch = pitch;
+    F.max_base = (uint32_t)(ly * pitch + lx);
+    F.row_bytes = 16 * pitch;
+    return F;
+}
 
 // One coordinate of a point, prepared once per point and attempt:
 // hi - 1/2 = ifl + fr with ifl integral, frl = fr + lo, and the bounds of the
@@ -111,15 +131,17 @@ __device__ inline Axis make_axis(float hi, float lo, int L)
     return a;
 }
 
-// Cell index in [-1, L-1] and fraction of the lookup at hi + lo + d, clamped
-// to the box.  The integer med3 keeps the index in range for any input
-// (NaN or Inf positions included).
-__device__ inline void locate(const Axis &a, float d, int L, int &idx, float &frac)
+// Cell index and fraction of the lookup at hi + lo + d, clamped to the box:
+// with t clamped to [lo_t, hi_t] the index is in [-1, L-1] for every finite
+// position (ifl and floor(t) are exact integers); the caller clamps the
+// combined node index once more, so that no input (NaN or Inf included) can
+// reach outside the fields.
+__device__ inline void locate(const Axis &a, float d, int &idx, float &frac)
 {
     float t = a.frl + d;
     t = __builtin_amdgcn_fmed3f(t, a.lo_t, a.hi_t);
     const float ft = floorf(t);
-    idx = min(max(a.ifl + (int)ft, -1), L - 1);
+    idx = a.ifl + (int)ft;
     frac = t - ft;
 }
 
@@ -131,10 +153,10 @@ struct CellCache {
     float3 c00, c10, c01, c11;
 };
 
-__device__ inline float3 ld3(const float4 *f, int idx)
+__device__ inline float3 ld3(const Field &F, uint32_t off, int soff)
 {
-    const float4 v = f[idx];
-    return make_float3(v.x, v.y, v.z);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(F.rs, (int)off, soff, 0);
+    return make_float3(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]));
 }
 
 // h * v at hi + lo + d, for the stage factors omh = (1 - t) / h and
@@ -144,15 +166,16 @@ __device__ inline float2 velocity(const Field &F, const Axis &ax, const Axis &ay
 {
     int i, j;
     float a, b;
-    locate(ax, dx, F.lx, i, a);
-    locate(ay, dy, F.ly, j, b);
-    const int base = __umul24(j + 1, F.pitch) + (i + 1);     // < (L+2)^2
+    locate(ax, dx, i, a);
+    locate(ay, dy, j, b);
+    const int base = (int)min(__umul24(j + 1, F.pitch) + (uint32_t)(i + 1), F.max_base);
     if (base != cc.key) {
         cc.key = base;
-        cc.c00 = ld3(F.f, base);
-        cc.c10 = ld3(F.f, base + 1);
-        cc.c01 = ld3(F.f, base + F.pitch);
-        cc.c11 = ld3(F.f, base + F.pitch + 1);
+        const uint32_t off = 16u * (uint32_t)base;
+        cc.c00 = ld3(F, off, 0);
+        cc.c10 = ld3(F, off + 16u, 0);
+        cc.c01 = ld3(F, off, F.row_bytes);
+        cc.c11 = ld3(F, off + 16u, F.row_bytes);
     }
     const float r00 = __builtin_amdgcn_rcpf(fmaf(cc.c00.z, omh, tbh));
     const float r10 = __builtin_amdgcn_rcpf(fmaf(cc.c10.z, omh, tbh));
@@ -334,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
     if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
 
     const double rho_bar = *p.rho_bar;
-    const Field F{p.fields, p.lx, p.ly, p.pitch};
+    const Field F = make_field(p.fields, p.lx, p.ly);
     const Span sp = span_of(blockIdx.x, gridDim.x, p.n);
     const int npts = sp.la + sp.lb;
     const bool replay = p.n_replay > 0;
@@ -528,7 +551,7 @@ __global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args
     if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     const double rho_bar = a.rho_bar[m];
     const int lx = bv.lx[m], ly = bv.ly[m];
-    const Field F{a.fields + bv.field_off[m], lx, ly, lx + 2};
+    const Field F = make_field(a.fields + bv.field_off[m], lx, ly);
     const int64_t p0 = bv.point_off[m];
     const int npts = (int)(bv.point_off[m + 1] - p0);
     const int n_replay = a.replay_off ? a.replay_off[m + 1] - a.replay_off[m] : 0;
