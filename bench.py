@@ -37,8 +37,11 @@ HBM_PEAK_GBS = 8000.0
 # from FETCH_SIZE and WRITE_SIZE counter runs calibrated on a copy of known
 # size, for the kernel source with this sha256 prefix; reported only while the
 # source is unchanged.
-ADVECT_TRAFFIC = {"bytes_per_attempt": 2.4114e10 / 274, "workload": "c3_L1024",
-                  "source_sha256": "bc23c1829c0fab44"}
+ADVECT_TRAFFIC = {"bytes_per_attempt": 2.4087e10 / 274,
+                  "valu_wave_insts_per_attempt": 3.3463e9 / 274,
+                  "workload": "c3_L1024", "source_sha256": "2e22c318152ada5c"}
+# non-packed FP32 issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def parse():
@@ -52,8 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="time whole oracle iterations until this much work is timed")
-    ap.add_argument("--loop", action="store_true",
-                    help="also run the full loop to < 1%% error and report it")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="skip the loop to < 1%% error")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the fwd+bwd / fwd measurement")
     ap.add_argument("--grad-steps", type=int, default=10)
@@ -129,10 +132,15 @@ def main():
     # are read once (16 B per node); S attempts per launch
     bytes_per_attempt = 16.0 * P + 16.0 * L * L
     achieved = float(np.mean(bytes_per_attempt * attempts / (adv_ms * 1e-3)) / 1e9)
-    traffic = None
+    traffic, valu = None, None
     if args.workload == ADVECT_TRAFFIC["workload"] and _advect_sha() == ADVECT_TRAFFIC["source_sha256"]:
         traffic = round(float(np.mean(ADVECT_TRAFFIC["bytes_per_attempt"] * attempts
                                       / (adv_ms * 1e-3)) / 1e9), 1)
+        lane_ops = float(np.mean(64 * ADVECT_TRAFFIC["valu_wave_insts_per_attempt"] * attempts
+                                 / (adv_ms * 1e-3)))
+        valu = {"achieved": round(lane_ops / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                "unit": "T lane-instructions/s (non-packed FP32 issue)",
+                "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4)}
     # ALU view: ~6 stage evaluations per attempt, counted from the kernel's
     # instruction mix -- reported for context only
     result = {
@@ -160,23 +168,31 @@ def main():
         "roofline": {"kernel": "k_advect", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_attempt": bytes_per_attempt},
+                     "bytes_per_attempt": bytes_per_attempt, "valu": valu},
     }
 
-    if args.loop:
+    if not args.no_loop:
+        # the converging run: rounds with blur 4 * 2^-k until max |e_r| < 1 %
         pts.copy_(pts0)
+        torch.cuda.synchronize()
         rounds, mxv, t_loop = 0, None, time.perf_counter()
-        area = None
+        area, round_ms, round_err, round_att = None, [], [], []
         for k in range(30):
+            t_r = time.perf_counter()
             res = ffb.iterate(ctx, geom, value, pts, ffb.default_sigma(k), opts, area_before=area)
             area = res.area_after
             rounds += 1
             mxv = float(res.max_err_after)     # sync point once per round
+            round_ms.append(round(1e3 * (time.perf_counter() - t_r), 3))
+            round_err.append(mxv)
+            round_att.append(int(res.stats[2]))
             if mxv < 0.01:
                 break
         torch.cuda.synchronize()
         result["loop"] = {"rounds": rounds, "max_area_error": mxv,
-                          "total_ms": round(1e3 * (time.perf_counter() - t_loop), 2)}
+                          "total_ms": round(1e3 * (time.perf_counter() - t_loop), 2),
+                          "ms_per_round": round_ms, "max_error_per_round": round_err,
+                          "attempts_per_round": round_att}
 
     ctx.close()
     if not args.no_grad:
