@@ -343,3 +343,41 @@ def fd_gradient(m, density, sigmas, schedules, step=1e-4, points=None):
         lm = rounds(m, dm, sigmas, points, schedules=schedules).loss
         g[r] = (lp - lm) / (2.0 * step)
     return g
+
+
+# ------------------------------------------------------------- distortion
+@dataclass
+class Distortion:
+    e: np.ndarray          # [ly-1, lx-1] ln(a / b) per unit square between four nodes
+    e_tilde: np.ndarray    # [ly-1, lx-1] 2 arcsin((a - b) / (a + b))
+    e_a: float
+    e_inf: float
+    e_tilde_a: float
+    e_tilde_inf: float
+    folded: int            # squares whose image has det(J) <= 0
+
+
+def distortion(nodes, lx: int, ly: int) -> Distortion:
+    """Angular distortion of a map T known at the grid nodes (main text,
+    section "Measures of distortion"; SI Appendix section 3, Tissot ellipses
+    and angular-distortion metrics).  ``nodes`` [ly*lx, 2] are the images of
+    the cell centres in row-major order.  On every unit square between four
+    neighbouring nodes, T is taken as the bilinear interpolant of the node
+    images and its Jacobian at the square's centre (the mean of the two
+    opposite-edge differences in each direction) as grad T; a >= b are the
+    singular values of that 2 x 2 matrix (numpy's SVD), e = ln(a / b),
+    e~ = 2 arcsin((a - b) / (a + b)); e_a and e~_a average over the squares
+    (all of unit area on the input map), e_inf and e~_inf take the maximum."""
+    T = _f64(nodes).reshape(ly, lx, 2)
+    d_dx = 0.5 * ((T[:-1, 1:] - T[:-1, :-1]) + (T[1:, 1:] - T[1:, :-1]))
+    d_dy = 0.5 * ((T[1:, :-1] - T[:-1, :-1]) + (T[1:, 1:] - T[:-1, 1:]))
+    J = np.stack([np.stack([d_dx[..., 0], d_dy[..., 0]], -1),
+                  np.stack([d_dx[..., 1], d_dy[..., 1]], -1)], -2)
+    s = np.linalg.svd(J, compute_uv=False)
+    a, b = s[..., 0], s[..., 1]
+    with np.errstate(divide="ignore"):
+        e = np.log(a / b)
+    et = 2.0 * np.arcsin((a - b) / (a + b))
+    det = J[..., 0, 0] * J[..., 1, 1] - J[..., 0, 1] * J[..., 1, 0]
+    return Distortion(e, et, float(e.mean()), float(e.max()), float(et.mean()),
+                      float(et.max()), int(np.sum(det <= 0)))
