@@ -193,6 +193,18 @@ def main():
                           "total_ms": round(1e3 * (time.perf_counter() - t_loop), 2),
                           "ms_per_round": round_ms, "max_error_per_round": round_err,
                           "attempts_per_round": round_att}
+        # angular distortion of the final map, from the advected grid nodes
+        d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.distortion(pts[V:], per_square=True)            # first launch loads the kernels
+        d0.record(stream)
+        dst, _, _ = ctx.distortion(pts[V:], per_square=True)
+        d1.record(stream)
+        torch.cuda.synchronize()
+        dst = dst.cpu().numpy()
+        result["loop"]["distortion"] = {
+            "e_a": float(dst[0]), "e_inf": float(dst[1]), "e_tilde_a": float(dst[2]),
+            "e_tilde_inf": float(dst[3]), "folded_squares": int(dst[4]),
+            "ms": round(d0.elapsed_time(d1), 4)}
 
     ctx.close()
     if not args.no_grad:

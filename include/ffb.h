@@ -196,6 +196,25 @@ int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, floa
                   int64_t n, const ffb_integrate_opts *opts, int32_t *stats,
                   double *h_out, int32_t h_cap);
 
+/* Angular distortion of the cartogram (main text, section "Measures of
+ * distortion"; SI Appendix section 3).  nodes (in, device, [ly][lx][2] FP32)
+ * are the images of the cell centres (i + 1/2, j + 1/2) of an lx x ly grid
+ * (any sizes >= 2, independent of the context's transform sizes; the context
+ * gives the stream and the reduction workspace) in row-major order, e.g. the
+ * grid nodes after the rounds.  On each of the (lx-1)(ly-1) unit squares
+ * between four neighbouring nodes, grad T is the Jacobian of the bilinear
+ * interpolant of the node images at the square's centre; its singular values
+ * a >= b (the semi-axes of the Tissot ellipse) give e = ln(a/b) and
+ * e~ = 2 arcsin((a-b)/(a+b)).  stats (out, [5] FP64) = e_a (mean of e over the
+ * squares, all of unit area on the input map), e_inf (max), e~_a, e~_inf and
+ * the number of squares with det(grad T) <= 0 (folded).  e and e_tilde (out,
+ * [(ly-1)][(lx-1)] FP32, each may be NULL) receive the per-square values.
+ * FP64 arithmetic on the FP32 positions.  Returns FFB_E_INVALID for NULL
+ * nodes or stats, or a grid below 2 x 2 nodes; all outputs device memory,
+ * written in stream order. */
+int ffb_distortion(ffb_ctx *ctx, int32_t lx, int32_t ly, const float *nodes, double *stats,
+                   float *e, float *e_tilde);
+
 /* ------------------------------------------------------------------ adjoints
  * Reverse-mode derivatives of the calls above, for a scalar L of the final
  * region areas.  The accepted step sizes of each integration are frozen at

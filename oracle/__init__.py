@@ -375,9 +375,9 @@ def distortion(nodes, lx: int, ly: int) -> Distortion:
                   np.stack([d_dx[..., 1], d_dy[..., 1]], -1)], -2)
     s = np.linalg.svd(J, compute_uv=False)
     a, b = s[..., 0], s[..., 1]
-    with np.errstate(divide="ignore"):
+    with np.errstate(divide="ignore", invalid="ignore"):      # b = 0, or a = b = 0
         e = np.log(a / b)
-    et = 2.0 * np.arcsin((a - b) / (a + b))
+        et = 2.0 * np.arcsin((a - b) / (a + b))
     det = J[..., 0, 0] * J[..., 1, 1] - J[..., 0, 1] * J[..., 1, 0]
     return Distortion(e, et, float(e.mean()), float(e.max()), float(et.mean()),
                       float(et.max()), int(np.sum(det <= 0)))

@@ -85,6 +85,7 @@ def lib():
         L.ffb_integrate.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(FFBIntegrateOpts),
                                     vp, vp, i32]
         L.ffb_set_option.argtypes = [vp, i32, i32]
+        L.ffb_distortion.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         L.ffb_area_adj.argtypes = [vp, G, vp, vp]
         L.ffb_density_adj.argtypes = [vp, G, vp, vp, vp, vp, vp, vp]
         L.ffb_flux_adj.argtypes = [vp, ctypes.c_float, vp, vp, vp]
@@ -109,7 +110,7 @@ def lib():
         L.ffb_batch_results.argtypes = [vp, vp, vp, vp, vp]
         for f in ("ffb_create", "ffb_destroy", "ffb_sync", "ffb_reset_status", "ffb_area_error",
                   "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option",
-                  "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
+                  "ffb_distortion", "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
                   "ffb_integrate_adj", "ffb_tape_begin", "ffb_tape_end", "ffb_tape_clear",
                   "ffb_backward", "ffb_batch_create", "ffb_batch_destroy", "ffb_batch_set_shapes",
                   "ffb_batch_get_shapes", "ffb_batch_autotune", "ffb_batch_reset",
@@ -268,6 +269,14 @@ def ffb_integrate(ctx, fields, rho_bar, xy, opts: IntegrateOpts, stats, h_out=No
                                     0 if h_out is None else h_out.numel()), "ffb_integrate")
 
 
+def ffb_distortion(ctx, lx: int, ly: int, nodes, stats, e=None, e_tilde=None) -> None:
+    n = max(lx - 1, 0) * max(ly - 1, 0)
+    _check(ctx, lib().ffb_distortion(ctx, lx, ly, _ptr(nodes, torch.float32, 2 * lx * ly, "nodes"),
+                                     _ptr(stats, torch.float64, 5, "stats"),
+                                     _ptr(e, torch.float32, n, "e"),
+                                     _ptr(e_tilde, torch.float32, n, "e_tilde")), "ffb_distortion")
+
+
 def ffb_area_adj(ctx, geom: Geometry, lam_area, lam_xy) -> None:
     g = geom.struct()
     _check(ctx, lib().ffb_area_adj(ctx, ctypes.byref(g),
@@ -410,6 +419,22 @@ class Context:
             h_out = self._f64(opts.max_attempts if h_cap is None else h_cap)
         ffb_integrate(self.handle, fields, rho_bar, xy, opts, stats, h_out, replay_h)
         return stats, h_out
+
+    def distortion(self, nodes, per_square: bool = False, lx: int | None = None,
+                   ly: int | None = None):
+        """Angular distortion of the map given by the images of the nodes of
+        an lx x ly grid (default: the context's): (stats [5] = e_a, e_inf,
+        e~_a, e~_inf, folded; per-square e; per-square e~)."""
+        lx = self.lx if lx is None else lx
+        ly = self.ly if ly is None else ly
+        stats = self._f64(5)
+        e = et = None
+        if per_square:
+            shape = (max(ly - 1, 0), max(lx - 1, 0))
+            e = torch.empty(shape, dtype=torch.float32, device=self.device)
+            et = torch.empty(shape, dtype=torch.float32, device=self.device)
+        ffb_distortion(self.handle, lx, ly, nodes.contiguous(), stats, e, et)
+        return stats, e, et
 
     # adjoints
     def tape_begin(self, max_steps: int = 512):

@@ -186,8 +186,8 @@ int ffb_create(ffb_ctx **out, int32_t lx, int32_t ly, int64_t max_points, void *
     float **planes[] = {&c->t1, &c->t2, &c->pa, &c->pb, &c->pc};
     for (float **pl : planes)
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(pl), sizeof(float) * plane);
-    if (e == hipSuccess) e = grow(&c->red, 0, 1024);
-    c->red_cap = 1024;
+    if (e == hipSuccess) e = grow(&c->red, 0, kRedDoubles);
+    c->red_cap = kRedDoubles;
     if (e == hipSuccess) e = grow(&c->acc, 0, (int64_t)ly * (lx + 1));
     if (e == hipSuccess) e = grow(&c->w_region, 0, 1024);
     if (e == hipSuccess) e = grow(&c->lam_w, 0, 1024);
@@ -327,6 +327,18 @@ int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, floa
     if (st) return st;
     return run_integrate(ctx, fields, rho_bar, xy, n, o, stats, h_out, h_cap,
                          record ? &rec : nullptr);
+}
+
+int ffb_distortion(ffb_ctx *ctx, int32_t lx, int32_t ly, const float *nodes, double *stats,
+                   float *e, float *e_tilde)
+{
+    if (!ctx) return FFB_E_INVALID;
+    if (!nodes || !stats) return fail(ctx, FFB_E_INVALID, "ffb_distortion: NULL argument%s");
+    if (lx < 2 || ly < 2 || (int64_t)lx * ly > ((int64_t)1 << 31))
+        return fail(ctx, FFB_E_INVALID, "ffb_distortion: grid must be at least 2 x 2 nodes%s");
+    hipError_t err = launch_distortion(ctx, lx, ly, reinterpret_cast<const float2 *>(nodes),
+                                       stats, e, e_tilde);
+    return err == hipSuccess ? FFB_OK : hip_fail(ctx, err, "ffb_distortion launch");
 }
 
 int ffb_integrate_record(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,

@@ -9,6 +9,10 @@
 #include "ffb.h"
 
 // Context: stream, sizes, sticky device status and the device workspace.
+// FP64 reduction workspace per context: block partials of the sums and
+// maxima (largest user: 5 statistics x 2048 blocks of the distortion pass).
+constexpr int kRedDoubles = 5 * 2048;
+
 struct ffb_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -22,7 +26,7 @@ struct ffb_ctx {
     float2 *tw_y = nullptr, *tq_y = nullptr;   // ... for length ly
     float *t1 = nullptr, *t2 = nullptr;        // [lx*ly] scratch planes
     float *pa = nullptr, *pb = nullptr, *pc = nullptr;
-    double *red = nullptr;                     // reduction partials
+    double *red = nullptr;                     // reduction partials (kRedDoubles)
     int32_t red_cap = 0;
 
     // raster workspace
@@ -111,6 +115,9 @@ struct advect_tape {
     double *h;            // [cap] accepted step sizes
     int32_t *count;       // [1] accepted steps of the integration
 };
+
+hipError_t launch_distortion(ffb_ctx *ctx, int lx, int ly, const float2 *nodes, double *stats,
+                             float *e, float *e_tilde);
 
 int advect_max_blocks(int *out);
 hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,

@@ -15,5 +15,6 @@ from .voronoi import (  # noqa: F401
     make_map,
     workload,
     grid_nodes,
+    warped_nodes,
     WORKLOADS,
 )

@@ -74,6 +74,26 @@ def grid_nodes(lx: int, ly: int) -> np.ndarray:
     return out
 
 
+def warped_nodes(lx: int, ly: int, seed: int, amp: float = 0.3, modes: int = 6,
+                 linear=((1.0, 0.0), (0.0, 1.0))) -> np.ndarray:
+    """Grid nodes moved by a seeded smooth displacement, float32 [ly*lx, 2]:
+    a linear part (rows of ``linear``) applied to the cell centres plus a sum
+    of ``modes`` random sinusoids per axis, each of amplitude ``amp`` grid
+    units and wavelength between 8 cells and the grid size (at least 8).  Stands in for
+    the positions of the grid nodes after the rounds of a cartogram."""
+    rng = np.random.default_rng(seed)
+    g = grid_nodes(lx, ly).astype(np.float64)
+    A = np.asarray(linear, dtype=np.float64)
+    out = g @ A.T
+    n = max(lx, ly, 8)
+    for axis in range(2):
+        for _ in range(modes):
+            kx, ky = rng.uniform(-1.0, 1.0, 2) * 2.0 * np.pi / rng.uniform(8.0, n)
+            ph = rng.uniform(0.0, 2.0 * np.pi)
+            out[:, axis] += amp * np.sin(kx * g[:, 0] + ky * g[:, 1] + ph)
+    return out.astype(np.float32)
+
+
 # --------------------------------------------------------------------------
 # Voronoi construction with labelled constraint lines
 # --------------------------------------------------------------------------
