@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-maps measurement")
     ap.add_argument("--batch-maps", type=int, default=256)
+    ap.add_argument("--no-rect", action="store_true",
+                    help="skip the rectangular map with holes and multipolygons")
     return ap.parse_args()
 
 
@@ -211,9 +213,66 @@ def main():
         result["grad"] = grad_leg(args, dev)
     if not args.no_batch:
         result["batch"] = batch_leg(args, dev)
+    if not args.no_rect:
+        result["rect"] = rect_leg(args, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(m, pts_h, args)
     print(json.dumps(result), flush=True)
+
+
+def rect_leg(args, dev, name="rect_1024x512", max_rounds=30):
+    """The converging loop on a 1024 x 512 box whose regions include
+    enclaves (host regions with clockwise hole rings) and multipolygons."""
+    import torch
+    import synth
+    import paper_1802_07625_amd as ffb
+
+    m = synth.workload(name)
+    V = m.n_vertices
+    pts_h = np.concatenate([m.xy, synth.grid_nodes(m.lx, m.ly)]).astype(np.float32)
+    pts0 = torch.as_tensor(pts_h, device=dev)
+    pts = pts0.clone()
+    geom = ffb.Geometry.from_map(m, xy=pts[:V])
+    value = torch.as_tensor(m.value, dtype=torch.float64, device=dev)
+    ctx = ffb.Context(m.lx, m.ly, max_points=pts_h.shape[0])
+    opts = ffb.IntegrateOpts(tol=args.tol)
+
+    def loop():
+        pts.copy_(pts0)
+        area, out = None, []
+        for k in range(max_rounds):
+            res = ffb.iterate(ctx, geom, value, pts, ffb.default_sigma(k), opts, area_before=area)
+            area = res.area_after
+            mx = float(res.max_err_after)
+            out.append(mx)
+            if mx < 0.01:
+                break
+        return out
+
+    loop()                                   # warm-up (kernel loading, allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    errs = loop()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    dst, _, _ = ctx.distortion(pts[V:])
+    dst = dst.cpu().numpy()
+    ctx.sync()
+    ctx.close()
+    holes = sum(1 for g in range(m.n_rings) if _signed_ring_area(m, g) < 0)
+    return {"workload": name, "lx": m.lx, "ly": m.ly, "regions": m.n_regions,
+            "rings": m.n_rings, "hole_rings": holes,
+            "multi_ring_regions": int(np.sum(np.bincount(m.ring_region) > 1)),
+            "vertices": V, "points": int(pts_h.shape[0]), "rounds": len(errs),
+            "max_area_error": errs[-1], "total_ms": round(1e3 * total, 2),
+            "distortion": {"e_a": float(dst[0]), "e_inf": float(dst[1]),
+                           "e_tilde_a": float(dst[2]), "e_tilde_inf": float(dst[3]),
+                           "folded_squares": int(dst[4])}}
+
+
+def _signed_ring_area(m, g):
+    p = m.xy[m.ring_vidx[m.ring_offsets[g]:m.ring_offsets[g + 1]]].astype(np.float64)
+    return 0.5 * float(np.sum(p[:, 0] * np.roll(p[:, 1], -1) - np.roll(p[:, 0], -1) * p[:, 1]))
 
 
 def batch_leg(args, dev, max_rounds=30):

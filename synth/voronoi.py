@@ -1,14 +1,14 @@
 """Seeded bounded-Voronoi maps standing in for the paper's country maps.
 
-A map is a set of regions inside an L x L box [0, L]^2 (the paper places the
+A map is a set of regions inside an Lx x Ly box [0, Lx] x [0, Ly] (the paper places the
 mapped area in a rectangular box with reflecting edges and fills the space
 around it with the mean density; main text, section "Flow-based cartogram
 with linear equalization" and the benchmarking section).  Regions are the
-Voronoi cells of seeds drawn uniformly in an inner square, clipped to it.
+Voronoi cells of seeds drawn uniformly in an inner rectangle, clipped to it.
 
 Construction (all FP64, then vertex coordinates rounded once to FP32):
 
-* every cell is built by clipping the inner square with the bisector
+* every cell is built by clipping the inner rectangle with the bisector
   half-planes of the other seeds, nearest first, stopping once no remaining
   seed can reach the cell;
 * every polygon corner carries the pair of constraint lines that meet there,
@@ -18,7 +18,9 @@ Construction (all FP64, then vertex coordinates rounded once to FP32):
 * every edge is split into ceil(length / s) equal parts along its canonical
   direction, so both cells that share an edge reference the same
   subdivision vertices;
-* rings are counter-clockwise, one ring per region (convex cells).
+* rings are counter-clockwise, one ring per region (convex cells), unless
+  enclaves (a region inside another, which then has a clockwise hole ring on
+  the same vertices) or merged cells (one region, two rings) are asked for.
 
 The statistic of region r is value_r = d_r * A_r, where d_r is the drawn
 target density and A_r the area of the cell's FP32 polygon (evaluated here
@@ -97,21 +99,23 @@ def warped_nodes(lx: int, ly: int, seed: int, amp: float = 0.3, modes: int = 6,
 # --------------------------------------------------------------------------
 # Voronoi construction with labelled constraint lines
 # --------------------------------------------------------------------------
-# Edge labels: ("B", side) for the inner square's sides 0=bottom, 1=right,
+# Edge labels: ("B", side) for the inner rectangle's sides 0=bottom, 1=right,
 # 2=top, 3=left; ("S", i, j) with i < j for the bisector of seeds i and j.
+# The inner rectangle is box = (x0, x1, y0, y1).
 
 
-def _line_of(label, seeds, lo, hi):
+def _line_of(label, seeds, box):
     """Return (n, c) with the line n . p = c for a constraint label."""
     if label[0] == "B":
         side = label[1]
+        x0, x1, y0, y1 = box
         if side == 0:
-            return np.array([0.0, 1.0]), lo
+            return np.array([0.0, 1.0]), y0
         if side == 1:
-            return np.array([1.0, 0.0]), hi
+            return np.array([1.0, 0.0]), x1
         if side == 2:
-            return np.array([0.0, 1.0]), hi
-        return np.array([1.0, 0.0]), lo
+            return np.array([0.0, 1.0]), y1
+        return np.array([1.0, 0.0]), x0
     _, i, j = label
     si, sj = seeds[i], seeds[j]
     n = sj - si
@@ -119,9 +123,9 @@ def _line_of(label, seeds, lo, hi):
     return n, c
 
 
-def _intersect(l1, l2, seeds, lo, hi):
-    n1, c1 = _line_of(l1, seeds, lo, hi)
-    n2, c2 = _line_of(l2, seeds, lo, hi)
+def _intersect(l1, l2, seeds, box):
+    n1, c1 = _line_of(l1, seeds, box)
+    n2, c2 = _line_of(l2, seeds, box)
     det = n1[0] * n2[1] - n1[1] * n2[0]
     x = (c1 * n2[1] - c2 * n1[1]) / det
     y = (n1[0] * c2 - n2[0] * c1) / det
@@ -140,25 +144,26 @@ def _vertex_key(l_in, l_out):
     return ("E", s[1], s[2], e[1])
 
 
-def _key_point(key, seeds, lo, hi):
+def _key_point(key, seeds, box):
     """Coordinates of a canonical corner, computed from its key only."""
     if key[0] == "V":
         i, j, k = key[1:]
-        return _intersect(("S", i, j), ("S", i, k), seeds, lo, hi)
+        return _intersect(("S", i, j), ("S", i, k), seeds, box)
     if key[0] == "C":
-        return _intersect(("B", key[1]), ("B", key[2]), seeds, lo, hi)
+        return _intersect(("B", key[1]), ("B", key[2]), seeds, box)
     _, i, j, side = key
-    return _intersect(("S", i, j), ("B", side), seeds, lo, hi)
+    return _intersect(("S", i, j), ("B", side), seeds, box)
 
 
-def _voronoi_cells(seeds: np.ndarray, lo: float, hi: float):
+def _voronoi_cells(seeds: np.ndarray, box):
     """List of cells; each cell is a list of (point, outgoing label)."""
     n = seeds.shape[0]
+    x0, x1, y0, y1 = box
     cells = []
     for i in range(n):
         si = seeds[i]
-        poly = [(np.array([lo, lo]), ("B", 0)), (np.array([hi, lo]), ("B", 1)),
-                (np.array([hi, hi]), ("B", 2)), (np.array([lo, hi]), ("B", 3))]
+        poly = [(np.array([x0, y0]), ("B", 0)), (np.array([x1, y0]), ("B", 1)),
+                (np.array([x1, y1]), ("B", 2)), (np.array([x0, y1]), ("B", 3))]
         d = np.hypot(seeds[:, 0] - si[0], seeds[:, 1] - si[1])
         order = np.argsort(d, kind="stable")
         for j in order:
@@ -190,7 +195,8 @@ def _voronoi_cells(seeds: np.ndarray, lo: float, hi: float):
 
 
 def _cell_area(pts: np.ndarray) -> float:
-    """Area of a convex polygon by a triangle fan from its first corner."""
+    """Signed area (counter-clockwise positive) of a simple polygon by a
+    triangle fan from its first corner."""
     o = pts[0]
     a = 0.0
     for k in range(1, len(pts) - 1):
@@ -213,21 +219,36 @@ def _draw_density(rng, kind: str, n: int) -> np.ndarray:
 def make_map(L: int, n_seeds: int, seed: int, density: str,
              inner: tuple[float, float] | None = None,
              target_vertices: int | None = None,
-             spacing: float | None = None, name: str = "") -> CartogramMap:
-    """Build one seeded Voronoi map.
+             spacing: float | None = None, name: str = "",
+             ly: int | None = None, inner_y: tuple[float, float] | None = None,
+             enclaves: int = 0, merges: int = 0) -> CartogramMap:
+    """Build one seeded Voronoi map in an L x ly box (ly defaults to L).
 
     Exactly one of ``target_vertices`` (total unique edge length divided by
     this count gives the subdivision spacing s) or ``spacing`` (s itself)
-    sets the edge subdivision.
+    sets the edge subdivision.  ``inner`` and ``inner_y`` bound the seeds
+    and the cells along x and y (default: the middle two thirds of each
+    side).  ``enclaves`` cells each get a region inside them (their seed's
+    cell scaled by 0.45 about the seed) that the host region surrounds as a
+    hole: a second, clockwise ring of the host on the same vertices.
+    ``merges`` pairs of cells become one region with two rings
+    (multipolygons).  Region densities are drawn per region.
     """
+    Ly = L if ly is None else int(ly)
     if inner is None:
         inner = (L / 6.0, 5.0 * L / 6.0)
+    if inner_y is None:
+        inner_y = inner if Ly == L else (Ly / 6.0, 5.0 * Ly / 6.0)
     lo, hi = float(inner[0]), float(inner[1])
+    box = (lo, hi, float(inner_y[0]), float(inner_y[1]))
     rng = np.random.default_rng(seed)
-    seeds = rng.uniform(lo, hi, size=(n_seeds, 2))
+    if box[2:] == box[:2]:
+        seeds = rng.uniform(lo, hi, size=(n_seeds, 2))
+    else:
+        seeds = rng.uniform((box[0], box[2]), (box[1], box[3]), size=(n_seeds, 2))
     dens = _draw_density(rng, density, n_seeds)
 
-    cells = _voronoi_cells(seeds, lo, hi)
+    cells = _voronoi_cells(seeds, box)
 
     # canonical corners
     key_id: dict = {}
@@ -242,7 +263,7 @@ def make_map(L: int, n_seeds: int, seed: int, density: str,
             key = _vertex_key(lin, lout)
             if key not in key_id:
                 key_id[key] = len(key_pts)
-                key_pts.append(_key_point(key, seeds, lo, hi))
+                key_pts.append(_key_point(key, seeds, box))
             ks.append(key_id[key])
         # drop repeated consecutive corners (degenerate zero-length edges)
         ks2 = [ks[k] for k in range(len(ks)) if ks[k] != ks[k - 1]]
@@ -301,19 +322,57 @@ def make_map(L: int, n_seeds: int, seed: int, density: str,
         ring_vidx.append(ring)
         ring_offsets.append(ring_offsets[-1] + ring.shape[0])
 
+    ring_region = list(range(n_seeds))
+    if enclaves or merges:
+        pick = rng.permutation(n_seeds)
+        hosts = pick[:enclaves]
+        pairs = pick[enclaves:enclaves + 2 * merges].reshape(-1, 2)
+        region_of_cell = np.arange(n_seeds)
+        for a, b in pairs:
+            region_of_cell[b] = region_of_cell[a]
+        ring_region = [int(region_of_cell[c]) for c in range(n_seeds)]
+        next_region = n_seeds
+        for c in hosts:
+            # enclave corners: the cell's corners pulled towards its seed
+            ks = cell_keys[c]
+            pts = seeds[c][None, :] + 0.45 * (corners[ks] - seeds[c][None, :])
+            ring = []
+            for k in range(len(ks)):
+                p0, p1 = pts[k], pts[(k + 1) % len(ks)]
+                length = float(np.hypot(*(p1 - p0)))
+                nseg = max(1, int(math.ceil(length / spacing))) if math.isfinite(spacing) else 1
+                w = np.arange(0, nseg, dtype=np.float64)[:, None] / nseg
+                xy_list.append(p0[None, :] + w * (p1 - p0)[None, :])
+                ring.append(np.arange(n_xy[0], n_xy[0] + nseg, dtype=np.int64))
+                n_xy[0] += nseg
+            ring = np.concatenate(ring)
+            # the host's hole (clockwise), then the enclave (counter-clockwise)
+            for rr, reg in ((ring[::-1], ring_region[c]), (ring, next_region)):
+                ring_vidx.append(rr)
+                ring_offsets.append(ring_offsets[-1] + rr.shape[0])
+                ring_region.append(reg)
+            next_region += 1
+        # compact region ids in order of first appearance
+        ids = {}
+        ring_region = [ids.setdefault(r, len(ids)) for r in ring_region]
+    n_regions = max(ring_region) + 1
+    if n_regions != n_seeds:
+        dens = np.concatenate([dens, _draw_density(rng, density, max(0, n_regions - n_seeds))])
+        dens = dens[:n_regions]
+
     xy = np.concatenate(xy_list, axis=0).astype(np.float32)
     ring_offsets_a = np.array(ring_offsets, dtype=np.int32)
     ring_vidx_a = np.concatenate(ring_vidx).astype(np.int32)
-    ring_region = np.arange(n_seeds, dtype=np.int32)
+    ring_region_a = np.array(ring_region, dtype=np.int32)
 
-    areas = np.empty(n_seeds)
-    for r in range(n_seeds):
-        pts = xy[ring_vidx_a[ring_offsets_a[r]:ring_offsets_a[r + 1]]].astype(np.float64)
-        areas[r] = _cell_area(pts)
+    areas = np.zeros(n_regions)
+    for g in range(ring_region_a.shape[0]):
+        pts = xy[ring_vidx_a[ring_offsets_a[g]:ring_offsets_a[g + 1]]].astype(np.float64)
+        areas[ring_region_a[g]] += _cell_area(pts)
     value = dens * areas
-    return CartogramMap(lx=L, ly=L, xy=xy, ring_offsets=ring_offsets_a,
-                        ring_vidx=ring_vidx_a, ring_region=ring_region,
-                        n_regions=n_seeds, density=dens, value=value,
+    return CartogramMap(lx=L, ly=Ly, xy=xy, ring_offsets=ring_offsets_a,
+                        ring_vidx=ring_vidx_a, ring_region=ring_region_a,
+                        n_regions=n_regions, density=dens, value=value,
                         seeds=seeds, name=name)
 
 
@@ -334,6 +393,16 @@ WORKLOADS = {
     # L = 512, 50 seeds, lognormal: the differentiation workload.
     "c5_L512": dict(L=512, n_seeds=50, seed=5, density="lognormal",
                     target_vertices=100_000),
+    # Rectangular boxes with holes and multipolygons: enclaves inside their
+    # host regions (the host has a clockwise ring around each) and pairs of
+    # cells merged into one region with two rings.
+    "rect_128x64": dict(L=128, ly=64, n_seeds=24, seed=6, density="loguniform",
+                        inner=(16.0, 112.0), inner_y=(8.0, 56.0), target_vertices=4000,
+                        enclaves=3, merges=2),
+    "rect_256x512": dict(L=256, ly=512, n_seeds=60, seed=7, density="lognormal",
+                         spacing=0.5, enclaves=4, merges=3),
+    "rect_1024x512": dict(L=1024, ly=512, n_seeds=300, seed=8, density="lognormal",
+                          target_vertices=500_000, enclaves=20, merges=10),
 }
 
 

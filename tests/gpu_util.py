@@ -67,3 +67,25 @@ def area_bound(m, xy_ref, dx):
     dx * sum over edges (|dx_e| + |dy_e|); 1 % covers the second order, and
     1e-12 relative the FP64 sums."""
     return 1.01 * dx * l1_perimeters(m, xy_ref)
+
+
+def gpu_gradient(m, density, sigmas, schedules=None, with_grid=False, max_steps=512):
+    """dL/dd on the device through FFBFunction and torch autograd."""
+    V = m.n_vertices
+    pts_np = m.xy.astype(np.float32)
+    if with_grid:
+        pts_np = np.concatenate([pts_np, synth.grid_nodes(m.lx, m.ly)])
+    pts = dev_f32(pts_np).reshape(-1, 2)
+    ctx = new_ctx(m.lx, m.ly, max_points=pts.shape[0])
+    geom = ffb.Geometry.from_map(m, pts[:V])
+    a0, _, _ = ctx.area_error(geom, dev_f64(np.ones(m.n_regions)))
+    d = dev_f64(density).requires_grad_(True)
+    value = d * a0
+    replay = None if schedules is None else [dev_f64(s) for s in schedules]
+    area = ffb.FFBFunction.apply(value, ctx, geom, pts, sigmas, None, max_steps, replay)
+    T = value * area.sum() / value.sum()
+    e = area / T - 1.0
+    loss = (e * e).sum()
+    loss.backward()
+    assert ctx.sync(check=False) == 0
+    return float(loss.detach()), to_np(d.grad)

@@ -17,7 +17,7 @@ import torch
 import oracle
 import paper_1802_07625_amd as ffb
 import synth
-from gpu_util import dev_f32, dev_f64, new_ctx, pack_oracle_fields, to_np
+from gpu_util import dev_f32, dev_f64, gpu_gradient, new_ctx, pack_oracle_fields, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -249,28 +249,6 @@ def test_integrate_adj_tape_overflow_sets_status():
 SIGMAS = [oracle.default_sigma(k) for k in range(3)]
 
 
-def _gpu_gradient(m, density, sigmas, schedules=None, with_grid=False, max_steps=512):
-    """dL/dd on the device through FFBFunction and torch autograd."""
-    V = m.n_vertices
-    pts_np = m.xy.astype(np.float32)
-    if with_grid:
-        pts_np = np.concatenate([pts_np, synth.grid_nodes(m.lx, m.ly)])
-    pts = dev_f32(pts_np).reshape(-1, 2)
-    ctx = new_ctx(m.lx, max_points=pts.shape[0])
-    geom = ffb.Geometry.from_map(m, pts[:V])
-    a0, _, _ = ctx.area_error(geom, dev_f64(np.ones(m.n_regions)))
-    d = dev_f64(density).requires_grad_(True)
-    value = d * a0
-    replay = None if schedules is None else [dev_f64(s) for s in schedules]
-    area = ffb.FFBFunction.apply(value, ctx, geom, pts, sigmas, None, max_steps, replay)
-    T = value * area.sum() / value.sum()
-    e = area / T - 1.0
-    loss = (e * e).sum()
-    loss.backward()
-    assert ctx.sync(check=False) == 0
-    return float(loss.detach()), to_np(d.grad)
-
-
 def test_backward_matches_oracle_fd_c1():
     """Gradient of the 3-round area loss w.r.t. the region densities vs the
     oracle's central differences (h = 1e-4), schedules frozen at the
@@ -278,7 +256,7 @@ def test_backward_matches_oracle_fd_c1():
     m = synth.workload("c1_L64")
     ref = oracle.rounds(m, m.density, SIGMAS)
     g_fd = oracle.fd_gradient(m, m.density, SIGMAS, ref.schedules, step=1e-4)
-    loss, g = _gpu_gradient(m, m.density, SIGMAS, ref.schedules)
+    loss, g = gpu_gradient(m, m.density, SIGMAS, ref.schedules)
     assert _rel(loss, ref.loss) < 1e-3
     err = np.max(np.abs(g - g_fd)) / np.max(np.abs(g_fd))
     assert err < 1e-3, (err, g, g_fd)
@@ -288,7 +266,7 @@ def test_backward_scale_invariance():
     """The loss is invariant under d -> c d (velocities and targets do not
     change), so sum_r d_r dL/dd_r = 0; holds at any size and schedule."""
     m = synth.workload("c1_L64")
-    _, g = _gpu_gradient(m, m.density, SIGMAS)
+    _, g = gpu_gradient(m, m.density, SIGMAS)
     s = float(np.dot(m.density, g))
     assert abs(s) < 1e-3 * float(np.sum(np.abs(m.density * g))), s
 
@@ -297,7 +275,7 @@ def test_backward_uniform_density_is_minimum():
     """Uniform densities: no flow, zero loss, zero gradient."""
     m = synth.workload("c1_L64")
     d = np.full(m.n_regions, 1.7)
-    loss, g = _gpu_gradient(m, d, SIGMAS)
+    loss, g = gpu_gradient(m, d, SIGMAS)
     # FP32 transforms of a constant leave ~1e-7 relative residue in the
     # higher modes, so the flow and the loss are zero only to that level
     assert loss < 1e-12
@@ -309,8 +287,8 @@ def test_backward_grid_points_do_not_change_gradient():
     leaves the area gradient unchanged up to FP32 rounding."""
     m = synth.workload("c1_L64")
     ref = oracle.rounds(m, m.density, SIGMAS)
-    _, g0 = _gpu_gradient(m, m.density, SIGMAS, ref.schedules)
-    _, g1 = _gpu_gradient(m, m.density, SIGMAS, ref.schedules, with_grid=True)
+    _, g0 = gpu_gradient(m, m.density, SIGMAS, ref.schedules)
+    _, g1 = gpu_gradient(m, m.density, SIGMAS, ref.schedules, with_grid=True)
     assert np.max(np.abs(g0 - g1)) <= 1e-5 * np.max(np.abs(g0))
 
 
@@ -377,7 +355,7 @@ def test_backward_matches_oracle_golden_c5_full_size(with_grid):
     alone), the oracle's schedules replayed on the device."""
     m = synth.workload("c5_L512")
     loss_ref, sched, g_fd = _golden_c5()
-    loss, g = _gpu_gradient(m, m.density, SIGMAS, sched, with_grid=with_grid)
+    loss, g = gpu_gradient(m, m.density, SIGMAS, sched, with_grid=with_grid)
     assert _rel(loss, loss_ref) < 1e-4
     err = np.max(np.abs(g - g_fd)) / np.max(np.abs(g_fd))
     print(f"[grad] c5 grid={with_grid} loss={loss:.9e} ref={loss_ref:.9e} max rel err={err:.3e}",
