@@ -54,12 +54,14 @@ _d = ctypes.POINTER(ctypes.c_double)
 _i32 = ctypes.POINTER(ctypes.c_int32)
 
 
-def lib():
+def lib(path: str | None = None):
+    """The oracle library (``path``: load another build of the same source,
+    e.g. to compare two revisions; it then becomes the one in use)."""
     global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+    if _lib is None or path is not None:
+        if path is None and not os.path.exists(_LIB):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path or _LIB)
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.ffbo_set_threads.argtypes = [ctypes.c_int]
         L.ffbo_region_areas.argtypes = [i64, _d, i32, _i32, _i32, _i32, i32, _d]
@@ -74,6 +76,11 @@ def lib():
         L.ffbo_integrate.argtypes = [i32, i32, _d, _d, _d, dbl, i64, _d,
                                      dbl, dbl, dbl, dbl, dbl, dbl, i32,
                                      _d, i32, _i32, _i32, _d, i32]
+        if hasattr(L, "ffbo_diff_fields"):
+            L.ffbo_diff_fields.argtypes = [i32, i32, _d, dbl, _d, _d, _d]
+            L.ffbo_diff_integrate.argtypes = [i32, i32, _d, dbl, i64, _d,
+                                              dbl, dbl, dbl, dbl, dbl, dbl, i32,
+                                              _d, i32, _i32, _i32, _d, i32]
         _lib = L
     return _lib
 
@@ -288,6 +295,73 @@ def iterate(m, value, points, n_vertices: int, sigma: float,
     res = integrate(F, pts, opts, replay_h)
     a1 = region_areas(m, res.xy[:n_vertices])
     e1, mx = area_error(value, a1)
+    return RoundResult(res.xy, a0, a1, e1, mx, rho, pad, F, res.accepted,
+                       res.rejected, res.h)
+
+
+# ------------------------------------------------------- diffusion variant
+# The improper integral of the diffusion cartogram is cut at
+# t_end = DIFF_K * max(lx, ly)^2: every non-constant mode has then decayed by
+# at least exp(-DIFF_K) (the slowest, m = 1 or n = 1 along the longer side,
+# decays as exp(-t / max(lx, ly)^2)).
+DIFF_K = 12.0
+
+
+def diffusion_t_end(lx: int, ly: int, K: float = DIFF_K) -> float:
+    return K * float(max(lx, ly)) ** 2
+
+
+def diffusion_fields(coef, t: float, rho_bar: float | None = None) -> Fields:
+    """rho(t), J(t) on the nodes for f_mn(t) = exp(-(m^2/lx^2 + n^2/ly^2) t)
+    (SI Appendix, section 2, the diffusion choice) from the blurred Eq. 7
+    coefficients ``coef`` [n, m] (as ``coefficients``)."""
+    coef = _f64(coef)
+    ly, lx = coef.shape
+    rt, jx, jy = np.zeros_like(coef), np.zeros_like(coef), np.zeros_like(coef)
+    _check(lib().ffbo_diff_fields(lx, ly, _p(coef), float(t), _p(rt), _p(jx), _p(jy)),
+           "diff_fields")
+    rb = float(coef[0, 0]) / (lx * ly) if rho_bar is None else rho_bar
+    return Fields(lx, ly, rt, jx, jy, rb, coef)
+
+
+def diffusion_integrate(coef, pts, t_end: float, opts: IntegrateOpts | None = None,
+                        replay_h=None) -> IntegrateResult:
+    """Advect points from t = 0 to t_end with v = J(t) / rho(t) of the
+    diffusion choice; the same controller as ``integrate``."""
+    opts = opts or IntegrateOpts()
+    coef = _f64(coef)
+    ly, lx = coef.shape
+    xy = _f64(pts).reshape(-1, 2).copy()
+    cap = opts.max_attempts + 1
+    hout = np.zeros(cap)
+    acc = np.zeros(1, np.int32)
+    rej = np.zeros(1, np.int32)
+    rh = None if replay_h is None else _f64(replay_h)
+    code = lib().ffbo_diff_integrate(lx, ly, _p(coef), float(t_end), xy.shape[0], _p(xy),
+                                     opts.tol, opts.h0, opts.safety, opts.fac_min,
+                                     opts.fac_max, opts.h_min, opts.max_attempts,
+                                     _p(rh) if rh is not None else None,
+                                     0 if rh is None else rh.shape[0],
+                                     _p(acc, _i32), _p(rej, _i32), _p(hout), cap)
+    _check(code, "diff_integrate")
+    return IntegrateResult(xy, int(acc[0]), int(rej[0]), hout[:int(acc[0])].copy())
+
+
+def iterate_diffusion(m, value, points, n_vertices: int, sigma: float,
+                      opts: IntegrateOpts | None = None, replay_h=None,
+                      t_end: float | None = None) -> RoundResult:
+    """One round of the diffusion variant: the same areas, raster, Eq. 7
+    coefficients and blur as ``iterate``, then the diffusion flow to t_end."""
+    pts = _f64(points).reshape(-1, 2)
+    verts = pts[:n_vertices]
+    a0 = region_areas(m, verts)
+    rho, pad = density(m, value, a0, xy=verts)
+    coef, rb = coefficients(rho, sigma)
+    te = diffusion_t_end(m.lx, m.ly) if t_end is None else t_end
+    res = diffusion_integrate(coef, pts, te, opts, replay_h)
+    a1 = region_areas(m, res.xy[:n_vertices])
+    e1, mx = area_error(value, a1)
+    F = diffusion_fields(coef, 0.0, rb)
     return RoundResult(res.xy, a0, a1, e1, mx, rho, pad, F, res.accepted,
                        res.rejected, res.h)
 

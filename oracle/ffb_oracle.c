@@ -16,7 +16,9 @@
  *   - the flux sums of the SI Appendix (section 2, the equations for J_x and
  *     J_y of linear equalisation) as direct separable sums;
  *   - the velocity v = J / rho_t with rho_t of Eq. 4, bilinear interpolation
- *     between grid points, and Dormand-Prince 5(4) integration to t = 1.
+ *     between grid points, and Dormand-Prince 5(4) integration to t = 1;
+ *   - the diffusion variant of the SI Appendix (section 2) for comparison:
+ *     fields rebuilt at every stage time, integration to a cut-off time.
  * Readings of points where the paper is silent are stated at each function.
  *
  * Parity of the integrator controller constants (tolerance, initial step,
@@ -555,13 +557,36 @@ void ffbo_tableau(double *c, double *a, double *b, double *bs)
     }
 }
 
+/* Where the stage velocities come from: the field set to use at stage time
+ * ts and the time argument that velocity_at takes with it.  For the fast
+ * flow-based method the fields are fixed and rho_t carries the time; a
+ * variant whose fields change with t returns fields already taken at ts. */
+typedef struct field_source {
+    const field_t *(*at)(struct field_source *self, double ts, double *tv, int *status);
+} field_source;
+
+typedef struct {
+    field_source base;
+    field_t F;
+} fixed_source;
+
+static const field_t *fixed_at(field_source *self, double ts, double *tv, int *status)
+{
+    (void)status;
+    *tv = ts;
+    return &((fixed_source *)self)->F;
+}
+
 /* One attempt of size h from (y, t) with k[0] = v(y, t) already known.
- * Writes the order-5 solution to ynew, its velocity to k[6], returns err. */
-static double dp_attempt(const field_t *F, int64_t n, const double *y, double t, double h,
-                         double *k[7], double *ynew)
+ * Writes the order-5 solution to ynew, its velocity to k[6], returns err
+ * (INFINITY with *status set when a field evaluation fails). */
+static double dp_attempt(field_source *src, int64_t n, const double *y, double t, double h,
+                         double *k[7], double *ynew, int *status)
 {
     for (int s = 1; s < 7; ++s) {
-        double ts = t + DP_C[s] * h;
+        double tv;
+        const field_t *F = src->at(src, t + DP_C[s] * h, &tv, status);
+        if (*status) return INFINITY;
         double *dst = (s == 6) ? ynew : NULL;
 #pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < n; ++p) {
@@ -571,7 +596,7 @@ static double dp_attempt(const field_t *F, int64_t n, const double *y, double t,
                 qy += h * DP_A[s][q] * k[q][2 * p + 1];
             }
             if (dst) { dst[2 * p] = qx; dst[2 * p + 1] = qy; }
-            velocity_at(F, ts, qx, qy, &k[s][2 * p], &k[s][2 * p + 1]);
+            velocity_at(F, tv, qx, qy, &k[s][2 * p], &k[s][2 * p + 1]);
         }
     }
     double err = 0.0;
@@ -587,19 +612,12 @@ static double dp_attempt(const field_t *F, int64_t n, const double *y, double t,
     return err;
 }
 
-int ffbo_integrate(int32_t lx, int32_t ly, const double *rho_s, const double *jx,
-                   const double *jy, double rho_bar, int64_t n, double *xy,
-                   double tol, double h0, double safety, double fac_min, double fac_max,
-                   double h_min, int32_t max_attempts,
-                   const double *replay_h, int32_t n_replay,
-                   int32_t *accepted_out, int32_t *rejected_out,
-                   double *h_out, int32_t h_cap)
+/* The controller described above, from t = 0 to exactly t = t_end. */
+static int dp_run(field_source *src, int64_t n, double *xy, double t_end, double tol, double h0,
+                  double safety, double fac_min, double fac_max, double h_min,
+                  int32_t max_attempts, const double *replay_h, int32_t n_replay,
+                  int32_t *accepted_out, int32_t *rejected_out, double *h_out, int32_t h_cap)
 {
-    if (lx <= 0 || ly <= 0 || n < 0 || !(rho_bar > 0.0)) return O_E_INVALID;
-    if (!replay_h && (!(tol > 0.0) || !(h0 > 0.0) || max_attempts <= 0)) return O_E_INVALID;
-    for (int64_t k = 0; k < 2 * n; ++k)
-        if (!isfinite(xy[k])) return O_E_NONFINITE;
-    field_t F = {lx, ly, rho_s, jx, jy, rho_bar};
     double *k[7];
     double *ynew = (double *)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
     int ok = ynew != NULL;
@@ -611,19 +629,25 @@ int ffbo_integrate(int32_t lx, int32_t ly, const double *rho_s, const double *jx
     int32_t acc = 0, rej = 0;
     if (!ok) { st = O_E_NOMEM; goto done; }
 
+    {
+        double tv;
+        const field_t *F0 = src->at(src, 0.0, &tv, &st);
+        if (st) goto done;
 #pragma omp parallel for schedule(static)
-    for (int64_t p = 0; p < n; ++p)
-        velocity_at(&F, 0.0, xy[2 * p], xy[2 * p + 1], &k[0][2 * p], &k[0][2 * p + 1]);
+        for (int64_t p = 0; p < n; ++p)
+            velocity_at(F0, tv, xy[2 * p], xy[2 * p + 1], &k[0][2 * p], &k[0][2 * p + 1]);
+    }
 
     double t = 0.0;
     if (replay_h) {
         for (int32_t s = 0; s < n_replay; ++s) {
             double h = replay_h[s];
-            double err = dp_attempt(&F, n, xy, t, h, k, ynew);
+            double err = dp_attempt(src, n, xy, t, h, k, ynew, &st);
+            if (st) break;
             if (!isfinite(err)) { st = O_E_NONFINITE; break; }
             memcpy(xy, ynew, sizeof(double) * 2 * (size_t)n);
             double *tmp = k[0]; k[0] = k[6]; k[6] = tmp;
-            t = (s == n_replay - 1) ? 1.0 : t + h;
+            t = (s == n_replay - 1) ? t_end : t + h;
             if (h_out && acc < h_cap) h_out[acc] = h;
             acc++;
         }
@@ -633,19 +657,20 @@ int ffbo_integrate(int32_t lx, int32_t ly, const double *rho_s, const double *jx
     double h = h0;
     int last_rejected = 0;
     int32_t attempts = 0;
-    while (t < 1.0) {
+    while (t < t_end) {
         if (attempts >= max_attempts) { st = O_E_MAX_ATTEMPTS; break; }
-        int final_step = h >= 1.0 - t;
-        if (final_step) h = 1.0 - t;
-        double err = dp_attempt(&F, n, xy, t, h, k, ynew);
+        int final_step = h >= t_end - t;
+        if (final_step) h = t_end - t;
+        double err = dp_attempt(src, n, xy, t, h, k, ynew, &st);
         attempts++;
+        if (st) break;
         if (!isfinite(err)) { st = O_E_NONFINITE; break; }
         if (err <= tol) {
             memcpy(xy, ynew, sizeof(double) * 2 * (size_t)n);
             double *tmp = k[0]; k[0] = k[6]; k[6] = tmp;
             if (h_out && acc < h_cap) h_out[acc] = h;
             acc++;
-            t = final_step ? 1.0 : t + h;
+            t = final_step ? t_end : t + h;
             double fac = (err == 0.0) ? fac_max : safety * pow(err / tol, -0.2);
             if (fac < fac_min) fac = fac_min;
             if (fac > fac_max) fac = fac_max;
@@ -659,12 +684,159 @@ int ffbo_integrate(int32_t lx, int32_t ly, const double *rho_s, const double *jx
             h *= fac;
             last_rejected = 1;
         }
-        if (t < 1.0 && h < h_min) { st = O_E_STEP_UNDERFLOW; break; }
+        if (t < t_end && h < h_min) { st = O_E_STEP_UNDERFLOW; break; }
     }
 done:
     free(ynew);
     for (int s = 0; s < 7; ++s) free(k[s]);
     if (accepted_out) *accepted_out = acc;
     if (rejected_out) *rejected_out = rej;
+    return st;
+}
+
+int ffbo_integrate(int32_t lx, int32_t ly, const double *rho_s, const double *jx,
+                   const double *jy, double rho_bar, int64_t n, double *xy,
+                   double tol, double h0, double safety, double fac_min, double fac_max,
+                   double h_min, int32_t max_attempts,
+                   const double *replay_h, int32_t n_replay,
+                   int32_t *accepted_out, int32_t *rejected_out,
+                   double *h_out, int32_t h_cap)
+{
+    if (lx <= 0 || ly <= 0 || n < 0 || !(rho_bar > 0.0)) return O_E_INVALID;
+    if (!replay_h && (!(tol > 0.0) || !(h0 > 0.0) || max_attempts <= 0)) return O_E_INVALID;
+    for (int64_t k = 0; k < 2 * n; ++k)
+        if (!isfinite(xy[k])) return O_E_NONFINITE;
+    fixed_source src = {{fixed_at}, {lx, ly, rho_s, jx, jy, rho_bar}};
+    return dp_run(&src.base, n, xy, 1.0, tol, h0, safety, fac_min, fac_max, h_min,
+                  max_attempts, replay_h, n_replay, accepted_out, rejected_out, h_out, h_cap);
+}
+
+/* ------------------------------------------------------------------------
+ * The diffusion cartogram as a flow-based projection (SI Appendix,
+ * section 2, the diffusion choice of f_mn): with the same coefficients
+ * rts_mn (Eq. 7 and the blur, as ffbo_coefficients),
+ *
+ *   f_mn(t) = exp(-(m^2/lx^2 + n^2/ly^2) t),
+ *   rho(t)  = (1/(lx ly)) sum_mn rts_mn f_mn(t) cos(m pi x/lx) cos(n pi y/ly),
+ *   J_x(t)  = (1/(lx ly)) sum_{m>=1,n>=0} (m / (pi lx)) rts_mn f_mn(t) sin cos,
+ *   J_y(t)  = (1/(lx ly)) sum_{m>=0,n>=1} (n / (pi ly)) rts_mn f_mn(t) cos sin,
+ *
+ * at the nodes (i + 1/2, j + 1/2), and v = J(t) / rho(t).  The fields
+ * depend on t, so every stage time of the integrator needs them anew.  The
+ * improper integral to t = infinity is cut at a caller-given t_end.
+ * ---------------------------------------------------------------------- */
+int ffbo_diff_fields(int32_t lx, int32_t ly, const double *coef, double t, double *rho_t,
+                     double *jx, double *jy)
+{
+    if (lx <= 0 || ly <= 0 || !(t >= 0.0)) return O_E_INVALID;
+    const int64_t N = (int64_t)lx * ly;
+    double *G = (double *)malloc(sizeof(double) * N);
+    double *A = (double *)malloc(sizeof(double) * N);
+    double *B = (double *)malloc(sizeof(double) * N);
+    double *C = (double *)malloc(sizeof(double) * N);
+    double *tx = make_table(lx), *ty = make_table(ly);
+    if (!G || !A || !B || !C || !tx || !ty) {
+        free(G); free(A); free(B); free(C); free(tx); free(ty);
+        return O_E_NOMEM;
+    }
+    const double LX = lx, LY = ly;
+    /* g_mn = rts_mn f_mn(t) */
+    for (int32_t n = 0; n < ly; ++n)
+        for (int32_t m = 0; m < lx; ++m) {
+            double k2 = (double)m * m / (LX * LX) + (double)n * n / (LY * LY);
+            G[(int64_t)n * lx + m] = coef[(int64_t)n * lx + m] * exp(-k2 * t);
+        }
+    /* pass over n for each node row j and x frequency m */
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t m = 0; m < lx; ++m) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int32_t n = 0; n < ly; ++n) {
+                double g = G[(int64_t)n * lx + m];
+                double cy = tcos(ty, ly, n, j), sy = tsin(ty, ly, n, j);
+                a += g * cy;
+                if (m > 0) b += ((double)m / (PI * LX)) * g * cy;
+                if (n > 0) c += ((double)n / (PI * LY)) * g * sy;
+            }
+            A[(int64_t)j * lx + m] = a;
+            B[(int64_t)j * lx + m] = b;
+            C[(int64_t)j * lx + m] = c;
+        }
+    /* pass over m for each node (i, j) */
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t i = 0; i < lx; ++i) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int32_t m = 0; m < lx; ++m) {
+                double cx = tcos(tx, lx, m, i), sx = tsin(tx, lx, m, i);
+                a += A[(int64_t)j * lx + m] * cx;
+                b += B[(int64_t)j * lx + m] * sx;
+                c += C[(int64_t)j * lx + m] * cx;
+            }
+            rho_t[(int64_t)j * lx + i] = a / (double)N;
+            jx[(int64_t)j * lx + i] = b / (double)N;
+            jy[(int64_t)j * lx + i] = c / (double)N;
+        }
+    free(G); free(A); free(B); free(C); free(tx); free(ty);
+    double mn = INFINITY;
+    for (int64_t c = 0; c < N; ++c) if (rho_t[c] < mn) mn = rho_t[c];
+    return (mn > 0.0) ? O_OK : O_E_NONPOSITIVE;
+}
+
+/* Fields recomputed at each new stage time; stages at equal times (the
+ * last two of an attempt) share one evaluation. */
+typedef struct {
+    field_source base;
+    int32_t lx, ly;
+    const double *coef;
+    double *rho_t, *jx, *jy;
+    double last_t;
+    int have;
+    field_t F;
+} diff_source;
+
+static const field_t *diff_at(field_source *self, double ts, double *tv, int *status)
+{
+    diff_source *d = (diff_source *)self;
+    if (!d->have || d->last_t != ts) {
+        int st = ffbo_diff_fields(d->lx, d->ly, d->coef, ts, d->rho_t, d->jx, d->jy);
+        if (st) { *status = st; return &d->F; }
+        d->last_t = ts;
+        d->have = 1;
+    }
+    *tv = 0.0;   /* rho_t of the field set is rho(ts) itself */
+    return &d->F;
+}
+
+int ffbo_diff_integrate(int32_t lx, int32_t ly, const double *coef, double t_end, int64_t n,
+                        double *xy, double tol, double h0, double safety, double fac_min,
+                        double fac_max, double h_min, int32_t max_attempts,
+                        const double *replay_h, int32_t n_replay, int32_t *accepted_out,
+                        int32_t *rejected_out, double *h_out, int32_t h_cap)
+{
+    if (lx <= 0 || ly <= 0 || n < 0 || !(t_end > 0.0) || !(coef[0] > 0.0)) return O_E_INVALID;
+    if (!replay_h && (!(tol > 0.0) || !(h0 > 0.0) || max_attempts <= 0)) return O_E_INVALID;
+    for (int64_t k = 0; k < 2 * n; ++k)
+        if (!isfinite(xy[k])) return O_E_NONFINITE;
+    const int64_t N = (int64_t)lx * ly;
+    diff_source src;
+    memset(&src, 0, sizeof src);
+    src.base.at = diff_at;
+    src.lx = lx;
+    src.ly = ly;
+    src.coef = coef;
+    src.rho_t = (double *)malloc(sizeof(double) * N);
+    src.jx = (double *)malloc(sizeof(double) * N);
+    src.jy = (double *)malloc(sizeof(double) * N);
+    if (!src.rho_t || !src.jx || !src.jy) {
+        free(src.rho_t); free(src.jx); free(src.jy);
+        return O_E_NOMEM;
+    }
+    /* rho_bar only enters velocity_at through t * rho_bar with t = 0 */
+    field_t F = {lx, ly, src.rho_t, src.jx, src.jy, coef[0] / (double)N};
+    src.F = F;
+    int st = dp_run(&src.base, n, xy, t_end, tol, h0, safety, fac_min, fac_max, h_min,
+                    max_attempts, replay_h, n_replay, accepted_out, rejected_out, h_out, h_cap);
+    free(src.rho_t); free(src.jx); free(src.jy);
     return st;
 }
