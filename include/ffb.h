@@ -131,8 +131,10 @@ const char *ffb_last_error(const ffb_ctx *ctx);
  *     (about 2.5 M points on 256 CUs); otherwise mode 0 runs.
  *   FFB_OPT_ADVECT_BLOCKS: cap on the persistent workgroups of
  *     ffb_integrate (0 = one per CU, the default).
+ *   FFB_OPT_DIFFUSION_GRAPH: ffb_diffusion replays one captured graph per
+ *     attempt (1, default) or launches each attempt's kernels (0).
  * Returns FFB_E_INVALID for an unknown option or value. */
-enum { FFB_OPT_ADVECT_STATE = 1, FFB_OPT_ADVECT_BLOCKS = 2 };
+enum { FFB_OPT_ADVECT_STATE = 1, FFB_OPT_ADVECT_BLOCKS = 2, FFB_OPT_DIFFUSION_GRAPH = 3 };
 int ffb_set_option(ffb_ctx *ctx, int32_t option, int32_t value);
 
 /* Areas and relative area errors (benchmarking section, stopping rule).
@@ -195,6 +197,38 @@ int ffb_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy, const float 
 int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
                   int64_t n, const ffb_integrate_opts *opts, int32_t *stats,
                   double *h_out, int32_t h_cap);
+
+/* ------------------------------------------------------- diffusion variant
+ * The diffusion cartogram written as a flow-based projection (SI Appendix,
+ * section 2, the diffusion choice of f_mn), the comparison method of the
+ * paper: with the blurred coefficients rts_mn of ffb_flux and
+ *   f_mn(t) = exp(-(m^2/lx^2 + n^2/ly^2) t),
+ *   rho(t)  = (1/(lx ly)) sum_mn rts_mn f_mn(t) cos(m pi x/lx) cos(n pi y/ly),
+ *   J_x(t)  = (1/(lx ly)) sum (m / (pi lx)) rts_mn f_mn(t) sin(...) cos(...),
+ *   J_y(t)  = (1/(lx ly)) sum (n / (pi ly)) rts_mn f_mn(t) cos(...) sin(...),
+ * the points move with v = J(t) / rho(t) (bilinear between the nodes, as
+ * ffb_integrate).  Unlike the main method the fields depend on t, so they
+ * are rebuilt at every stage time, and the flow runs to t = infinity,
+ * approximated by a cut-off t_end.
+ *
+ * ffb_diffusion_fields: fields (out, ghosted layout as ffb_flux) at time t
+ * (>= 0) for the raster density rho (in, [ly][lx] FP32) blurred by sigma.
+ * Enqueue-only. */
+int ffb_diffusion_fields(ffb_ctx *ctx, const float *rho, float sigma, double t, float *fields);
+
+/* ffb_diffusion: advect xy (in/out, [n][2] FP32) from t = 0 to t_end (> 0)
+ * with the same controller as ffb_integrate (opts; a replayed schedule must
+ * sum to t_end), stats (out, [4]: accepted, rejected, attempts, status) and
+ * h_out (out, [h_cap] accepted steps, may be NULL with h_cap = 0).  Per
+ * attempt the fields at the five distinct stage times are rebuilt in one
+ * batched set of transforms, then every point takes the six stages.  The
+ * call returns when the integration has ended: it waits for its work once
+ * per few attempts (the number of attempts is decided on the device).  Host
+ * argument errors return FFB_E_INVALID before any launch; device errors
+ * (non-positive rho(t), non-finite steps, step underflow, too many
+ * attempts) land in stats[3] and the sticky status, and leave xy as it was. */
+int ffb_diffusion(ffb_ctx *ctx, const float *rho, float sigma, double t_end, float *xy, int64_t n,
+                  const ffb_integrate_opts *opts, int32_t *stats, double *h_out, int32_t h_cap);
 
 /* Angular distortion of the cartogram (main text, section "Measures of
  * distortion"; SI Appendix section 3).  nodes (in, device, [ly][lx][2] FP32)

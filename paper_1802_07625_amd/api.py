@@ -86,6 +86,9 @@ def lib():
                                     vp, vp, i32]
         L.ffb_set_option.argtypes = [vp, i32, i32]
         L.ffb_distortion.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+        L.ffb_diffusion_fields.argtypes = [vp, vp, ctypes.c_float, ctypes.c_double, vp]
+        L.ffb_diffusion.argtypes = [vp, vp, ctypes.c_float, ctypes.c_double, vp, i64,
+                                    ctypes.POINTER(FFBIntegrateOpts), vp, vp, ctypes.c_int32]
         L.ffb_area_adj.argtypes = [vp, G, vp, vp]
         L.ffb_density_adj.argtypes = [vp, G, vp, vp, vp, vp, vp, vp]
         L.ffb_flux_adj.argtypes = [vp, ctypes.c_float, vp, vp, vp]
@@ -110,7 +113,7 @@ def lib():
         L.ffb_batch_results.argtypes = [vp, vp, vp, vp, vp]
         for f in ("ffb_create", "ffb_destroy", "ffb_sync", "ffb_reset_status", "ffb_area_error",
                   "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option",
-                  "ffb_distortion", "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
+                  "ffb_distortion", "ffb_diffusion_fields", "ffb_diffusion", "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
                   "ffb_integrate_adj", "ffb_tape_begin", "ffb_tape_end", "ffb_tape_clear",
                   "ffb_backward", "ffb_batch_create", "ffb_batch_destroy", "ffb_batch_set_shapes",
                   "ffb_batch_get_shapes", "ffb_batch_autotune", "ffb_batch_reset",
@@ -216,7 +219,7 @@ def ffb_last_error(ctx) -> str:
     return lib().ffb_last_error(ctx).decode()
 
 
-OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS = 1, 2
+OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS, OPT_DIFFUSION_GRAPH = 1, 2, 3
 
 
 def ffb_set_option(ctx, option: int, value: int) -> None:
@@ -267,6 +270,24 @@ def ffb_integrate(ctx, fields, rho_bar, xy, opts: IntegrateOpts, stats, h_out=No
                                     _ptr(stats, torch.int32, 4, "stats"),
                                     _ptr(h_out, torch.float64, name="h_out"),
                                     0 if h_out is None else h_out.numel()), "ffb_integrate")
+
+
+def ffb_diffusion_fields(ctx, rho, sigma: float, t: float, fields, lx: int, ly: int) -> None:
+    _check(ctx, lib().ffb_diffusion_fields(ctx, _ptr(rho, torch.float32, lx * ly, "rho"),
+                                           float(sigma), float(t),
+                                           _ptr(fields, torch.float32, 4 * (lx + 2) * (ly + 2),
+                                                "fields")), "ffb_diffusion_fields")
+
+
+def ffb_diffusion(ctx, rho, sigma: float, t_end: float, xy, opts: IntegrateOpts, stats,
+                  h_out=None, replay_h=None, lx: int = 0, ly: int = 0) -> None:
+    n = xy.shape[0]
+    o = opts.struct(replay_h)
+    _check(ctx, lib().ffb_diffusion(ctx, _ptr(rho, torch.float32, lx * ly, "rho"), float(sigma),
+                                    float(t_end), _ptr(xy, torch.float32, 2 * n, "xy"), n,
+                                    ctypes.byref(o), _ptr(stats, torch.int32, 4, "stats"),
+                                    _ptr(h_out, torch.float64, name="h_out"),
+                                    0 if h_out is None else h_out.numel()), "ffb_diffusion")
 
 
 def ffb_distortion(ctx, lx: int, ly: int, nodes, stats, e=None, e_tilde=None) -> None:
@@ -420,6 +441,27 @@ class Context:
         ffb_integrate(self.handle, fields, rho_bar, xy, opts, stats, h_out, replay_h)
         return stats, h_out
 
+    def diffusion_fields(self, rho, sigma: float, t: float, fields=None):
+        """Fields (J_x, J_y, rho(t)) of the diffusion variant at time t."""
+        fields = self.new_fields() if fields is None else fields
+        ffb_diffusion_fields(self.handle, rho, sigma, t, fields, self.lx, self.ly)
+        return fields
+
+    def diffusion(self, rho, sigma: float, xy, t_end: float | None = None,
+                  opts: IntegrateOpts | None = None, replay_h=None, h_cap: int | None = None):
+        """Advect xy with the diffusion variant to t_end (default
+        diffusion_t_end); returns (stats, accepted steps).  Waits for the
+        integration to end."""
+        opts = opts or IntegrateOpts()
+        te = diffusion_t_end(self.lx, self.ly) if t_end is None else t_end
+        stats = torch.empty(4, dtype=torch.int32, device=self.device)
+        h_out = None
+        if h_cap is None or h_cap > 0:
+            h_out = self._f64(opts.max_attempts if h_cap is None else h_cap)
+        ffb_diffusion(self.handle, rho, sigma, te, xy, opts, stats, h_out, replay_h,
+                      self.lx, self.ly)
+        return stats, h_out
+
     def distortion(self, nodes, per_square: bool = False, lx: int | None = None,
                    ly: int | None = None):
         """Angular distortion of the map given by the images of the nodes of
@@ -459,6 +501,16 @@ def default_sigma(k: int) -> float:
     return 4.0 * 2.0 ** (-k)
 
 
+# The diffusion flow runs to t = infinity; it is cut where every
+# non-constant mode has decayed by exp(-DIFFUSION_K) (the slowest decays as
+# exp(-t / max(lx, ly)^2)).
+DIFFUSION_K = 12.0
+
+
+def diffusion_t_end(lx: int, ly: int, K: float = DIFFUSION_K) -> float:
+    return K * float(max(lx, ly)) ** 2
+
+
 @dataclass
 class IterationResult:
     area_before: torch.Tensor
@@ -485,6 +537,21 @@ def iterate(ctx: Context, geom: Geometry, value, points, sigma: float,
     stats, h = ctx.integrate(fields, rho_bar, points, opts)
     area, err, mx = ctx.area_error(geom, value)
     return IterationResult(area_before, rho, pad, fields, rho_bar, stats, h, area, err, mx)
+
+
+def iterate_diffusion(ctx: Context, geom: Geometry, value, points, sigma: float,
+                      opts: IntegrateOpts | None = None, area_before=None,
+                      t_end: float | None = None) -> IterationResult:
+    """One round of the diffusion variant on the device: the same areas,
+    density and blur as ``iterate``, then the diffusion flow to t_end.
+    Waits for the integration (the number of steps is found on the device);
+    ``fields`` and ``rho_bar`` of the result are None."""
+    if area_before is None:
+        area_before, _, _ = ctx.area_error(geom, value)
+    rho, pad = ctx.density(geom, value, area_before)
+    stats, h = ctx.diffusion(rho, sigma, points, t_end, opts)
+    area, err, mx = ctx.area_error(geom, value)
+    return IterationResult(area_before, rho, pad, None, None, stats, h, area, err, mx)
 
 
 class FFBFunction(torch.autograd.Function):

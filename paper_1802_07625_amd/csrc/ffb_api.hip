@@ -28,6 +28,36 @@ int hip_fail(ffb_ctx *ctx, hipError_t e, const char *where)
     return e == hipErrorOutOfMemory ? FFB_E_NOMEM : FFB_E_DEVICE;
 }
 
+int check_controller(ffb_ctx *ctx, const ffb_integrate_opts *o, const double *h_out,
+                     int32_t h_cap, const char *what)
+{
+    if (h_cap < 0 || (h_cap > 0 && !h_out))
+        return fail(ctx, FFB_E_INVALID, "%s: bad h_out/h_cap", what);
+    if (o->max_attempts <= 0 || o->max_attempts > (1 << 20))
+        return fail(ctx, FFB_E_INVALID, "%s: max_attempts out of range", what);
+    if (o->n_replay < 0 || (o->n_replay > 0 && !o->replay_h))
+        return fail(ctx, FFB_E_INVALID, "%s: bad replay schedule", what);
+    if (o->n_replay == 0) {
+        if (!(o->tol > 0.0) || !(o->h0 > 0.0) || !(o->safety > 0.0) || !(o->fac_min > 0.0) ||
+            !(o->fac_min <= 1.0) || !(o->fac_max >= 1.0) || !(o->h_min >= 0.0) ||
+            !isfinite(o->tol) || !isfinite(o->h0) || !isfinite(o->fac_max))
+            return fail(ctx, FFB_E_INVALID, "%s: bad controller constants", what);
+    }
+    return FFB_OK;
+}
+
+hipError_t ensure_state_capacity(ffb_ctx *ctx, int64_t n)
+{
+    if (n <= ctx->st_cap) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = grow(&ctx->st[b], ctx->st_cap, n);
+        if (e == hipSuccess) e = grow(&ctx->kv[b], ctx->st_cap, n);
+    }
+    ctx->st_cap = e == hipSuccess ? n : 0;
+    return e;
+}
+
 hipError_t grow_bytes(void **p, int64_t have, int64_t need)
 {
     if (need <= have && *p) return hipSuccess;
@@ -114,6 +144,7 @@ void free_all(ffb_ctx *c)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     tape_free(c);
+    diff_free(c);
 }
 
 int check_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
@@ -125,38 +156,16 @@ int check_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, fl
         return fail(ctx, FFB_E_INVALID, "ffb_integrate: NULL argument%s");
     if (n < 0 || n > INT32_MAX - 4096)
         return fail(ctx, FFB_E_INVALID, "ffb_integrate: n out of range%s");
-    if (h_cap < 0 || (h_cap > 0 && !h_out))
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad h_out/h_cap%s");
-    if (o->max_attempts <= 0 || o->max_attempts > (1 << 20))
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: max_attempts out of range%s");
-    if (o->n_replay < 0 || (o->n_replay > 0 && !o->replay_h))
-        return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad replay schedule%s");
-    if (o->n_replay == 0) {
-        if (!(o->tol > 0.0) || !(o->h0 > 0.0) || !(o->safety > 0.0) || !(o->fac_min > 0.0) ||
-            !(o->fac_min <= 1.0) || !(o->fac_max >= 1.0) || !(o->h_min >= 0.0) ||
-            !isfinite(o->tol) || !isfinite(o->h0) || !isfinite(o->fac_max))
-            return fail(ctx, FFB_E_INVALID, "ffb_integrate: bad controller constants%s");
-    }
-    return FFB_OK;
+    return check_controller(ctx, o, h_out, h_cap, "ffb_integrate");
 }
 
 int run_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy, int64_t n,
                   const ffb_integrate_opts *o, int32_t *stats, double *h_out, int32_t h_cap,
                   const advect_tape *rec)
 {
-    if (n > ctx->st_cap) {
-        hipError_t e = hipSuccess;
-        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-            e = grow(&ctx->st[b], ctx->st_cap, n);
-            if (e == hipSuccess) e = grow(&ctx->kv[b], ctx->st_cap, n);
-        }
-        if (e != hipSuccess) {
-            ctx->st_cap = 0;
-            return hip_fail(ctx, e, "ffb_integrate state buffers");
-        }
-        ctx->st_cap = n;
-    }
-    hipError_t e = launch_fill_i32(stats, 4, 0, ctx->stream);
+    hipError_t e = ensure_state_capacity(ctx, n);
+    if (e != hipSuccess) return hip_fail(ctx, e, "ffb_integrate state buffers");
+    e = launch_fill_i32(stats, 4, 0, ctx->stream);
     if (e == hipSuccess && rec && rec->count) e = launch_fill_i32(rec->count, 1, 0, ctx->stream);
     if (e == hipSuccess)
         e = launch_advect(ctx, reinterpret_cast<const float4 *>(fields), rho_bar,
@@ -258,6 +267,12 @@ int ffb_set_option(ffb_ctx *ctx, int32_t option, int32_t value)
     if (option == FFB_OPT_ADVECT_BLOCKS) {
         if (value < 0) return fail(ctx, FFB_E_INVALID, "negative workgroup cap%s");
         ctx->adv_cap = value;
+        return FFB_OK;
+    }
+    if (option == FFB_OPT_DIFFUSION_GRAPH) {
+        if (value < 0 || value > 1) return fail(ctx, FFB_E_INVALID, "graph flag must be 0 or 1%s");
+        ctx->diff_graph = value;
+        if (ctx->diff) ctx->diff->use_graph = value != 0;
         return FFB_OK;
     }
     return fail(ctx, FFB_E_INVALID, "unknown option%s");

@@ -46,6 +46,8 @@ struct ffb_ctx {
     int adv_cap = 0;                           // cap on advection workgroups, 0 = none
 
     struct ffb_tape *tape = nullptr;           // recording for ffb_backward
+    struct diff_ws *diff = nullptr;            // diffusion-variant buffers (on first use)
+    int diff_graph = 1;                        // FFB_OPT_DIFFUSION_GRAPH
     double *adj_t = nullptr;                   // [cap] step start times (adjoint)
     int64_t adj_t_cap = 0;
     float4 *adj_jac = nullptr;                 // [cap][n] step Jacobians (adjoint)
@@ -72,6 +74,13 @@ hipError_t grow(T **p, int64_t have, int64_t need)
 hipError_t ensure_region_capacity(ffb_ctx *ctx, int32_t R);
 // Integration adjoint workspace for `cap` steps of n points.
 hipError_t ensure_adjoint_capacity(ffb_ctx *ctx, int32_t cap, int64_t n);
+// Double-buffered integrator state (st, kv) for at least n points.
+hipError_t ensure_state_capacity(ffb_ctx *ctx, int64_t n);
+// Controller options, step record and replay schedule of an integration.
+int check_controller(ffb_ctx *ctx, const ffb_integrate_opts *o, const double *h_out,
+                     int32_t h_cap, const char *what);
+// Release the diffusion-variant buffers of a context (if any).
+void diff_free(ffb_ctx *ctx);
 }  // namespace ffbi
 
 // Context tape (recording for ffb_backward).  Each hook returns FFB_OK when
@@ -136,6 +145,59 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
 hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                              const advect_tape *tape, double *lam_xy, float4 *lam_fields,
                              double *lam_rho_bar);
+
+// ---------------------------------------------------------------- diffusion
+// Control block of a diffusion integration (device memory).  The attempt's
+// kernels read the step and the stage times from it; the control kernel
+// takes the accept/reject decision and arms the next attempt.  Every kernel
+// of an attempt returns at once when `done` is set, so surplus replays of
+// the attempt graph do nothing.
+constexpr int kDiffSlots = 5;        // distinct stage times of an attempt
+struct diff_ctl {
+    double t, h, h_att, t_end;
+    double ts[kDiffSlots];           // stage times t + c_s h of the armed attempt
+    double tol, h0, safety, fac_min, fac_max, h_min;
+    const double *replay_h;
+    double *h_out;
+    int32_t *stats;                  // [4] accepted, rejected, attempts, status
+    int32_t n_replay, max_attempts, h_cap;
+    int32_t acc, rej, attempts, cur, done, last_rejected, final_step, status;
+};
+
+// Device buffers of the diffusion path of one context.
+struct diff_ws {
+    int64_t plane = 0;               // lx * ly
+    int64_t fplane = 0;              // (lx + 2) * (ly + 2)
+    float *spec = nullptr;           // [lx][ly] blurred coefficients (m-major)
+    float *q = nullptr;              // [3][kDiffSlots][lx][ly] column-pass output
+    float *r = nullptr;              // [3][kDiffSlots][ly][lx] transposed
+    float4 *fields = nullptr;        // [kDiffSlots][(ly+2)(lx+2)] fields per stage time
+    diff_ctl *ctl = nullptr;
+    float *part = nullptr;           // [kDiffMaxBlocks] error maxima per workgroup
+    int32_t *done_host = nullptr;    // pinned host copy of ctl->done
+    hipStream_t stream = nullptr;    // private stream (capturable), ordered with the caller's
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // the captured attempt and what it was captured for
+    hipGraphExec_t exec = nullptr;
+    int64_t exec_n = -1;
+    const void *exec_st = nullptr, *exec_st1 = nullptr, *exec_kv = nullptr, *exec_kv1 = nullptr;
+    bool use_graph = true;
+};
+constexpr int kDiffMaxBlocks = 2048;
+
+// Blurred cosine coefficients of rho (Eq. 7 and the blur), m-major, into spec.
+hipError_t launch_diff_spectrum(ffb_ctx *ctx, const float *rho, float sigma, float *spec);
+// Fields at the first `slots` stage times of ctl (slots <= kDiffSlots).
+hipError_t launch_diff_fields(ffb_ctx *ctx, diff_ws *w, int slots);
+// Initial state (hi = xy, lo = 0) and first-stage velocity at t = 0 (slot 0).
+hipError_t launch_diff_init_points(ffb_ctx *ctx, diff_ws *w, const float2 *xy, int64_t n);
+// One attempt's point pass and its control step.
+hipError_t launch_diff_points(ffb_ctx *ctx, diff_ws *w, int64_t n);
+hipError_t launch_diff_control(ffb_ctx *ctx, diff_ws *w, int64_t n, int arm_only);
+// Positions out of the current state buffer (if the integration succeeded).
+hipError_t launch_diff_finish(ffb_ctx *ctx, diff_ws *w, float2 *xy, int64_t n);
+// Copy `init` into the device control block (a kernel, so graph-safe).
+hipError_t launch_diff_setup(ffb_ctx *ctx, diff_ws *w, const diff_ctl &init);
 
 // ---------------------------------------------------------------- batches
 // Device view of a batch of maps, passed by value to the batched kernels.

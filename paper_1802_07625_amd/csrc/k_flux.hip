@@ -700,6 +700,143 @@ __global__ __launch_bounds__(512) void kb_row_final(batch_view bv, const int2 *_
                    fields + bv.field_off[m], status, sa, sb, rs, jx, stw);
 }
 
+// ------------------------------------------------------- diffusion variant
+// The diffusion choice of the SI Appendix (section 2): f_mn(t) =
+// exp(-(m^2/lx^2 + n^2/ly^2) t) multiplies the blurred coefficients, and the
+// flux coefficients become (m / (pi lx)) and (n / (pi ly)) times them, so
+//   rho(t) = (1/(lx ly)) sum rts f cos cos,
+//   J_x(t) = sum (m / (pi lx^2 ly)) rts f sin cos,
+//   J_y(t) = sum (n / (pi lx ly^2)) rts f cos sin.
+// The forward half (rows, transpose, columns with the Eq. 7 factor and the
+// blur) runs once per round into spec; each stage time needs only the three
+// inverse column transforms, a transpose and the row pass.
+
+// Blurred coefficients of rows m0, m0 + 1 of T2 into spec [lx][ly].
+__global__ __launch_bounds__(512) void kd_spectrum(const float *__restrict__ t2, int lx, int ly,
+                                                   float sigma, const float2 *__restrict__ tw,
+                                                   const float2 *__restrict__ tq,
+                                                   float *__restrict__ spec)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
+    const int m0 = 2 * blockIdx.x, N = ly;
+    load_twiddles(stw, tw, N, 1);
+    const float *ra = t2 + (int64_t)m0 * N, *rb = ra + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = make_float2(ra[i], rb[i]);
+    dct2_pair(sa, sb, coef, N, stw, tq, 1);
+    const float PI_F = 3.14159265358979f;
+    const float cgx = PI_F * PI_F * sigma * sigma / (2.0f * (float)lx * (float)lx);
+    const float cgy = PI_F * PI_F * sigma * sigma / (2.0f * (float)ly * (float)ly);
+    const float gx0 = expf(-cgx * (float)m0 * (float)m0) * (m0 == 0 ? 2.0f : 4.0f);
+    const float gx1 = expf(-cgx * (float)(m0 + 1) * (float)(m0 + 1)) * 4.0f;
+    float *o0 = spec + (int64_t)m0 * N, *o1 = o0 + N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const float gy = expf(-cgy * (float)n * (float)n) * (n == 0 ? 0.5f : 1.0f);
+        const float2 c = coef[n];
+        o0[n] = c.x * gx0 * gy;
+        o1[n] = c.y * gx1 * gy;
+    }
+}
+
+// Column pass at stage time slot blockIdx.y: rows m0, m0 + 1 of spec times
+// f_mn(ts), then a (DCT-III), b (DCT-III, weight of m) and c (DST-III,
+// weight of n) along y into q [3][slots][lx][ly].
+__global__ __launch_bounds__(512) void kd_col(const diff_ctl *__restrict__ ctl,
+                                              const float *__restrict__ spec, int lx, int ly,
+                                              int slots, const float2 *__restrict__ tw,
+                                              const float2 *__restrict__ tq, float *__restrict__ q)
+{
+    if (ctl->done) return;
+    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
+    const int m0 = 2 * blockIdx.x, z = blockIdx.y, N = ly;
+    const double ts = ctl->ts[z];
+    load_twiddles(stw, tw, N, 1);
+    const double ix2 = 1.0 / ((double)lx * (double)lx), iy2 = 1.0 / ((double)ly * (double)ly);
+    const float fx0 = expf((float)(-(double)m0 * m0 * ix2 * ts));
+    const float fx1 = expf((float)(-(double)(m0 + 1) * (m0 + 1) * ix2 * ts));
+    const float *s0 = spec + (int64_t)m0 * N, *s1 = s0 + N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const float fy = expf((float)(-(double)n * n * iy2 * ts));
+        coef[n] = make_float2(s0[n] * fx0 * fy, s1[n] * fx1 * fy);
+    }
+    __syncthreads();
+    const float inv_pi = 0.318309886183790672f;
+    const float flx = (float)lx, fly = (float)ly;
+    const float wb0 = (float)m0 * inv_pi / (flx * flx * fly);
+    const float wb1 = (float)(m0 + 1) * inv_pi / (flx * flx * fly);
+    const float wc = inv_pi / (flx * fly * fly);
+    const int64_t plane = (int64_t)lx * ly;
+    float *pa = q + (int64_t)z * plane, *pb = pa + (int64_t)slots * plane,
+          *pc = pb + (int64_t)slots * plane;
+
+    dct3_input(sa, N, tq, [&](int n) { return coef[n]; }, 1);
+    float2 *v = fft_lds(sa, sb, N, stw, true);
+    float *oa0 = pa + (int64_t)m0 * N, *oa1 = oa0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        oa0[i] = y.x;
+        oa1[i] = y.y;
+    }
+    __syncthreads();
+    dct3_input(sa, N, tq, [&](int n) {
+        const float2 c = coef[n];
+        return make_float2(wb0 * c.x, wb1 * c.y);
+    }, 1);
+    v = fft_lds(sa, sb, N, stw, true);
+    float *ob0 = pb + (int64_t)m0 * N, *ob1 = ob0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        ob0[i] = y.x;
+        ob1[i] = y.y;
+    }
+    __syncthreads();
+    dct3_input(sa, N, tq, [&](int mm) {
+        if (mm == 0) return make_float2(0.f, 0.f);
+        const int n = N - mm;
+        const float2 c = coef[n];
+        const float w = wc * (float)n;
+        return make_float2(w * c.x, w * c.y);
+    }, 1);
+    v = fft_lds(sa, sb, N, stw, true);
+    float *oc0 = pc + (int64_t)m0 * N, *oc1 = oc0 + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float2 y = dct3_output(v, i, N);
+        const float sg = (i & 1) ? -1.0f : 1.0f;
+        oc0[i] = sg * y.x;
+        oc1[i] = sg * y.y;
+    }
+}
+
+// Planes [R][C] -> [C][R]; plane blockIdx.z of `in`/`out`, `stride` apart.
+__global__ __launch_bounds__(256) void kd_transpose(const diff_ctl *__restrict__ ctl,
+                                                    const float *__restrict__ in,
+                                                    float *__restrict__ out, int R, int C,
+                                                    int slots, int64_t plane)
+{
+    if (ctl->done) return;
+    __shared__ float tile[32][33];
+    // plane index: kind * kDiffSlots + slot, for the first `slots` slots
+    const int kind = blockIdx.z / slots, z = blockIdx.z % slots;
+    const int64_t off = ((int64_t)kind * slots + z) * plane;
+    transpose_tile(in + off, out + off, R, C, blockIdx.x * 32, blockIdx.y * 32, tile);
+}
+
+// Row pass at slot blockIdx.y: fields (J_x, J_y, rho(ts)) of that slot.
+__global__ __launch_bounds__(512) void kd_row(const diff_ctl *__restrict__ ctl,
+                                              const float *__restrict__ r, int lx, int ly,
+                                              int slots, const float2 *__restrict__ tw,
+                                              const float2 *__restrict__ tq,
+                                              float4 *__restrict__ fields, int32_t *status)
+{
+    if (ctl->done) return;
+    __shared__ float2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
+    const int z = blockIdx.y;
+    const int64_t plane = (int64_t)lx * ly;
+    const float *pa = r + (int64_t)z * plane, *pb = pa + (int64_t)slots * plane,
+                *pc = pb + (int64_t)slots * plane;
+    row_final_body(pa, pb, pc, 2 * blockIdx.x, lx, ly, tw, tq, 1,
+                   fields + (int64_t)z * (lx + 2) * (ly + 2), status, sa, sb, rs, jx, stw);
+}
+
 inline int threads_for(int N)
 {
     int t = N / 2;
@@ -746,6 +883,33 @@ hipError_t launch_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy,
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, jx, jy, rho_s,
                        ctx->lx, ctx->ly, fields);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_spectrum(ffb_ctx *ctx, const float *rho, float sigma, float *spec)
+{
+    hipStream_t s = ctx->stream;
+    const int lx = ctx->lx, ly = ctx->ly;
+    hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, ctx->t1, lx,
+                       ctx->tw_x, ctx->tq_x);
+    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
+                       ctx->t1, ctx->t1, ctx->t1, ctx->t2, ctx->t2, ctx->t2, ly, lx);
+    hipLaunchKernelGGL(kd_spectrum, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t2, lx, ly,
+                       sigma, ctx->tw_y, ctx->tq_y, spec);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_fields(ffb_ctx *ctx, diff_ws *w, int slots)
+{
+    hipStream_t s = ctx->stream;
+    const int lx = ctx->lx, ly = ctx->ly;
+    hipLaunchKernelGGL(kd_col, dim3(lx / 2, slots), dim3(threads_for(ly)), 0, s, w->ctl, w->spec,
+                       lx, ly, slots, ctx->tw_y, ctx->tq_y, w->q);
+    // [lx][ly] -> [ly][lx], 3 * slots planes
+    hipLaunchKernelGGL(kd_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 3 * slots), dim3(256),
+                       0, s, w->ctl, w->q, w->r, lx, ly, slots, w->plane);
+    hipLaunchKernelGGL(kd_row, dim3(ly / 2, slots), dim3(threads_for(lx)), 0, s, w->ctl, w->r,
+                       lx, ly, slots, ctx->tw_x, ctx->tq_x, w->fields, ctx->d_status);
     return hipGetLastError();
 }
 
