@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--batch-maps", type=int, default=256)
     ap.add_argument("--no-rect", action="store_true",
                     help="skip the rectangular map with holes and multipolygons")
+    ap.add_argument("--no-diffusion", action="store_true",
+                    help="skip the diffusion-cartogram comparison")
     return ap.parse_args()
 
 
@@ -208,6 +210,9 @@ def main():
             "e_tilde_inf": float(dst[3]), "folded_squares": int(dst[4]),
             "ms": round(d0.elapsed_time(d1), 4)}
 
+    if not args.no_diffusion:
+        result["diffusion"] = diffusion_leg(args, dev, m, ctx, geom, value, pts0, pts, V,
+                                            result.get("loop"))
     ctx.close()
     if not args.no_grad:
         result["grad"] = grad_leg(args, dev)
@@ -218,6 +223,50 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(m, pts_h, args)
     print(json.dumps(result), flush=True)
+
+
+def diffusion_leg(args, dev, m, ctx, geom, value, pts0, pts, V, ffb_loop, max_rounds=30):
+    """The comparison method of the paper on the same map and grid: the
+    diffusion cartogram written as a flow-based projection (fields rebuilt
+    at every stage time, integration to the cut-off time), rounds with the
+    same blur schedule until max |e_r| < 1 %."""
+    import torch
+    import paper_1802_07625_amd as ffb
+
+    opts = ffb.IntegrateOpts(tol=args.tol)
+    pts.copy_(pts0)                                   # warm-up round (graph capture, buffers)
+    ffb.iterate_diffusion(ctx, geom, value, pts, ffb.default_sigma(0), opts)
+    torch.cuda.synchronize()
+    pts.copy_(pts0)
+    torch.cuda.synchronize()
+    area, errs, atts, round_ms = None, [], [], []
+    t0 = time.perf_counter()
+    for k in range(max_rounds):
+        t_r = time.perf_counter()
+        res = ffb.iterate_diffusion(ctx, geom, value, pts, ffb.default_sigma(k), opts,
+                                    area_before=area)
+        area = res.area_after
+        mx = float(res.max_err_after)
+        round_ms.append(round(1e3 * (time.perf_counter() - t_r), 3))
+        errs.append(mx)
+        atts.append(int(res.stats[2]))
+        if mx < 0.01:
+            break
+    torch.cuda.synchronize()
+    total = 1e3 * (time.perf_counter() - t0)
+    dst, _, _ = ctx.distortion(pts[V:])
+    dst = dst.cpu().numpy()
+    out = {"rounds": len(errs), "max_area_error": errs[-1], "total_ms": round(total, 2),
+           "ms_per_round": round_ms, "attempts_per_round": atts,
+           "ms_per_attempt": round(total / max(1, sum(atts)), 4),
+           "t_end": ffb.diffusion_t_end(m.lx, m.ly),
+           "distortion": {"e_a": float(dst[0]), "e_inf": float(dst[1]),
+                          "e_tilde_a": float(dst[2]), "e_tilde_inf": float(dst[3]),
+                          "folded_squares": int(dst[4])}}
+    if ffb_loop:
+        out["ffb_loop_ms"] = ffb_loop["total_ms"]
+        out["diffusion_over_ffb"] = round(total / ffb_loop["total_ms"], 3)
+    return out
 
 
 def rect_leg(args, dev, name="rect_1024x512", max_rounds=30):

@@ -820,13 +820,25 @@ __device__ inline void diff_stop(diff_ctl *c, int32_t code, int32_t *status)
     if (code) set_status(status, code);
 }
 
-// One thread: the grid maximum of the attempt's errors, the decision, the
-// step update (the controller of k_advect, with t_end in place of 1) and
-// the next attempt's stage times.  arm_only: start of the integration.
-__global__ __launch_bounds__(64) void kd_control(diff_ctl *c, const float *__restrict__ part,
-                                                 int nb, int arm_only, int32_t *status)
+// The grid maximum of the attempt's errors (all lanes; the maximum does not
+// depend on the order), then on one lane the decision, the step update (the
+// controller of k_advect, with t_end in place of 1) and the next attempt's
+// stage times.  arm_only: start of the integration.
+constexpr int kControlThreads = 256;
+__global__ __launch_bounds__(kControlThreads) void kd_control(diff_ctl *c,
+                                                              const float *__restrict__ part,
+                                                              int nb, int arm_only,
+                                                              int32_t *status)
 {
-    if (threadIdx.x != 0 || c->done) return;
+    if (c->done) return;
+    __shared__ float s_max[kControlThreads / 64];
+    float v = 0.0f;
+    if (!arm_only)
+        for (int b = threadIdx.x; b < nb; b += kControlThreads) v = fmaxf(v, part[b]);
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const int32_t st = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (st != 0) {
         diff_stop(c, st, status);
@@ -834,8 +846,9 @@ __global__ __launch_bounds__(64) void kd_control(diff_ctl *c, const float *__res
         if (c->max_attempts <= 0) diff_stop(c, FFB_E_MAX_ATTEMPTS, status);
         else diff_arm(c);
     } else {
-        float gm = 0.0f;
-        for (int b = 0; b < nb; ++b) gm = fmaxf(gm, part[b]);
+        float gm = s_max[0];
+#pragma unroll
+        for (int w = 1; w < kControlThreads / 64; ++w) gm = fmaxf(gm, s_max[w]);
         const double err = (double)gm;
         const double h = c->h_att;
         c->attempts += 1;
@@ -934,8 +947,8 @@ hipError_t launch_diff_points(ffb_ctx *ctx, diff_ws *w, int64_t n)
 
 hipError_t launch_diff_control(ffb_ctx *ctx, diff_ws *w, int64_t n, int arm_only)
 {
-    hipLaunchKernelGGL(kd_control, dim3(1), dim3(64), 0, ctx->stream, w->ctl, w->part,
-                       diff_blocks(n), arm_only, ctx->d_status);
+    hipLaunchKernelGGL(kd_control, dim3(1), dim3(kControlThreads), 0, ctx->stream, w->ctl,
+                       w->part, diff_blocks(n), arm_only, ctx->d_status);
     return hipGetLastError();
 }
 
