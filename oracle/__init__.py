@@ -38,10 +38,12 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C11, OpenMP, no fast-math)."""
+    """Compile the oracle with gcc (plain C11, OpenMP, no fast-math, no
+    fused multiply-add)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                        "-shared",
                         "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"],
                        check=True)
         os.replace(tmp, _LIB)
@@ -51,6 +53,7 @@ def build(force: bool = True) -> str:
 _lib = None
 
 _d = ctypes.POINTER(ctypes.c_double)
+_f = ctypes.POINTER(ctypes.c_float)
 _i32 = ctypes.POINTER(ctypes.c_int32)
 
 
@@ -76,6 +79,8 @@ def lib(path: str | None = None):
         L.ffbo_integrate.argtypes = [i32, i32, _d, _d, _d, dbl, i64, _d,
                                      dbl, dbl, dbl, dbl, dbl, dbl, i32,
                                      _d, i32, _i32, _i32, _d, i32]
+        if hasattr(L, "ffbo_inverse"):
+            L.ffbo_inverse.argtypes = [i32, i32, _f, i64, _f, _i32, _d]
         if hasattr(L, "ffbo_diff_fields"):
             L.ffbo_diff_fields.argtypes = [i32, i32, _d, dbl, _d, _d, _d]
             L.ffbo_diff_integrate.argtypes = [i32, i32, _d, dbl, i64, _d,
@@ -364,6 +369,25 @@ def iterate_diffusion(m, value, points, n_vertices: int, sigma: float,
     F = diffusion_fields(coef, 0.0, rb)
     return RoundResult(res.xy, a0, a1, e1, mx, rho, pad, F, res.accepted,
                        res.rejected, res.h)
+
+
+# ------------------------------------------------ inverse transformation
+def inverse(nodes, lx: int, ly: int, queries):
+    """Preimages of ``queries`` [Q, 2] under the piecewise-linear T given by
+    ``nodes`` [ly*lx, 2] (images of the cell centres; each cell split along
+    its (i,j)-(i+1,j+1) diagonal): (triangle index [Q] int32, -1 where no
+    triangle's image contains the query; preimage [Q, 2] FP64, NaN there).
+    Brute force over all triangles in index order (Conclusion: the
+    graticule of the inverse transformation).  Inputs are rounded to FP32."""
+    nd = np.ascontiguousarray(np.asarray(nodes, dtype=np.float32).reshape(-1, 2))
+    qs = np.ascontiguousarray(np.asarray(queries, dtype=np.float32).reshape(-1, 2))
+    if nd.shape[0] != lx * ly:
+        raise ValueError("nodes must hold lx * ly points")
+    tri = np.empty(qs.shape[0], dtype=np.int32)
+    pre = np.empty((qs.shape[0], 2), dtype=np.float64)
+    _check(lib().ffbo_inverse(lx, ly, _p(nd, _f), qs.shape[0], _p(qs, _f), _p(tri, _i32),
+                              _p(pre)), "inverse")
+    return tri, pre
 
 
 # ------------------------------------------------------- loss and gradient

@@ -840,3 +840,80 @@ int ffbo_diff_integrate(int32_t lx, int32_t ly, const double *coef, double t_end
     free(src.rho_t); free(src.jx); free(src.jy);
     return st;
 }
+
+/* ------------------------------------------------------------------------
+ * Inverse of the piecewise-linear approximation of T (Conclusion: the
+ * graticule of the inverse transformation; T is approximated as piecewise
+ * linear and that approximation is inverted).
+ *
+ * T is known at the nodes: nodes[j][i] (FP32 pairs) is the image of the
+ * cell centre (i + 1/2, j + 1/2).  Reading: each cell between four nodes,
+ * c = j (lx - 1) + i, is split along its (i,j)-(i+1,j+1) diagonal into
+ * triangle 2c with corners (i,j), (i+1,j), (i+1,j+1) and triangle 2c + 1
+ * with corners (i,j), (i+1,j+1), (i,j+1); on each, T is the affine map that
+ * takes the three original corners to their images.
+ *
+ * For a query q the preimage is the original point whose image is q, taken
+ * in the lowest-numbered triangle whose image contains q (edges included;
+ * on a folded map several images may contain q).  A triangle with a
+ * zero-area image contains nothing.  No triangle: tri = -1, pre = NaN.
+ * The orientation of q against an edge is
+ *   (b.x - a.x)(q.y - a.y) - (b.y - a.y)(q.x - a.x)
+ * in FP64 on the FP32 inputs, with no fused multiply-add.
+ * ---------------------------------------------------------------------- */
+static double orient2(double ax, double ay, double bx, double by, double qx, double qy)
+{
+    double u = (bx - ax) * (qy - ay);
+    double v = (by - ay) * (qx - ax);
+    return u - v;
+}
+
+int ffbo_inverse(int32_t lx, int32_t ly, const float *nodes, int64_t nq, const float *queries,
+                 int32_t *tri, double *pre)
+{
+    if (lx < 2 || ly < 2 || nq < 0) return O_E_INVALID;
+    const int64_t ncell = (int64_t)(lx - 1) * (ly - 1);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nq; ++k) {
+        const double qx = queries[2 * k], qy = queries[2 * k + 1];
+        tri[k] = -1;
+        pre[2 * k] = NAN;
+        pre[2 * k + 1] = NAN;
+        for (int64_t t = 0; t < 2 * ncell; ++t) {
+            const int64_t c = t >> 1;
+            const int32_t i = (int32_t)(c % (lx - 1)), j = (int32_t)(c / (lx - 1));
+            /* original corners and their node indices */
+            int32_t ci[3], cj[3];
+            ci[0] = i; cj[0] = j;
+            if ((t & 1) == 0) { ci[1] = i + 1; cj[1] = j; ci[2] = i + 1; cj[2] = j + 1; }
+            else { ci[1] = i + 1; cj[1] = j + 1; ci[2] = i; cj[2] = j + 1; }
+            double X[3], Y[3];
+            for (int s = 0; s < 3; ++s) {
+                const int64_t n = (int64_t)cj[s] * lx + ci[s];
+                X[s] = nodes[2 * n];
+                Y[s] = nodes[2 * n + 1];
+            }
+            const double o = orient2(X[0], Y[0], X[1], Y[1], X[2], Y[2]);
+            if (o == 0.0) continue;
+            const double d0 = orient2(X[1], Y[1], X[2], Y[2], qx, qy);
+            const double d1 = orient2(X[2], Y[2], X[0], Y[0], qx, qy);
+            const double d2 = orient2(X[0], Y[0], X[1], Y[1], qx, qy);
+            const int inside = (o > 0.0) ? (d0 >= 0.0 && d1 >= 0.0 && d2 >= 0.0)
+                                         : (d0 <= 0.0 && d1 <= 0.0 && d2 <= 0.0);
+            if (!inside) continue;
+            /* barycentric weights of q in the image, applied to the originals */
+            const double l0 = d0 / o, l1 = d1 / o, l2 = d2 / o;
+            double px = l0 * (ci[0] + 0.5);
+            px += l1 * (ci[1] + 0.5);
+            px += l2 * (ci[2] + 0.5);
+            double py = l0 * (cj[0] + 0.5);
+            py += l1 * (cj[1] + 0.5);
+            py += l2 * (cj[2] + 0.5);
+            tri[k] = (int32_t)t;
+            pre[2 * k] = px;
+            pre[2 * k + 1] = py;
+            break;
+        }
+    }
+    return O_OK;
+}
