@@ -209,6 +209,20 @@ def main():
             "e_a": float(dst[0]), "e_inf": float(dst[1]), "e_tilde_a": float(dst[2]),
             "e_tilde_inf": float(dst[3]), "folded_squares": int(dst[4]),
             "ms": round(d0.elapsed_time(d1), 4)}
+        # inverse of the piecewise-linear map at a graticule sampled every
+        # half cell of the cartogram box
+        sq = torch.arange(0.25, L, 0.5, device=dev, dtype=torch.float32)
+        gq = torch.stack(torch.meshgrid(sq, sq, indexing="xy"), -1).reshape(-1, 2).contiguous()
+        ctx.inverse(pts[V:], gq)                              # warm-up (workspace)
+        d0.record(stream)
+        tri, pre = ctx.inverse(pts[V:], gq)
+        d1.record(stream)
+        torch.cuda.synchronize()
+        ms_inv = d0.elapsed_time(d1)
+        found = int((tri >= 0).sum())
+        result["loop"]["inverse"] = {"queries": int(gq.shape[0]), "found": found,
+                                     "ms": round(ms_inv, 4),
+                                     "queries_per_s": round(gq.shape[0] / (ms_inv * 1e-3), 1)}
 
     if not args.no_diffusion:
         result["diffusion"] = diffusion_leg(args, dev, m, ctx, geom, value, pts0, pts, V,

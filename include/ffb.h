@@ -249,6 +249,23 @@ int ffb_diffusion(ffb_ctx *ctx, const float *rho, float sigma, double t_end, flo
 int ffb_distortion(ffb_ctx *ctx, int32_t lx, int32_t ly, const float *nodes, double *stats,
                    float *e, float *e_tilde);
 
+/* Inverse of the piecewise-linear approximation of T (Conclusion: the
+ * graticule of the inverse transformation, obtained by approximating T as
+ * piecewise linear and inverting it).  nodes (in, device, [ly][lx][2] FP32):
+ * images of the cell centres (i + 1/2, j + 1/2) of an lx x ly grid (any
+ * sizes >= 2 up to 2^26 nodes; the context lends its stream and a workspace
+ * grown on demand).  Each cell c = j (lx-1) + i is split along its
+ * (i,j)-(i+1,j+1) diagonal into triangles 2c = (i,j),(i+1,j),(i+1,j+1) and
+ * 2c+1 = (i,j),(i+1,j+1),(i,j+1), on which T is affine.  For each of the nq
+ * queries (in, [nq][2] FP32, points on the cartogram) tri (out, [nq] int32)
+ * receives the lowest-numbered triangle whose image contains it (edges
+ * included; -1 if none; image triangles of zero area contain nothing) and
+ * pre (out, [nq][2] FP64) the preimage, the original point mapped to the
+ * query (NaN if none).  Containment signs are plain FP64 on the FP32
+ * inputs.  Returns FFB_E_INVALID for NULL pointers or bad sizes. */
+int ffb_inverse(ffb_ctx *ctx, int32_t lx, int32_t ly, const float *nodes, const float *queries,
+                int64_t nq, int32_t *tri, double *pre);
+
 /* ------------------------------------------------------------------ adjoints
  * Reverse-mode derivatives of the calls above, for a scalar L of the final
  * region areas.  The accepted step sizes of each integration are frozen at

@@ -87,6 +87,7 @@ def lib():
         L.ffb_set_option.argtypes = [vp, i32, i32]
         L.ffb_distortion.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         L.ffb_diffusion_fields.argtypes = [vp, vp, ctypes.c_float, ctypes.c_double, vp]
+        L.ffb_inverse.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, i64, vp, vp]
         L.ffb_diffusion.argtypes = [vp, vp, ctypes.c_float, ctypes.c_double, vp, i64,
                                     ctypes.POINTER(FFBIntegrateOpts), vp, vp, ctypes.c_int32]
         L.ffb_area_adj.argtypes = [vp, G, vp, vp]
@@ -113,7 +114,7 @@ def lib():
         L.ffb_batch_results.argtypes = [vp, vp, vp, vp, vp]
         for f in ("ffb_create", "ffb_destroy", "ffb_sync", "ffb_reset_status", "ffb_area_error",
                   "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option",
-                  "ffb_distortion", "ffb_diffusion_fields", "ffb_diffusion", "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
+                  "ffb_distortion", "ffb_diffusion_fields", "ffb_diffusion", "ffb_inverse", "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
                   "ffb_integrate_adj", "ffb_tape_begin", "ffb_tape_end", "ffb_tape_clear",
                   "ffb_backward", "ffb_batch_create", "ffb_batch_destroy", "ffb_batch_set_shapes",
                   "ffb_batch_get_shapes", "ffb_batch_autotune", "ffb_batch_reset",
@@ -290,6 +291,14 @@ def ffb_diffusion(ctx, rho, sigma: float, t_end: float, xy, opts: IntegrateOpts,
                                     0 if h_out is None else h_out.numel()), "ffb_diffusion")
 
 
+def ffb_inverse(ctx, lx: int, ly: int, nodes, queries, tri, pre) -> None:
+    nq = queries.shape[0]
+    _check(ctx, lib().ffb_inverse(ctx, lx, ly, _ptr(nodes, torch.float32, 2 * lx * ly, "nodes"),
+                                  _ptr(queries, torch.float32, 2 * nq, "queries"), nq,
+                                  _ptr(tri, torch.int32, nq, "tri"),
+                                  _ptr(pre, torch.float64, 2 * nq, "pre")), "ffb_inverse")
+
+
 def ffb_distortion(ctx, lx: int, ly: int, nodes, stats, e=None, e_tilde=None) -> None:
     n = max(lx - 1, 0) * max(ly - 1, 0)
     _check(ctx, lib().ffb_distortion(ctx, lx, ly, _ptr(nodes, torch.float32, 2 * lx * ly, "nodes"),
@@ -461,6 +470,38 @@ class Context:
         ffb_diffusion(self.handle, rho, sigma, te, xy, opts, stats, h_out, replay_h,
                       self.lx, self.ly)
         return stats, h_out
+
+    def inverse(self, nodes, queries, lx: int | None = None, ly: int | None = None):
+        """Preimages of cartogram points under the piecewise-linear T given by
+        the images of the nodes of an lx x ly grid: (triangle [Q] int32, -1
+        outside; preimage [Q, 2] FP64, NaN outside)."""
+        lx = self.lx if lx is None else lx
+        ly = self.ly if ly is None else ly
+        q = queries.reshape(-1, 2).contiguous()
+        tri = torch.empty(q.shape[0], dtype=torch.int32, device=self.device)
+        pre = torch.empty((q.shape[0], 2), dtype=torch.float64, device=self.device)
+        ffb_inverse(self.handle, lx, ly, nodes.contiguous(), q, tri, pre)
+        return tri, pre
+
+    def graticule(self, nodes, spacing: float = 8.0, samples: int = 4, lx: int | None = None,
+                  ly: int | None = None):
+        """The graticule of the inverse transformation: the lines x = k
+        spacing and y = k spacing of the cartogram box, sampled `samples`
+        times per unit length, mapped back to the original map.  Returns
+        (vertical, horizontal) preimage polylines as [lines, points, 2]
+        FP64 tensors (NaN where a sample lies outside the node hull)."""
+        lx = self.lx if lx is None else lx
+        ly = self.ly if ly is None else ly
+        xs = torch.arange(spacing, lx, spacing, dtype=torch.float64)
+        ys = torch.arange(spacing, ly, spacing, dtype=torch.float64)
+        tx = torch.linspace(0.0, float(lx), int(lx * samples) + 1, dtype=torch.float64)
+        ty = torch.linspace(0.0, float(ly), int(ly * samples) + 1, dtype=torch.float64)
+        vert = torch.stack(torch.broadcast_tensors(xs[:, None], ty[None, :]), -1)
+        horz = torch.stack(torch.broadcast_tensors(tx[None, :], ys[:, None]), -1)
+        q = torch.cat([vert.reshape(-1, 2), horz.reshape(-1, 2)]).to(torch.float32)
+        _, pre = self.inverse(nodes, q.to(self.device), lx, ly)
+        nv = vert.shape[0] * vert.shape[1]
+        return pre[:nv].reshape(vert.shape), pre[nv:].reshape(horz.shape)
 
     def distortion(self, nodes, per_square: bool = False, lx: int | None = None,
                    ly: int | None = None):

@@ -145,6 +145,15 @@ void free_all(ffb_ctx *c)
         if (p) (void)hipFree(p);
     tape_free(c);
     diff_free(c);
+    if (c->inv) {
+        void *iv[] = {c->inv->count, c->inv->offs, c->inv->fill, c->inv->sums, c->inv->order,
+                      c->inv->best, c->inv->big, c->inv->big_nb, c->inv->big_off,
+                      c->inv->sums64, c->inv->n_big};
+        for (void *p : iv)
+            if (p) (void)hipFree(p);
+        delete c->inv;
+        c->inv = nullptr;
+    }
 }
 
 int check_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,
@@ -354,6 +363,55 @@ int ffb_distortion(ffb_ctx *ctx, int32_t lx, int32_t ly, const float *nodes, dou
     hipError_t err = launch_distortion(ctx, lx, ly, reinterpret_cast<const float2 *>(nodes),
                                        stats, e, e_tilde);
     return err == hipSuccess ? FFB_OK : hip_fail(ctx, err, "ffb_distortion launch");
+}
+
+int ffb_inverse(ffb_ctx *ctx, int32_t lx, int32_t ly, const float *nodes, const float *queries,
+                int64_t nq, int32_t *tri, double *pre)
+{
+    if (!ctx) return FFB_E_INVALID;
+    if (!nodes || (nq > 0 && (!queries || !tri || !pre)))
+        return fail(ctx, FFB_E_INVALID, "ffb_inverse: NULL argument%s");
+    if (lx < 2 || ly < 2 || (int64_t)lx * ly > ((int64_t)1 << 26))
+        return fail(ctx, FFB_E_INVALID, "ffb_inverse: grid must be 2 x 2 to 2^26 nodes%s");
+    if (nq < 0 || nq > INT32_MAX - 1)
+        return fail(ctx, FFB_E_INVALID, "ffb_inverse: query count out of range%s");
+    if (!ctx->inv) ctx->inv = new inverse_ws();
+    inverse_ws *w = ctx->inv;
+    const int64_t bins = (int64_t)lx * ly;
+    const int64_t sums = inverse_scan_blocks(bins + 1);
+    const int64_t qn = nq > 0 ? nq : 1;
+    hipError_t e = hipSuccess;
+    if (bins > w->bins_cap) {
+        e = grow(&w->count, w->bins_cap + 1, bins + 1);
+        if (e == hipSuccess) e = grow(&w->offs, w->bins_cap + 1, bins + 1);
+        if (e == hipSuccess) e = grow(&w->fill, w->bins_cap, bins);
+        w->bins_cap = e == hipSuccess ? bins : 0;
+    }
+    if (e == hipSuccess && sums > w->sums_cap) {
+        e = grow(&w->sums, w->sums_cap, sums);
+        w->sums_cap = e == hipSuccess ? sums : 0;
+    }
+    if (e == hipSuccess && qn > w->q_cap) {
+        e = grow(&w->order, w->q_cap, qn);
+        if (e == hipSuccess) e = grow(&w->best, w->q_cap, qn);
+        w->q_cap = e == hipSuccess ? qn : 0;
+    }
+    const int64_t ntri = 2 * (int64_t)(lx - 1) * (ly - 1);
+    if (e == hipSuccess && ntri > w->tri_cap) {
+        e = grow(&w->big, w->tri_cap, ntri);
+        if (e == hipSuccess) e = grow(&w->big_nb, w->tri_cap + 1, ntri + 1);
+        if (e == hipSuccess) e = grow(&w->big_off, w->tri_cap + 1, ntri + 1);
+        if (e == hipSuccess)
+            e = grow(&w->sums64, inverse_scan_blocks(w->tri_cap + 1),
+                     inverse_scan_blocks(ntri + 1));
+        if (e == hipSuccess && !w->n_big) e = grow(&w->n_big, 0, 1);
+        w->tri_cap = e == hipSuccess ? ntri : 0;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "ffb_inverse workspace");
+    e = launch_inverse(ctx, lx, ly, reinterpret_cast<const float2 *>(nodes),
+                       reinterpret_cast<const float2 *>(queries), nq, tri,
+                       reinterpret_cast<double2 *>(pre), w);
+    return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_inverse launch");
 }
 
 int ffb_integrate_record(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy,

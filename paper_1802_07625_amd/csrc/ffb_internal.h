@@ -48,6 +48,7 @@ struct ffb_ctx {
     struct ffb_tape *tape = nullptr;           // recording for ffb_backward
     struct diff_ws *diff = nullptr;            // diffusion-variant buffers (on first use)
     int diff_graph = 1;                        // FFB_OPT_DIFFUSION_GRAPH
+    struct inverse_ws *inv = nullptr;          // inverse-map workspace (on first use)
     double *adj_t = nullptr;                   // [cap] step start times (adjoint)
     int64_t adj_t_cap = 0;
     float4 *adj_jac = nullptr;                 // [cap][n] step Jacobians (adjoint)
@@ -145,6 +146,23 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
 hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                              const advect_tape *tape, double *lam_xy, float4 *lam_fields,
                              double *lam_rho_bar);
+
+// ---------------------------------------------------------------- inverse
+// Workspace of the inverse of the piecewise-linear T (grown on demand).
+struct inverse_ws {
+    int32_t *count = nullptr, *offs = nullptr;   // [bins + 1]
+    int32_t *fill = nullptr;                     // [bins]
+    int32_t *sums = nullptr;                     // [scan workgroups]
+    int32_t *order = nullptr, *best = nullptr;   // [queries]
+    int32_t *big = nullptr;                      // [triangles] list of large image boxes
+    int64_t *big_nb = nullptr, *big_off = nullptr;  // [triangles + 1] their bin counts, scanned
+    int64_t *sums64 = nullptr;                   // [scan workgroups of triangles + 1]
+    int32_t *n_big = nullptr;                    // [1]
+    int64_t bins_cap = 0, q_cap = 0, sums_cap = 0, tri_cap = 0;
+};
+int inverse_scan_blocks(int64_t nscan);
+hipError_t launch_inverse(ffb_ctx *ctx, int lx, int ly, const float2 *nodes, const float2 *q,
+                          int64_t nq, int32_t *tri, double2 *pre, inverse_ws *w);
 
 // ---------------------------------------------------------------- diffusion
 // Control block of a diffusion integration (device memory).  The attempt's

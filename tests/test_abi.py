@@ -101,6 +101,7 @@ def test_host_validation_without_gpu(lib):
                              0) == 1
     assert lib.ffb_diffusion_fields(None, None, ctypes.c_float(1.0), 0.0, None) == 1
     assert lib.ffb_distortion(None, 4, 4, None, None, None, None) == 1
+    assert lib.ffb_inverse(None, 4, 4, None, None, 0, None, None) == 1
     assert lib.ffb_destroy(None) == 1
     assert lib.ffb_last_error(None) == b"null context"
     # batches: descriptions are checked before any device work
