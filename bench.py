@@ -407,10 +407,14 @@ def batch_leg(args, dev, max_rounds=30):
 
 
 def _advect_sha():
+    """Hash of the sources k_advect is compiled from (its file and the shared
+    advection helpers): the counter figures above hold only for them."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1802_07625_amd", "csrc", "k_advect.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("k_advect.hip", "advect_common.h"):
+        with open(os.path.join(ROOT, "paper_1802_07625_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def grad_leg(args, dev, workload="c5_L512", rounds=3, max_steps=256):
