@@ -108,46 +108,31 @@ __device__ inline int32_t lines_between(double a, double b, double *first, doubl
     return 0;
 }
 
-__global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
-    const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
-    const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t G,
-    int32_t R, int64_t E, const double *__restrict__ w, int32_t lx, int32_t ly,
-    double *__restrict__ acc, int32_t *status)
+// The deposits of one edge (x0, y0) -> (x1, y1) with weight wt into the
+// accumulation rows at acc + base.  An edge inside one cell (the common
+// case: borders are subdivided far below the cell size) is returned as a
+// keyed pair (acc[key] += va, acc[key + 1] += vb) for run_add; an edge that
+// crosses grid lines deposits its pieces directly.
+__device__ inline void edge_deposits(double *__restrict__ acc, int64_t base, int32_t lx,
+                                     int32_t ly, double wt, double x0, double y0, double x1,
+                                     double y1, int64_t &key, double &va, double &vb)
 {
-    const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
-    if (k >= E) return;
-    // ring of entry k: largest g with off[g] <= k
-    int32_t lo = 0, hi = G;     // off[lo] <= k < off[hi] if offsets are sane
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= k) lo = mid; else hi = mid;
-    }
-    const int32_t g = lo;
-    const int64_t b = off[g], e = off[g + 1];
-    if (!(b <= k && k < e) || e - b < 3 || e > E) { set_status(status, FFB_E_INVALID); return; }
-    const int32_t r = region[g];
-    const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
-    if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
-        set_status(status, FFB_E_INVALID);
-        return;
-    }
-    const float2 p = xy[i0], q = xy[i1];
-    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
-        set_status(status, FFB_E_NONFINITE);
-        return;
-    }
-    const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
-    if (x0 < 0.0 || x0 > lx || y0 < 0.0 || y0 > ly || x1 < 0.0 || x1 > lx || y1 < 0.0 ||
-        y1 > ly) {
-        set_status(status, FFB_E_DOMAIN);
-        return;
-    }
     if (y0 == y1) return;                       // horizontal edges add nothing
-    const double wt = w[r];
     const double dx = x1 - x0, dy = y1 - y0;
     double fx, sx, fy, sy;
     const int32_t nx = lines_between(x0, x1, &fx, &sx);
     const int32_t ny = lines_between(y0, y1, &fy, &sy);
+    if (nx == 0 && ny == 0) {
+        const double D = y0 - y1, xm = 0.5 * (x0 + x1);
+        int32_t k = (int32_t)floor(xm), j = (int32_t)floor(0.5 * (y0 + y1));
+        k = min(max(k, 0), lx - 1);
+        j = min(max(j, 0), ly - 1);
+        key = base + (int64_t)j * (lx + 1) + k;
+        va = wt * D * ((double)(k + 1) - xm);
+        vb = wt * D * (xm - (double)k);
+        return;
+    }
+    double *a = acc + base;
     int32_t ix = 0, iy = 0;
     double xa = x0, ya = y0;
     // merge the crossings with x- and y-lines in order of the edge parameter
@@ -170,11 +155,85 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
             ++ix;
             ++iy;
         }
-        deposit(acc, lx, ly, wt, xa, ya, xb, yb);
+        deposit(a, lx, ly, wt, xa, ya, xb, yb);
         xa = xb;
         ya = yb;
     }
-    deposit(acc, lx, ly, wt, xa, ya, x1, y1);
+    deposit(a, lx, ly, wt, xa, ya, x1, y1);
+}
+
+// Lanes of a wave hold consecutive edges of a ring, so runs of lanes deposit
+// into the same cell.  A segmented sum over each run of equal keys (a run
+// starts where the key differs from the previous lane's) leaves one pair of
+// atomic adds per run instead of one per edge.  Every lane of the wave must
+// call this; key < 0 means no keyed deposit.
+__device__ inline void run_add(double *__restrict__ acc, int64_t key, double va, double vb)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t prev = __shfl_up(key, 1, 64);
+    int seg = (lane == 0 || prev != key) ? 1 : 0;   // a run head lies in (lane - span, lane]
+    for (int o = 1; o < 64; o <<= 1) {
+        const double ta = __shfl_up(va, o, 64), tb = __shfl_up(vb, o, 64);
+        const int ts = __shfl_up(seg, o, 64);
+        if (lane >= o) {
+            if (!seg) {
+                va += ta;
+                vb += tb;
+            }
+            seg |= ts;
+        }
+    }
+    const int64_t next = __shfl_down(key, 1, 64);
+    if (key >= 0 && (lane == 63 || next != key)) {
+        unsafeAtomicAdd(acc + key, va);
+        unsafeAtomicAdd(acc + key + 1, vb);
+    }
+}
+
+__global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
+    const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
+    const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t G,
+    int32_t R, int64_t E, const double *__restrict__ w, int32_t lx, int32_t ly,
+    double *__restrict__ acc, int32_t *status)
+{
+    const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
+    int64_t key = -1;
+    double va = 0.0, vb = 0.0;
+    // no early return: every lane of the wave takes part in run_add
+    do {
+        if (k >= E) break;
+        // ring of entry k: largest g with off[g] <= k
+        int32_t lo = 0, hi = G;     // off[lo] <= k < off[hi] if offsets are sane
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (off[mid] <= k) lo = mid; else hi = mid;
+        }
+        const int32_t g = lo;
+        const int64_t b = off[g], e = off[g + 1];
+        if (!(b <= k && k < e) || e - b < 3 || e > E) {
+            set_status(status, FFB_E_INVALID);
+            break;
+        }
+        const int32_t r = region[g];
+        const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
+        if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
+            set_status(status, FFB_E_INVALID);
+            break;
+        }
+        const float2 p = xy[i0], q = xy[i1];
+        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
+            set_status(status, FFB_E_NONFINITE);
+            break;
+        }
+        const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
+        if (x0 < 0.0 || x0 > lx || y0 < 0.0 || y0 > ly || x1 < 0.0 || x1 > lx || y1 < 0.0 ||
+            y1 > ly) {
+            set_status(status, FFB_E_DOMAIN);
+            break;
+        }
+        edge_deposits(acc, 0, lx, ly, w[r], x0, y0, x1, y1, key, va, vb);
+    } while (false);
+    run_add(acc, key, va, vb);
 }
 
 // rho[j][i] = rho_pad + inclusive prefix sum of acc[j][0..i] (FP64), one row
@@ -242,62 +301,49 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
     int64_t E, const double *__restrict__ w, double *__restrict__ acc, int32_t *status)
 {
     const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
-    if (k >= E) return;
-    int32_t lo = 0, hi = G;
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= k) lo = mid; else hi = mid;
-    }
-    const int32_t g = lo;
-    const int64_t b = off[g], e = off[g + 1];
-    if (!(b <= k && k < e) || e - b < 3 || e > E) { set_status(status, FFB_E_INVALID); return; }
-    const int32_t m = bv.ring_map[g];
-    if (m < 0 || m >= bv.n_maps) { set_status(status, FFB_E_INVALID); return; }
-    if (!bv.active[m]) return;
-    const int32_t lx = bv.lx[m], ly = bv.ly[m];
-    const int32_t r = region[g];
-    const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
-    if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
-        set_status(status, FFB_E_INVALID);
-        return;
-    }
-    const float2 p = xy[i0], q = xy[i1];
-    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
-        set_status(status, FFB_E_NONFINITE);
-        return;
-    }
-    const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
-    if (x0 < 0.0 || x0 > lx || y0 < 0.0 || y0 > ly || x1 < 0.0 || x1 > lx || y1 < 0.0 ||
-        y1 > ly) {
-        set_status(status, FFB_E_DOMAIN);
-        return;
-    }
-    if (y0 == y1) return;
-    double *macc = acc + bv.acc_off[m];
-    const double wt = w[r];
-    const double dx = x1 - x0, dy = y1 - y0;
-    double fx, sx, fy, sy;
-    const int32_t nx = lines_between(x0, x1, &fx, &sx);
-    const int32_t ny = lines_between(y0, y1, &fy, &sy);
-    int32_t ix = 0, iy = 0;
-    double xa = x0, ya = y0;
-    while (ix < nx || iy < ny) {
-        const double X = fx + sx * ix, Y = fy + sy * iy;
-        const double tx = (ix < nx) ? (X - x0) / dx : 2.0;
-        const double ty = (iy < ny) ? (Y - y0) / dy : 2.0;
-        double xb, yb;
-        if (tx < ty) {
-            xb = X; yb = y0 + tx * dy; ++ix;
-        } else if (ty < tx) {
-            xb = x0 + ty * dx; yb = Y; ++iy;
-        } else {
-            xb = X; yb = Y; ++ix; ++iy;
+    int64_t key = -1;
+    double va = 0.0, vb = 0.0;
+    // no early return: every lane of the wave takes part in run_add
+    do {
+        if (k >= E) break;
+        int32_t lo = 0, hi = G;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (off[mid] <= k) lo = mid; else hi = mid;
         }
-        deposit(macc, lx, ly, wt, xa, ya, xb, yb);
-        xa = xb;
-        ya = yb;
-    }
-    deposit(macc, lx, ly, wt, xa, ya, x1, y1);
+        const int32_t g = lo;
+        const int64_t b = off[g], e = off[g + 1];
+        if (!(b <= k && k < e) || e - b < 3 || e > E) {
+            set_status(status, FFB_E_INVALID);
+            break;
+        }
+        const int32_t m = bv.ring_map[g];
+        if (m < 0 || m >= bv.n_maps) {
+            set_status(status, FFB_E_INVALID);
+            break;
+        }
+        if (!bv.active[m]) break;
+        const int32_t lx = bv.lx[m], ly = bv.ly[m];
+        const int32_t r = region[g];
+        const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
+        if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
+            set_status(status, FFB_E_INVALID);
+            break;
+        }
+        const float2 p = xy[i0], q = xy[i1];
+        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
+            set_status(status, FFB_E_NONFINITE);
+            break;
+        }
+        const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
+        if (x0 < 0.0 || x0 > lx || y0 < 0.0 || y0 > ly || x1 < 0.0 || x1 > lx || y1 < 0.0 ||
+            y1 > ly) {
+            set_status(status, FFB_E_DOMAIN);
+            break;
+        }
+        edge_deposits(acc, bv.acc_off[m], lx, ly, w[r], x0, y0, x1, y1, key, va, vb);
+    } while (false);
+    run_add(acc, key, va, vb);
 }
 
 // Row prefix sums of every active map, one workgroup per (map, row).
