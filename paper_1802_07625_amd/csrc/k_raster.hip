@@ -190,6 +190,61 @@ __device__ inline void run_add(double *__restrict__ acc, int64_t key, double va,
     }
 }
 
+// Ring entry k of the CSR rings: its ring g, region r and edge endpoints
+// (x0, y0) -> (x1, y1) in FP64.  Malformed rings, indices out of range,
+// non-finite vertices and vertices outside [0, lx] x [0, ly] set the status
+// word and return false.  lx and ly come from the caller, or (batches,
+// lx = ly = 0) from the map that owns the ring through `map_of`.
+struct EdgeOf {
+    int32_t g, r;
+    double x0, y0, x1, y1;
+};
+
+template <typename MapOf>
+__device__ inline bool edge_of(int64_t k, const float2 *__restrict__ xy, int64_t nv,
+                               const int32_t *__restrict__ off, const int32_t *__restrict__ vidx,
+                               const int32_t *__restrict__ region, int32_t G, int32_t R,
+                               int64_t E, MapOf map_of, int32_t *status, EdgeOf &ed)
+{
+    // ring of entry k: largest g with off[g] <= k
+    int32_t lo = 0, hi = G;     // off[lo] <= k < off[hi] if offsets are sane
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    const int32_t g = lo;
+    const int64_t b = off[g], e = off[g + 1];
+    if (!(b <= k && k < e) || e - b < 3 || e > E) {
+        set_status(status, FFB_E_INVALID);
+        return false;
+    }
+    int32_t lx, ly;
+    if (!map_of(g, lx, ly)) return false;
+    const int32_t r = region[g];
+    const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
+    if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
+        set_status(status, FFB_E_INVALID);
+        return false;
+    }
+    const float2 p = xy[i0], q = xy[i1];
+    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
+        set_status(status, FFB_E_NONFINITE);
+        return false;
+    }
+    if (p.x < 0.0f || p.x > lx || p.y < 0.0f || p.y > ly || q.x < 0.0f || q.x > lx ||
+        q.y < 0.0f || q.y > ly) {
+        set_status(status, FFB_E_DOMAIN);
+        return false;
+    }
+    ed.g = g;
+    ed.r = r;
+    ed.x0 = p.x;
+    ed.y0 = p.y;
+    ed.x1 = q.x;
+    ed.y1 = q.y;
+    return true;
+}
+
 __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
     const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
     const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t G,
@@ -199,40 +254,15 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
     const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
     int64_t key = -1;
     double va = 0.0, vb = 0.0;
+    EdgeOf ed;
+    auto one_map = [&](int32_t, int32_t &mx, int32_t &my) {
+        mx = lx;
+        my = ly;
+        return true;
+    };
     // no early return: every lane of the wave takes part in run_add
-    do {
-        if (k >= E) break;
-        // ring of entry k: largest g with off[g] <= k
-        int32_t lo = 0, hi = G;     // off[lo] <= k < off[hi] if offsets are sane
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (off[mid] <= k) lo = mid; else hi = mid;
-        }
-        const int32_t g = lo;
-        const int64_t b = off[g], e = off[g + 1];
-        if (!(b <= k && k < e) || e - b < 3 || e > E) {
-            set_status(status, FFB_E_INVALID);
-            break;
-        }
-        const int32_t r = region[g];
-        const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
-        if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
-            set_status(status, FFB_E_INVALID);
-            break;
-        }
-        const float2 p = xy[i0], q = xy[i1];
-        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
-            set_status(status, FFB_E_NONFINITE);
-            break;
-        }
-        const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
-        if (x0 < 0.0 || x0 > lx || y0 < 0.0 || y0 > ly || x1 < 0.0 || x1 > lx || y1 < 0.0 ||
-            y1 > ly) {
-            set_status(status, FFB_E_DOMAIN);
-            break;
-        }
-        edge_deposits(acc, 0, lx, ly, w[r], x0, y0, x1, y1, key, va, vb);
-    } while (false);
+    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, one_map, status, ed))
+        edge_deposits(acc, 0, lx, ly, w[ed.r], ed.x0, ed.y0, ed.x1, ed.y1, key, va, vb);
     run_add(acc, key, va, vb);
 }
 
@@ -303,46 +333,24 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
     const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
     int64_t key = -1;
     double va = 0.0, vb = 0.0;
-    // no early return: every lane of the wave takes part in run_add
-    do {
-        if (k >= E) break;
-        int32_t lo = 0, hi = G;
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (off[mid] <= k) lo = mid; else hi = mid;
-        }
-        const int32_t g = lo;
-        const int64_t b = off[g], e = off[g + 1];
-        if (!(b <= k && k < e) || e - b < 3 || e > E) {
-            set_status(status, FFB_E_INVALID);
-            break;
-        }
-        const int32_t m = bv.ring_map[g];
+    EdgeOf ed;
+    int32_t m = -1;
+    // the map of the ring; rings of maps that have stopped deposit nothing
+    auto map_of = [&](int32_t g, int32_t &mx, int32_t &my) {
+        m = bv.ring_map[g];
         if (m < 0 || m >= bv.n_maps) {
             set_status(status, FFB_E_INVALID);
-            break;
+            return false;
         }
-        if (!bv.active[m]) break;
-        const int32_t lx = bv.lx[m], ly = bv.ly[m];
-        const int32_t r = region[g];
-        const int32_t i0 = vidx[k], i1 = vidx[(k + 1 == e) ? b : k + 1];
-        if (r < 0 || r >= R || i0 < 0 || i0 >= nv || i1 < 0 || i1 >= nv) {
-            set_status(status, FFB_E_INVALID);
-            break;
-        }
-        const float2 p = xy[i0], q = xy[i1];
-        if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(q.x) || !isfinite(q.y)) {
-            set_status(status, FFB_E_NONFINITE);
-            break;
-        }
-        const double x0 = p.x, y0 = p.y, x1 = q.x, y1 = q.y;
-        if (x0 < 0.0 || x0 > lx || y0 < 0.0 || y0 > ly || x1 < 0.0 || x1 > lx || y1 < 0.0 ||
-            y1 > ly) {
-            set_status(status, FFB_E_DOMAIN);
-            break;
-        }
-        edge_deposits(acc, bv.acc_off[m], lx, ly, w[r], x0, y0, x1, y1, key, va, vb);
-    } while (false);
+        if (!bv.active[m]) return false;
+        mx = bv.lx[m];
+        my = bv.ly[m];
+        return true;
+    };
+    // no early return: every lane of the wave takes part in run_add
+    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, map_of, status, ed))
+        edge_deposits(acc, bv.acc_off[m], bv.lx[m], bv.ly[m], w[ed.r], ed.x0, ed.y0, ed.x1,
+                      ed.y1, key, va, vb);
     run_add(acc, key, va, vb);
 }
 
