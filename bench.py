@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="time whole oracle iterations until this much work is timed")
+    ap.add_argument("--no-cpu-single", dest="cpu_single", action="store_false",
+                    help="skip the single-core timing of the oracle")
     ap.add_argument("--no-loop", action="store_true",
                     help="skip the loop to < 1%% error")
     ap.add_argument("--no-grad", action="store_true",
@@ -236,6 +238,15 @@ def main():
         result["rect"] = rect_leg(args, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(m, pts_h, args)
+    # the paper's own timings (context only: whole cartograms of real maps at
+    # L = 512 on a 12-core Xeon E5-2680v3, divided by their round counts)
+    result["paper_context"] = {
+        "hardware": "Dell Precision T7810, 12-core Intel Xeon E5-2680v3 (multi-core C program with an FFT library)",
+        "grid": "L = 512", "maps": "USA / India / China (real data, not available here)",
+        "s_per_round": {"USA": round(1.5 / 5, 3), "India": round(2.6 / 12, 3),
+                        "China": round(2.7 / 6, 3)},
+        "note": "whole-run wall time / rounds, including set-up and I/O; different maps, "
+                "grid size and hardware: context, not a target"}
     print(json.dumps(result), flush=True)
 
 
@@ -477,11 +488,25 @@ def grad_leg(args, dev, workload="c5_L512", rounds=3, max_steps=256):
     return out
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(m, pts_h, args):
     """The FP64 oracle, untuned, on the host cores: whole iterations of the
     same workload (areas, raster, direct-sum transforms, advection of every
     vertex and grid node with the oracle's own step control, areas), repeated
-    until about ten seconds of work have been timed."""
+    until about ten seconds of work have been timed; then the same phases on
+    one core, the advection on a 1/32 sample of the points with the step
+    schedule of the all-core run replayed (its cost is proportional to the
+    number of points), scaled to the whole iteration."""
     import oracle
     cores = oracle.set_threads(0)
     runs, t = [], {}
@@ -502,12 +527,37 @@ def cpu_baseline(m, pts_h, args):
         oracle.region_areas(m, r.xy[:m.n_vertices])
         t["area_after"] = time.perf_counter() - t0
         runs.append(sum(t.values()))
-    return {"value": round(1e3 * float(np.mean(runs)), 1), "unit": "ms/iteration",
-            "cores": cores, "kind": "oracle",
-            "sample": (f"{len(runs)} whole iterations of the same workload at full size "
-                       f"({pts_h.shape[0]} points; the oracle's own step control took "
-                       f"{r.accepted} accepted and {r.rejected} rejected steps)"),
-            "phases_s": {k: round(v, 3) for k, v in t.items()}}
+    out = {"value": round(1e3 * float(np.mean(runs)), 1), "unit": "ms/iteration",
+           "cores": cores, "kind": "oracle", "cpu_model": _cpu_model(),
+           "sample": (f"{len(runs)} whole iterations of the same workload at full size "
+                      f"({pts_h.shape[0]} points; the oracle's own step control took "
+                      f"{r.accepted} accepted and {r.rejected} rejected steps)"),
+           "phases_s": {k: round(v, 3) for k, v in t.items()}}
+    if args.cpu_single:
+        oracle.set_threads(1)
+        one = {}
+        t0 = time.perf_counter()
+        a = oracle.region_areas(m)
+        one["area"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rho, _ = oracle.density(m, m.value, a)
+        one["density"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        F = oracle.flux(rho, args.sigma)
+        one["flux"] = time.perf_counter() - t0
+        sub = pts_h[::32].astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.integrate(F, sub, oracle.IntegrateOpts(tol=args.tol), replay_h=r.h)
+        one["advect"] = (time.perf_counter() - t0) * pts_h.shape[0] / sub.shape[0]
+        one["area_after"] = one["area"]
+        oracle.set_threads(0)
+        out["single_core"] = {
+            "value": round(1e3 * sum(one.values()), 1), "unit": "ms/iteration", "cores": 1,
+            "sample": (f"areas, raster and transforms once at full size; advection of every "
+                       f"32nd point ({sub.shape[0]}) with the {len(r.h)} accepted steps of the "
+                       f"all-core run replayed, scaled by {pts_h.shape[0] / sub.shape[0]:.2f}"),
+            "phases_s": {k: round(v, 3) for k, v in one.items()}}
+    return out
 
 
 if __name__ == "__main__":
