@@ -147,8 +147,9 @@ def main():
         valu = {"achieved": round(lane_ops / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
                 "unit": "T lane-instructions/s (non-packed FP32 issue)",
                 "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4)}
-    # ALU view: ~6 stage evaluations per attempt, counted from the kernel's
-    # instruction mix -- reported for context only
+    # the VALU view (SQ_INSTS_VALU per attempt from the counter run, times 64
+    # lanes, over the measured attempt time) shows the bound that binds: the
+    # kernel is instruction-issue bound, the byte model above is not
     result = {
         "metric": "ms per FFB iteration at L=1024 (FP32 vs FP64 oracle); fwd+bwd/fwd time",
         "value": round(ms_step, 4),
