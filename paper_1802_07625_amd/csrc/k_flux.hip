@@ -35,26 +35,66 @@ __device__ inline float2 cmul(float2 a, float2 b)
 
 __device__ inline int ilog2(int n) { return 31 - __clz(n); }
 
-// Radix-2 Stockham FFT (unnormalised).  `a` holds the input; returns the
+// Stockham autosort FFT (unnormalised), decimation in time, radix 4 with one
+// radix-2 pass first when log2 N is odd.  `a` holds the input; returns the
 // buffer holding the output (a or b).  `tw` (LDS) = exp(-2 pi i k / N),
 // k < N/2; the inverse uses the conjugates.
-__device__ float2 *fft_lds(float2 *a, float2 *b, int N, const float2 *tw, bool inverse)
+//
+// Before a pass with sub-length Ls, a[p Ls + j] holds bin j of the length-Ls
+// DFT of the decimated sequence x[p + r N/Ls].  A radix-4 pass combines the
+// four sequences p = q + m N/(4 Ls), m = 0..3 (stored N/4 apart):
+//   X[j + t Ls] = sum_m w_{4Ls}^{m j} w_4^{m t} x_m,  t = 0..3,
+// written to b[q 4Ls + j + t Ls].  Half as many passes as radix 2, so half
+// the LDS traffic and barriers.
+__device__ __forceinline__ float2 *fft_lds(float2 *a, float2 *b, int N, const float2 *tw, bool inverse)
 {
-    const int half = N >> 1;
     const int lgN = ilog2(N);
-    for (int lgL = 0; lgL < lgN; ++lgL) {
-        const int Ls = 1 << lgL;
+    const int half = N >> 1, quarter = N >> 2;
+    int lgL = 0;
+    if (lgN & 1) {
+        // radix 2 with Ls = 1: every twiddle is 1
         __syncthreads();
         for (int bi = threadIdx.x; bi < half; bi += blockDim.x) {
+            const float2 u = a[bi], v = a[bi + half];
+            b[2 * bi] = make_float2(u.x + v.x, u.y + v.y);
+            b[2 * bi + 1] = make_float2(u.x - v.x, u.y - v.y);
+        }
+        float2 *t = a;
+        a = b;
+        b = t;
+        lgL = 1;
+    }
+    for (; lgL < lgN; lgL += 2) {
+        const int Ls = 1 << lgL;
+        const int sh = lgN - 2 - lgL;                 // log2 of N / (4 Ls)
+        __syncthreads();
+        for (int bi = threadIdx.x; bi < quarter; bi += blockDim.x) {
             const int j = bi & (Ls - 1);
             const int k = bi >> lgL;
-            float2 w = tw[j << (lgN - 1 - lgL)];
-            if (inverse) w.y = -w.y;
-            const float2 u = a[bi];
-            const float2 v = cmul(a[bi + half], w);
-            const int o = (k << (lgL + 1)) + j;
-            b[o] = make_float2(u.x + v.x, u.y + v.y);
-            b[o + Ls] = make_float2(u.x - v.x, u.y - v.y);
+            const int e1 = j << sh, e3 = 3 * e1;     // e1 < N/4, 2 e1 < N/2, e3 < 3N/4
+            float2 w1 = tw[e1], w2 = tw[2 * e1];
+            float2 w3 = e3 < half ? tw[e3] : tw[e3 - half];
+            if (e3 >= half) w3 = make_float2(-w3.x, -w3.y);   // exp(-i pi) = -1
+            if (inverse) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+                w3.y = -w3.y;
+            }
+            const float2 x0 = a[bi];
+            const float2 x1 = cmul(a[bi + quarter], w1);
+            const float2 x2 = cmul(a[bi + 2 * quarter], w2);
+            const float2 x3 = cmul(a[bi + 3 * quarter], w3);
+            const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y);
+            const float2 a1 = make_float2(x0.x - x2.x, x0.y - x2.y);
+            const float2 b0 = make_float2(x1.x + x3.x, x1.y + x3.y);
+            const float2 b1 = make_float2(x1.x - x3.x, x1.y - x3.y);
+            // w_4 b1: -i b1 forward, +i b1 inverse
+            const float2 rb = inverse ? make_float2(-b1.y, b1.x) : make_float2(b1.y, -b1.x);
+            const int o = (k << (lgL + 2)) + j;
+            b[o] = make_float2(a0.x + b0.x, a0.y + b0.y);
+            b[o + Ls] = make_float2(a1.x + rb.x, a1.y + rb.y);
+            b[o + 2 * Ls] = make_float2(a0.x - b0.x, a0.y - b0.y);
+            b[o + 3 * Ls] = make_float2(a1.x - rb.x, a1.y - rb.y);
         }
         float2 *t = a;
         a = b;
@@ -79,7 +119,7 @@ __device__ inline int mk_pos(int i, int N) { return (i & 1) ? (N - 1 - (i >> 1))
 // DCT-II of two rows held as (ra[i], rb[i]) pairs already placed in `a` in
 // Makhoul order; leaves X_a[m], X_b[m] (unnormalised: sum x_i cos(pi m (i+1/2)/N))
 // in `out` as float2 pairs.
-__device__ void dct2_pair(float2 *a, float2 *b, float2 *out, int N, const float2 *tw,
+__device__ __forceinline__ void dct2_pair(float2 *a, float2 *b, float2 *out, int N, const float2 *tw,
                           const float2 *__restrict__ tq, int qs = 1)
 {
     float2 *Z = fft_lds(a, b, N, tw, false);
@@ -124,7 +164,7 @@ __device__ inline float2 dct3_output(const float2 *v, int i, int N) { return v[m
 // ------------------------------------------------------------------ kernels
 // DCT-II of rows r0, r0 + 1 of `in` [rows][N] into `out` (LDS: sa, sb of
 // kMaxN and stw of kMaxN / 2 float2).
-__device__ void dct2_rows_body(const float *__restrict__ in, float *__restrict__ out, int64_t r0,
+__device__ __forceinline__ void dct2_rows_body(const float *__restrict__ in, float *__restrict__ out, int64_t r0,
                                int N, const float2 *__restrict__ tw, const float2 *__restrict__ tq,
                                int qs, float2 *sa, float2 *sb, float2 *stw)
 {
@@ -192,7 +232,7 @@ __global__ __launch_bounds__(256) void k_transpose(const float *__restrict__ in0
 
 // Column pass on rows m0, m1 = m0 + 1 of T2 [lx][ly] (LDS: sa, sb, coef of
 // kMaxN and stw of kMaxN / 2 float2).
-__device__ void col_pass_body(const float *__restrict__ t2, int m0, int lx, int ly, float sigma,
+__device__ __forceinline__ void col_pass_body(const float *__restrict__ t2, int m0, int lx, int ly, float sigma,
                               const float2 *__restrict__ tw, const float2 *__restrict__ tq, int qs,
                               float *__restrict__ pa, float *__restrict__ pb,
                               float *__restrict__ pc, float2 *sa, float2 *sb, float2 *coef,
@@ -285,7 +325,7 @@ __global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, 
 // Row pass on rows j0, j1 = j0 + 1 of a, b, c [ly][lx]; writes the ghosted
 // float4 fields (J_x, J_y, rho_s, 0) (LDS: sa, sb, rs, jx of kMaxN and stw of
 // kMaxN / 2 float2).
-__device__ void row_final_body(const float *__restrict__ pa, const float *__restrict__ pb,
+__device__ __forceinline__ void row_final_body(const float *__restrict__ pa, const float *__restrict__ pb,
                                const float *__restrict__ pc, int j0, int lx, int ly,
                                const float2 *__restrict__ tw, const float2 *__restrict__ tq,
                                int qs, float4 *__restrict__ fields, int32_t *status, float2 *sa,
