@@ -17,7 +17,7 @@
 //                              J_y = sum_m c cos  -> ghosted float4 fields
 // with wx = (ly/pi) m/(m^2 ly^2 + n^2 lx^2), wy = (lx/pi) n/(...).
 //
-// Every 1D transform is a length-N complex FFT in LDS (radix-2 Stockham,
+// Every 1D transform is a length-N complex FFT in LDS (radix-4 Stockham,
 // twiddles staged in LDS) serving two real rows at once (one as the real,
 // one as the imaginary part), with the even/odd reordering of Makhoul
 // (1980) turning the real DCT-II/DCT-III into a plain FFT; the DST-III is a
