@@ -1,7 +1,8 @@
 // Region areas and relative area errors (the stopping rule of the paper's
 // benchmarking section: a maximum relative area error below 1 %).
 //
-// k_ring_area: one workgroup per ring.  Each lane forms FP64 shoelace terms
+// k_ring_area: one workgroup per ring (1024 lanes when rings average 2048
+// entries or more, else 256).  Each lane forms FP64 shoelace terms
 // x_k y_{k+1} - x_{k+1} y_k from FP32 coordinates (the products are exact in
 // FP64), the block reduces them with wavefront shuffles and one FP64 atomic
 // adds half the sum to the ring's region (regions with one ring are therefore
@@ -77,12 +78,13 @@ __device__ double block_sum(double v, double *lds)
     return r;
 }
 
-__global__ __launch_bounds__(kAreaThreads) void k_ring_area(
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ring_area(
     const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
     const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t n_rings,
     int32_t n_regions, int64_t n_entries, double *__restrict__ area, int32_t *status)
 {
-    __shared__ double lds[kAreaThreads / 64 + 1];
+    __shared__ double lds[NT / 64 + 1];
     const int32_t g = blockIdx.x;
     const int64_t b = off[g], e = off[g + 1];
     const int32_t r = region[g];
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(kAreaThreads) void k_ring_area(
     }
     double s = 0.0;
     int bad = 0;
-    for (int64_t k = b + threadIdx.x; k < e; k += kAreaThreads) {
+    for (int64_t k = b + threadIdx.x; k < e; k += NT) {
         const int64_t k1 = (k + 1 == e) ? b : k + 1;
         const int32_t i = vidx[k], j = vidx[k1];
         if (i < 0 || i >= nv || j < 0 || j >= nv) { bad |= 1; continue; }
@@ -103,8 +105,25 @@ __global__ __launch_bounds__(kAreaThreads) void k_ring_area(
     }
     if (bad & 1) set_status(status, FFB_E_INVALID);
     else if (bad & 2) set_status(status, FFB_E_NONFINITE);
-    s = block_sum<kAreaThreads>(s, lds);
+    s = block_sum<NT>(s, lds);
     if (threadIdx.x == 0) atomicAdd(&area[r], 0.5 * s);
+}
+
+// One workgroup per ring; long rings (detailed borders) get 1024 lanes so
+// that each lane takes only a few entries.
+hipError_t launch_ring_area_kernel(hipStream_t s, const ffb_geometry *g, double *area,
+                                   int32_t *status)
+{
+    const float2 *xy = reinterpret_cast<const float2 *>(g->xy);
+    if (g->n_entries >= (int64_t)2048 * g->n_rings)
+        hipLaunchKernelGGL(k_ring_area<1024>, dim3(g->n_rings), dim3(1024), 0, s, xy,
+                           g->n_vertices, g->ring_offsets, g->ring_vidx, g->ring_region,
+                           g->n_rings, g->n_regions, g->n_entries, area, status);
+    else
+        hipLaunchKernelGGL(k_ring_area<kAreaThreads>, dim3(g->n_rings), dim3(kAreaThreads), 0,
+                           s, xy, g->n_vertices, g->ring_offsets, g->ring_vidx, g->ring_region,
+                           g->n_rings, g->n_regions, g->n_entries, area, status);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_area_finalize(
@@ -253,11 +272,7 @@ hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *
     hipError_t e = launch_fill_f64(area, g->n_regions, 0.0, ctx->stream);
     if (e != hipSuccess) return e;
     if (g->n_rings > 0) {
-        hipLaunchKernelGGL(k_ring_area, dim3(g->n_rings), dim3(kAreaThreads), 0, ctx->stream,
-                           reinterpret_cast<const float2 *>(g->xy), g->n_vertices,
-                           g->ring_offsets, g->ring_vidx, g->ring_region, g->n_rings,
-                           g->n_regions, g->n_entries, area, ctx->d_status);
-        e = hipGetLastError();
+        e = launch_ring_area_kernel(ctx->stream, g, area, ctx->d_status);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_area_finalize, dim3(1), dim3(kFinThreads), 0, ctx->stream, value,
@@ -269,11 +284,7 @@ hipError_t launch_ring_areas(hipStream_t s, const ffb_geometry *g, double *area,
 {
     hipError_t e = launch_fill_f64(area, g->n_regions, 0.0, s);
     if (e != hipSuccess || g->n_rings == 0) return e;
-    hipLaunchKernelGGL(k_ring_area, dim3(g->n_rings), dim3(kAreaThreads), 0, s,
-                       reinterpret_cast<const float2 *>(g->xy), g->n_vertices, g->ring_offsets,
-                       g->ring_vidx, g->ring_region, g->n_rings, g->n_regions, g->n_entries, area,
-                       status);
-    return hipGetLastError();
+    return launch_ring_area_kernel(s, g, area, status);
 }
 
 hipError_t launch_batch_finalize(hipStream_t s, const batch_view &bv, const double *value,
