@@ -81,8 +81,8 @@ __device__ double block_sum(double v, double *lds)
 template <int NT>
 __global__ __launch_bounds__(NT) void k_ring_area(
     const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
-    const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t n_rings,
-    int32_t n_regions, int64_t n_entries, double *__restrict__ area, int32_t *status)
+    const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t n_regions,
+    int64_t n_entries, double *__restrict__ area, int32_t *status)
 {
     __shared__ double lds[NT / 64 + 1];
     const int32_t g = blockIdx.x;
@@ -118,11 +118,11 @@ hipError_t launch_ring_area_kernel(hipStream_t s, const ffb_geometry *g, double 
     if (g->n_entries >= (int64_t)2048 * g->n_rings)
         hipLaunchKernelGGL(k_ring_area<1024>, dim3(g->n_rings), dim3(1024), 0, s, xy,
                            g->n_vertices, g->ring_offsets, g->ring_vidx, g->ring_region,
-                           g->n_rings, g->n_regions, g->n_entries, area, status);
+                           g->n_regions, g->n_entries, area, status);
     else
         hipLaunchKernelGGL(k_ring_area<kAreaThreads>, dim3(g->n_rings), dim3(kAreaThreads), 0,
                            s, xy, g->n_vertices, g->ring_offsets, g->ring_vidx, g->ring_region,
-                           g->n_rings, g->n_regions, g->n_entries, area, status);
+                           g->n_regions, g->n_entries, area, status);
     return hipGetLastError();
 }
 

@@ -112,3 +112,25 @@ def test_full_size_sampled_and_round_trip():
     t_ref, p_ref = oracle.inverse(nodes, L, L, q[idx])
     np.testing.assert_array_equal(t[idx], t_ref)
     np.testing.assert_allclose(p[idx], p_ref, rtol=0, atol=1e-12)
+
+
+def test_graticule_helper_on_identity_and_warp():
+    L = 32
+    ctx = new_ctx(L, L)
+    g = torch.as_tensor(synth.grid_nodes(L, L), device="cuda")
+    vert, horz = ctx.graticule(g, spacing=8.0, samples=2)
+    v, h = to_np(vert), to_np(horz)
+    assert v.shape == (3, 2 * L + 1, 2) and h.shape == (3, 2 * L + 1, 2)
+    inside = (np.abs(v[..., 1] - L / 2) <= L / 2 - 0.5)
+    # the identity map: the line x = 8 k maps to itself
+    np.testing.assert_allclose(v[..., 0][inside], np.repeat([8.0, 16.0, 24.0], inside.sum(1)),
+                               atol=1e-12)
+    assert np.all(np.isnan(v[~inside]))
+    # a warped map: every sample inside the hull maps back onto its line
+    nodes = synth.warped_nodes(L, L, 9, amp=0.3)
+    vert, _ = ctx.graticule(torch.as_tensor(nodes, device="cuda"), spacing=8.0, samples=2)
+    v = to_np(vert)
+    ok = ~np.isnan(v[..., 0])
+    back = _forward_pl(nodes, L, L, v[ok])
+    np.testing.assert_allclose(back[:, 0], np.repeat([8.0, 16.0, 24.0], ok.sum(1)), atol=1e-9)
+    ctx.close()
