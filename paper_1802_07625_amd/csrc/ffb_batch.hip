@@ -256,7 +256,7 @@ hipError_t enqueue_step(ffb_batch *b, const ffb_batch_opts &o, float *xy,
                                         b->acc, b->acc_total, b->rho, b->d_status);
     if (e == hipSuccess)
         e = launch_batch_flux(s, bv, bt, plan_of(b, b->fft_threads), b->tw1024, b->tq1024, b->rho,
-                              b->t1, b->t2, b->pa, b->pb, b->pc, b->fields, b->rho_bar,
+                              b->acc, b->t1, b->t2, b->pa, b->pb, b->pc, b->fields, b->rho_bar,
                               b->d_status);
     if (e == hipSuccess)
         e = launch_batch_advect(s, bv, advect_args(b, o, xy, replay_off, replay_h),
@@ -646,8 +646,8 @@ int ffb_batch_autotune(ffb_batch *b, const ffb_batch_opts *o)
             const batch_fft_plan plan = plan_of(b, threads);
             float ms = time_it(b, [&]() {
                 return launch_batch_flux(b->stream, bv0, tables_of(b), plan, b->tw1024, b->tq1024,
-                                         b->rho, b->t1, b->t2, b->pa, b->pb, b->pc, b->fields,
-                                         b->rho_bar, b->d_status);
+                                         b->rho, b->acc, b->t1, b->t2, b->pa, b->pb, b->pc,
+                                         b->fields, b->rho_bar, b->d_status);
             }, 3, &e);
             if (e == hipSuccess && ms < best) {
                 best = ms;

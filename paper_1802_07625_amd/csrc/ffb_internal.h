@@ -269,7 +269,8 @@ struct batch_fft_plan {
 };
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const float2 *tw1024,
-                             const float2 *tq1024, float *rho, float *t1, float *t2, float *pa,
+                             const float2 *tq1024, float *rho, const double *acc, float *t1,
+                             float *t2, float *pa,
                              float *pb, float *pc, float4 *fields, double *rho_bar,
                              int32_t *status);
 struct batch_advect_args {

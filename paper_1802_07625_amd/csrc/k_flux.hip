@@ -649,24 +649,26 @@ __global__ __launch_bounds__(512) void k_adj_rows_final(const float *__restrict_
 // bodies as the single-map kernels with the length-1024 twiddle tables read
 // at stride 1024 / N.  Maps that stopped iterating are skipped.
 
-__global__ __launch_bounds__(1024) void kb_mean(batch_view bv, const float *__restrict__ rho,
-                                                double *__restrict__ rho_bar, int32_t *status)
+// Mean density of every active map in FP64 from the row sums the raster
+// scan left in the spare last slot of each accumulation row (fixed order).
+__global__ __launch_bounds__(256) void kb_mean(batch_view bv, const double *__restrict__ acc,
+                                               double *__restrict__ rho_bar, int32_t *status)
 {
-    __shared__ double lds[1024];
+    __shared__ double lds[256];
     const int m = blockIdx.x;
     if (!bv.active[m]) return;
-    const int64_t n = (int64_t)bv.lx[m] * bv.ly[m];
-    const float *x = rho + bv.plane_off[m];
+    const int lx = bv.lx[m], ly = bv.ly[m];
+    const double *a = acc + bv.acc_off[m];
     double sum = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) sum += (double)x[i];
+    for (int j = threadIdx.x; j < ly; j += 256) sum += a[(int64_t)j * (lx + 1) + lx];
     lds[threadIdx.x] = sum;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
+    for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < (unsigned)o) lds[threadIdx.x] += lds[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double mean = lds[0] / (double)n;
+        const double mean = lds[0] / ((double)lx * (double)ly);
         rho_bar[m] = mean;
         if (!(mean > 0.0)) set_status(status, FFB_E_NONPOSITIVE);
     }
@@ -980,11 +982,11 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
 
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const float2 *tw1024,
-                             const float2 *tq1024, float *rho, float *t1, float *t2, float *pa,
-                             float *pb, float *pc, float4 *fields, double *rho_bar,
-                             int32_t *status)
+                             const float2 *tq1024, float *rho, const double *acc, float *t1,
+                             float *t2, float *pa, float *pb, float *pc, float4 *fields,
+                             double *rho_bar, int32_t *status)
 {
-    hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(1024), 0, s, bv, rho, rho_bar, status);
+    hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, s, bv, acc, rho_bar, status);
     for (int c = 0; c < plan.n_classes; ++c) {
         const int n = plan.row_beg[c + 1] - plan.row_beg[c];
         if (n > 0)

@@ -354,9 +354,13 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
     run_add(acc, key, va, vb);
 }
 
-// Row prefix sums of every active map, one workgroup per (map, row).
+// Row prefix sums of every active map, one workgroup per (map, row).  The
+// FP64 sum of the row's stored FP32 densities (fixed order: each lane's
+// cells in order, then a tree over the lanes) goes to the row's spare last
+// slot acc[j][lx], which the deposits may have touched but the prefix sum
+// never reads; kb_mean turns the row sums into the map's mean density.
 __global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
-    batch_view bv, const int2 *__restrict__ rows, const double *__restrict__ acc,
+    batch_view bv, const int2 *__restrict__ rows, double *__restrict__ acc,
     const double *__restrict__ rho_pad, float *__restrict__ rho)
 {
     __shared__ double part[kScanThreads];
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
     const int m = e.x, j = e.y;
     if (!bv.active[m]) return;
     const int32_t lx = bv.lx[m];
-    const double *row = acc + bv.acc_off[m] + (int64_t)j * (lx + 1);
+    double *row = acc + bv.acc_off[m] + (int64_t)j * (lx + 1);
     const int32_t chunk = (lx + kScanThreads - 1) / kScanThreads;
     const int32_t beg = threadIdx.x * chunk;
     const int32_t end = min(beg + chunk, lx);
@@ -380,10 +384,21 @@ __global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
     }
     double run = part[threadIdx.x] - s + rho_pad[m];
     float *out = rho + bv.plane_off[m] + (int64_t)j * lx;
+    double stored = 0.0;
     for (int32_t i = beg; i < end; ++i) {
         run += row[i];
-        out[i] = (float)run;
+        const float v = (float)run;
+        out[i] = v;
+        stored += (double)v;
     }
+    __syncthreads();
+    part[threadIdx.x] = stored;
+    __syncthreads();
+    for (int o = kScanThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) row[lx] = part[0];
 }
 
 }  // namespace
