@@ -47,8 +47,8 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3_L1024")
     ap.add_argument("--sigma", type=float, default=4.0)
     ap.add_argument("--tol", type=float, default=1e-3)
@@ -103,9 +103,14 @@ def main():
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    # whole-step events, for the median step time
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
     stats_all = torch.zeros((max(args.steps, 1), 4), dtype=torch.int32, device=dev)
 
     def step(i=None):
+        if i is not None:
+            evs[i][0].record(stream)
         pts.copy_(pts0)
         area0, _, _ = ctx.area_error(geom, value)
         rho, pad = ctx.density(geom, value, area0)
@@ -117,6 +122,8 @@ def main():
         if i is not None:
             ev[i][1].record(stream)
         area1, err1, mx = ctx.area_error(geom, value)
+        if i is not None:
+            evs[i][1].record(stream)
         return stats, mx
 
     for _ in range(args.warmup):
@@ -169,6 +176,9 @@ def main():
                    "sigma": args.sigma, "tol": args.tol,
                    "rk_attempts_mean": float(attempts.mean()),
                    "rk_accepted_mean": float(st[:, 0].mean()),
+                   "rk_rejected_mean": float(st[:, 1].mean()),
+                   "ms_median_step": round(float(np.median(
+                       [a.elapsed_time(b) for a, b in evs])), 4),
                    "advect_ms_mean": round(float(adv_ms.mean()), 4),
                    "us_per_attempt": round(float((adv_ms / attempts).mean() * 1e3), 3),
                    "final_max_area_error": float(mx)},
