@@ -137,6 +137,26 @@ __device__ inline float2 velocity(const Field &F, const Axis &ax, const Axis &ay
     return make_float2(fmaf(b, xr1 - xr0, xr0), fmaf(b, yr1 - yr0, yr0));
 }
 
+// Step-size update of the adaptive controller (all integrators): after an
+// accepted attempt the step grows or shrinks by safety * (err / tol)^(-1/5)
+// within [fac_min, fac_max] (fac_max when err = 0) and does not grow right
+// after a rejection; after a rejected attempt it shrinks by the same factor,
+// at most down to fac_min.
+__device__ inline double step_after_accept(double h, double err, double tol, double safety,
+                                           double fac_min, double fac_max, bool last_rejected)
+{
+    double fac = (err == 0.0) ? fac_max : safety * pow(err / tol, -0.2);
+    fac = fmin(fmax(fac, fac_min), fac_max);
+    if (last_rejected && fac > 1.0) fac = 1.0;
+    return h * fac;
+}
+
+__device__ inline double step_after_reject(double h, double err, double tol, double safety,
+                                           double fac_min)
+{
+    return h * fmax(fac_min, safety * pow(err / tol, -0.2));
+}
+
 // A wave-uniform float kept in a scalar register.
 __device__ inline float uniform(float v)
 {

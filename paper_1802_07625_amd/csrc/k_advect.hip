@@ -335,15 +335,13 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             ++acc;
             t = final_step ? 1.0 : t + h;
             if (!replay) {
-                double fac = (err == 0.0) ? p.fac_max : p.safety * pow(err / p.tol, -0.2);
-                fac = fmin(fmax(fac, p.fac_min), p.fac_max);
-                if (last_rejected && fac > 1.0) fac = 1.0;
-                h *= fac;
+                h = step_after_accept(h, err, p.tol, p.safety, p.fac_min, p.fac_max,
+                                      last_rejected);
                 last_rejected = 0;
             }
         } else {
             ++rej;
-            h *= fmax(p.fac_min, p.safety * pow(err / p.tol, -0.2));
+            h = step_after_reject(h, err, p.tol, p.safety, p.fac_min);
             last_rejected = 1;
             if (MODE != kGlobalState) {
                 // undo the attempt: every lane restores its own points
@@ -492,15 +490,13 @@ __global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args
             ++acc;
             t = final_step ? 1.0 : t + h;
             if (!replay) {
-                double fac = (err == 0.0) ? a.fac_max : a.safety * pow(err / a.tol, -0.2);
-                fac = fmin(fmax(fac, a.fac_min), a.fac_max);
-                if (last_rejected && fac > 1.0) fac = 1.0;
-                h *= fac;
+                h = step_after_accept(h, err, a.tol, a.safety, a.fac_min, a.fac_max,
+                                      last_rejected);
                 last_rejected = 0;
             }
         } else {
             ++rej;
-            h *= fmax(a.fac_min, a.safety * pow(err / a.tol, -0.2));
+            h = step_after_reject(h, err, a.tol, a.safety, a.fac_min);
             last_rejected = 1;
         }
         if (!replay && t < 1.0 && h < a.h_min) {

@@ -198,15 +198,13 @@ __global__ __launch_bounds__(kControlThreads) void kd_control(diff_ctl *c,
                 c->acc += 1;
                 c->t = c->final_step ? c->t_end : c->t + h;
                 if (!replay) {
-                    double fac = (err == 0.0) ? c->fac_max : c->safety * pow(err / c->tol, -0.2);
-                    fac = fmin(fmax(fac, c->fac_min), c->fac_max);
-                    if (c->last_rejected && fac > 1.0) fac = 1.0;
-                    c->h = h * fac;
+                    c->h = step_after_accept(h, err, c->tol, c->safety, c->fac_min, c->fac_max,
+                                             c->last_rejected != 0);
                     c->last_rejected = 0;
                 }
             } else {
                 c->rej += 1;
-                c->h = h * fmax(c->fac_min, c->safety * pow(err / c->tol, -0.2));
+                c->h = step_after_reject(h, err, c->tol, c->safety, c->fac_min);
                 c->last_rejected = 1;
             }
             if (c->t >= c->t_end) {
