@@ -137,6 +137,24 @@ __device__ inline float2 velocity(const Field &F, const Axis &ax, const Axis &ay
     return make_float2(fmaf(b, xr1 - xr0, xr0), fmaf(b, yr1 - yr0, yr0));
 }
 
+// x^(-1/5) for x > 0, to a few ulp: a single-precision estimate refined by
+// two Newton steps on y^-5 = x, y <- y (6 - x y^5) / 5, each of which about
+// squares the relative error (1e-7, 1e-14, then rounding level).  The chain
+// is a third as long as a double-precision pow, and it sits on the critical
+// path between the grid-wide error maximum and the next attempt.  Inputs
+// whose single-precision estimate could under- or overflow take pow.
+__device__ inline double inv_fifth_root(double x)
+{
+    if (!(x >= 1e-30 && x <= 1e30)) return pow(x, -0.2);
+    double y = (double)powf((float)x, -0.2f);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double y2 = y * y;
+        y *= fma(-0.2, x * (y2 * y2 * y), 1.2);
+    }
+    return y;
+}
+
 // Step-size update of the adaptive controller (all integrators): after an
 // accepted attempt the step grows or shrinks by safety * (err / tol)^(-1/5)
 // within [fac_min, fac_max] (fac_max when err = 0) and does not grow right
@@ -145,7 +163,7 @@ __device__ inline float2 velocity(const Field &F, const Axis &ax, const Axis &ay
 __device__ inline double step_after_accept(double h, double err, double tol, double safety,
                                            double fac_min, double fac_max, bool last_rejected)
 {
-    double fac = (err == 0.0) ? fac_max : safety * pow(err / tol, -0.2);
+    double fac = (err == 0.0) ? fac_max : safety * inv_fifth_root(err / tol);
     fac = fmin(fmax(fac, fac_min), fac_max);
     if (last_rejected && fac > 1.0) fac = 1.0;
     return h * fac;
@@ -154,7 +172,7 @@ __device__ inline double step_after_accept(double h, double err, double tol, dou
 __device__ inline double step_after_reject(double h, double err, double tol, double safety,
                                            double fac_min)
 {
-    return h * fmax(fac_min, safety * pow(err / tol, -0.2));
+    return h * fmax(fac_min, safety * inv_fifth_root(err / tol));
 }
 
 // A wave-uniform float kept in a scalar register.
