@@ -133,8 +133,25 @@ const char *ffb_last_error(const ffb_ctx *ctx);
  *     ffb_integrate (0 = one per CU, the default).
  *   FFB_OPT_DIFFUSION_GRAPH: ffb_diffusion replays one captured graph per
  *     attempt (1, default) or launches each attempt's kernels (0).
+ *   FFB_OPT_POINT_ORDER: order in which ffb_integrate, the recording
+ *     forward and ffb_diffusion visit the points; results are the same bits
+ *     in every mode, only the cost of the field lookups changes.
+ *     0 = the caller's order;
+ *     1 = sorted by the grid cell each point starts in when n >= 65536
+ *         and the packed fields exceed 8 MB (lx * ly > 2^19; default; the
+ *         sort is five short launches on the call's stream, ~45 us at
+ *         1024 x 1024 with 2 M points);
+ *     2 = sorted for every n > 0;
+ *     3 = as 1, but a call with the same xy pointer and n as the call that
+ *         last sorted reuses that order instead of sorting again (for
+ *         loops of rounds over one point array, whose points move smoothly;
+ *         any order gives the same results, a kept one may only be slower).
+ *         Setting the option (any value) drops a kept order.
+ *     The sort keeps n int32 slots and 2 (lx*ly + 1) int32 cell tables in
+ *     the context.
  * Returns FFB_E_INVALID for an unknown option or value. */
-enum { FFB_OPT_ADVECT_STATE = 1, FFB_OPT_ADVECT_BLOCKS = 2, FFB_OPT_DIFFUSION_GRAPH = 3 };
+enum { FFB_OPT_ADVECT_STATE = 1, FFB_OPT_ADVECT_BLOCKS = 2, FFB_OPT_DIFFUSION_GRAPH = 3,
+       FFB_OPT_POINT_ORDER = 4 };
 int ffb_set_option(ffb_ctx *ctx, int32_t option, int32_t value);
 
 /* Areas and relative area errors (benchmarking section, stopping rule).

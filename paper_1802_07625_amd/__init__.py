@@ -9,7 +9,8 @@ from .api import (  # noqa: F401
     default_sigma, iterate, lib, LIB_PATH,
     ffb_create, ffb_destroy, ffb_sync, ffb_reset_status, ffb_last_error,
     ffb_area_error, ffb_density, ffb_flux, ffb_pack_fields, ffb_integrate,
-    ffb_set_option, OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS, OPT_DIFFUSION_GRAPH,
+    ffb_set_option, OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS, OPT_DIFFUSION_GRAPH, OPT_POINT_ORDER,
+    POINT_ORDER_GIVEN, POINT_ORDER_AUTO, POINT_ORDER_ALWAYS, POINT_ORDER_KEEP,
     ffb_diffusion, ffb_diffusion_fields, iterate_diffusion, diffusion_t_end, DIFFUSION_K,
     ffb_area_adj, ffb_density_adj, ffb_flux_adj, ffb_integrate_record, ffb_integrate_adj,
     ffb_tape_begin, ffb_tape_end, ffb_tape_clear, ffb_backward, FFBFunction,

@@ -220,7 +220,9 @@ def ffb_last_error(ctx) -> str:
     return lib().ffb_last_error(ctx).decode()
 
 
-OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS, OPT_DIFFUSION_GRAPH = 1, 2, 3
+OPT_ADVECT_STATE, OPT_ADVECT_BLOCKS, OPT_DIFFUSION_GRAPH, OPT_POINT_ORDER = 1, 2, 3, 4
+# values of OPT_POINT_ORDER
+POINT_ORDER_GIVEN, POINT_ORDER_AUTO, POINT_ORDER_ALWAYS, POINT_ORDER_KEEP = 0, 1, 2, 3
 
 
 def ffb_set_option(ctx, option: int, value: int) -> None:

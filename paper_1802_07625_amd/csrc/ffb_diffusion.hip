@@ -185,7 +185,10 @@ int ffb_diffusion(ffb_ctx *ctx, const float *rho, float sigma, double t_end, flo
     if (e == hipSuccess) e = launch_diff_setup(ctx, w, init);
     if (e == hipSuccess) e = launch_diff_spectrum(ctx, rho, sigma, w->spec);
     if (e == hipSuccess) e = launch_diff_fields(ctx, w, 1);      // t = 0 (stage times all 0)
-    if (e == hipSuccess) e = launch_diff_init_points(ctx, w, reinterpret_cast<float2 *>(xy), n);
+    const int32_t *perm = nullptr;
+    if (e == hipSuccess) perm = prepare_point_order(ctx, xy, n, &e);
+    if (e == hipSuccess)
+        e = launch_diff_init_points(ctx, w, reinterpret_cast<float2 *>(xy), n, perm);
     if (e == hipSuccess) e = launch_diff_control(ctx, w, n, 1);
     if (e == hipSuccess && w->use_graph) e = ensure_graph(ctx, w, n);
     // at most max_attempts attempts do work; the control block stops the rest
@@ -199,7 +202,7 @@ int ffb_diffusion(ffb_ctx *ctx, const float *rho, float sigma, double t_end, flo
         if (e == hipSuccess) e = hipStreamSynchronize(w->stream);
         if (e == hipSuccess && *w->done_host) break;
     }
-    if (e == hipSuccess) e = launch_diff_finish(ctx, w, reinterpret_cast<float2 *>(xy), n);
+    if (e == hipSuccess) e = launch_diff_finish(ctx, w, reinterpret_cast<float2 *>(xy), n, perm);
     ctx->stream = user;
     hipError_t e2 = hipEventRecord(w->ev_out, w->stream);
     if (e2 == hipSuccess) e2 = hipStreamWaitEvent(user, w->ev_out, 0);

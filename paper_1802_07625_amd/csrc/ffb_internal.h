@@ -45,6 +45,17 @@ struct ffb_ctx {
     int adv_mode = 1;                          // advection state placement (FFB_OPT_ADVECT_STATE)
     int adv_cap = 0;                           // cap on advection workgroups, 0 = none
 
+    // spatial point order of the integration (FFB_OPT_POINT_ORDER)
+    int ord_mode = 1;
+    int32_t *ord_perm = nullptr;               // [n] point index of each sorted slot
+    int32_t *ord_rank = nullptr;               // [n] rank of a point within its cell
+    int64_t ord_cap = 0;
+    int32_t *ord_count = nullptr;              // [lx*ly + 1] points per cell
+    int32_t *ord_offs = nullptr;               // [lx*ly + 1] their exclusive scan
+    int32_t *ord_sums = nullptr;               // [scan workgroups of lx*ly + 1]
+    const void *ord_xy = nullptr;              // mode 3: points and count the saved
+    int64_t ord_n = -1;                        // order was computed for
+
     struct ffb_tape *tape = nullptr;           // recording for ffb_backward
     struct diff_ws *diff = nullptr;            // diffusion-variant buffers (on first use)
     int diff_graph = 1;                        // FFB_OPT_DIFFUSION_GRAPH
@@ -77,6 +88,14 @@ hipError_t ensure_region_capacity(ffb_ctx *ctx, int32_t R);
 hipError_t ensure_adjoint_capacity(ffb_ctx *ctx, int32_t cap, int64_t n);
 // Double-buffered integrator state (st, kv) for at least n points.
 hipError_t ensure_state_capacity(ffb_ctx *ctx, int64_t n);
+// Whether an integration of n points visits them sorted by start cell
+// (FFB_OPT_POINT_ORDER), and the sort's buffers for n points.
+bool use_point_order(const ffb_ctx *ctx, int64_t n);
+hipError_t ensure_order_capacity(ffb_ctx *ctx, int64_t n);
+// The visiting order of an integration of the n points at xy, enqueued on
+// the context's stream: nullptr (the caller's order) or ctx->ord_perm, sorted
+// afresh or, in mode 3, kept from the last sort of the same xy and n.
+int32_t *prepare_point_order(ffb_ctx *ctx, const float *xy, int64_t n, hipError_t *err);
 // Controller options, step record and replay schedule of an integration.
 int check_controller(ffb_ctx *ctx, const ffb_integrate_opts *o, const double *h_out,
                      int32_t h_cap, const char *what);
@@ -99,6 +118,16 @@ void tape_free(ffb_ctx *ctx);
 // Every launcher enqueues on ctx->stream and returns hipSuccess or the
 // launch error.  Arguments are validated by the C-ABI layer beforehand.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// Exclusive prefix sums of n values (out must not alias a); `sums` holds
+// scan_blocks(n) values.
+int scan_blocks(int64_t n);
+hipError_t launch_scan_i32(const int32_t *a, int32_t *out, int64_t n, int32_t *sums,
+                           hipStream_t s);
+hipError_t launch_scan_i64(const int64_t *a, int64_t *out, int64_t n, int64_t *sums,
+                           hipStream_t s);
+// Sorted-slot order of n points by their start cell into ctx->ord_perm
+// (workspace ensured by the caller).
+hipError_t launch_point_order(ffb_ctx *ctx, const float2 *xy, int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
@@ -132,7 +161,8 @@ hipError_t launch_distortion(ffb_ctx *ctx, int lx, int ly, const float2 *nodes, 
 int advect_max_blocks(int *out);
 hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                          float2 *xy, int64_t n, const ffb_integrate_opts *o,
-                         int32_t *stats, double *h_out, int32_t h_cap, const advect_tape *tape);
+                         int32_t *stats, double *h_out, int32_t h_cap, const advect_tape *tape,
+                         const int32_t *perm);
 
 // Adjoints.  lam_fields has the ghosted layout of the fields, [(ly+2)(lx+2)]
 // float4 (J_x, J_y, rho_s, unused); lam_xy is [n][2] FP64.
@@ -160,7 +190,6 @@ struct inverse_ws {
     int32_t *n_big = nullptr;                    // [1]
     int64_t bins_cap = 0, q_cap = 0, sums_cap = 0, tri_cap = 0;
 };
-int inverse_scan_blocks(int64_t nscan);
 hipError_t launch_inverse(ffb_ctx *ctx, int lx, int ly, const float2 *nodes, const float2 *q,
                           int64_t nq, int32_t *tri, double2 *pre, inverse_ws *w);
 
@@ -208,12 +237,15 @@ hipError_t launch_diff_spectrum(ffb_ctx *ctx, const float *rho, float sigma, flo
 // Fields at the first `slots` stage times of ctl (slots <= kDiffSlots).
 hipError_t launch_diff_fields(ffb_ctx *ctx, diff_ws *w, int slots);
 // Initial state (hi = xy, lo = 0) and first-stage velocity at t = 0 (slot 0).
-hipError_t launch_diff_init_points(ffb_ctx *ctx, diff_ws *w, const float2 *xy, int64_t n);
+// perm (optional): slot k of the state holds point perm[k]
+hipError_t launch_diff_init_points(ffb_ctx *ctx, diff_ws *w, const float2 *xy, int64_t n,
+                                   const int32_t *perm);
 // One attempt's point pass and its control step.
 hipError_t launch_diff_points(ffb_ctx *ctx, diff_ws *w, int64_t n);
 hipError_t launch_diff_control(ffb_ctx *ctx, diff_ws *w, int64_t n, int arm_only);
 // Positions out of the current state buffer (if the integration succeeded).
-hipError_t launch_diff_finish(ffb_ctx *ctx, diff_ws *w, float2 *xy, int64_t n);
+hipError_t launch_diff_finish(ffb_ctx *ctx, diff_ws *w, float2 *xy, int64_t n,
+                              const int32_t *perm);
 // Copy `init` into the device control block (a kernel, so graph-safe).
 hipError_t launch_diff_setup(ffb_ctx *ctx, diff_ws *w, const diff_ctl &init);
 

@@ -12,13 +12,18 @@
 // size for all points.  The whole integration is ONE cooperative launch:
 //   * each lane owns a fixed set of points (grid-stride), so a point's state
 //     (compensated position hi + lo and its FSAL stage velocity) is private
-//     to one lane and lives in a double-buffered array;
+//     to one lane; the position lives in LDS (or, for too many points, in a
+//     double-buffered device array), the FSAL velocity in a double-buffered
+//     device array;
 //   * per attempt every lane evaluates the six new stages of its points,
-//     writes the candidate state to the other buffer and takes the max error;
-//   * the workgroup max goes to a per-attempt slot with one atomic max and a
-//     grid barrier follows; every workgroup then reads the same maximum and
-//     takes the same accept/reject decision and step update in FP64, so no
-//     second barrier and no host round trip are needed;
+//     stores the candidate state (keeping the previous one for a rejection)
+//     and takes the max error;
+//   * each workgroup stores its max in a tagged per-attempt slot and reads
+//     all slots (the grid barrier and the grid-wide max in one); every
+//     workgroup then takes the same accept/reject decision and step update
+//     in FP64, so no second barrier and no host round trip are needed;
+//   * the points may be visited in any order (a permutation from the caller
+//     of the launch): no result depends on it;
 //   * the barrier has a bounded wait, so every wave exits even if something
 //     goes wrong (the status word then says FFB_E_DEVICE).
 //
@@ -56,6 +61,9 @@ struct Params {
     int32_t max_attempts;
     int32_t n_replay;
     const double *replay_h;
+    // optional visiting order: slot k of the launch integrates point perm[k]
+    // (state, carried velocity and the point ranges are per slot)
+    const int32_t *perm;
     // optional record for the adjoint: the state of the first tape_n points
     // before every accepted step, [tape_cap][tape_n], the accepted steps and
     // their count
@@ -65,13 +73,13 @@ struct Params {
     int32_t *tape_count;
 };
 
-// Point ranges of a workgroup.  Points are cut into kXcds * kSegments equal
+// Slot ranges of a workgroup.  Slots are cut into kXcds * kSegments equal
 // segments; segment s belongs to XCD s mod kXcds, so each XCD (whose L2 is
-// private) works on kSegments contiguous runs of points -- with the usual
-// [vertices | grid nodes] layout, one run of each, which also balances the
-// cheap vertex lookups against the wider grid-node lookups.  Within an XCD
-// the two runs are concatenated and cut into one chunk per workgroup, which
-// is at most two contiguous point ranges [a0, a0 + la) and [b0, b0 + lb).
+// private) works on kSegments contiguous runs of slots -- with the points
+// sorted by cell, two bands of the box; with the caller's [vertices | grid
+// nodes] order, one run of each.  Within an XCD the two runs are
+// concatenated and cut into one chunk per workgroup, which is at most two
+// contiguous slot ranges [a0, a0 + la) and [b0, b0 + lb).
 struct Span {
     int a0, la, b0, lb;
 };
@@ -221,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
     // initial state: hi = xy, lo = 0 (and the FSAL velocity at t = 0)
     for (int k = threadIdx.x; k < npts; k += kThreads) {
         const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
-        const float2 y = p.xy[i];
+        const float2 y = p.xy[p.perm ? p.perm[i] : i];
         const float4 s0 = make_float4(y.x, y.y, 0.f, 0.f);
         if (MODE == kGlobalState) p.st0[i] = s0;
         else lds_state[k] = s0;
@@ -274,7 +282,10 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         for (int k = threadIdx.x; k < npts; k += kThreads) {
             const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
             const float4 s0 = MODE == kGlobalState ? stc[i] : lds_state[k];
-            if (rec && i < p.tape_n) rec[i] = s0;
+            if (rec) {
+                const int g = p.perm ? p.perm[i] : i;
+                if (g < p.tape_n) rec[g] = s0;
+            }
             const float hx = s0.x, hy = s0.y, lx = s0.z, ly = s0.w;
             const Axis ax = make_axis(hx, lx, p.lx), ay = make_axis(hy, ly, p.ly);
             CellCache cc;
@@ -362,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         for (int k = threadIdx.x; k < npts; k += kThreads) {
             const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
             const float4 s = MODE == kGlobalState ? stc[i] : lds_state[k];
-            p.xy[i] = make_float2(s.x + s.z, s.y + s.w);
+            p.xy[p.perm ? p.perm[i] : i] = make_float2(s.x + s.z, s.y + s.w);
         }
     }
     if (lead) {
@@ -538,7 +549,8 @@ int advect_max_blocks(int *out)
 
 hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                          float2 *xy, int64_t n, const ffb_integrate_opts *o, int32_t *stats,
-                         double *h_out, int32_t h_cap, const advect_tape *tape)
+                         double *h_out, int32_t h_cap, const advect_tape *tape,
+                         const int32_t *perm)
 {
     int64_t want = (n + kThreads - 1) / kThreads;
     if (want < 1) want = 1;
@@ -575,6 +587,7 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
     p.max_attempts = o->max_attempts;
     p.n_replay = o->n_replay;
     p.replay_h = o->replay_h;
+    p.perm = perm;
     p.tape = tape ? tape->states : nullptr;
     p.tape_n = tape ? (int)tape->n : 0;
     p.tape_cap = tape ? tape->cap : 0;

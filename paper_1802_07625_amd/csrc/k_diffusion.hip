@@ -30,6 +30,7 @@ __device__ inline void diff_range(int b, int nb, int64_t n, int64_t &lo, int64_t
 __global__ __launch_bounds__(kDiffThreads) void kd_init_points(const float4 *__restrict__ fields,
                                                                int lx, int ly,
                                                                const float2 *__restrict__ xy,
+                                                               const int32_t *__restrict__ perm,
                                                                int64_t n, float4 *__restrict__ st0,
                                                                float2 *__restrict__ kv0,
                                                                const int32_t *status)
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(kDiffThreads) void kd_init_points(const float4 *__r
     const Field F = make_field(fields, lx, ly);
     for (int64_t i = blockIdx.x * (int64_t)kDiffThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kDiffThreads) {
-        const float2 y = xy[i];
+        const float2 y = xy[perm ? perm[i] : i];
         st0[i] = make_float4(y.x, y.y, 0.f, 0.f);
         CellCache cc;
         cc.key = -1;
@@ -226,14 +227,16 @@ __global__ __launch_bounds__(kControlThreads) void kd_control(diff_ctl *c,
 
 __global__ __launch_bounds__(kDiffThreads) void kd_finish(const diff_ctl *__restrict__ c,
                                                           const float4 *st0, const float4 *st1,
-                                                          float2 *__restrict__ xy, int64_t n)
+                                                          float2 *__restrict__ xy,
+                                                          const int32_t *__restrict__ perm,
+                                                          int64_t n)
 {
     if (c->status != 0 || !c->done) return;
     const float4 *s = c->cur ? st1 : st0;
     for (int64_t i = blockIdx.x * (int64_t)kDiffThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kDiffThreads) {
         const float4 q = s[i];
-        xy[i] = make_float2(q.x + q.z, q.y + q.w);
+        xy[perm ? perm[i] : i] = make_float2(q.x + q.z, q.y + q.w);
     }
 }
 
@@ -259,13 +262,14 @@ hipError_t launch_diff_setup(ffb_ctx *ctx, diff_ws *w, const diff_ctl &init)
     return hipGetLastError();
 }
 
-hipError_t launch_diff_init_points(ffb_ctx *ctx, diff_ws *w, const float2 *xy, int64_t n)
+hipError_t launch_diff_init_points(ffb_ctx *ctx, diff_ws *w, const float2 *xy, int64_t n,
+                                   const int32_t *perm)
 {
     if (n == 0) return hipSuccess;
     int64_t nb = (n + kDiffThreads - 1) / kDiffThreads;
     if (nb > 8192) nb = 8192;
     hipLaunchKernelGGL(kd_init_points, dim3((unsigned)nb), dim3(kDiffThreads), 0, ctx->stream,
-                       w->fields, ctx->lx, ctx->ly, xy, n, ctx->st[0], ctx->kv[0],
+                       w->fields, ctx->lx, ctx->ly, xy, perm, n, ctx->st[0], ctx->kv[0],
                        ctx->d_status);
     return hipGetLastError();
 }
@@ -286,13 +290,14 @@ hipError_t launch_diff_control(ffb_ctx *ctx, diff_ws *w, int64_t n, int arm_only
     return hipGetLastError();
 }
 
-hipError_t launch_diff_finish(ffb_ctx *ctx, diff_ws *w, float2 *xy, int64_t n)
+hipError_t launch_diff_finish(ffb_ctx *ctx, diff_ws *w, float2 *xy, int64_t n,
+                              const int32_t *perm)
 {
     if (n == 0) return hipSuccess;
     int64_t nb = (n + kDiffThreads - 1) / kDiffThreads;
     if (nb > 8192) nb = 8192;
     hipLaunchKernelGGL(kd_finish, dim3((unsigned)nb), dim3(kDiffThreads), 0, ctx->stream, w->ctl,
-                       ctx->st[0], ctx->st[1], xy, n);
+                       ctx->st[0], ctx->st[1], xy, perm, n);
     return hipGetLastError();
 }
 

@@ -24,7 +24,6 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kScanItems = 2048;            // elements per workgroup of the scan
 
 __device__ inline double orient2(double ax, double ay, double bx, double by, double qx, double qy)
 {
@@ -65,93 +64,6 @@ __global__ __launch_bounds__(kThreads) void k_inv_count(const float2 *__restrict
         const float2 p = q[k];
         atomicAdd(&count[bin_of(p.y, ly) * lx + bin_of(p.x, lx)], 1);
     }
-}
-
-// Exclusive scan of n values, three passes: per-workgroup sums, a scan of
-// those in one workgroup, then the per-workgroup scans.
-template <typename T>
-__device__ T block_exclusive(T v, T *lds)
-{
-    // Hillis-Steele over kThreads lanes (each lane holds the sum of its items)
-    lds[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < kThreads; o <<= 1) {
-        const T x = threadIdx.x >= (unsigned)o ? lds[threadIdx.x - o] : T(0);
-        __syncthreads();
-        lds[threadIdx.x] += x;
-        __syncthreads();
-    }
-    const T incl = lds[threadIdx.x];
-    __syncthreads();
-    return incl - v;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_sums(const T *__restrict__ a, int64_t n,
-                                                        T *__restrict__ sums)
-{
-    __shared__ T lds[kThreads];
-    const int64_t base = (int64_t)blockIdx.x * kScanItems;
-    T s = 0;
-    for (int k = threadIdx.x; k < kScanItems; k += kThreads)
-        if (base + k < n) s += a[base + k];
-    lds[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = kThreads / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) lds[threadIdx.x] += lds[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) sums[blockIdx.x] = lds[0];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_top(T *__restrict__ sums, int nb)
-{
-    __shared__ T lds[kThreads];
-    __shared__ T carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int b0 = 0; b0 < nb; b0 += kThreads) {
-        const T v = (b0 + (int)threadIdx.x < nb) ? sums[b0 + threadIdx.x] : T(0);
-        const T ex = block_exclusive(v, lds);
-        const T c = carry;
-        if (b0 + (int)threadIdx.x < nb) sums[b0 + threadIdx.x] = c + ex;
-        __syncthreads();
-        if (threadIdx.x == kThreads - 1) carry = c + ex + v;
-        __syncthreads();
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const T *__restrict__ a, int64_t n,
-                                                         const T *__restrict__ sums,
-                                                         T *__restrict__ out)
-{
-    __shared__ T lds[kThreads];
-    constexpr int kPer = kScanItems / kThreads;  // consecutive items per lane
-    const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kPer;
-    T v[kPer];
-    T s = 0;
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        v[r] = (base + r < n) ? a[base + r] : T(0);
-        s += v[r];
-    }
-    T run = block_exclusive(s, lds) + sums[blockIdx.x];
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        if (base + r < n) out[base + r] = run;
-        run += v[r];
-    }
-}
-
-template <typename T>
-void scan_exclusive(const T *a, T *out, int64_t n, T *sums, hipStream_t s)
-{
-    const int nb = (int)((n + kScanItems - 1) / kScanItems);
-    hipLaunchKernelGGL(k_scan_sums<T>, dim3(nb), dim3(kThreads), 0, s, a, n, sums);
-    hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kThreads), 0, s, sums, nb);
-    hipLaunchKernelGGL(k_scan_apply<T>, dim3(nb), dim3(kThreads), 0, s, a, n, sums, out);
 }
 
 __global__ __launch_bounds__(kThreads) void k_inv_scatter(const float2 *__restrict__ q, int64_t nq,
@@ -337,7 +249,8 @@ hipError_t launch_inverse(ffb_ctx *ctx, int lx, int ly, const float2 *nodes, con
     if (nq == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_inv_count, dim3(grid_for(nq)), dim3(kThreads), 0, s, q, nq, lx, ly,
                        w->count);
-    scan_exclusive<int32_t>(w->count, w->offs, nscan, w->sums, s);
+    e = launch_scan_i32(w->count, w->offs, nscan, w->sums, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_inv_scatter, dim3(grid_for(nq)), dim3(kThreads), 0, s, q, nq, lx, ly,
                        w->offs, w->fill, w->order);
     const int64_t ntri = 2 * (int64_t)(lx - 1) * (ly - 1);
@@ -348,7 +261,8 @@ hipError_t launch_inverse(ffb_ctx *ctx, int lx, int ly, const float2 *nodes, con
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_inv_claim, dim3(grid_for(ntri)), dim3(kThreads), 0, s, nodes, lx, ly, q,
                        w->offs, w->order, w->best, w->big, w->big_nb, w->n_big);
-    scan_exclusive<int64_t>(w->big_nb, w->big_off, ntri + 1, w->sums64, s);
+    e = launch_scan_i64(w->big_nb, w->big_off, ntri + 1, w->sums64, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_inv_claim_items, dim3(8192), dim3(kThreads), 0, s, nodes, lx, ly, q,
                        w->offs, w->order, w->best, w->big, w->big_off, w->n_big, ntri);
     hipLaunchKernelGGL(k_inv_resolve, dim3(grid_for(nq)), dim3(kThreads), 0, s, nodes, lx, q, nq,
@@ -356,4 +270,3 @@ hipError_t launch_inverse(ffb_ctx *ctx, int lx, int ly, const float2 *nodes, con
     return hipGetLastError();
 }
 
-int inverse_scan_blocks(int64_t nscan) { return (int)((nscan + kScanItems - 1) / kScanItems); }
