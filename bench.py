@@ -279,6 +279,9 @@ def diffusion_leg(args, dev, m, ctx, geom, value, pts0, pts, V, ffb_loop, max_ro
     pts.copy_(pts0)                                   # warm-up round (graph capture, buffers)
     ffb.iterate_diffusion(ctx, geom, value, pts, ffb.default_sigma(0), opts)
     torch.cuda.synchronize()
+    # as in the FFB loop: sorted in round 0, that order kept for later rounds
+    # (setting the option drops the order kept by the warm-up)
+    ctx.set_option(ffb.OPT_POINT_ORDER, ffb.POINT_ORDER_KEEP)
     pts.copy_(pts0)
     torch.cuda.synchronize()
     area, errs, atts, round_ms = None, [], [], []
