@@ -73,36 +73,53 @@ struct Params {
     int32_t *tape_count;
 };
 
-// Slot ranges of a workgroup.  Slots are cut into kXcds * kSegments equal
+// Slots of a workgroup.  Slots are cut into kXcds * kSegments equal
 // segments; segment s belongs to XCD s mod kXcds, so each XCD (whose L2 is
 // private) works on kSegments contiguous runs of slots -- with the points
 // sorted by cell, two bands of the box; with the caller's [vertices | grid
-// nodes] order, one run of each.  Within an XCD the two runs are
-// concatenated and cut into one chunk per workgroup, which is at most two
-// contiguous slot ranges [a0, a0 + la) and [b0, b0 + lb).
-struct Span {
-    int a0, la, b0, lb;
+// nodes] order, one run of each.  The valid slots of an XCD's runs are dealt
+// to its workgroups in chunks of kChunk, round robin: the cost of a point
+// depends on where it is, and each workgroup then samples the XCD's whole
+// share (with contiguous per-workgroup ranges the slowest workgroup ran
+// 10-15 % behind the mean, and every attempt waits for it).  A wave still
+// takes kChunk consecutive slots per pass.  (Spreading each XCD's share
+// over four or eight bands, to even out the XCDs too, and finding a chunk's
+// start with scalar arithmetic both measured slower.)
+constexpr int kChunk = 64;
+
+struct Slots {
+    int base0, va, base1;   // share slot j: base0 + j for j < va, else base1 + (j - va)
+    int first, stride;      // this workgroup's chunks: first, first + stride, ...
+    int npts;               // slots of this workgroup
+
+    // the slot of this workgroup's k-th point
+    __device__ int slot(int k) const
+    {
+        const int j = (first + stride * (k / kChunk)) * kChunk + k % kChunk;
+        return j < va ? base0 + j : base1 + (j - va);
+    }
 };
 
-__device__ inline Span span_of(int b, int nb, int n)
+__device__ inline Slots slots_of(int b, int nb, int n)
 {
     const int nx = nb < kXcds ? nb : kXcds;
     const int x = b % nx, rank = b / nx;
-    const int size = nb / nx + (x < nb % nx ? 1 : 0);       // workgroups on this XCD
+    const int size = nb / nx + (x < nb % nx ? 1 : 0);
     const int seg = (n + nx * kSegments - 1) / (nx * kSegments);
-    const int total = seg * kSegments;                       // this XCD's share
-    const int chunk = (total + size - 1) / size;
-    const int j0 = min(total, rank * chunk), j1 = min(total, j0 + chunk);
-    Span sp;
-    // run 0: points x * seg + j for j in [0, seg)
-    const int ja = j0, jb = min(j1, seg);
-    sp.a0 = x * seg + ja;
-    sp.la = max(0, min(n, x * seg + jb) - sp.a0);
-    // run 1: points (nx + x) * seg + (j - seg) for j in [seg, 2 seg)
-    const int jc = max(j0, seg) - seg, jd = j1 - seg;
-    sp.b0 = (nx + x) * seg + jc;
-    sp.lb = max(0, min(n, (nx + x) * seg + max(jd, jc)) - sp.b0);
-    return sp;
+    Slots s;
+    s.base0 = x * seg;
+    s.base1 = (nx + x) * seg;
+    s.va = max(0, min(seg, n - s.base0));
+    const int vb = max(0, min(seg, n - s.base1));
+    const int total = s.va + vb;                             // valid slots of the share
+    const int nch = (total + kChunk - 1) / kChunk;
+    s.first = rank;
+    s.stride = size;
+    // chunks rank, rank + size, ... below nch; only the last one may be short
+    const int q = rank < nch ? (nch - 1 - rank) / size + 1 : 0;
+    s.npts = q * kChunk;
+    if (q > 0 && (nch - 1 - rank) % size == 0) s.npts -= nch * kChunk - total;
+    return s;
 }
 
 // Grid-wide maximum of the workgroups' values for attempt n; it doubles as
@@ -220,15 +237,15 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
 
     const double rho_bar = *p.rho_bar;
     const Field F = make_field(p.fields, p.lx, p.ly);
-    const Span sp = span_of(blockIdx.x, gridDim.x, p.n);
-    const int npts = sp.la + sp.lb;
+    const Slots sl = slots_of(blockIdx.x, gridDim.x, p.n);
+    const int npts = sl.npts;
     const bool replay = p.n_replay > 0;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     float4 *bak = p.st0;                       // LDS modes: state before the attempt
 
     // initial state: hi = xy, lo = 0 (and the FSAL velocity at t = 0)
     for (int k = threadIdx.x; k < npts; k += kThreads) {
-        const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+        const int i = sl.slot(k);
         const float2 y = p.xy[p.perm ? p.perm[i] : i];
         const float4 s0 = make_float4(y.x, y.y, 0.f, 0.f);
         if (MODE == kGlobalState) p.st0[i] = s0;
@@ -280,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
         // the same record again
         float4 *rec = (p.tape && acc < p.tape_cap) ? p.tape + (int64_t)acc * p.tape_n : nullptr;
         for (int k = threadIdx.x; k < npts; k += kThreads) {
-            const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+            const int i = sl.slot(k);
             const float4 s0 = MODE == kGlobalState ? stc[i] : lds_state[k];
             if (rec) {
                 const int g = p.perm ? p.perm[i] : i;
@@ -357,7 +374,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             if (MODE != kGlobalState) {
                 // undo the attempt: every lane restores its own points
                 for (int k = threadIdx.x; k < npts; k += kThreads) {
-                    const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+                    const int i = sl.slot(k);
                     lds_state[k] = bak[i];
                 }
             }
@@ -371,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
     if (final_status == 0) {
         const float4 *stc = cur ? p.st1 : p.st0;
         for (int k = threadIdx.x; k < npts; k += kThreads) {
-            const int i = k < sp.la ? sp.a0 + k : sp.b0 + (k - sp.la);
+            const int i = sl.slot(k);
             const float4 s = MODE == kGlobalState ? stc[i] : lds_state[k];
             p.xy[p.perm ? p.perm[i] : i] = make_float2(s.x + s.z, s.y + s.w);
         }
@@ -392,10 +409,9 @@ inline int64_t lds_bytes_for(int nb, int64_t n)
 {
     const int64_t nx = nb < kXcds ? nb : kXcds;
     const int64_t seg = (n + nx * kSegments - 1) / (nx * kSegments);
-    const int64_t total = seg * kSegments;
+    const int64_t nch = (seg * kSegments + kChunk - 1) / kChunk;   // chunks of the largest share
     const int64_t size_min = nb / nx;
-    const int64_t chunk = (total + size_min - 1) / size_min;
-    return chunk * (int64_t)sizeof(float4);
+    return (nch + size_min - 1) / size_min * kChunk * (int64_t)sizeof(float4);
 }
 
 // ------------------------------------------------------------- batched
