@@ -185,3 +185,32 @@ def test_diffusion_sorted_equals_given_order_bitwise():
     assert sa == sb and sa["accepted"] > 0
     np.testing.assert_array_equal(ha, hb)
     np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("order", [0, 2])
+def test_workgroup_counts_change_no_bit(order):
+    """The points are dealt to the persistent workgroups in 64-slot chunks
+    per XCD; any workgroup count (capped by FFB_OPT_ADVECT_BLOCKS, including
+    counts that do not divide by the 8 XCDs) must integrate every point
+    exactly once and give the same bits."""
+    import paper_1802_07625_amd as ffb
+    from gpu_util import new_ctx
+    m = synth.workload("c1_L64")
+    n = 30011
+    pts = _clouds(64, n, 17)
+    ctx = new_ctx(64, max_points=n)
+    fields, rb, _ = _fields(ctx, m)
+    ref = None
+    for cap in (0, 1, 3, 7, 8, 13, 29, 100):
+        print(f"[order] workgroup cap={cap} order={order}", flush=True)
+        ctx.set_option(ffb.OPT_ADVECT_BLOCKS, cap)
+        got = _run(ctx, order, fields, rb, pts)
+        assert got[3] == 0
+        if ref is None:
+            ref = got
+            assert ref[1]["accepted"] > 0
+            assert np.abs(ref[0] - pts).max() > 0.01        # the points did move
+        else:
+            assert got[1] == ref[1]
+            np.testing.assert_array_equal(got[2], ref[2])
+            np.testing.assert_array_equal(got[0], ref[0])
