@@ -82,13 +82,24 @@ __device__ inline Axis make_axis(float hi, float lo, int L)
 // position (ifl and floor(t) are exact integers); the caller clamps the
 // combined node index once more, so that no input (NaN or Inf included) can
 // reach outside the fields.
+//
+// floor(t) as an integer is one instruction (v_cvt_flr_i32_f32; the compiler
+// emits a floor and a convert), and the fraction is v_fract_f32, which
+// equals t - floor(t) except where that difference would round up to 1: it
+// then returns the largest float below 1, so the fraction stays in [0, 1).
+__device__ inline int floor_to_int(float t)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(t));
+    return r;
+}
+
 __device__ inline void locate(const Axis &a, float d, int &idx, float &frac)
 {
     float t = a.frl + d;
     t = __builtin_amdgcn_fmed3f(t, a.lo_t, a.hi_t);
-    const float ft = floorf(t);
-    idx = a.ifl + (int)ft;
-    frac = t - ft;
+    idx = a.ifl + floor_to_int(t);
+    frac = __builtin_amdgcn_fractf(t);
 }
 
 // The four field records around the last looked-up cell of one point.  The

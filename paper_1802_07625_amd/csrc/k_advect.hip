@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             // a NaN or Inf in the error estimate or in the new position
             // poisons the maximum (fmaxf alone would drop a NaN)
             const float poison = (ex + ey) + (sx + sy);
-            const float e = (poison - poison == 0.0f) ? fmaxf(fabsf(ex), fabsf(ey))
+            const float e = __builtin_isfinite(poison) ? fmaxf(fabsf(ex), fabsf(ey))
                                                       : __builtin_inff();
             emax = fmaxf(emax, e);
             if (MODE == kGlobalState) {
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args
             two_sum(s0.y, iy, sy, ey2);
             stn[k] = make_float4(sx, sy, s0.z + ex2, s0.w + ey2);
             const float poison = (ex + ey) + (sx + sy);
-            const float e = (poison - poison == 0.0f) ? fmaxf(fabsf(ex), fabsf(ey))
+            const float e = __builtin_isfinite(poison) ? fmaxf(fabsf(ex), fabsf(ey))
                                                       : __builtin_inff();
             emax = fmaxf(emax, e);
             kvn[k] = make_float2(q7.x * rhf, q7.y * rhf);

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kDiffThreads) void kd_points(const diff_ctl *__rest
         two_sum(s0.y, iy, sy, ey2);
         stn[i] = make_float4(sx, sy, s0.z + ex2, s0.w + ey2);
         const float poison = (ex + ey) + (sx + sy);
-        const float e = (poison - poison == 0.0f) ? fmaxf(fabsf(ex), fabsf(ey))
+        const float e = __builtin_isfinite(poison) ? fmaxf(fabsf(ex), fabsf(ey))
                                                   : __builtin_inff();
         emax = fmaxf(emax, e);
         kvn[i] = make_float2(q7.x * rhf, q7.y * rhf);
