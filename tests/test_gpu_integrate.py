@@ -226,3 +226,31 @@ def test_full_size_sampled_points(mode):
     d = np.abs(got[idx] - ref.xy).max()
     print(f"[integrate] c3 sampled max|dx|={d:.3e}", flush=True)
     assert d < TOL_POS
+
+
+def test_beyond_lds_capacity_falls_back_to_device_state():
+    """2.8 M points at L = 1024 (more than one workgroup per CU can hold in
+    LDS): the default state mode falls back to device-memory state, the
+    points are still sorted by cell, and sampled points agree with the
+    oracle.  The schedule is the oracle's own adaptive one for the sampled
+    points, replayed on the GPU for all of them (equal steps as coarse as
+    1/16 leave this flow unresolved by up to 49 cells, where rounding
+    differences between FP32 and FP64 grow past the tolerance)."""
+    from gpu_util import map_points, new_ctx, pack_oracle_fields
+    m = synth.workload("c3_L1024")
+    base = map_points(m)
+    rng = np.random.default_rng(31)
+    extra = rng.uniform(0.0, 1024.0, (2_800_000 - base.shape[0], 2)).astype(np.float32)
+    pts = np.concatenate([base, extra])
+    print(f"[integrate] beyond LDS P={pts.shape[0]}", flush=True)
+    ctx = new_ctx(m.lx, m.ly, pts.shape[0])
+    F = _oracle_fields(m, 4.0)
+    fields, rb, Fr = pack_oracle_fields(ctx, F)
+    idx = np.concatenate([rng.choice(base.shape[0], 1500, replace=False),
+                          base.shape[0] + rng.choice(extra.shape[0], 1500, replace=False)])
+    ref = oracle.integrate(Fr, pts[idx].astype(np.float64))
+    got, st, _, code = _gpu_integrate(ctx, fields, rb, pts, replay=ref.h)
+    assert code == 0 and st["accepted"] == ref.accepted
+    d = np.abs(got[idx] - ref.xy).max()
+    print(f"[integrate] beyond LDS sampled max|dx|={d:.3e}", flush=True)
+    assert d < TOL_POS
