@@ -225,8 +225,6 @@ int check_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, fl
     return check_controller(ctx, o, h_out, h_cap, "ffb_integrate");
 }
 
-
-
 int run_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, float *xy, int64_t n,
                   const ffb_integrate_opts *o, int32_t *stats, double *h_out, int32_t h_cap,
                   const advect_tape *rec)
