@@ -214,3 +214,20 @@ def test_workgroup_counts_change_no_bit(order):
             assert got[1] == ref[1]
             np.testing.assert_array_equal(got[2], ref[2])
             np.testing.assert_array_equal(got[0], ref[0])
+
+
+def test_sorted_nan_point_reports_nonfinite_and_leaves_points():
+    """A NaN position sorts into the first cell (its key is clamped) and the
+    integration reports a non-finite error as in the caller's order; no
+    point is written back."""
+    import paper_1802_07625_amd as ffb
+    from gpu_util import new_ctx
+    m = synth.workload("c1_L64")
+    ctx = new_ctx(64)
+    fields, rb, _ = _fields(ctx, m)
+    pts = _clouds(64, 500, 9)
+    pts[123] = [np.nan, 7.0]
+    got, st, _, code = _run(ctx, 2, fields, rb, pts)
+    assert code == ffb.api.FFB_E_NONFINITE and st["status"] == code
+    np.testing.assert_array_equal(got[~np.isnan(pts[:, 0])], pts[~np.isnan(pts[:, 0])])
+    ctx.reset_status()
