@@ -280,7 +280,7 @@ __constant__ float kA[6][5] = {
 __constant__ float kB[6] = {(float)(35.0 / 384), 0.f, (float)(500.0 / 1113),
                             (float)(125.0 / 192), (float)(-2187.0 / 6784), (float)(11.0 / 84)};
 
-constexpr int kChunk = 8;          // consecutive steps of one point per work item
+constexpr int kChunk = 4;          // consecutive steps of one point per work item
 
 // Lookup of one stage position: the cell of the ghosted field layout (key =
 // (j + 1) pitch + (i + 1) of its lower-left node), the bilinear fractions,
