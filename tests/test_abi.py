@@ -86,6 +86,21 @@ def test_status_codes_match_header():
         assert codes[name] == code
 
 
+def test_option_ids_match_header():
+    import paper_1802_07625_amd.api as api
+    txt = open(HEADER).read()
+    ids = {n: int(v) for n, v in re.findall(r"(FFB_OPT_\w+)\s*=\s*(\d+)", txt)}
+    assert ids == {"FFB_OPT_ADVECT_STATE": api.OPT_ADVECT_STATE,
+                   "FFB_OPT_ADVECT_BLOCKS": api.OPT_ADVECT_BLOCKS,
+                   "FFB_OPT_DIFFUSION_GRAPH": api.OPT_DIFFUSION_GRAPH,
+                   "FFB_OPT_POINT_ORDER": api.OPT_POINT_ORDER}
+    # the point-order values the header documents
+    for v, name in ((0, "POINT_ORDER_GIVEN"), (1, "POINT_ORDER_AUTO"),
+                    (2, "POINT_ORDER_ALWAYS"), (3, "POINT_ORDER_KEEP")):
+        assert getattr(api, name) == v
+        assert f"{v} = " in txt.split("FFB_OPT_POINT_ORDER:")[1].split("Returns FFB_E_INVALID")[0]
+
+
 def test_host_validation_without_gpu(lib):
     ctx = ctypes.c_void_p()
     # grid sizes must be powers of two in [8, 1024]
