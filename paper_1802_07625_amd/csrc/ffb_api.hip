@@ -194,7 +194,7 @@ hipError_t upload_twiddles(float2 **tw, float2 **tq, int N)
 
 void free_all(ffb_ctx *c)
 {
-    void *ptrs[] = {c->d_status, c->tw_x, c->tq_x, c->tw_y, c->tq_y, c->t1, c->t2, c->pa,
+    void *ptrs[] = {c->d_status, c->tw_x, c->tq_x, c->tw_y, c->tq_y, c->t1, c->t2, c->t3, c->pa,
                     c->pb, c->pc, c->red, c->acc, c->w_region, c->st[0], c->st[1], c->kv[0],
                     c->kv[1], c->errslot, c->lam_w, c->adj_t, c->adj_jac, c->ord_perm,
                     c->ord_rank, c->ord_count, c->ord_offs, c->ord_sums};
@@ -260,7 +260,7 @@ int ffb_create(ffb_ctx **out, int32_t lx, int32_t ly, int64_t max_points, void *
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int32_t));
     if (e == hipSuccess) e = upload_twiddles(&c->tw_x, &c->tq_x, lx);
     if (e == hipSuccess) e = upload_twiddles(&c->tw_y, &c->tq_y, ly);
-    float **planes[] = {&c->t1, &c->t2, &c->pa, &c->pb, &c->pc};
+    float **planes[] = {&c->t1, &c->t2, &c->t3, &c->pa, &c->pb, &c->pc};
     for (float **pl : planes)
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(pl), sizeof(float) * plane);
     if (e == hipSuccess) e = grow(&c->red, 0, kRedDoubles);

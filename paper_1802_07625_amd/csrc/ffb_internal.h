@@ -24,7 +24,7 @@ struct ffb_ctx {
     // transform workspace
     float2 *tw_x = nullptr, *tq_x = nullptr;   // FFT and DCT twiddles for length lx
     float2 *tw_y = nullptr, *tq_y = nullptr;   // ... for length ly
-    float *t1 = nullptr, *t2 = nullptr;        // [lx*ly] scratch planes
+    float *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;   // [lx*ly] scratch planes
     float *pa = nullptr, *pb = nullptr, *pc = nullptr;
     double *red = nullptr;                     // reduction partials (kRedDoubles)
     int32_t red_cap = 0;

@@ -190,13 +190,30 @@ __device__ __forceinline__ void dct2_rows_body(const float *__restrict__ in, flo
     }
 }
 
+// Two rows per workgroup; with `rowsum` set, also the FP64 sum of the two
+// input rows (in a fixed order), for the mean density.
 __global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
                                                    float *__restrict__ out, int N,
                                                    const float2 *__restrict__ tw,
-                                                   const float2 *__restrict__ tq)
+                                                   const float2 *__restrict__ tq,
+                                                   double *__restrict__ rowsum)
 {
     __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    __shared__ double ssum[512 / 64];
+    if (rowsum) {
+        const float *r = in + 2 * (int64_t)blockIdx.x * N;
+        double v = 0.0;
+        for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) v += (double)r[i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) ssum[threadIdx.x >> 6] = v;
+    }
     dct2_rows_body(in, out, 2 * (int64_t)blockIdx.x, N, tw, tq, 1, sa, sb, stw);
+    if (rowsum && threadIdx.x == 0) {
+        // dct2_rows_body passes workgroup barriers after the writes above
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += ssum[w];
+        rowsum[blockIdx.x] = t;
+    }
 }
 
 // One 32 x 32 tile (columns c0.., rows r0..) of in [R][C] -> out [C][R],
@@ -427,21 +444,6 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ jx,
 }
 
 // Fixed-order FP64 sum of a float array: per-block partials then one block.
-__global__ __launch_bounds__(256) void k_sum_partial(const float *__restrict__ x, int64_t n,
-                                                     double *__restrict__ part)
-{
-    __shared__ double lds[256];
-    double s = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        s += (double)x[i];
-    lds[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) lds[threadIdx.x] += lds[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
-}
 
 __global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ part, int np,
                                                    double scale, double *__restrict__ out,
@@ -895,25 +897,20 @@ hipError_t launch_flux(ffb_ctx *ctx, const float *rho, float sigma, float4 *fiel
     hipStream_t s = ctx->stream;
     const int lx = ctx->lx, ly = ctx->ly;
     const int64_t n = (int64_t)lx * ly;
-    constexpr int kParts = 256;
-    hipLaunchKernelGGL(k_sum_partial, dim3(kParts), dim3(256), 0, s, rho, n, ctx->red);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, ctx->red, kParts,
-                       1.0 / (double)n, rho_bar, ctx->d_status);
+    // row DCTs, with the FP64 sums of each row pair for the mean density
     hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, ctx->t1, lx,
-                       ctx->tw_x, ctx->tq_x);
+                       ctx->tw_x, ctx->tq_x, ctx->red);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, ctx->red, ly / 2,
+                       1.0 / (double)n, rho_bar, ctx->d_status);
     hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
                        ctx->t1, ctx->t1, ctx->t1, ctx->t2, ctx->t2, ctx->t2, ly, lx);
     hipLaunchKernelGGL(k_col_pass, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t2, lx, ly,
                        sigma, ctx->tw_y, ctx->tq_y, ctx->pa, ctx->pb, ctx->pc);
-    // [lx][ly] -> [ly][lx]: a, b, c into t1 and the two spare planes
-    float *qa = ctx->t1, *qb = ctx->t2, *qc = ctx->pa;
-    // pa is an input of this transpose: move planes through spare buffers
-    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 2), dim3(256), 0, s,
-                       ctx->pa, ctx->pb, ctx->pb, qa, qb, qb, lx, ly);
-    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 1), dim3(256), 0, s,
-                       ctx->pc, ctx->pc, ctx->pc, qc, qc, qc, lx, ly);
-    hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, qa, qb, qc, lx,
-                       ly, ctx->tw_x, ctx->tq_x, fields, ctx->d_status);
+    // [lx][ly] -> [ly][lx]: a, b, c into the free planes t1, t2, t3 (one launch)
+    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 3), dim3(256), 0, s,
+                       ctx->pa, ctx->pb, ctx->pc, ctx->t1, ctx->t2, ctx->t3, lx, ly);
+    hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->t1, ctx->t2,
+                       ctx->t3, lx, ly, ctx->tw_x, ctx->tq_x, fields, ctx->d_status);
     return hipGetLastError();
 }
 
@@ -933,7 +930,7 @@ hipError_t launch_diff_spectrum(ffb_ctx *ctx, const float *rho, float sigma, flo
     hipStream_t s = ctx->stream;
     const int lx = ctx->lx, ly = ctx->ly;
     hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, ctx->t1, lx,
-                       ctx->tw_x, ctx->tq_x);
+                       ctx->tw_x, ctx->tq_x, nullptr);
     hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
                        ctx->t1, ctx->t1, ctx->t1, ctx->t2, ctx->t2, ctx->t2, ly, lx);
     hipLaunchKernelGGL(kd_spectrum, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t2, lx, ly,
