@@ -962,13 +962,11 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
                        lam_fields, lx, ly, ctx->pa, ctx->pb, ctx->pc);
     hipLaunchKernelGGL(k_adj_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, lx, ctx->tw_x,
                        ctx->tq_x, ctx->pa, ctx->pb, ctx->pc);
-    // [ly][lx] -> [lx][ly]
-    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 2), dim3(256), 0, s,
-                       ctx->pa, ctx->pb, ctx->pb, ctx->t1, ctx->t2, ctx->t2, ly, lx);
-    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
-                       ctx->pc, ctx->pc, ctx->pc, ctx->pa, ctx->pa, ctx->pa, ly, lx);
+    // [ly][lx] -> [lx][ly], the three planes in one launch
+    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 3), dim3(256), 0, s,
+                       ctx->pa, ctx->pb, ctx->pc, ctx->t1, ctx->t2, ctx->t3, ly, lx);
     hipLaunchKernelGGL(k_adj_cols, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t1, ctx->t2,
-                       ctx->pa, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->pb);
+                       ctx->t3, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->pb);
     // [lx][ly] -> [ly][lx]
     hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 1), dim3(256), 0, s,
                        ctx->pb, ctx->pb, ctx->pb, ctx->pc, ctx->pc, ctx->pc, lx, ly);
