@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # source is unchanged.
 ADVECT_TRAFFIC = {"bytes_per_attempt": 2.3151e+10 / 270,
                   "valu_wave_insts_per_attempt": 3.1188e9 / 270,
-                  "workload": "c3_L1024", "source_sha256": "2a21817e71213b27"}
+                  "workload": "c3_L1024", "source_sha256": "a79554a37b6e0e8b"}
 # non-packed FP32 issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 

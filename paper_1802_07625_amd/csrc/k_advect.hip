@@ -10,7 +10,7 @@
 //
 // Integrator: Dormand-Prince 5(4) with first-same-as-last stages, one step
 // size for all points.  The whole integration is ONE cooperative launch:
-//   * each lane owns a fixed set of points (grid-stride), so a point's state
+//   * each lane owns a fixed set of points (see Slots below), so a point's state
 //     (compensated position hi + lo and its FSAL stage velocity) is private
 //     to one lane; the position lives in LDS (or, for too many points, in a
 //     double-buffered device array), the FSAL velocity in a double-buffered
