@@ -247,3 +247,100 @@ def test_velocity_lookup_clamps_to_box():
     q = np.array([[-1.0, 3.3], [F.lx + 2.0, 5.1], [4.2, -0.5], [7.7, F.ly + 9]])
     qc = np.clip(q, 0, [F.lx, F.ly])
     np.testing.assert_array_equal(oracle.velocity(F, 0.4, q), oracle.velocity(F, 0.4, qc))
+
+
+# ------------------------------------------- series extension at the ghosts
+MODES = [(1, 0, 0.21), (0, 1, -0.17), (2, 3, 0.11), (3, 1, 0.13), (1, 2, -0.09)]
+
+
+def band_limited(lx, ly):
+    """rho = 2 + sum a cos(pi m x/lx) cos(pi n y/ly) on the cell centres."""
+    rho = np.full((ly, lx), 2.0)
+    for m, n, a in MODES:
+        rho += a * mode(lx, ly, m, n)
+    return rho
+
+
+def exact_series(lx, ly, x, y):
+    """Closed-form density and flux of ``band_limited`` at any (x, y), the
+    mirrored centres outside the box included: per mode, J is the gradient of
+    the Neumann solution of lap(phi) = rho - rho_bar (SI Appendix, section 2:
+    J_x is a sine series in x and a cosine series in y, J_y the mirror
+    image).  Nothing here uses the oracle's sums or its ghost rule."""
+    rho = np.full(np.broadcast(x, y).shape, 2.0)
+    jx = np.zeros_like(rho)
+    jy = np.zeros_like(rho)
+    for m, n, a in MODES:
+        k2 = PI ** 2 * (m ** 2 / lx ** 2 + n ** 2 / ly ** 2)
+        cx, sx = np.cos(PI * m * x / lx), np.sin(PI * m * x / lx)
+        cy, sy = np.cos(PI * n * y / ly), np.sin(PI * n * y / ly)
+        rho = rho + a * cx * cy
+        jx = jx + a * (PI * m / lx) / k2 * sx * cy
+        jy = jy + a * (PI * n / ly) / k2 * cx * sy
+    return rho, jx, jy
+
+
+@pytest.mark.parametrize("lx,ly", [(16, 16), (24, 12)])
+@pytest.mark.parametrize("t", [0.0, 0.35, 1.0])
+def test_velocity_ghosts_are_the_series_at_mirrored_centres(lx, ly, t):
+    """In the half-cell bands along the edges the lookup blends real nodes
+    with ghost nodes.  The ghosts must carry what the series take at the
+    mirrored cell centres x = -1/2, lx + 1/2 (and likewise in y): the normal
+    component odd, the tangential component even, the density even.  The
+    expected velocity is bilinear in the exact node velocities of an
+    (lx + 2) x (ly + 2) lattice of centres, ghosts included."""
+    F = oracle.flux(band_limited(lx, ly), 0.0)
+    xc = np.arange(-1, lx + 1) + 0.5
+    yc = np.arange(-1, ly + 1) + 0.5
+    X, Y = np.meshgrid(xc, yc)
+    r, jx, jy = exact_series(lx, ly, X, Y)
+    rt = (1 - t) * r + t * F.rho_bar
+    vx, vy = jx / rt, jy / rt                 # [ly + 2, lx + 2]
+    rng = np.random.default_rng(lx + ly)
+    bands = [
+        np.stack([rng.uniform(0, 0.5, 64), rng.uniform(0, ly, 64)], 1),        # x = 0
+        np.stack([rng.uniform(lx - 0.5, lx, 64), rng.uniform(0, ly, 64)], 1),  # x = lx
+        np.stack([rng.uniform(0, lx, 64), rng.uniform(0, 0.5, 64)], 1),        # y = 0
+        np.stack([rng.uniform(0, lx, 64), rng.uniform(ly - 0.5, ly, 64)], 1),  # y = ly
+        np.array([[0.1, 0.2], [lx - 0.2, 0.3], [0.4, ly - 0.1], [lx - 0.3, ly - 0.45]]),
+    ]
+    q = np.concatenate(bands)
+    v = oracle.velocity(F, t, q)
+    u, w = q[:, 0] + 0.5, q[:, 1] + 0.5       # lattice coordinates (ghost row 0)
+    i0, j0 = np.floor(u).astype(int), np.floor(w).astype(int)
+    a, b = u - i0, w - j0
+    for comp, grid in ((0, vx), (1, vy)):
+        g00, g10 = grid[j0, i0], grid[j0, i0 + 1]
+        g01, g11 = grid[j0 + 1, i0], grid[j0 + 1, i0 + 1]
+        ref = (1 - b) * ((1 - a) * g00 + a * g10) + b * ((1 - a) * g01 + a * g11)
+        np.testing.assert_allclose(v[:, comp], ref, rtol=0, atol=1e-12)
+    # the tangential component is not trivially zero in these bands
+    assert np.abs(v[:64, 1]).max() > 1e-3 and np.abs(v[128:192, 0]).max() > 1e-3
+
+
+@pytest.mark.parametrize("lx,ly", [(16, 16), (24, 12)])
+def test_flux_nodes_match_closed_form(lx, ly):
+    """The node-by-node full double sums give the closed-form flux and
+    density of a band-limited map at every node."""
+    F = oracle.flux(band_limited(lx, ly), 0.0, keep_coef=True)
+    jj, ii = np.meshgrid(np.arange(ly), np.arange(lx), indexing="ij")
+    out = oracle.flux_nodes(F.coef, ii.ravel(), jj.ravel())
+    r, jx, jy = exact_series(lx, ly, ii.ravel() + 0.5, jj.ravel() + 0.5)
+    np.testing.assert_allclose(out[:, 0], jx, atol=1e-13)
+    np.testing.assert_allclose(out[:, 1], jy, atol=1e-13)
+    np.testing.assert_allclose(out[:, 2], r, atol=1e-13)
+
+
+@pytest.mark.parametrize("lx,ly,sigma", [(16, 16, 1.3), (32, 8, 0.0), (12, 20, 2.5)])
+def test_flux_nodes_equal_separable_sums(lx, ly, sigma):
+    """The full double sums at chosen nodes agree with the separable sums of
+    the whole-grid flux on a random (not band-limited) density."""
+    rng = np.random.default_rng(lx * ly)
+    rho = rng.uniform(0.3, 3.0, (ly, lx))
+    F = oracle.flux(rho, sigma, keep_coef=True)
+    jj, ii = np.meshgrid(np.arange(ly), np.arange(lx), indexing="ij")
+    out = oracle.flux_nodes(F.coef, ii.ravel(), jj.ravel())
+    scale = max(np.abs(F.jx).max(), np.abs(F.jy).max())
+    np.testing.assert_allclose(out[:, 0], F.jx.ravel(), rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(out[:, 1], F.jy.ravel(), rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(out[:, 2], F.rho_s.ravel(), rtol=0, atol=1e-12 * rho.max())
