@@ -343,8 +343,9 @@ int ffb_integrate_adj(ffb_ctx *ctx, const float *fields, const double *rho_bar,
                       int32_t tape_cap, const double *tape_h, double *lam_xy, float *lam_fields,
                       double *lam_rho_bar);
 
-/* Context tape (host calls).  ffb_tape_begin clears any previous record
- * (waiting for the stream) and starts recording: every later ffb_area_error,
+/* Context tape (host calls).  ffb_tape_begin drops any previous record
+ * (its device buffers are reused in stream order, so no wait is needed) and
+ * starts recording: every later ffb_area_error,
  * ffb_density, ffb_flux and ffb_integrate call appends what its adjoint
  * needs to the context (device copies of its vertices, values, areas,
  * fields and rho_bar, made on the stream, so callers may reuse those
@@ -357,6 +358,16 @@ int ffb_integrate_adj(ffb_ctx *ctx, const float *fields, const double *rho_bar,
 int ffb_tape_begin(ffb_ctx *ctx, int32_t max_steps);
 int ffb_tape_end(ffb_ctx *ctx);
 int ffb_tape_clear(ffb_ctx *ctx);
+
+/* Generation of the context's record: a counter that ffb_tape_begin and
+ * ffb_tape_clear increase.  A caller that keeps a handle to one recording
+ * (e.g. an autograd graph) reads it right after ffb_tape_begin and later
+ * asks ffb_tape_check whether that recording is still the context's:
+ * FFB_OK if it is and is not empty, FFB_E_NO_TAPE (with ffb_last_error
+ * detail) if another ffb_tape_begin or ffb_tape_clear came in between or
+ * nothing was recorded.  out is host memory. */
+int ffb_tape_generation(const ffb_ctx *ctx, int64_t *out);
+int ffb_tape_check(ffb_ctx *ctx, int64_t generation);
 
 /* Reverse pass over the context's record, which must read
  *   area+ (density flux integrate area+)*

@@ -13,7 +13,8 @@ from .api import (  # noqa: F401
     POINT_ORDER_GIVEN, POINT_ORDER_AUTO, POINT_ORDER_ALWAYS, POINT_ORDER_KEEP,
     ffb_diffusion, ffb_diffusion_fields, iterate_diffusion, diffusion_t_end, DIFFUSION_K,
     ffb_area_adj, ffb_density_adj, ffb_flux_adj, ffb_integrate_record, ffb_integrate_adj,
-    ffb_tape_begin, ffb_tape_end, ffb_tape_clear, ffb_backward, FFBFunction,
+    ffb_tape_begin, ffb_tape_end, ffb_tape_clear, ffb_tape_generation, ffb_tape_check,
+    ffb_backward, FFBFunction,
     FFB_OK, FFB_E_INVALID, FFB_E_NOMEM, FFB_E_DEVICE, FFB_E_NONPOSITIVE, FFB_E_DOMAIN,
     FFB_E_STEP_UNDERFLOW, FFB_E_NONFINITE, FFB_E_NO_TAPE, FFB_E_MAX_ATTEMPTS,
     Batch, BatchOpts, ffb_distortion, ffb_inverse,

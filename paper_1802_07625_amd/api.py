@@ -100,6 +100,8 @@ def lib():
         L.ffb_tape_end.argtypes = [vp]
         L.ffb_tape_clear.argtypes = [vp]
         L.ffb_backward.argtypes = [vp, vp, vp, vp]
+        L.ffb_tape_generation.argtypes = [vp, ctypes.POINTER(i64)]
+        L.ffb_tape_check.argtypes = [vp, i64]
         B, BO = ctypes.POINTER(FFBBatchDesc), ctypes.POINTER(FFBBatchOpts)
         L.ffb_batch_create.argtypes = [ctypes.POINTER(vp), B, vp]
         L.ffb_batch_destroy.argtypes = [vp]
@@ -116,7 +118,7 @@ def lib():
                   "ffb_density", "ffb_flux", "ffb_pack_fields", "ffb_integrate", "ffb_set_option",
                   "ffb_distortion", "ffb_diffusion_fields", "ffb_diffusion", "ffb_inverse", "ffb_area_adj", "ffb_density_adj", "ffb_flux_adj", "ffb_integrate_record",
                   "ffb_integrate_adj", "ffb_tape_begin", "ffb_tape_end", "ffb_tape_clear",
-                  "ffb_backward", "ffb_batch_create", "ffb_batch_destroy", "ffb_batch_set_shapes",
+                  "ffb_backward", "ffb_tape_generation", "ffb_tape_check", "ffb_batch_create", "ffb_batch_destroy", "ffb_batch_set_shapes",
                   "ffb_batch_get_shapes", "ffb_batch_autotune", "ffb_batch_reset",
                   "ffb_batch_step", "ffb_batch_run", "ffb_batch_results"):
             getattr(L, f).restype = ctypes.c_int
@@ -374,6 +376,16 @@ def ffb_tape_clear(ctx) -> None:
     _check(ctx, lib().ffb_tape_clear(ctx), "ffb_tape_clear")
 
 
+def ffb_tape_generation(ctx) -> int:
+    g = ctypes.c_int64()
+    _check(ctx, lib().ffb_tape_generation(ctx, ctypes.byref(g)), "ffb_tape_generation")
+    return g.value
+
+
+def ffb_tape_check(ctx, generation: int) -> None:
+    _check(ctx, lib().ffb_tape_check(ctx, int(generation)), "ffb_tape_check")
+
+
 def ffb_backward(ctx, dL_darea, dL_dvalue, dL_dxy0=None) -> None:
     R = dL_darea.numel()
     _check(ctx, lib().ffb_backward(ctx, _ptr(dL_darea, torch.float64, R, "dL_darea"),
@@ -531,8 +543,15 @@ class Context:
     def tape_clear(self):
         ffb_tape_clear(self.handle)
 
-    def backward(self, dL_darea, n_vertices: int | None = None):
-        """Reverse pass over the recorded rounds: (dL/dvalue, dL/dxy0 or None)."""
+    def tape_generation(self) -> int:
+        return ffb_tape_generation(self.handle)
+
+    def backward(self, dL_darea, n_vertices: int | None = None, generation: int | None = None):
+        """Reverse pass over the recorded rounds: (dL/dvalue, dL/dxy0 or None).
+        With ``generation`` (from tape_generation() after tape_begin) the
+        call fails with FFB_E_NO_TAPE if the record was replaced since."""
+        if generation is not None:
+            ffb_tape_check(self.handle, generation)
         dval = torch.empty_like(dL_darea)
         dxy = None if n_vertices is None else self._f64(n_vertices, 2)
         ffb_backward(self.handle, dL_darea.contiguous(), dval, dxy)
@@ -607,12 +626,17 @@ class FFBFunction(torch.autograd.Function):
       after); returns the final areas [R] FP64.  ``replay`` (one FP64 device
       tensor of step sizes per round, or None) freezes the step schedules;
       otherwise the adaptive controller chooses them.
-    backward: dL/dvalue by ffb_backward, with the forward's steps frozen."""
+    backward: dL/dvalue by ffb_backward, with the forward's steps frozen.
+    The context holds one record at a time: a later forward (or tape_begin)
+    on the same context replaces it, and the backward of the earlier graph
+    then raises FFBError(FFB_E_NO_TAPE) rather than differentiate the other
+    forward."""
 
     @staticmethod
     def forward(fctx, value, ctx, geom, points, sigmas, opts=None, max_steps=512, replay=None):
         value = value.detach().contiguous()
         ctx.tape_begin(max_steps)
+        fctx.generation = ctx.tape_generation()
         area, _, _ = ctx.area_error(geom, value)
         for k, sigma in enumerate(sigmas):
             rho, _ = ctx.density(geom, value, area)
@@ -626,7 +650,8 @@ class FFBFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(fctx, g_area):
-        dval, _ = fctx.ffb.backward(g_area.detach().to(torch.float64).contiguous())
+        dval, _ = fctx.ffb.backward(g_area.detach().to(torch.float64).contiguous(),
+                                    generation=fctx.generation)
         return dval, None, None, None, None, None, None, None
 
 

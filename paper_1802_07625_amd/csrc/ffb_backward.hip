@@ -269,7 +269,8 @@ int ffb_tape_begin(ffb_ctx *ctx, int32_t max_steps)
     if (max_steps < 1 || max_steps > (1 << 20))
         return fail(ctx, FFB_E_INVALID, "ffb_tape_begin: max_steps out of range%s");
     if (!ctx->tape) ctx->tape = new ffb_tape();
-    ctx->tape->used = 0;          // buffers are kept for reuse
+    ctx->tape->used = 0;          // buffers are kept and reused in stream order
+    ++ctx->tape_gen;
     ctx->tape->recording = true;
     ctx->tape->max_steps = max_steps;
     return FFB_OK;
@@ -288,6 +289,25 @@ int ffb_tape_clear(ffb_ctx *ctx)
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "ffb_tape_clear");
     tape_free(ctx);
+    ++ctx->tape_gen;
+    return FFB_OK;
+}
+
+int ffb_tape_generation(const ffb_ctx *ctx, int64_t *out)
+{
+    if (!ctx || !out) return FFB_E_INVALID;
+    *out = ctx->tape_gen;
+    return FFB_OK;
+}
+
+int ffb_tape_check(ffb_ctx *ctx, int64_t generation)
+{
+    if (!ctx) return FFB_E_INVALID;
+    if (generation != ctx->tape_gen)
+        return fail(ctx, FFB_E_NO_TAPE,
+                    "ffb_tape_check: the record was replaced or cleared since it was begun%s");
+    if (!ctx->tape || ctx->tape->used == 0)
+        return fail(ctx, FFB_E_NO_TAPE, "ffb_tape_check: nothing recorded%s");
     return FFB_OK;
 }
 

@@ -57,6 +57,7 @@ struct ffb_ctx {
     int64_t ord_n = -1;                        // order was computed for
 
     struct ffb_tape *tape = nullptr;           // recording for ffb_backward
+    int64_t tape_gen = 0;                      // bumped by ffb_tape_begin and ffb_tape_clear
     struct diff_ws *diff = nullptr;            // diffusion-variant buffers (on first use)
     int diff_graph = 1;                        // FFB_OPT_DIFFUSION_GRAPH
     struct inverse_ws *inv = nullptr;          // inverse-map workspace (on first use)

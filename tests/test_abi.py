@@ -118,6 +118,9 @@ def test_host_validation_without_gpu(lib):
     assert lib.ffb_distortion(None, 4, 4, None, None, None, None) == 1
     assert lib.ffb_inverse(None, 4, 4, None, None, 0, None, None) == 1
     assert lib.ffb_destroy(None) == 1
+    g = ctypes.c_int64()
+    assert lib.ffb_tape_generation(None, ctypes.byref(g)) == 1
+    assert lib.ffb_tape_check(None, 0) == 1
     assert lib.ffb_last_error(None) == b"null context"
     # batches: descriptions are checked before any device work
     import paper_1802_07625_amd.api as api

@@ -315,6 +315,44 @@ def test_backward_requires_complete_tape():
     assert ctx.sync(check=False) == 0
 
 
+def test_backward_of_a_replaced_record_fails():
+    """The context keeps one record: a second forward replaces the first
+    one's, so the first graph's backward must fail (FFB_E_NO_TAPE) instead of
+    returning the second forward's gradient; the second graph's backward
+    still works and equals a fresh single forward's."""
+    m = synth.workload("c1_L64")
+    ctx = new_ctx(m.lx, max_points=m.n_vertices)
+    a0 = oracle.region_areas(m)
+
+    def forward(scale):
+        pts = dev_f32(m.xy).reshape(-1, 2)
+        geom = ffb.Geometry.from_map(m, pts)
+        d = dev_f64(m.density * scale).requires_grad_(True)
+        val = d * dev_f64(a0)
+        area = ffb.FFBFunction.apply(val, ctx, geom, pts, SIGMAS[:1], None, 64)
+        e = area / (val * area.sum() / val.sum()) - 1.0
+        return d, (e * e).sum()
+
+    d1, l1 = forward(1.0)
+    d2, l2 = forward(2.0)
+    with pytest.raises(ffb.FFBError) as ei:
+        l1.backward()
+    assert ei.value.code == ffb.FFB_E_NO_TAPE
+    l2.backward()
+    assert ctx.sync(check=False) == 0
+    d3, l3 = forward(2.0)
+    l3.backward()
+    assert ctx.sync(check=False) == 0
+    np.testing.assert_allclose(to_np(d2.grad), to_np(d3.grad), rtol=0,
+                               atol=1e-5 * np.abs(to_np(d3.grad)).max())
+    # a cleared record is gone too
+    gen = ctx.tape_generation()
+    ctx.tape_clear()
+    with pytest.raises(ffb.FFBError) as ei:
+        ffb.ffb_tape_check(ctx.handle, gen)
+    assert ei.value.code == ffb.FFB_E_NO_TAPE
+
+
 def test_backward_max_steps_too_small_sets_status():
     m = synth.workload("c1_L64")
     ref = oracle.rounds(m, m.density, SIGMAS[:1])
