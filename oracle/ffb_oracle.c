@@ -178,12 +178,16 @@ static int clip_half(const poly_t *in, poly_t *out, int axis, double c, double s
     return 0;
 }
 
-static double poly_area(const poly_t *p)
+/* Signed shoelace area of p, with the corners taken relative to (ox, oy):
+ * the sum is unchanged by the translation, and with (ox, oy) the corner of
+ * the clipped cell the products are of numbers below 1 instead of ~L, so
+ * the rounding of the sum stays at FP64 level relative to the area. */
+static double poly_area(const poly_t *p, double ox, double oy)
 {
     double s = 0.0;
     for (int32_t k = 0; k < p->n; ++k) {
         int32_t k1 = (k + 1) % p->n;
-        s += p->x[k] * p->y[k1] - p->x[k1] * p->y[k];
+        s += (p->x[k] - ox) * (p->y[k1] - oy) - (p->x[k1] - ox) * (p->y[k] - oy);
     }
     return 0.5 * s;
 }
@@ -254,7 +258,8 @@ int ffbo_density(int32_t lx, int32_t ly, int64_t nv, const double *xy, int32_t n
                     if (clip_half(&band, &t2, 0, (double)i, -1.0)) { fail = 1; break; }
                     if (clip_half(&t2, &cell, 0, (double)(i + 1), 1.0)) { fail = 1; break; }
                     if (cell.n < 3) continue;
-                    rho[(int64_t)j * lx + i] += w[ring_region[g]] * poly_area(&cell);
+                    rho[(int64_t)j * lx + i] +=
+                        w[ring_region[g]] * poly_area(&cell, (double)i, (double)j);
                 }
             }
         }

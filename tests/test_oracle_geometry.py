@@ -205,3 +205,27 @@ def test_raster_rejects_nonpositive_area():
     with pytest.raises(oracle.OracleError) as ei:
         oracle.density(m, m.value, oracle.region_areas(m))
     assert ei.value.code == oracle.E_NONPOSITIVE
+
+
+def test_raster_translation_by_whole_cells():
+    """Moving the map by whole cells moves its density grid with it: cell
+    coverage depends only on the geometry relative to the cell (shoelace
+    translation invariance).  Far from the origin (coordinates ~1000) the
+    coverage of small clipped pieces must keep FP64 accuracy relative to the
+    piece, which an area taken on absolute coordinates (products ~1e6) loses
+    by ~1e-10 of a cell."""
+    rings = [[(1.3, 1.1), (6.7, 1.45), (5.2, 6.9), (1.05, 5.5)],
+             [(2.2, 2.6), (2.9, 4.7), (4.1, 3.3)],          # clockwise hole
+             [(6.7, 1.45), (7.9, 1.2), (7.6, 7.7), (5.2, 6.9)]]
+    base = poly_map(rings, [900.0, 1.0], 8, 8, regions=[0, 0, 1])
+    area = oracle.region_areas(base)
+    rho0, pad0 = oracle.density(base, base.value, area)
+    shift = np.array([1000.0, 996.0])
+    far = SimpleNamespace(**{**vars(base), "lx": 1024, "ly": 1024})
+    rho1, pad1 = oracle.density(far, base.value, area, xy=base.xy + shift)
+    assert pad1 == pad0
+    win = rho1[996:1004, 1000:1008]
+    np.testing.assert_allclose(win, rho0, rtol=0, atol=1e-12 * np.abs(rho0).max())
+    rest = rho1.copy()
+    rest[996:1004, 1000:1008] = pad1
+    assert np.all(rest == pad1)
