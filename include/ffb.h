@@ -34,8 +34,13 @@
  *    is element j * lx + i; its node (centre) is (i + 1/2, j + 1/2).
  *  - lx and ly are powers of two in [8, 1024].  Coordinates live in the box
  *    [0, lx] x [0, ly] whose edges reflect the flow.
- *  - Precision: FP32 grids, fields and positions; FP64 for area sums, the
- *    padding density, the mean density rho_bar and the step controller.
+ *  - Precision: FP32 fields and positions; FP64 for area sums, the
+ *    density grid, the transforms of ffb_flux (the fields are rounded to
+ *    FP32 once, at the end), the padding density, the mean density rho_bar
+ *    and the step controller.  The density grid is FP64 because rounding it
+ *    to FP32 (a relative change of 6e-8 per cell) already moves the most
+ *    sensitive trajectories of a 1024 x 1024 map with a 700:1 density
+ *    range by up to 5e-4 grid units.
  *  - One context per stream; a context is not thread-safe.
  *
  * Gradients (not part of the paper's method): the adjoint calls at the end
@@ -173,13 +178,13 @@ int ffb_area_error(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
  * rho_pad = sum(value) / sum(area),
  *   rho[j][i] = rho_pad + sum_r (d_r - rho_pad) * |cell(i,j) ∩ region_r|
  * (exact signed coverage of each cell).  area is ffb_area_error's output for
- * the same vertices.  rho (out) is [ly][lx] FP32, rho_pad (out) [1] FP64.
+ * the same vertices.  rho (out) is [ly][lx] FP64, rho_pad (out) [1] FP64.
  * Vertices outside [0,lx] x [0,ly] give FFB_E_DOMAIN on the device. */
 int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                const double *area, float *rho, double *rho_pad);
+                const double *area, double *rho, double *rho_pad);
 
 /* Blur and flux (Eq. 7; SI Appendix section 2, flux of linear equalisation).
- * From rho [ly][lx] (in):
+ * From rho [ly][lx] (in, FP64), with FP64 transforms:
  *   rt_mn  = 4 S_mn / ((1+delta_m0)(1+delta_n0)),
  *            S_mn = sum_ij rho_ij cos(pi m (i+1/2)/lx) cos(pi n (j+1/2)/ly);
  *   rts_mn = rt_mn exp(-pi^2 sigma^2 (m^2/lx^2 + n^2/ly^2) / 2)   (sigma >= 0,
@@ -193,7 +198,7 @@ int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
  * cell centres (J_x odd and J_y even across x edges, J_x even and J_y odd
  * across y edges, rho_s even).  rho_bar (out, [1], FP64) = mean of rho.
  * min rho_s <= 0 gives FFB_E_NONPOSITIVE on the device. */
-int ffb_flux(ffb_ctx *ctx, const float *rho, float sigma, float *fields, double *rho_bar);
+int ffb_flux(ffb_ctx *ctx, const double *rho, float sigma, float *fields, double *rho_bar);
 
 /* Pack node arrays jx, jy, rho_s ([ly][lx] each, in) into the ghosted
  * float4 field layout of ffb_flux (out, [(ly+2)][(lx+2)][4]). */
@@ -229,9 +234,9 @@ int ffb_integrate(ffb_ctx *ctx, const float *fields, const double *rho_bar, floa
  * approximated by a cut-off t_end.
  *
  * ffb_diffusion_fields: fields (out, ghosted layout as ffb_flux) at time t
- * (>= 0) for the raster density rho (in, [ly][lx] FP32) blurred by sigma.
- * Enqueue-only. */
-int ffb_diffusion_fields(ffb_ctx *ctx, const float *rho, float sigma, double t, float *fields);
+ * (>= 0) for the raster density rho (in, [ly][lx] FP64) blurred by sigma
+ * (FP32 transforms).  Enqueue-only. */
+int ffb_diffusion_fields(ffb_ctx *ctx, const double *rho, float sigma, double t, float *fields);
 
 /* ffb_diffusion: advect xy (in/out, [n][2] FP32) from t = 0 to t_end (> 0)
  * with the same controller as ffb_integrate (opts; a replayed schedule must
@@ -244,7 +249,7 @@ int ffb_diffusion_fields(ffb_ctx *ctx, const float *rho, float sigma, double t, 
  * argument errors return FFB_E_INVALID before any launch; device errors
  * (non-positive rho(t), non-finite steps, step underflow, too many
  * attempts) land in stats[3] and the sticky status, and leave xy as it was. */
-int ffb_diffusion(ffb_ctx *ctx, const float *rho, float sigma, double t_end, float *xy, int64_t n,
+int ffb_diffusion(ffb_ctx *ctx, const double *rho, float sigma, double t_end, float *xy, int64_t n,
                   const ffb_integrate_opts *opts, int32_t *stats, double *h_out, int32_t h_cap);
 
 /* Angular distortion of the cartogram (main text, section "Measures of

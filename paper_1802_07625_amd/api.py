@@ -246,12 +246,12 @@ def ffb_density(ctx, geom: Geometry, value, area, rho, rho_pad, lx: int, ly: int
     g = geom.struct()
     _check(ctx, lib().ffb_density(ctx, ctypes.byref(g), _ptr(value, torch.float64, R, "value"),
                                   _ptr(area, torch.float64, R, "area"),
-                                  _ptr(rho, torch.float32, lx * ly, "rho"),
+                                  _ptr(rho, torch.float64, lx * ly, "rho"),
                                   _ptr(rho_pad, torch.float64, 1, "rho_pad")), "ffb_density")
 
 
 def ffb_flux(ctx, rho, sigma: float, fields, rho_bar, lx: int, ly: int) -> None:
-    _check(ctx, lib().ffb_flux(ctx, _ptr(rho, torch.float32, lx * ly, "rho"), float(sigma),
+    _check(ctx, lib().ffb_flux(ctx, _ptr(rho, torch.float64, lx * ly, "rho"), float(sigma),
                                _ptr(fields, torch.float32, 4 * (lx + 2) * (ly + 2), "fields"),
                                _ptr(rho_bar, torch.float64, 1, "rho_bar")), "ffb_flux")
 
@@ -278,7 +278,7 @@ def ffb_integrate(ctx, fields, rho_bar, xy, opts: IntegrateOpts, stats, h_out=No
 
 
 def ffb_diffusion_fields(ctx, rho, sigma: float, t: float, fields, lx: int, ly: int) -> None:
-    _check(ctx, lib().ffb_diffusion_fields(ctx, _ptr(rho, torch.float32, lx * ly, "rho"),
+    _check(ctx, lib().ffb_diffusion_fields(ctx, _ptr(rho, torch.float64, lx * ly, "rho"),
                                            float(sigma), float(t),
                                            _ptr(fields, torch.float32, 4 * (lx + 2) * (ly + 2),
                                                 "fields")), "ffb_diffusion_fields")
@@ -288,7 +288,7 @@ def ffb_diffusion(ctx, rho, sigma: float, t_end: float, xy, opts: IntegrateOpts,
                   h_out=None, replay_h=None, lx: int = 0, ly: int = 0) -> None:
     n = xy.shape[0]
     o = opts.struct(replay_h)
-    _check(ctx, lib().ffb_diffusion(ctx, _ptr(rho, torch.float32, lx * ly, "rho"), float(sigma),
+    _check(ctx, lib().ffb_diffusion(ctx, _ptr(rho, torch.float64, lx * ly, "rho"), float(sigma),
                                     float(t_end), _ptr(xy, torch.float32, 2 * n, "xy"), n,
                                     ctypes.byref(o), _ptr(stats, torch.int32, 4, "stats"),
                                     _ptr(h_out, torch.float64, name="h_out"),
@@ -402,6 +402,10 @@ class Context:
         self.lx, self.ly = int(lx), int(ly)
         self.device = torch.device(device)
         self.handle = ffb_create(lx, ly, max_points, stream)
+        # the record references the ring arrays of the geometries it saw
+        # (the library keeps pointers, not copies): hold them while it exists
+        self._recording = False
+        self._tape_refs = []
 
     def close(self):
         if self.handle is not None:
@@ -433,12 +437,14 @@ class Context:
         R = geom.n_regions
         area, err, mx = self._f64(R), self._f64(R), self._f64(1)
         ffb_area_error(self.handle, geom, value, area, err, mx)
+        self._hold(geom)
         return area, err, mx
 
     def density(self, geom: Geometry, value, area):
-        rho = torch.empty((self.ly, self.lx), dtype=torch.float32, device=self.device)
+        rho = torch.empty((self.ly, self.lx), dtype=torch.float64, device=self.device)
         pad = self._f64(1)
         ffb_density(self.handle, geom, value, area, rho, pad, self.lx, self.ly)
+        self._hold(geom)
         return rho, pad
 
     def new_fields(self):
@@ -534,14 +540,23 @@ class Context:
         return stats, e, et
 
     # adjoints
+    def _hold(self, geom):
+        if self._recording and not any(g is geom for g in self._tape_refs):
+            self._tape_refs.append(geom)
+
     def tape_begin(self, max_steps: int = 512):
         ffb_tape_begin(self.handle, max_steps)
+        self._recording = True
+        self._tape_refs = []
 
     def tape_end(self):
         ffb_tape_end(self.handle)
+        self._recording = False
 
     def tape_clear(self):
         ffb_tape_clear(self.handle)
+        self._recording = False
+        self._tape_refs = []
 
     def tape_generation(self) -> int:
         return ffb_tape_generation(self.handle)
@@ -555,6 +570,7 @@ class Context:
         dval = torch.empty_like(dL_darea)
         dxy = None if n_vertices is None else self._f64(n_vertices, 2)
         ffb_backward(self.handle, dL_darea.contiguous(), dval, dxy)
+        self._recording = False
         return dval, dxy
 
 

@@ -174,27 +174,40 @@ namespace {
 
 bool pow2_in_range(int32_t n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
 
-// exp(-2 pi i k / N), k < N/2 and exp(-i pi m / (2N)), m < N, in FP64 then rounded.
-hipError_t upload_twiddles(float2 **tw, float2 **tq, int N)
+// exp(-2 pi i k / N), k < N/2 and exp(-i pi m / (2N)), m < N, in FP64: the
+// tables as computed (tw64, tq64) and rounded to FP32 (tw, tq).
+hipError_t upload_twiddles(float2 **tw, float2 **tq, double2 **tw64, double2 **tq64, int N)
 {
     std::vector<float2> a(N / 2), b(N);
+    std::vector<double2> a64(N / 2), b64(N);
     const double pi = 3.14159265358979323846;
-    for (int k = 0; k < N / 2; ++k)
-        a[k] = make_float2((float)cos(2 * pi * k / N), (float)(-sin(2 * pi * k / N)));
-    for (int m = 0; m < N; ++m)
-        b[m] = make_float2((float)cos(pi * m / (2.0 * N)), (float)(-sin(pi * m / (2.0 * N))));
+    for (int k = 0; k < N / 2; ++k) {
+        a64[k] = make_double2(cos(2 * pi * k / N), -sin(2 * pi * k / N));
+        a[k] = make_float2((float)a64[k].x, (float)a64[k].y);
+    }
+    for (int m = 0; m < N; ++m) {
+        b64[m] = make_double2(cos(pi * m / (2.0 * N)), -sin(pi * m / (2.0 * N)));
+        b[m] = make_float2((float)b64[m].x, (float)b64[m].y);
+    }
     hipError_t e = hipMalloc(reinterpret_cast<void **>(tw), sizeof(float2) * a.size());
-    if (e != hipSuccess) return e;
-    e = hipMalloc(reinterpret_cast<void **>(tq), sizeof(float2) * b.size());
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(*tw, a.data(), sizeof(float2) * a.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    return hipMemcpy(*tq, b.data(), sizeof(float2) * b.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(tq), sizeof(float2) * b.size());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(tw64), sizeof(double2) * a.size());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(tq64), sizeof(double2) * b.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(*tw, a.data(), sizeof(float2) * a.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(*tq, b.data(), sizeof(float2) * b.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(*tw64, a64.data(), sizeof(double2) * a64.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(*tq64, b64.data(), sizeof(double2) * b64.size(), hipMemcpyHostToDevice);
+    return e;
 }
 
 void free_all(ffb_ctx *c)
 {
-    void *ptrs[] = {c->d_status, c->tw_x, c->tq_x, c->tw_y, c->tq_y, c->t1, c->t2, c->t3, c->pa,
+    void *ptrs[] = {c->d_status, c->tw_x, c->tq_x, c->tw_y, c->tq_y, c->tw64_x, c->tq64_x,
+                    c->tw64_y, c->tq64_y, c->t1, c->t2, c->t3, c->pa,
                     c->pb, c->pc, c->red, c->acc, c->w_region, c->st[0], c->st[1], c->kv[0],
                     c->kv[1], c->errslot, c->lam_w, c->adj_t, c->adj_jac, c->ord_perm,
                     c->ord_rank, c->ord_count, c->ord_offs, c->ord_sums};
@@ -258,11 +271,11 @@ int ffb_create(ffb_ctx **out, int32_t lx, int32_t ly, int64_t max_points, void *
     const int64_t plane = (int64_t)lx * ly;
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&c->d_status), sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(c->d_status, 0, sizeof(int32_t));
-    if (e == hipSuccess) e = upload_twiddles(&c->tw_x, &c->tq_x, lx);
-    if (e == hipSuccess) e = upload_twiddles(&c->tw_y, &c->tq_y, ly);
+    if (e == hipSuccess) e = upload_twiddles(&c->tw_x, &c->tq_x, &c->tw64_x, &c->tq64_x, lx);
+    if (e == hipSuccess) e = upload_twiddles(&c->tw_y, &c->tq_y, &c->tw64_y, &c->tq64_y, ly);
     float **planes[] = {&c->t1, &c->t2, &c->t3, &c->pa, &c->pb, &c->pc};
     for (float **pl : planes)
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(pl), sizeof(float) * plane);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(pl), sizeof(double) * plane);
     if (e == hipSuccess) e = grow(&c->red, 0, kRedDoubles);
     c->red_cap = kRedDoubles;
     if (e == hipSuccess) e = grow(&c->acc, 0, (int64_t)ly * (lx + 1));
@@ -368,7 +381,7 @@ int ffb_area_error(ffb_ctx *ctx, const ffb_geometry *g, const double *value, dou
 }
 
 int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const double *area,
-                float *rho, double *rho_pad)
+                double *rho, double *rho_pad)
 {
     if (!ctx) return FFB_E_INVALID;
     int st = check_geometry(ctx, g);
@@ -383,7 +396,7 @@ int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const 
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_density launch");
 }
 
-int ffb_flux(ffb_ctx *ctx, const float *rho, float sigma, float *fields, double *rho_bar)
+int ffb_flux(ffb_ctx *ctx, const double *rho, float sigma, float *fields, double *rho_bar)
 {
     if (!ctx) return FFB_E_INVALID;
     if (!rho || !fields || !rho_bar) return fail(ctx, FFB_E_INVALID, "ffb_flux: NULL argument%s");

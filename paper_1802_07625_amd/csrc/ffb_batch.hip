@@ -69,13 +69,15 @@ struct ffb_batch {
     int32_t class_n[kMaxClasses];                  // grid width of each class
     int32_t row_beg[kMaxClasses + 1], col_beg[kMaxClasses + 1];
     // workspace
-    float *rho = nullptr, *t1 = nullptr, *t2 = nullptr, *pa = nullptr, *pb = nullptr, *pc = nullptr;
+    // density grids and transform planes (FP64)
+    double *rho = nullptr, *t1 = nullptr, *t2 = nullptr, *pa = nullptr, *pb = nullptr,
+           *pc = nullptr;
     float4 *fields = nullptr;
     double *acc = nullptr, *w_region = nullptr, *rho_pad = nullptr, *rho_bar = nullptr,
            *area = nullptr, *err = nullptr;
     float4 *st0 = nullptr, *st1 = nullptr;
     float2 *kv0 = nullptr, *kv1 = nullptr, *scratch_xy = nullptr;
-    float2 *tw1024 = nullptr, *tq1024 = nullptr;
+    double2 *tw1024 = nullptr, *tq1024 = nullptr;
     int32_t *h_n_active = nullptr;                 // pinned host word
     // launch shapes
     int fft_threads[kMaxClasses];
@@ -461,8 +463,8 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) e = alloc(&b->d_n_active, 1);
     if (e == hipSuccess) e = alloc(&b->d_status, 1);
     if (e == hipSuccess) e = alloc(&b->d_max_err, M);
-    float **planes[] = {&b->rho, &b->t1, &b->t2, &b->pa, &b->pb, &b->pc};
-    for (float **pl : planes)
+    double **planes[] = {&b->rho, &b->t1, &b->t2, &b->pa, &b->pb, &b->pc};
+    for (double **pl : planes)
         if (e == hipSuccess) e = alloc(pl, b->plane_total);
     if (e == hipSuccess) e = alloc(&b->fields, b->field_total);
     if (e == hipSuccess) e = alloc(&b->acc, b->acc_total);
@@ -479,12 +481,11 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) {
         // twiddles of the longest transform; shorter ones read them at a stride
         const int N = 1024;
-        std::vector<float2> tw(N / 2), tq(N);
+        std::vector<double2> tw(N / 2), tq(N);
         const double pi = 3.14159265358979323846;
-        for (int k = 0; k < N / 2; ++k)
-            tw[k] = make_float2((float)cos(2 * pi * k / N), (float)(-sin(2 * pi * k / N)));
+        for (int k = 0; k < N / 2; ++k) tw[k] = make_double2(cos(2 * pi * k / N), -sin(2 * pi * k / N));
         for (int m = 0; m < N; ++m)
-            tq[m] = make_float2((float)cos(pi * m / (2.0 * N)), (float)(-sin(pi * m / (2.0 * N))));
+            tq[m] = make_double2(cos(pi * m / (2.0 * N)), -sin(pi * m / (2.0 * N)));
         e = upload(&b->tw1024, tw);
         if (e == hipSuccess) e = upload(&b->tq1024, tq);
     }

@@ -87,7 +87,7 @@ hipError_t ensure_graph(ffb_ctx *ctx, diff_ws *w, int64_t n)
     return hipSuccess;
 }
 
-int check_common(ffb_ctx *ctx, const float *rho, float sigma, const char *what)
+int check_common(ffb_ctx *ctx, const double *rho, float sigma, const char *what)
 {
     if (!rho) return fail(ctx, FFB_E_INVALID, "%s: NULL density", what);
     if (!(sigma >= 0.f) || !std::isfinite(sigma))
@@ -118,7 +118,7 @@ void diff_free(ffb_ctx *ctx)
 
 extern "C" {
 
-int ffb_diffusion_fields(ffb_ctx *ctx, const float *rho, float sigma, double t, float *fields)
+int ffb_diffusion_fields(ffb_ctx *ctx, const double *rho, float sigma, double t, float *fields)
 {
     if (!ctx) return FFB_E_INVALID;
     int st = check_common(ctx, rho, sigma, "ffb_diffusion_fields");
@@ -140,7 +140,7 @@ int ffb_diffusion_fields(ffb_ctx *ctx, const float *rho, float sigma, double t, 
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_diffusion_fields");
 }
 
-int ffb_diffusion(ffb_ctx *ctx, const float *rho, float sigma, double t_end, float *xy, int64_t n,
+int ffb_diffusion(ffb_ctx *ctx, const double *rho, float sigma, double t_end, float *xy, int64_t n,
                   const ffb_integrate_opts *o, int32_t *stats, double *h_out, int32_t h_cap)
 {
     if (!ctx) return FFB_E_INVALID;

@@ -24,7 +24,11 @@ struct ffb_ctx {
     // transform workspace
     float2 *tw_x = nullptr, *tq_x = nullptr;   // FFT and DCT twiddles for length lx
     float2 *tw_y = nullptr, *tq_y = nullptr;   // ... for length ly
-    float *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;   // [lx*ly] scratch planes
+    double2 *tw64_x = nullptr, *tq64_x = nullptr;   // the same tables in FP64 (flux)
+    double2 *tw64_y = nullptr, *tq64_y = nullptr;
+    // [lx*ly] scratch planes, sized for FP64 (the flux); FP32 users take
+    // the first half
+    float *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
     float *pa = nullptr, *pb = nullptr, *pc = nullptr;
     double *red = nullptr;                     // reduction partials (kRedDoubles)
     int32_t red_cap = 0;
@@ -137,9 +141,20 @@ hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *
                        double *area, double *err, double *max_abs_err);
 
 hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                          const double *area, float *rho, double *rho_pad);
+                          const double *area, double *rho, double *rho_pad);
 
-hipError_t launch_flux(ffb_ctx *ctx, const float *rho, float sigma, float4 *fields,
+// Transform workspace of one flux call (FP64): twiddle tables of both
+// lengths, six [lx*ly] planes and kRedDoubles reduction partials.
+struct flux_ws {
+    double2 *tw_x, *tq_x, *tw_y, *tq_y;
+    double *t1, *t2, *t3, *pa, *pb, *pc;
+    double *red;
+};
+hipError_t launch_flux_ws(hipStream_t s, int lx, int ly, const flux_ws &w, const double *rho,
+                          float sigma, float4 *fields, double *rho_bar, int32_t *status);
+// FP64 twiddle tables of length N on the device (tw: N/2 entries, tq: N).
+hipError_t launch_twiddles(hipStream_t s, int N, double2 *tw, double2 *tq);
+hipError_t launch_flux(ffb_ctx *ctx, const double *rho, float sigma, float4 *fields,
                        double *rho_bar);
 hipError_t launch_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy,
                               const float *rho_s, float4 *fields);
@@ -234,7 +249,7 @@ struct diff_ws {
 constexpr int kDiffMaxBlocks = 2048;
 
 // Blurred cosine coefficients of rho (Eq. 7 and the blur), m-major, into spec.
-hipError_t launch_diff_spectrum(ffb_ctx *ctx, const float *rho, float sigma, float *spec);
+hipError_t launch_diff_spectrum(ffb_ctx *ctx, const double *rho, float sigma, float *spec);
 // Fields at the first `slots` stage times of ctl (slots <= kDiffSlots).
 hipError_t launch_diff_fields(ffb_ctx *ctx, diff_ws *w, int slots);
 // Initial state (hi = xy, lo = 0) and first-stage velocity at t = 0 (slot 0).
@@ -290,7 +305,7 @@ hipError_t launch_batch_finalize(hipStream_t s, const batch_view &bv, const doub
 hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                                 const ffb_geometry *g, const double *value, const double *area,
                                 double *w_region, double *rho_pad, double *acc, int64_t acc_total,
-                                float *rho, int32_t *status);
+                                double *rho, int32_t *status);
 // Row and column tables are sorted by grid width; class c owns entries
 // [row_beg[c], row_beg[c+1]) and [col_beg[c], col_beg[c+1]) and its passes
 // run with threads[c] lanes per workgroup.
@@ -301,11 +316,10 @@ struct batch_fft_plan {
     int threads[kBatchMaxClasses];
 };
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
-                             const batch_fft_plan &plan, const float2 *tw1024,
-                             const float2 *tq1024, float *rho, const double *acc, float *t1,
-                             float *t2, float *pa,
-                             float *pb, float *pc, float4 *fields, double *rho_bar,
-                             int32_t *status);
+                             const batch_fft_plan &plan, const double2 *tw1024,
+                             const double2 *tq1024, const double *rho, const double *acc,
+                             double *t1, double *t2, double *pa, double *pb, double *pc,
+                             float4 *fields, double *rho_bar, int32_t *status);
 struct batch_advect_args {
     const float4 *fields;
     const double *rho_bar;         // [M]

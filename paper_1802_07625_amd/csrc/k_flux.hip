@@ -28,9 +28,34 @@ namespace {
 
 constexpr int kMaxN = 1024;
 
-__device__ inline float2 cmul(float2 a, float2 b)
+// Real and complex types of one precision: the single-map flux runs in FP64
+// (double / double2), the batched, diffusion and adjoint transforms in FP32
+// (float / float2).
+template <typename R> struct cx_of;
+template <> struct cx_of<float> { using T = float2; };
+template <> struct cx_of<double> { using T = double2; };
+template <typename R> using cx = typename cx_of<R>::T;
+
+template <typename C> struct re_of;
+template <> struct re_of<float2> { using T = float; };
+template <> struct re_of<double2> { using T = double; };
+
+template <typename C>
+__device__ inline C mkc(typename re_of<C>::T x, typename re_of<C>::T y)
 {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    C c;
+    c.x = x;
+    c.y = y;
+    return c;
+}
+
+__device__ inline float rexp(float x) { return expf(x); }
+__device__ inline double rexp(double x) { return exp(x); }
+
+template <typename C>
+__device__ inline C cmul(C a, C b)
+{
+    return mkc<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
 __device__ inline int ilog2(int n) { return 31 - __clz(n); }
@@ -46,7 +71,8 @@ __device__ inline int ilog2(int n) { return 31 - __clz(n); }
 //   X[j + t Ls] = sum_m w_{4Ls}^{m j} w_4^{m t} x_m,  t = 0..3,
 // written to b[q 4Ls + j + t Ls].  Half as many passes as radix 2, so half
 // the LDS traffic and barriers.
-__device__ __forceinline__ float2 *fft_lds(float2 *a, float2 *b, int N, const float2 *tw, bool inverse)
+template <typename C>
+__device__ __forceinline__ C *fft_lds(C *a, C *b, int N, const C *tw, bool inverse)
 {
     const int lgN = ilog2(N);
     const int half = N >> 1, quarter = N >> 2;
@@ -55,11 +81,11 @@ __device__ __forceinline__ float2 *fft_lds(float2 *a, float2 *b, int N, const fl
         // radix 2 with Ls = 1: every twiddle is 1
         __syncthreads();
         for (int bi = threadIdx.x; bi < half; bi += blockDim.x) {
-            const float2 u = a[bi], v = a[bi + half];
-            b[2 * bi] = make_float2(u.x + v.x, u.y + v.y);
-            b[2 * bi + 1] = make_float2(u.x - v.x, u.y - v.y);
+            const C u = a[bi], v = a[bi + half];
+            b[2 * bi] = mkc<C>(u.x + v.x, u.y + v.y);
+            b[2 * bi + 1] = mkc<C>(u.x - v.x, u.y - v.y);
         }
-        float2 *t = a;
+        C *t = a;
         a = b;
         b = t;
         lgL = 1;
@@ -72,31 +98,31 @@ __device__ __forceinline__ float2 *fft_lds(float2 *a, float2 *b, int N, const fl
             const int j = bi & (Ls - 1);
             const int k = bi >> lgL;
             const int e1 = j << sh, e3 = 3 * e1;     // e1 < N/4, 2 e1 < N/2, e3 < 3N/4
-            float2 w1 = tw[e1], w2 = tw[2 * e1];
-            float2 w3 = e3 < half ? tw[e3] : tw[e3 - half];
-            if (e3 >= half) w3 = make_float2(-w3.x, -w3.y);   // exp(-i pi) = -1
+            C w1 = tw[e1], w2 = tw[2 * e1];
+            C w3 = e3 < half ? tw[e3] : tw[e3 - half];
+            if (e3 >= half) w3 = mkc<C>(-w3.x, -w3.y);   // exp(-i pi) = -1
             if (inverse) {
                 w1.y = -w1.y;
                 w2.y = -w2.y;
                 w3.y = -w3.y;
             }
-            const float2 x0 = a[bi];
-            const float2 x1 = cmul(a[bi + quarter], w1);
-            const float2 x2 = cmul(a[bi + 2 * quarter], w2);
-            const float2 x3 = cmul(a[bi + 3 * quarter], w3);
-            const float2 a0 = make_float2(x0.x + x2.x, x0.y + x2.y);
-            const float2 a1 = make_float2(x0.x - x2.x, x0.y - x2.y);
-            const float2 b0 = make_float2(x1.x + x3.x, x1.y + x3.y);
-            const float2 b1 = make_float2(x1.x - x3.x, x1.y - x3.y);
+            const C x0 = a[bi];
+            const C x1 = cmul(a[bi + quarter], w1);
+            const C x2 = cmul(a[bi + 2 * quarter], w2);
+            const C x3 = cmul(a[bi + 3 * quarter], w3);
+            const C a0 = mkc<C>(x0.x + x2.x, x0.y + x2.y);
+            const C a1 = mkc<C>(x0.x - x2.x, x0.y - x2.y);
+            const C b0 = mkc<C>(x1.x + x3.x, x1.y + x3.y);
+            const C b1 = mkc<C>(x1.x - x3.x, x1.y - x3.y);
             // w_4 b1: -i b1 forward, +i b1 inverse
-            const float2 rb = inverse ? make_float2(-b1.y, b1.x) : make_float2(b1.y, -b1.x);
+            const C rb = inverse ? mkc<C>(-b1.y, b1.x) : mkc<C>(b1.y, -b1.x);
             const int o = (k << (lgL + 2)) + j;
-            b[o] = make_float2(a0.x + b0.x, a0.y + b0.y);
-            b[o + Ls] = make_float2(a1.x + rb.x, a1.y + rb.y);
-            b[o + 2 * Ls] = make_float2(a0.x - b0.x, a0.y - b0.y);
-            b[o + 3 * Ls] = make_float2(a1.x - rb.x, a1.y - rb.y);
+            b[o] = mkc<C>(a0.x + b0.x, a0.y + b0.y);
+            b[o + Ls] = mkc<C>(a1.x + rb.x, a1.y + rb.y);
+            b[o + 2 * Ls] = mkc<C>(a0.x - b0.x, a0.y - b0.y);
+            b[o + 3 * Ls] = mkc<C>(a1.x - rb.x, a1.y - rb.y);
         }
-        float2 *t = a;
+        C *t = a;
         a = b;
         b = t;
     }
@@ -106,8 +132,8 @@ __device__ __forceinline__ float2 *fft_lds(float2 *a, float2 *b, int N, const fl
 
 // `s`: stride into a table built for a longer transform (tables for length
 // 1024 serve every power of two N <= 1024 with s = 1024 / N).
-__device__ inline void load_twiddles(float2 *tw_lds, const float2 *__restrict__ tw, int N,
-                                     int s = 1)
+template <typename C>
+__device__ inline void load_twiddles(C *tw_lds, const C *__restrict__ tw, int N, int s = 1)
 {
     for (int k = threadIdx.x; k < (N >> 1); k += blockDim.x) tw_lds[k] = tw[k * s];
 }
@@ -116,22 +142,30 @@ __device__ inline void load_twiddles(float2 *tw_lds, const float2 *__restrict__ 
 // v[N-1-(i-1)/2] for odd i.
 __device__ inline int mk_pos(int i, int N) { return (i & 1) ? (N - 1 - (i >> 1)) : (i >> 1); }
 
-// DCT-II of two rows held as (ra[i], rb[i]) pairs already placed in `a` in
-// Makhoul order; leaves X_a[m], X_b[m] (unnormalised: sum x_i cos(pi m (i+1/2)/N))
-// in `out` as float2 pairs.
-__device__ __forceinline__ void dct2_pair(float2 *a, float2 *b, float2 *out, int N, const float2 *tw,
-                          const float2 *__restrict__ tq, int qs = 1)
+// From the FFT Z of a Makhoul-ordered pair (rows a + i b), the DCT-II pair
+// (X_a[m], X_b[m]) (unnormalised: sum x_i cos(pi m (i+1/2)/N)).
+template <typename C>
+__device__ inline C dct2_bin(const C *Z, int m, int N, const C *__restrict__ tq, int qs)
 {
-    float2 *Z = fft_lds(a, b, N, tw, false);
-    for (int m = threadIdx.x; m < N; m += blockDim.x) {
-        const float2 zm = Z[m];
-        const float2 zc = Z[(N - m) & (N - 1)];
-        // Va = (Zm + conj Zc)/2, Vb = (Zm - conj Zc)/(2i)
-        const float2 va = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
-        const float2 vb = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
-        const float2 q = tq[m * qs];      // exp(-i pi m / (2N))
-        out[m] = make_float2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
-    }
+    using R = typename re_of<C>::T;
+    const C zm = Z[m];
+    const C zc = Z[(N - m) & (N - 1)];
+    // Va = (Zm + conj Zc)/2, Vb = (Zm - conj Zc)/(2i)
+    const R h = R(0.5);
+    const C va = mkc<C>(h * (zm.x + zc.x), h * (zm.y - zc.y));
+    const C vb = mkc<C>(h * (zm.y + zc.y), -h * (zm.x - zc.x));
+    const C q = tq[m * qs];      // exp(-i pi m / (2N))
+    return mkc<C>(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
+}
+
+// DCT-II of two rows held as (ra[i], rb[i]) pairs already placed in `a` in
+// Makhoul order; leaves the pairs in `out`.
+template <typename C>
+__device__ __forceinline__ void dct2_pair(C *a, C *b, C *out, int N, const C *tw,
+                                          const C *__restrict__ tq, int qs = 1)
+{
+    C *Z = fft_lds(a, b, N, tw, false);
+    for (int m = threadIdx.x; m < N; m += blockDim.x) out[m] = dct2_bin(Z, m, N, tq, qs);
     __syncthreads();
 }
 
@@ -140,74 +174,73 @@ __device__ __forceinline__ void dct2_pair(float2 *a, float2 *b, float2 *out, int
 // from coefficient pairs cpair(m) = (c_a[m], c_b[m]) into `a`:
 //   X_0 = c_0, X_m = c_m / 2, W_m = exp(i pi m/(2N)) (X_m - i X_{N-m}), X_N = 0,
 // and the pair is packed as W_a + i W_b.
-template <typename F>
-__device__ void dct3_input(float2 *a, int N, const float2 *__restrict__ tq, F cpair, int qs = 1)
+template <typename C, typename F>
+__device__ void dct3_input(C *a, int N, const C *__restrict__ tq, F cpair, int qs = 1)
 {
+    using R = typename re_of<C>::T;
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
-        float2 xm = cpair(m);
-        if (m) { xm.x *= 0.5f; xm.y *= 0.5f; }
-        float2 xr = make_float2(0.f, 0.f);
-        if (m) { xr = cpair(N - m); xr.x *= 0.5f; xr.y *= 0.5f; }
-        const float2 q = tq[m * qs];
-        const float cr = q.x, ci = -q.y;          // exp(+i pi m/(2N))
+        C xm = cpair(m);
+        if (m) { xm.x *= R(0.5); xm.y *= R(0.5); }
+        C xr = mkc<C>(R(0), R(0));
+        if (m) { xr = cpair(N - m); xr.x *= R(0.5); xr.y *= R(0.5); }
+        const C q = tq[m * qs];
+        const R cr = q.x, ci = -q.y;          // exp(+i pi m/(2N))
         // Wa = (cr + i ci)(xm.x - i xr.x), Wb likewise with .y
-        const float war = cr * xm.x + ci * xr.x, wai = ci * xm.x - cr * xr.x;
-        const float wbr = cr * xm.y + ci * xr.y, wbi = ci * xm.y - cr * xr.y;
-        a[m] = make_float2(war - wbi, wai + wbr);   // Wa + i Wb
+        const R war = cr * xm.x + ci * xr.x, wai = ci * xm.x - cr * xr.x;
+        const R wbr = cr * xm.y + ci * xr.y, wbi = ci * xm.y - cr * xr.y;
+        a[m] = mkc<C>(war - wbi, wai + wbr);   // Wa + i Wb
     }
 }
 
 // After the inverse FFT of dct3_input, output y[i] of the pair:
 // even i -> v[i/2], odd i -> v[N-1-(i-1)/2]; real part = row a, imag = row b.
-__device__ inline float2 dct3_output(const float2 *v, int i, int N) { return v[mk_pos(i, N)]; }
+template <typename C>
+__device__ inline C dct3_output(const C *v, int i, int N) { return v[mk_pos(i, N)]; }
 
 // ------------------------------------------------------------------ kernels
-// DCT-II of rows r0, r0 + 1 of `in` [rows][N] into `out` (LDS: sa, sb of
-// kMaxN and stw of kMaxN / 2 float2).
-__device__ __forceinline__ void dct2_rows_body(const float *__restrict__ in, float *__restrict__ out, int64_t r0,
-                               int N, const float2 *__restrict__ tw, const float2 *__restrict__ tq,
-                               int qs, float2 *sa, float2 *sb, float2 *stw)
+// DCT-II of rows r0, r0 + 1 of `in` [rows][N] (densities) into `out`
+// (precision R; LDS: sa, sb of kMaxN and stw of kMaxN / 2 complex).
+template <typename R, typename In>
+__device__ __forceinline__ void dct2_rows_body(const In *__restrict__ in, R *__restrict__ out,
+                                               int64_t r0, int N, const cx<R> *__restrict__ tw,
+                                               const cx<R> *__restrict__ tq, int qs, cx<R> *sa,
+                                               cx<R> *sb, cx<R> *stw)
 {
+    using C = cx<R>;
     load_twiddles(stw, tw, N, qs);
-    const float *ra = in + r0 * N, *rb = ra + N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = make_float2(ra[i], rb[i]);
+    const In *ra = in + r0 * N, *rb = ra + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        sa[mk_pos(i, N)] = mkc<C>((R)ra[i], (R)rb[i]);
     // result pairs land in sa or sb; reuse the other as output staging
-    float2 *Z = fft_lds(sa, sb, N, stw, false);
-    float2 *o = (Z == sa) ? sb : sa;
-    for (int m = threadIdx.x; m < N; m += blockDim.x) {
-        const float2 zm = Z[m];
-        const float2 zc = Z[(N - m) & (N - 1)];
-        const float2 va = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y - zc.y));
-        const float2 vb = make_float2(0.5f * (zm.y + zc.y), -0.5f * (zm.x - zc.x));
-        const float2 q = tq[m * qs];
-        o[m] = make_float2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
-    }
+    C *Z = fft_lds(sa, sb, N, stw, false);
+    C *o = (Z == sa) ? sb : sa;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) o[m] = dct2_bin(Z, m, N, tq, qs);
     __syncthreads();
-    float *oa = out + r0 * N, *ob = oa + N;
+    R *oa = out + r0 * N, *ob = oa + N;
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
         oa[m] = o[m].x;
         ob[m] = o[m].y;
     }
 }
 
-// Two rows per workgroup; with `rowsum` set, also the FP64 sum of the two
-// input rows (in a fixed order), for the mean density.
-__global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
-                                                   float *__restrict__ out, int N,
-                                                   const float2 *__restrict__ tw,
-                                                   const float2 *__restrict__ tq,
+// Two rows per workgroup (FP64); with `rowsum` set, also the FP64 sum of the
+// two input rows (in a fixed order), for the mean density.
+__global__ __launch_bounds__(512) void k_dct2_rows(const double *__restrict__ in,
+                                                   double *__restrict__ out, int N,
+                                                   const double2 *__restrict__ tw,
+                                                   const double2 *__restrict__ tq,
                                                    double *__restrict__ rowsum)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    __shared__ double2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
     __shared__ double ssum[512 / 64];
     if (rowsum) {
-        const float *r = in + 2 * (int64_t)blockIdx.x * N;
+        const double *r = in + 2 * (int64_t)blockIdx.x * N;
         double v = 0.0;
-        for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) v += (double)r[i];
+        for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) v += r[i];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if ((threadIdx.x & 63) == 0) ssum[threadIdx.x >> 6] = v;
     }
-    dct2_rows_body(in, out, 2 * (int64_t)blockIdx.x, N, tw, tq, 1, sa, sb, stw);
+    dct2_rows_body<double, double>(in, out, 2 * (int64_t)blockIdx.x, N, tw, tq, 1, sa, sb, stw);
     if (rowsum && threadIdx.x == 0) {
         // dct2_rows_body passes workgroup barriers after the writes above
         double t = 0.0;
@@ -216,10 +249,22 @@ __global__ __launch_bounds__(512) void k_dct2_rows(const float *__restrict__ in,
     }
 }
 
+// Two rows per workgroup, FP32 transform of the FP64 densities (diffusion
+// spectrum).
+__global__ __launch_bounds__(512) void k_dct2_rows_f32(const double *__restrict__ in,
+                                                       float *__restrict__ out, int N,
+                                                       const float2 *__restrict__ tw,
+                                                       const float2 *__restrict__ tq)
+{
+    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    dct2_rows_body<float, double>(in, out, 2 * (int64_t)blockIdx.x, N, tw, tq, 1, sa, sb, stw);
+}
+
 // One 32 x 32 tile (columns c0.., rows r0..) of in [R][C] -> out [C][R],
 // through LDS; 256 threads.
-__device__ void transpose_tile(const float *__restrict__ in, float *__restrict__ out, int R, int C,
-                               int c0, int r0, float (*tile)[33])
+template <typename T>
+__device__ void transpose_tile(const T *__restrict__ in, T *__restrict__ out, int R, int C,
+                               int c0, int r0, T (*tile)[33])
 {
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     for (int k = ty; k < 32; k += 8) {
@@ -234,156 +279,166 @@ __device__ void transpose_tile(const float *__restrict__ in, float *__restrict__
 }
 
 // 32 x 32 tiles through LDS; in [R][C] -> out [C][R]; z selects the plane.
-__global__ __launch_bounds__(256) void k_transpose(const float *__restrict__ in0,
-                                                   const float *__restrict__ in1,
-                                                   const float *__restrict__ in2,
-                                                   float *__restrict__ out0,
-                                                   float *__restrict__ out1,
-                                                   float *__restrict__ out2, int R, int C)
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ in0,
+                                                   const T *__restrict__ in1,
+                                                   const T *__restrict__ in2, T *__restrict__ out0,
+                                                   T *__restrict__ out1, T *__restrict__ out2,
+                                                   int R, int C)
 {
-    __shared__ float tile[32][33];
-    const float *in = blockIdx.z == 0 ? in0 : (blockIdx.z == 1 ? in1 : in2);
-    float *out = blockIdx.z == 0 ? out0 : (blockIdx.z == 1 ? out1 : out2);
+    __shared__ T tile[32][33];
+    const T *in = blockIdx.z == 0 ? in0 : (blockIdx.z == 1 ? in1 : in2);
+    T *out = blockIdx.z == 0 ? out0 : (blockIdx.z == 1 ? out1 : out2);
     transpose_tile(in, out, R, C, blockIdx.x * 32, blockIdx.y * 32, tile);
 }
 
-// Column pass on rows m0, m1 = m0 + 1 of T2 [lx][ly] (LDS: sa, sb, coef of
-// kMaxN and stw of kMaxN / 2 float2).
-__device__ __forceinline__ void col_pass_body(const float *__restrict__ t2, int m0, int lx, int ly, float sigma,
-                              const float2 *__restrict__ tw, const float2 *__restrict__ tq, int qs,
-                              float *__restrict__ pa, float *__restrict__ pb,
-                              float *__restrict__ pc, float2 *sa, float2 *sb, float2 *coef,
-                              float2 *stw)
+// Column pass on rows m0, m1 = m0 + 1 of T2 [lx][ly] (precision R; LDS: sa,
+// sb, coef of kMaxN and stw of kMaxN / 2 complex).
+template <typename R>
+__device__ __forceinline__ void col_pass_body(const R *__restrict__ t2, int m0, int lx, int ly,
+                                              float sigma, const cx<R> *__restrict__ tw,
+                                              const cx<R> *__restrict__ tq, int qs,
+                                              R *__restrict__ pa, R *__restrict__ pb,
+                                              R *__restrict__ pc, cx<R> *sa, cx<R> *sb,
+                                              cx<R> *coef, cx<R> *stw)
 {
+    using C = cx<R>;
     const int N = ly;
     load_twiddles(stw, tw, N, qs);
-    const float *ra = t2 + (int64_t)m0 * N, *rb = ra + N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = make_float2(ra[i], rb[i]);
+    const R *ra = t2 + (int64_t)m0 * N, *rb = ra + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = mkc<C>(ra[i], rb[i]);
     dct2_pair(sa, sb, coef, N, stw, tq, qs);   // coef[n] = (S[m0][n], S[m1][n])
 
     // normalisation of Eq. 7 and the blur, separable in m and n
-    const float PI_F = 3.14159265358979f;
-    const float cgx = PI_F * PI_F * sigma * sigma / (2.0f * (float)lx * (float)lx);
-    const float cgy = PI_F * PI_F * sigma * sigma / (2.0f * (float)ly * (float)ly);
-    const float gx0 = expf(-cgx * (float)m0 * (float)m0) * (m0 == 0 ? 2.0f : 4.0f);
-    const float gx1 = expf(-cgx * (float)(m0 + 1) * (float)(m0 + 1)) * 4.0f;
+    const R PI = R(3.14159265358979323846);
+    const R sg = (R)sigma;
+    const R cgx = PI * PI * sg * sg / (R(2) * (R)lx * (R)lx);
+    const R cgy = PI * PI * sg * sg / (R(2) * (R)ly * (R)ly);
+    const R gx0 = rexp(-cgx * (R)m0 * (R)m0) * (m0 == 0 ? R(2) : R(4));
+    const R gx1 = rexp(-cgx * (R)(m0 + 1) * (R)(m0 + 1)) * R(4);
     for (int n = threadIdx.x; n < N; n += blockDim.x) {
-        const float gy = expf(-cgy * (float)n * (float)n) * (n == 0 ? 0.5f : 1.0f);
-        const float2 s = coef[n];
-        coef[n] = make_float2(s.x * gx0 * gy, s.y * gx1 * gy);
+        const R gy = rexp(-cgy * (R)n * (R)n) * (n == 0 ? R(0.5) : R(1));
+        const C s = coef[n];
+        coef[n] = mkc<C>(s.x * gx0 * gy, s.y * gx1 * gy);
     }
     __syncthreads();
 
-    const float flx = (float)lx, fly = (float)ly;
-    const float inv_pi = 0.318309886183790672f;
-    const float ma = (float)m0, mb = (float)(m0 + 1);
+    const R flx = (R)lx, fly = (R)ly;
+    const R inv_pi = R(0.318309886183790671537767526745);
+    const R ma = (R)m0, mb = (R)(m0 + 1);
     // wx(m, n) and wy(m, n); zero where the numerator vanishes
-    auto wx = [&](float m, int n) {
-        if (m == 0.f) return 0.f;
-        const float den = (m * fly) * (m * fly) + ((float)n * flx) * ((float)n * flx);
+    auto wx = [&](R m, int n) {
+        if (m == R(0)) return R(0);
+        const R den = (m * fly) * (m * fly) + ((R)n * flx) * ((R)n * flx);
         return fly * inv_pi * m / den;
     };
-    auto wy = [&](float m, int n) {
-        if (n == 0) return 0.f;
-        const float den = (m * fly) * (m * fly) + ((float)n * flx) * ((float)n * flx);
-        return flx * inv_pi * (float)n / den;
+    auto wy = [&](R m, int n) {
+        if (n == 0) return R(0);
+        const R den = (m * fly) * (m * fly) + ((R)n * flx) * ((R)n * flx);
+        return flx * inv_pi * (R)n / den;
     };
 
     // a: plain DCT-III of the coefficients
     dct3_input(sa, N, tq, [&](int n) { return coef[n]; }, qs);
-    float2 *v = fft_lds(sa, sb, N, stw, true);
-    float *oa0 = pa + (int64_t)m0 * N, *oa1 = oa0 + N;
+    C *v = fft_lds(sa, sb, N, stw, true);
+    R *oa0 = pa + (int64_t)m0 * N, *oa1 = oa0 + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const float2 y = dct3_output(v, i, N);
+        const C y = dct3_output(v, i, N);
         oa0[i] = y.x;
         oa1[i] = y.y;
     }
     __syncthreads();
     // b: DCT-III of wx * coefficients
     dct3_input(sa, N, tq, [&](int n) {
-        const float2 c = coef[n];
-        return make_float2(wx(ma, n) * c.x, wx(mb, n) * c.y);
+        const C c = coef[n];
+        return mkc<C>(wx(ma, n) * c.x, wx(mb, n) * c.y);
     }, qs);
     v = fft_lds(sa, sb, N, stw, true);
-    float *ob0 = pb + (int64_t)m0 * N, *ob1 = ob0 + N;
+    R *ob0 = pb + (int64_t)m0 * N, *ob1 = ob0 + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const float2 y = dct3_output(v, i, N);
+        const C y = dct3_output(v, i, N);
         ob0[i] = y.x;
         ob1[i] = y.y;
     }
     __syncthreads();
     // c: DST-III of wy * coefficients = (-1)^j DCT-III of the reversed sequence
     dct3_input(sa, N, tq, [&](int mm) {
-        if (mm == 0) return make_float2(0.f, 0.f);
+        if (mm == 0) return mkc<C>(R(0), R(0));
         const int n = N - mm;
-        const float2 c = coef[n];
-        return make_float2(wy(ma, n) * c.x, wy(mb, n) * c.y);
+        const C c = coef[n];
+        return mkc<C>(wy(ma, n) * c.x, wy(mb, n) * c.y);
     }, qs);
     v = fft_lds(sa, sb, N, stw, true);
-    float *oc0 = pc + (int64_t)m0 * N, *oc1 = oc0 + N;
+    R *oc0 = pc + (int64_t)m0 * N, *oc1 = oc0 + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const float2 y = dct3_output(v, i, N);
-        const float s = (i & 1) ? -1.0f : 1.0f;
+        const C y = dct3_output(v, i, N);
+        const R s = (i & 1) ? R(-1) : R(1);
         oc0[i] = s * y.x;
         oc1[i] = s * y.y;
     }
 }
 
-__global__ __launch_bounds__(512) void k_col_pass(const float *__restrict__ t2, int lx, int ly,
-                                                  float sigma, const float2 *__restrict__ tw,
-                                                  const float2 *__restrict__ tq,
-                                                  float *__restrict__ pa, float *__restrict__ pb,
-                                                  float *__restrict__ pc)
+__global__ __launch_bounds__(512) void k_col_pass(const double *__restrict__ t2, int lx, int ly,
+                                                  float sigma, const double2 *__restrict__ tw,
+                                                  const double2 *__restrict__ tq,
+                                                  double *__restrict__ pa, double *__restrict__ pb,
+                                                  double *__restrict__ pc)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
-    col_pass_body(t2, 2 * blockIdx.x, lx, ly, sigma, tw, tq, 1, pa, pb, pc, sa, sb, coef, stw);
+    __shared__ double2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
+    col_pass_body<double>(t2, 2 * blockIdx.x, lx, ly, sigma, tw, tq, 1, pa, pb, pc, sa, sb, coef,
+                          stw);
 }
 
-// Row pass on rows j0, j1 = j0 + 1 of a, b, c [ly][lx]; writes the ghosted
-// float4 fields (J_x, J_y, rho_s, 0) (LDS: sa, sb, rs, jx of kMaxN and stw of
-// kMaxN / 2 float2).
-__device__ __forceinline__ void row_final_body(const float *__restrict__ pa, const float *__restrict__ pb,
-                               const float *__restrict__ pc, int j0, int lx, int ly,
-                               const float2 *__restrict__ tw, const float2 *__restrict__ tq,
-                               int qs, float4 *__restrict__ fields, int32_t *status, float2 *sa,
-                               float2 *sb, float2 *rs, float2 *jx, float2 *stw)
+// Row pass on rows j0, j1 = j0 + 1 of a, b, c [ly][lx] (precision R);
+// writes the ghosted FP32 float4 fields (J_x, J_y, rho_s, 0), each value
+// rounded once from R (LDS: sa, sb, rs, jx of kMaxN and stw of kMaxN / 2
+// complex).
+template <typename R>
+__device__ __forceinline__ void row_final_body(const R *__restrict__ pa, const R *__restrict__ pb,
+                                               const R *__restrict__ pc, int j0, int lx, int ly,
+                                               const cx<R> *__restrict__ tw,
+                                               const cx<R> *__restrict__ tq, int qs,
+                                               float4 *__restrict__ fields, int32_t *status,
+                                               cx<R> *sa, cx<R> *sb, cx<R> *rs, cx<R> *jx,
+                                               cx<R> *stw)
 {
+    using C = cx<R>;
     const int N = lx;
     load_twiddles(stw, tw, N, qs);
-    const float norm = 1.0f / ((float)lx * (float)ly);
+    const R norm = R(1) / ((R)lx * (R)ly);
 
-    const float *a0 = pa + (int64_t)j0 * N, *a1 = a0 + N;
-    dct3_input(sa, N, tq, [&](int m) { return make_float2(a0[m], a1[m]); }, qs);
-    float2 *v = fft_lds(sa, sb, N, stw, true);
+    const R *a0 = pa + (int64_t)j0 * N, *a1 = a0 + N;
+    dct3_input(sa, N, tq, [&](int m) { return mkc<C>(a0[m], a1[m]); }, qs);
+    C *v = fft_lds(sa, sb, N, stw, true);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const float2 y = dct3_output(v, i, N);
-        rs[i] = make_float2(y.x * norm, y.y * norm);
+        const C y = dct3_output(v, i, N);
+        rs[i] = mkc<C>(y.x * norm, y.y * norm);
     }
     __syncthreads();
-    const float *b0 = pb + (int64_t)j0 * N, *b1 = b0 + N;
+    const R *b0 = pb + (int64_t)j0 * N, *b1 = b0 + N;
     dct3_input(sa, N, tq, [&](int mm) {
-        if (mm == 0) return make_float2(0.f, 0.f);
-        return make_float2(b0[N - mm], b1[N - mm]);
+        if (mm == 0) return mkc<C>(R(0), R(0));
+        return mkc<C>(b0[N - mm], b1[N - mm]);
     }, qs);
     v = fft_lds(sa, sb, N, stw, true);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const float2 y = dct3_output(v, i, N);
-        const float s = (i & 1) ? -1.0f : 1.0f;
-        jx[i] = make_float2(s * y.x, s * y.y);
+        const C y = dct3_output(v, i, N);
+        const R s = (i & 1) ? R(-1) : R(1);
+        jx[i] = mkc<C>(s * y.x, s * y.y);
     }
     __syncthreads();
-    const float *c0 = pc + (int64_t)j0 * N, *c1 = c0 + N;
-    dct3_input(sa, N, tq, [&](int m) { return make_float2(c0[m], c1[m]); }, qs);
+    const R *c0 = pc + (int64_t)j0 * N, *c1 = c0 + N;
+    dct3_input(sa, N, tq, [&](int m) { return mkc<C>(c0[m], c1[m]); }, qs);
     v = fft_lds(sa, sb, N, stw, true);
 
     const int P = lx + 2;
     int bad = 0;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const float2 jy = dct3_output(v, i, N);
-        const float2 r = rs[i], x = jx[i];
-        bad |= !(r.x > 0.f) || !(r.y > 0.f);
-        const float4 f0 = make_float4(x.x, jy.x, r.x, 0.f);
-        const float4 f1 = make_float4(x.y, jy.y, r.y, 0.f);
+        const C jy = dct3_output(v, i, N);
+        const C r = rs[i], x = jx[i];
+        const float4 f0 = make_float4((float)x.x, (float)jy.x, (float)r.x, 0.f);
+        const float4 f1 = make_float4((float)x.y, (float)jy.y, (float)r.y, 0.f);
+        bad |= !(f0.z > 0.f) || !(f1.z > 0.f);
         float4 *row0 = fields + (int64_t)(j0 + 1) * P;
         float4 *row1 = row0 + P;
         row0[i + 1] = f0;
@@ -409,16 +464,16 @@ __device__ __forceinline__ void row_final_body(const float *__restrict__ pa, con
     if (bad) set_status(status, FFB_E_NONPOSITIVE);
 }
 
-__global__ __launch_bounds__(512) void k_row_final(const float *__restrict__ pa,
-                                                   const float *__restrict__ pb,
-                                                   const float *__restrict__ pc, int lx, int ly,
-                                                   const float2 *__restrict__ tw,
-                                                   const float2 *__restrict__ tq,
+__global__ __launch_bounds__(512) void k_row_final(const double *__restrict__ pa,
+                                                   const double *__restrict__ pb,
+                                                   const double *__restrict__ pc, int lx, int ly,
+                                                   const double2 *__restrict__ tw,
+                                                   const double2 *__restrict__ tq,
                                                    float4 *__restrict__ fields, int32_t *status)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
-    row_final_body(pa, pb, pc, 2 * blockIdx.x, lx, ly, tw, tq, 1, fields, status, sa, sb, rs, jx,
-                   stw);
+    __shared__ double2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
+    row_final_body<double>(pa, pb, pc, 2 * blockIdx.x, lx, ly, tw, tq, 1, fields, status, sa, sb,
+                           rs, jx, stw);
 }
 
 // Pack caller node arrays into the ghosted layout (same ghost rule).
@@ -677,12 +732,12 @@ __global__ __launch_bounds__(256) void kb_mean(batch_view bv, const double *__re
 }
 
 __global__ __launch_bounds__(512) void kb_dct2_rows(batch_view bv, const int2 *__restrict__ rows,
-                                                    const float *__restrict__ in,
-                                                    float *__restrict__ out,
-                                                    const float2 *__restrict__ tw,
-                                                    const float2 *__restrict__ tq)
+                                                    const double *__restrict__ in,
+                                                    double *__restrict__ out,
+                                                    const double2 *__restrict__ tw,
+                                                    const double2 *__restrict__ tq)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    __shared__ double2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
     const int2 e = rows[blockIdx.x];
     const int m = e.x;
     if (!bv.active[m]) return;
@@ -693,29 +748,29 @@ __global__ __launch_bounds__(512) void kb_dct2_rows(batch_view bv, const int2 *_
 
 // blockIdx.y selects the plane pair (in_k -> out_k).
 __global__ __launch_bounds__(256) void kb_transpose(batch_view bv, const int4 *__restrict__ tiles,
-                                                    bool rows_are_y, const float *in0,
-                                                    const float *in1, float *out0, float *out1)
+                                                    bool rows_are_y, const double *in0,
+                                                    const double *in1, double *out0, double *out1)
 {
-    __shared__ float tile[32][33];
+    __shared__ double tile[32][33];
     const int4 t = tiles[blockIdx.x];
     const int m = t.x;
     if (!bv.active[m]) return;
     const int R = rows_are_y ? bv.ly[m] : bv.lx[m];
     const int C = rows_are_y ? bv.lx[m] : bv.ly[m];
     const int64_t o = bv.plane_off[m];
-    const float *in = (blockIdx.y == 0 ? in0 : in1) + o;
-    float *out = (blockIdx.y == 0 ? out0 : out1) + o;
+    const double *in = (blockIdx.y == 0 ? in0 : in1) + o;
+    double *out = (blockIdx.y == 0 ? out0 : out1) + o;
     transpose_tile(in, out, R, C, t.y, t.z, tile);
 }
 
 __global__ __launch_bounds__(512) void kb_col_pass(batch_view bv, const int2 *__restrict__ cols,
-                                                   const float *__restrict__ t2,
-                                                   const float2 *__restrict__ tw,
-                                                   const float2 *__restrict__ tq,
-                                                   float *__restrict__ pa, float *__restrict__ pb,
-                                                   float *__restrict__ pc)
+                                                   const double *__restrict__ t2,
+                                                   const double2 *__restrict__ tw,
+                                                   const double2 *__restrict__ tq,
+                                                   double *__restrict__ pa, double *__restrict__ pb,
+                                                   double *__restrict__ pc)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
+    __shared__ double2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
     const int2 e = cols[blockIdx.x];
     const int m = e.x;
     if (!bv.active[m]) return;
@@ -727,14 +782,14 @@ __global__ __launch_bounds__(512) void kb_col_pass(batch_view bv, const int2 *__
 }
 
 __global__ __launch_bounds__(512) void kb_row_final(batch_view bv, const int2 *__restrict__ rows,
-                                                    const float *__restrict__ pa,
-                                                    const float *__restrict__ pb,
-                                                    const float *__restrict__ pc,
-                                                    const float2 *__restrict__ tw,
-                                                    const float2 *__restrict__ tq,
+                                                    const double *__restrict__ pa,
+                                                    const double *__restrict__ pb,
+                                                    const double *__restrict__ pc,
+                                                    const double2 *__restrict__ tw,
+                                                    const double2 *__restrict__ tq,
                                                     float4 *__restrict__ fields, int32_t *status)
 {
-    __shared__ float2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
+    __shared__ double2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
     const int2 e = rows[blockIdx.x];
     const int m = e.x;
     if (!bv.active[m]) return;
@@ -881,6 +936,23 @@ __global__ __launch_bounds__(512) void kd_row(const diff_ctl *__restrict__ ctl,
                    fields + (int64_t)z * (lx + 2) * (ly + 2), status, sa, sb, rs, jx, stw);
 }
 
+// The FP64 transform tables on the device (same definitions as the host
+// tables of a context): tw[k] = exp(-2 pi i k / N), k < N/2, and
+// tq[m] = exp(-i pi m / (2N)), m < N.
+__global__ __launch_bounds__(256) void k_twiddles(int N, double2 *__restrict__ tw,
+                                                  double2 *__restrict__ tq)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= N) return;
+    double sn, cs;
+    if (k < N / 2) {
+        sincospi(2.0 * k / N, &sn, &cs);
+        tw[k] = make_double2(cs, -sn);
+    }
+    sincospi(k / (2.0 * N), &sn, &cs);
+    tq[k] = make_double2(cs, -sn);
+}
+
 inline int threads_for(int N)
 {
     int t = N / 2;
@@ -891,26 +963,43 @@ inline int threads_for(int N)
 
 }  // namespace
 
-hipError_t launch_flux(ffb_ctx *ctx, const float *rho, float sigma, float4 *fields,
-                       double *rho_bar)
+hipError_t launch_flux_ws(hipStream_t s, int lx, int ly, const flux_ws &w, const double *rho,
+                          float sigma, float4 *fields, double *rho_bar, int32_t *status)
 {
-    hipStream_t s = ctx->stream;
-    const int lx = ctx->lx, ly = ctx->ly;
     const int64_t n = (int64_t)lx * ly;
     // row DCTs, with the FP64 sums of each row pair for the mean density
-    hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, ctx->t1, lx,
-                       ctx->tw_x, ctx->tq_x, ctx->red);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, ctx->red, ly / 2,
-                       1.0 / (double)n, rho_bar, ctx->d_status);
-    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
-                       ctx->t1, ctx->t1, ctx->t1, ctx->t2, ctx->t2, ctx->t2, ly, lx);
-    hipLaunchKernelGGL(k_col_pass, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t2, lx, ly,
-                       sigma, ctx->tw_y, ctx->tq_y, ctx->pa, ctx->pb, ctx->pc);
+    hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, w.t1, lx,
+                       w.tw_x, w.tq_x, w.red);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, w.red, ly / 2, 1.0 / (double)n,
+                       rho_bar, status);
+    hipLaunchKernelGGL(k_transpose<double>, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256),
+                       0, s, w.t1, w.t1, w.t1, w.t2, w.t2, w.t2, ly, lx);
+    hipLaunchKernelGGL(k_col_pass, dim3(lx / 2), dim3(threads_for(ly)), 0, s, w.t2, lx, ly,
+                       sigma, w.tw_y, w.tq_y, w.pa, w.pb, w.pc);
     // [lx][ly] -> [ly][lx]: a, b, c into the free planes t1, t2, t3 (one launch)
-    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 3), dim3(256), 0, s,
-                       ctx->pa, ctx->pb, ctx->pc, ctx->t1, ctx->t2, ctx->t3, lx, ly);
-    hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->t1, ctx->t2,
-                       ctx->t3, lx, ly, ctx->tw_x, ctx->tq_x, fields, ctx->d_status);
+    hipLaunchKernelGGL(k_transpose<double>, dim3((ly + 31) / 32, (lx + 31) / 32, 3), dim3(256),
+                       0, s, w.pa, w.pb, w.pc, w.t1, w.t2, w.t3, lx, ly);
+    hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, w.t1, w.t2, w.t3,
+                       lx, ly, w.tw_x, w.tq_x, fields, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux(ffb_ctx *ctx, const double *rho, float sigma, float4 *fields,
+                       double *rho_bar)
+{
+    // the context's planes are sized for FP64
+    double *pl[6] = {reinterpret_cast<double *>(ctx->t1), reinterpret_cast<double *>(ctx->t2),
+                     reinterpret_cast<double *>(ctx->t3), reinterpret_cast<double *>(ctx->pa),
+                     reinterpret_cast<double *>(ctx->pb), reinterpret_cast<double *>(ctx->pc)};
+    flux_ws w{ctx->tw64_x, ctx->tq64_x, ctx->tw64_y, ctx->tq64_y, pl[0], pl[1],
+              pl[2],       pl[3],       pl[4],       pl[5],       ctx->red};
+    return launch_flux_ws(ctx->stream, ctx->lx, ctx->ly, w, rho, sigma, fields, rho_bar,
+                          ctx->d_status);
+}
+
+hipError_t launch_twiddles(hipStream_t s, int N, double2 *tw, double2 *tq)
+{
+    hipLaunchKernelGGL(k_twiddles, dim3((N + 255) / 256), dim3(256), 0, s, N, tw, tq);
     return hipGetLastError();
 }
 
@@ -925,14 +1014,14 @@ hipError_t launch_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy,
     return hipGetLastError();
 }
 
-hipError_t launch_diff_spectrum(ffb_ctx *ctx, const float *rho, float sigma, float *spec)
+hipError_t launch_diff_spectrum(ffb_ctx *ctx, const double *rho, float sigma, float *spec)
 {
     hipStream_t s = ctx->stream;
     const int lx = ctx->lx, ly = ctx->ly;
-    hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, ctx->t1, lx,
-                       ctx->tw_x, ctx->tq_x, nullptr);
-    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0, s,
-                       ctx->t1, ctx->t1, ctx->t1, ctx->t2, ctx->t2, ctx->t2, ly, lx);
+    hipLaunchKernelGGL(k_dct2_rows_f32, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, ctx->t1,
+                       lx, ctx->tw_x, ctx->tq_x);
+    hipLaunchKernelGGL(k_transpose<float>, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256), 0,
+                       s, ctx->t1, ctx->t1, ctx->t1, ctx->t2, ctx->t2, ctx->t2, ly, lx);
     hipLaunchKernelGGL(kd_spectrum, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t2, lx, ly,
                        sigma, ctx->tw_y, ctx->tq_y, spec);
     return hipGetLastError();
@@ -963,23 +1052,23 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
     hipLaunchKernelGGL(k_adj_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, lx, ctx->tw_x,
                        ctx->tq_x, ctx->pa, ctx->pb, ctx->pc);
     // [ly][lx] -> [lx][ly], the three planes in one launch
-    hipLaunchKernelGGL(k_transpose, dim3((lx + 31) / 32, (ly + 31) / 32, 3), dim3(256), 0, s,
-                       ctx->pa, ctx->pb, ctx->pc, ctx->t1, ctx->t2, ctx->t3, ly, lx);
+    hipLaunchKernelGGL(k_transpose<float>, dim3((lx + 31) / 32, (ly + 31) / 32, 3), dim3(256), 0,
+                       s, ctx->pa, ctx->pb, ctx->pc, ctx->t1, ctx->t2, ctx->t3, ly, lx);
     hipLaunchKernelGGL(k_adj_cols, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t1, ctx->t2,
                        ctx->t3, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->pb);
     // [lx][ly] -> [ly][lx]
-    hipLaunchKernelGGL(k_transpose, dim3((ly + 31) / 32, (lx + 31) / 32, 1), dim3(256), 0, s,
-                       ctx->pb, ctx->pb, ctx->pb, ctx->pc, ctx->pc, ctx->pc, lx, ly);
+    hipLaunchKernelGGL(k_transpose<float>, dim3((ly + 31) / 32, (lx + 31) / 32, 1), dim3(256), 0,
+                       s, ctx->pb, ctx->pb, ctx->pb, ctx->pc, ctx->pc, ctx->pc, lx, ly);
     hipLaunchKernelGGL(k_adj_rows_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->pc, lx,
                        ctx->tw_x, ctx->tq_x, lam_rho);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
-                             const batch_fft_plan &plan, const float2 *tw1024,
-                             const float2 *tq1024, float *rho, const double *acc, float *t1,
-                             float *t2, float *pa, float *pb, float *pc, float4 *fields,
-                             double *rho_bar, int32_t *status)
+                             const batch_fft_plan &plan, const double2 *tw1024,
+                             const double2 *tq1024, const double *rho, const double *acc,
+                             double *t1, double *t2, double *pa, double *pb, double *pc,
+                             float4 *fields, double *rho_bar, int32_t *status)
 {
     hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, s, bv, acc, rho_bar, status);
     for (int c = 0; c < plan.n_classes; ++c) {

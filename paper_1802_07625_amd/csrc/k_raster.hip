@@ -266,11 +266,11 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
     run_add(acc, key, va, vb);
 }
 
-// rho[j][i] = rho_pad + inclusive prefix sum of acc[j][0..i] (FP64), one row
-// per workgroup, contiguous chunks per lane.
+// rho[j][i] = rho_pad + inclusive prefix sum of acc[j][0..i] (FP64, stored
+// in FP64), one row per workgroup, contiguous chunks per lane.
 __global__ __launch_bounds__(kScanThreads) void k_raster_scan(
     const double *__restrict__ acc, int32_t lx, const double *__restrict__ rho_pad,
-    float *__restrict__ rho)
+    double *__restrict__ rho)
 {
     __shared__ double part[kScanThreads];
     const int32_t j = blockIdx.x;
@@ -290,10 +290,10 @@ __global__ __launch_bounds__(kScanThreads) void k_raster_scan(
         __syncthreads();
     }
     double run = part[threadIdx.x] - s + *rho_pad;
-    float *out = rho + (int64_t)j * lx;
+    double *out = rho + (int64_t)j * lx;
     for (int32_t i = beg; i < end; ++i) {
         run += row[i];
-        out[i] = (float)run;
+        out[i] = run;
     }
 }
 
@@ -355,13 +355,13 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
 }
 
 // Row prefix sums of every active map, one workgroup per (map, row).  The
-// FP64 sum of the row's stored FP32 densities (fixed order: each lane's
+// FP64 sum of the row's densities (fixed order: each lane's
 // cells in order, then a tree over the lanes) goes to the row's spare last
 // slot acc[j][lx], which the deposits may have touched but the prefix sum
 // never reads; kb_mean turns the row sums into the map's mean density.
 __global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
     batch_view bv, const int2 *__restrict__ rows, double *__restrict__ acc,
-    const double *__restrict__ rho_pad, float *__restrict__ rho)
+    const double *__restrict__ rho_pad, double *__restrict__ rho)
 {
     __shared__ double part[kScanThreads];
     const int2 e = rows[blockIdx.x];
@@ -383,13 +383,12 @@ __global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
         __syncthreads();
     }
     double run = part[threadIdx.x] - s + rho_pad[m];
-    float *out = rho + bv.plane_off[m] + (int64_t)j * lx;
+    double *out = rho + bv.plane_off[m] + (int64_t)j * lx;
     double stored = 0.0;
     for (int32_t i = beg; i < end; ++i) {
         run += row[i];
-        const float v = (float)run;
-        out[i] = v;
-        stored += (double)v;
+        out[i] = run;
+        stored += run;
     }
     __syncthreads();
     part[threadIdx.x] = stored;
@@ -412,7 +411,7 @@ hipError_t launch_density_weights(ffb_ctx *ctx, int32_t R, const double *value,
 }
 
 hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                          const double *area, float *rho, double *rho_pad)
+                          const double *area, double *rho, double *rho_pad)
 {
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_density_prep, dim3(1), dim3(kPrepThreads), 0, s, value, area,
@@ -439,7 +438,7 @@ hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *val
 hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                                 const ffb_geometry *g, const double *value, const double *area,
                                 double *w_region, double *rho_pad, double *acc, int64_t acc_total,
-                                float *rho, int32_t *status)
+                                double *rho, int32_t *status)
 {
     hipLaunchKernelGGL(kb_density_prep, dim3(bv.n_maps), dim3(kPrepThreads), 0, s, bv, value,
                        area, w_region, rho_pad, status);

@@ -30,7 +30,7 @@ def _interior(fields, lx, ly):
 def _raster(m):
     a = oracle.region_areas(m)
     rho, _ = oracle.density(m, m.value, a)
-    return rho.astype(np.float32)
+    return rho
 
 
 @pytest.mark.parametrize("name,sigma", [("c1_L64", 4.0), ("rect_128x64", 2.0), ("c2_L512", 4.0)])
@@ -38,11 +38,11 @@ def _raster(m):
 def test_fields_match_oracle(name, sigma, t):
     m = synth.workload(name)
     rho = _raster(m)
-    coef, rb = oracle.coefficients(rho.astype(np.float64), sigma)
+    coef, rb = oracle.coefficients(rho, sigma)
     F = oracle.diffusion_fields(coef, t)
     ctx = new_ctx(m.lx, m.ly)
     print(f"[diffusion] fields {name} sigma={sigma} t={t}", flush=True)
-    fields = ctx.diffusion_fields(dev_f32(rho), sigma, t)
+    fields = ctx.diffusion_fields(dev_f64(rho), sigma, t)
     assert ctx.sync(check=False) == 0
     jx, jy, r = _interior(fields, m.lx, m.ly)
     for got, ref, what in ((jx, F.jx, "jx"), (jy, F.jy, "jy"), (r, F.rho_s, "rho")):
@@ -53,16 +53,20 @@ def test_fields_match_oracle(name, sigma, t):
 
 
 def test_time_zero_density_equals_main_method_full_size():
+    """At t = 0 the diffusion density is the blurred density of the main
+    method (ffb_flux, FP64 transforms rounded once); the diffusion fields
+    come from FP32 transforms, so the two agree to their rounding: 1e-6 of
+    the largest density."""
     m = synth.workload("c3_L1024")
     rng = np.random.default_rng(0)
-    rho = dev_f32(rng.lognormal(0.0, 1.0, (m.ly, m.lx)))
+    rho = dev_f64(rng.lognormal(0.0, 1.0, (m.ly, m.lx)))
     ctx = new_ctx(m.lx, m.ly)
     f_ffb, _ = ctx.flux(rho, 4.0)
     f_diff = ctx.diffusion_fields(rho, 4.0, 0.0)
     assert ctx.sync(check=False) == 0
-    a = to_np(f_ffb).reshape(m.ly + 2, m.lx + 2, 4)[..., 2]
-    b = to_np(f_diff).reshape(m.ly + 2, m.lx + 2, 4)[..., 2]
-    np.testing.assert_array_equal(a, b)
+    a = to_np(f_ffb).reshape(m.ly + 2, m.lx + 2, 4)[..., 2].astype(np.float64)
+    b = to_np(f_diff).reshape(m.ly + 2, m.lx + 2, 4)[..., 2].astype(np.float64)
+    np.testing.assert_allclose(b, a, rtol=0, atol=1e-6 * np.abs(a).max())
 
 
 def _gpu_round(m, pts, sigma, replay=None, opts=None):
@@ -157,7 +161,7 @@ def test_graph_equals_direct_launches():
 
 def test_repeated_calls_and_ragged_point_counts():
     m = synth.workload("c1_L64")
-    rho = dev_f32(_raster(m))
+    rho = dev_f64(_raster(m))
     ctx = new_ctx(m.lx, m.ly, 1000)
     base = map_points(m)
     res, sched = [], None
@@ -179,7 +183,7 @@ def test_repeated_calls_and_ragged_point_counts():
 
 def test_errors():
     m = synth.workload("c1_L64")
-    rho = dev_f32(_raster(m))
+    rho = dev_f64(_raster(m))
     ctx = new_ctx(m.lx, m.ly, 100)
     d0 = torch.as_tensor(map_points(m)[:100].copy(), device="cuda")
     # too few attempts: status in stats and the sticky word, points unchanged

@@ -196,9 +196,9 @@ def test_points_outside_box_and_errors():
     assert code == ffb.api.FFB_E_MAX_ATTEMPTS
     ctx.reset_status()
     # a sticky status from an earlier call stops the integration untouched
-    bad = np.ones((64, 64), np.float32)
+    bad = np.ones((64, 64))
     bad[:8, :8] = -50
-    ctx.flux(dev_f32(bad), 0.0)
+    ctx.flux(dev_f64(bad), 0.0)
     got, st, _, code = _gpu_integrate(ctx, fields, rb, q)
     assert code == ffb.api.FFB_E_NONPOSITIVE
     np.testing.assert_array_equal(got, q.astype(np.float64))

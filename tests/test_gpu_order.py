@@ -129,7 +129,7 @@ def test_kept_order_over_rounds_equals_given_order():
     over one array give the bits of three rounds in the caller's order."""
     import paper_1802_07625_amd as ffb
     import torch
-    from gpu_util import dev_f32, new_ctx, stats_of, to_np
+    from gpu_util import dev_f32, dev_f64, new_ctx, stats_of, to_np
     L, n = 1024, 70000
     ii = (np.arange(L) + 0.5) / L
     rho = 1.0 + 0.6 * np.outer(np.sin(3.1 * ii) ** 2, np.cos(2.3 * ii) ** 2)
@@ -142,7 +142,7 @@ def test_kept_order_over_rounds_equals_given_order():
         xy = dev_f32(pts)
         rounds = []
         for sigma in (8.0, 4.0, 2.0):
-            fields, rb = ctx.flux(dev_f32(rho * (1.0 + sigma / 16.0)), sigma)
+            fields, rb = ctx.flux(dev_f64(rho * (1.0 + sigma / 16.0)), sigma)
             stats, h = ctx.integrate(fields, rb, xy, ffb.IntegrateOpts())
             assert ctx.sync(check=False) == 0
             st = stats_of(stats)
@@ -168,7 +168,7 @@ def test_option_values():
 
 def test_diffusion_sorted_equals_given_order_bitwise():
     import paper_1802_07625_amd as ffb
-    from gpu_util import dev_f32, new_ctx, stats_of, to_np
+    from gpu_util import dev_f32, dev_f64, new_ctx, stats_of, to_np
     m = synth.workload("c1_L64")
     rho, _ = oracle.density(m, m.value, oracle.region_areas(m))
     pts = _clouds(64, 5000, 5)
@@ -177,7 +177,7 @@ def test_diffusion_sorted_equals_given_order_bitwise():
     for order in (0, 2):
         ctx.set_option(ffb.OPT_POINT_ORDER, order)
         xy = dev_f32(pts)
-        stats, h = ctx.diffusion(dev_f32(rho), 4.0, xy)
+        stats, h = ctx.diffusion(dev_f64(rho), 4.0, xy)
         assert ctx.sync(check=False) == 0
         st = stats_of(stats)
         out.append((to_np(xy), st, to_np(h)[:st["accepted"]]))

@@ -2,10 +2,12 @@
 density, flux, advection, areas) against the oracle doing every step in FP64
 from the same FP32 input map.
 
-Here the two sides compute their own fields, so the GPU's FP32 transforms
-(field error <= 1e-5 of the field scale, see test_gpu_flux) enter the
-velocities.  With the oracle's step schedule replayed, positions (vertices
-and grid nodes) agree within the stated 1e-4 grid units.  The stated 1e-6
+Here the two sides compute their own density grids and fields: the GPU's
+density grid and transforms are FP64 and its fields are the FP64 values
+rounded once to FP32 (see test_gpu_flux), so the velocities differ from the
+oracle's by that rounding and the integration's FP32 arithmetic.  With the
+oracle's step schedule replayed, positions (vertices and grid nodes) agree
+within the stated 1e-4 grid units.  The stated 1e-6
 relative tolerance for areas applies to the area kernel on identical
 vertices (test_gpu_geometry, met at 1e-12); after a round the vertices
 differ by up to the position difference dx, which moves a region's area by
@@ -49,7 +51,7 @@ def test_one_iteration_replayed(name):
     s = stats_of(stats)
     assert s["accepted"] == ref.accepted
     np.testing.assert_allclose(to_np(area0), ref.area_before, rtol=1e-12)
-    np.testing.assert_allclose(to_np(rho), ref.rho, rtol=0, atol=1e-5 * np.abs(ref.rho).max())
+    np.testing.assert_allclose(to_np(rho), ref.rho, rtol=0, atol=1e-11 * np.abs(ref.rho).max())
     assert float(rb) == pytest.approx(ref.fields.rho_bar, rel=1e-6)
     dx = np.abs(to_np(d).astype(np.float64) - ref.points).max()
     de = np.abs(to_np(err1) - ref.err_after).max()
@@ -94,7 +96,7 @@ def test_c3_round_end_to_end():
     """The headline configuration (L = 1024, 600 regions, 1.0 M vertices +
     1024^2 grid nodes): both sides run a whole round on their own from the
     same FP32 map -- areas, density, flux, integration, areas -- so the
-    GPU's FP32 field error travels through the full C3 flow.  The oracle
+    GPU's field rounding travels through the full C3 flow.  The oracle
     integrates all 2.05 M points with its own adaptive controller; the GPU
     replays the oracle's accepted steps, and every point is compared."""
     import paper_1802_07625_amd as ffb
@@ -112,7 +114,7 @@ def test_c3_round_end_to_end():
     assert ctx.sync(check=False) == 0
     assert stats_of(stats)["accepted"] == ref.accepted
     np.testing.assert_allclose(to_np(area0), ref.area_before, rtol=1e-12)
-    np.testing.assert_allclose(to_np(rho), ref.rho, rtol=0, atol=1e-5 * np.abs(ref.rho).max())
+    np.testing.assert_allclose(to_np(rho), ref.rho, rtol=0, atol=1e-11 * np.abs(ref.rho).max())
     got = to_np(d).astype(np.float64)
     dxv = np.abs(got[:V] - ref.points[:V]).max()
     dxn = np.abs(got[V:] - ref.points[V:]).max()
