@@ -7,8 +7,10 @@ fallback: if the library is not built, importing the binding fails.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -60,6 +62,30 @@ class FFBBatchOpts(ctypes.Structure):
 
 
 _lib = None
+
+# Contexts and batches still open when the interpreter exits are closed by
+# an exit hook, while the HIP runtime, torch and any profiler attached to the
+# process are all still up; otherwise their streams, graph executables and
+# device memory would be released by __del__ during interpreter teardown, in
+# whatever order the collector picks, or not at all before the runtime's own
+# teardown at exit().
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    live = list(_LIVE)
+    if not live:
+        return
+    try:
+        torch.cuda.synchronize()
+    except Exception:
+        pass
+    for obj in live:
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -402,6 +428,7 @@ class Context:
         self.lx, self.ly = int(lx), int(ly)
         self.device = torch.device(device)
         self.handle = ffb_create(lx, ly, max_points, stream)
+        _LIVE.add(self)
         # the record references the ring arrays of the geometries it saw
         # (the library keeps pointers, not copies): hold them while it exists
         self._recording = False
@@ -745,6 +772,7 @@ class Batch:
         if code != FFB_OK:
             raise FFBError(code, "ffb_batch_create")
         self.handle = h
+        _LIVE.add(self)
 
     def _check(self, code, what):
         if code != FFB_OK:
