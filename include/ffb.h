@@ -69,7 +69,8 @@ enum {
     FFB_E_STEP_UNDERFLOW = 6,   /* adaptive step fell below h_min           */
     FFB_E_NONFINITE = 7,        /* NaN or Inf in coordinates or velocities  */
     FFB_E_NO_TAPE = 8,          /* backward without a complete record       */
-    FFB_E_MAX_ATTEMPTS = 9      /* integration used up max_attempts         */
+    FFB_E_MAX_ATTEMPTS = 9,     /* integration used up max_attempts         */
+    FFB_E_TOO_LARGE = 10        /* size beyond a fixed workspace's maximum  */
 };
 
 /* Polygon geometry in CSR-ring form over unique vertices (a region is one or
@@ -199,6 +200,23 @@ int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
  * across y edges, rho_s even).  rho_bar (out, [1], FP64) = mean of rho.
  * min rho_s <= 0 gives FFB_E_NONPOSITIVE on the device. */
 int ffb_flux(ffb_ctx *ctx, const double *rho, float sigma, float *fields, double *rho_bar);
+
+/* ffb_flux for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and output as ffb_flux, with no context.  lx, ly: powers
+ * of two in [8, 512] (FFB_E_TOO_LARGE above 512, FFB_E_INVALID otherwise);
+ * rho (in, [ly][lx] FP64), fields (out, ghosted layout as ffb_flux),
+ * rho_bar (out, [1] FP64), status (in/out, [1] int32, device): a sticky
+ * status word the call sets to FFB_E_NONPOSITIVE if min rho_s <= 0 (the
+ * caller clears it); hip_stream: the stream to enqueue on (the current
+ * device must be the stream's).  The transform workspace (about 12.7 MB) is
+ * a fixed device array of the library, one per device, looked up on the
+ * first call on a device; the call allocates nothing.  Calls that overlap
+ * on one device (several streams or host threads) race on that array.
+ * Returns FFB_E_INVALID for NULL pointers, bad sizes or sigma, and
+ * FFB_E_DEVICE for a launch failure. */
+int ffb_flux_noalloc(int32_t lx, int32_t ly, const double *rho, float sigma, float *fields,
+                     double *rho_bar, int32_t *status, void *hip_stream);
 
 /* Pack node arrays jx, jy, rho_s ([ly][lx] each, in) into the ghosted
  * float4 field layout of ffb_flux (out, [(ly+2)][(lx+2)][4]). */

@@ -16,6 +16,6 @@ from .api import (  # noqa: F401
     ffb_tape_begin, ffb_tape_end, ffb_tape_clear, ffb_tape_generation, ffb_tape_check,
     ffb_backward, FFBFunction,
     FFB_OK, FFB_E_INVALID, FFB_E_NOMEM, FFB_E_DEVICE, FFB_E_NONPOSITIVE, FFB_E_DOMAIN,
-    FFB_E_STEP_UNDERFLOW, FFB_E_NONFINITE, FFB_E_NO_TAPE, FFB_E_MAX_ATTEMPTS,
+    FFB_E_STEP_UNDERFLOW, FFB_E_NONFINITE, FFB_E_NO_TAPE, FFB_E_MAX_ATTEMPTS, FFB_E_TOO_LARGE,
     Batch, BatchOpts, ffb_distortion, ffb_inverse,
 )

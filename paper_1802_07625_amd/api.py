@@ -23,6 +23,7 @@ STATUS = {
     0: "FFB_OK", 1: "FFB_E_INVALID", 2: "FFB_E_NOMEM", 3: "FFB_E_DEVICE",
     4: "FFB_E_NONPOSITIVE", 5: "FFB_E_DOMAIN", 6: "FFB_E_STEP_UNDERFLOW",
     7: "FFB_E_NONFINITE", 8: "FFB_E_NO_TAPE", 9: "FFB_E_MAX_ATTEMPTS",
+    10: "FFB_E_TOO_LARGE",
 }
 globals().update({name: code for code, name in STATUS.items()})
 
@@ -107,6 +108,7 @@ def lib():
         L.ffb_area_error.argtypes = [vp, G, vp, vp, vp, vp]
         L.ffb_density.argtypes = [vp, G, vp, vp, vp, vp]
         L.ffb_flux.argtypes = [vp, vp, ctypes.c_float, vp, vp]
+        L.ffb_flux_noalloc.argtypes = [i32, i32, vp, ctypes.c_float, vp, vp, vp, vp]
         L.ffb_pack_fields.argtypes = [vp, vp, vp, vp, vp]
         L.ffb_integrate.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(FFBIntegrateOpts),
                                     vp, vp, i32]
