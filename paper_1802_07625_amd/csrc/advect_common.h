@@ -148,6 +148,47 @@ __device__ inline float2 velocity(const Field &F, const Axis &ax, const Axis &ay
     return make_float2(fmaf(b, xr1 - xr0, xr0), fmaf(b, yr1 - yr0, yr0));
 }
 
+// h * v as velocity(), with the stage position given in the point's frame
+// (tx = frl + offset, ty likewise, not yet clamped) and B the node index of
+// the cell of the point's integer part (ghost offset included): the cell of
+// a stage is B + floor(ty) pitch + floor(tx), clamped once more as an
+// unsigned index so that no input reaches outside the fields.
+__device__ inline float2 velocity_at(const Field &F, const Axis &ax, const Axis &ay, int B,
+                                     float tx, float ty, float omh, float tbh, CellCache &cc)
+{
+    tx = __builtin_amdgcn_fmed3f(tx, ax.lo_t, ax.hi_t);
+    ty = __builtin_amdgcn_fmed3f(ty, ay.lo_t, ay.hi_t);
+    const int fx = floor_to_int(tx), fy = floor_to_int(ty);
+    const float a = __builtin_amdgcn_fractf(tx), b = __builtin_amdgcn_fractf(ty);
+    const int base = (int)min((uint32_t)(__mul24(fy, F.pitch) + (B + fx)), F.max_base);
+    if (base != cc.key) {
+        cc.key = base;
+        const uint32_t off = 16u * (uint32_t)base;
+        cc.c00 = ld3(F, off, 0);
+        cc.c10 = ld3(F, off + 16u, 0);
+        cc.c01 = ld3(F, off, F.row_bytes);
+        cc.c11 = ld3(F, off + 16u, F.row_bytes);
+    }
+    const float r00 = __builtin_amdgcn_rcpf(fmaf(cc.c00.z, omh, tbh));
+    const float r10 = __builtin_amdgcn_rcpf(fmaf(cc.c10.z, omh, tbh));
+    const float r01 = __builtin_amdgcn_rcpf(fmaf(cc.c01.z, omh, tbh));
+    const float r11 = __builtin_amdgcn_rcpf(fmaf(cc.c11.z, omh, tbh));
+    const float x00 = cc.c00.x * r00, x10 = cc.c10.x * r10;
+    const float x01 = cc.c01.x * r01, x11 = cc.c11.x * r11;
+    const float y00 = cc.c00.y * r00, y10 = cc.c10.y * r10;
+    const float y01 = cc.c01.y * r01, y11 = cc.c11.y * r11;
+    const float xr0 = fmaf(a, x10 - x00, x00), xr1 = fmaf(a, x11 - x01, x01);
+    const float yr0 = fmaf(a, y10 - y00, y00), yr1 = fmaf(a, y11 - y01, y01);
+    return make_float2(fmaf(b, xr1 - xr0, xr0), fmaf(b, yr1 - yr0, yr0));
+}
+
+// Node index of the cell holding the point's integer part (ghost offset
+// included), the base of velocity_at's cell arithmetic.
+__device__ inline int cell_base(const Axis &ax, const Axis &ay, int pitch)
+{
+    return __mul24(ay.ifl, pitch) + ax.ifl + (pitch + 1);
+}
+
 // x^(-1/5) for x > 0, to a few ulp: a single-precision estimate refined by
 // two Newton steps on y^-5 = x, y <- y (6 - x y^5) / 5, each of which about
 // squares the relative error (1e-7, 1e-14, then rounding level).  The chain

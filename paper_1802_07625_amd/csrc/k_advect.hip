@@ -196,32 +196,35 @@ enum StateMode {
     kLdsRecompute = 2,  // (hi, lo) in LDS, first-stage velocity recomputed
 };
 
-// The six new stages of one attempt for one point, from q1 = h k1.  Returns
-// the order-5 increment (ix, iy), q7 = h k7 and the error estimate (ex, ey).
-__device__ inline void dp_stages(const Field &F, const Axis &ax, const Axis &ay, float2 q1,
+// The six new stages of one attempt for one point, from q1 = h k1.  Stage
+// positions are formed in the point's frame with the in-cell fraction folded
+// into the stage sums.  Returns the order-5 increment (ix, iy), q7 = h k7
+// and the error estimate (ex, ey).
+__device__ inline void dp_stages(const Field &F, const Axis &ax, const Axis &ay, int B, float2 q1,
                                  const float *omh, const float *tbh, CellCache &cc, float &ix,
                                  float &iy, float2 &q7, float &ex, float &ey)
 {
-    float dx, dy;
-    dx = A21 * q1.x;
-    dy = A21 * q1.y;
-    const float2 q2 = velocity(F, ax, ay, dx, dy, omh[1], tbh[1], cc);
-    dx = fmaf(A32, q2.x, A31 * q1.x);
-    dy = fmaf(A32, q2.y, A31 * q1.y);
-    const float2 q3 = velocity(F, ax, ay, dx, dy, omh[2], tbh[2], cc);
-    dx = fmaf(A43, q3.x, fmaf(A42, q2.x, A41 * q1.x));
-    dy = fmaf(A43, q3.y, fmaf(A42, q2.y, A41 * q1.y));
-    const float2 q4 = velocity(F, ax, ay, dx, dy, omh[3], tbh[3], cc);
-    dx = fmaf(A54, q4.x, fmaf(A53, q3.x, fmaf(A52, q2.x, A51 * q1.x)));
-    dy = fmaf(A54, q4.y, fmaf(A53, q3.y, fmaf(A52, q2.y, A51 * q1.y)));
-    const float2 q5 = velocity(F, ax, ay, dx, dy, omh[4], tbh[4], cc);
-    dx = fmaf(A65, q5.x, fmaf(A64, q4.x, fmaf(A63, q3.x, fmaf(A62, q2.x, A61 * q1.x))));
-    dy = fmaf(A65, q5.y, fmaf(A64, q4.y, fmaf(A63, q3.y, fmaf(A62, q2.y, A61 * q1.y))));
-    const float2 q6 = velocity(F, ax, ay, dx, dy, omh[5], tbh[5], cc);
+    const float fx = ax.frl, fy = ay.frl;
+    const float2 q2 = velocity_at(F, ax, ay, B, fmaf(A21, q1.x, fx), fmaf(A21, q1.y, fy), omh[1],
+                                  tbh[1], cc);
+    const float2 q3 = velocity_at(F, ax, ay, B, fmaf(A32, q2.x, fmaf(A31, q1.x, fx)),
+                                  fmaf(A32, q2.y, fmaf(A31, q1.y, fy)), omh[2], tbh[2], cc);
+    const float2 q4 = velocity_at(
+        F, ax, ay, B, fmaf(A43, q3.x, fmaf(A42, q2.x, fmaf(A41, q1.x, fx))),
+        fmaf(A43, q3.y, fmaf(A42, q2.y, fmaf(A41, q1.y, fy))), omh[3], tbh[3], cc);
+    const float2 q5 = velocity_at(
+        F, ax, ay, B, fmaf(A54, q4.x, fmaf(A53, q3.x, fmaf(A52, q2.x, fmaf(A51, q1.x, fx)))),
+        fmaf(A54, q4.y, fmaf(A53, q3.y, fmaf(A52, q2.y, fmaf(A51, q1.y, fy)))), omh[4], tbh[4],
+        cc);
+    const float2 q6 = velocity_at(
+        F, ax, ay, B,
+        fmaf(A65, q5.x, fmaf(A64, q4.x, fmaf(A63, q3.x, fmaf(A62, q2.x, fmaf(A61, q1.x, fx))))),
+        fmaf(A65, q5.y, fmaf(A64, q4.y, fmaf(A63, q3.y, fmaf(A62, q2.y, fmaf(A61, q1.y, fy))))),
+        omh[5], tbh[5], cc);
     // order-5 increment (weights of the last stage row; the k2 weight is 0)
     ix = fmaf(B6, q6.x, fmaf(B5, q5.x, fmaf(B4, q4.x, fmaf(B3, q3.x, B1 * q1.x))));
     iy = fmaf(B6, q6.y, fmaf(B5, q5.y, fmaf(B4, q4.y, fmaf(B3, q3.y, B1 * q1.y))));
-    q7 = velocity(F, ax, ay, ix, iy, omh[6], tbh[6], cc);
+    q7 = velocity_at(F, ax, ay, B, fx + ix, fy + iy, omh[6], tbh[6], cc);
     ex = fmaf(E7, q7.x, fmaf(E6, q6.x, fmaf(E5, q5.x, fmaf(E4, q4.x, fmaf(E3, q3.x, E1 * q1.x)))));
     ey = fmaf(E7, q7.y, fmaf(E6, q6.y, fmaf(E5, q5.y, fmaf(E4, q4.y, fmaf(E3, q3.y, E1 * q1.y)))));
 }
@@ -254,7 +257,8 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             CellCache cc;
             cc.key = -1;
             const Axis ax = make_axis(y.x, 0.f, p.lx), ay = make_axis(y.y, 0.f, p.ly);
-            p.kv0[i] = velocity(F, ax, ay, 0.f, 0.f, 1.0f, 0.0f, cc);
+            p.kv0[i] = velocity_at(F, ax, ay, cell_base(ax, ay, p.pitch), ax.frl, ay.frl, 1.0f,
+                                   0.0f, cc);
         }
     }
 
@@ -305,19 +309,20 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             }
             const float hx = s0.x, hy = s0.y, lx = s0.z, ly = s0.w;
             const Axis ax = make_axis(hx, lx, p.lx), ay = make_axis(hy, ly, p.ly);
+            const int B = cell_base(ax, ay, p.pitch);
             CellCache cc;
             cc.key = -1;
             // stage velocities scaled by the step: q_s = h k_s
             float2 q1;
             if (MODE == kLdsRecompute) {
-                q1 = velocity(F, ax, ay, 0.f, 0.f, omh[0], tbh[0], cc);
+                q1 = velocity_at(F, ax, ay, B, ax.frl, ay.frl, omh[0], tbh[0], cc);
             } else {
                 const float2 k1 = kvc[i];
                 q1 = make_float2(hf * k1.x, hf * k1.y);
             }
             float ix, iy, ex, ey;
             float2 q7;
-            dp_stages(F, ax, ay, q1, omh, tbh, cc, ix, iy, q7, ex, ey);
+            dp_stages(F, ax, ay, B, q1, omh, tbh, cc, ix, iy, q7, ex, ey);
             // candidate state: hi + increment split error-free, the rounding
             // error added to lo (whose own rounding stays ~1e-12 cells)
             float sx, ex2, sy, ey2;
@@ -446,7 +451,8 @@ __global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args
         CellCache cc;
         cc.key = -1;
         const Axis ax = make_axis(y.x, 0.f, lx), ay = make_axis(y.y, 0.f, ly);
-        kv0[k] = velocity(F, ax, ay, 0.f, 0.f, 1.0f, 0.0f, cc);
+        kv0[k] = velocity_at(F, ax, ay, cell_base(ax, ay, lx + 2), ax.frl, ay.frl, 1.0f, 0.0f,
+                             cc);
     }
 
     double t = 0.0, h = replay ? replay_h[0] : a.h0;
@@ -488,7 +494,7 @@ __global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args
             const float2 q1 = make_float2(hf * k1.x, hf * k1.y);
             float ix, iy, ex, ey;
             float2 q7;
-            dp_stages(F, ax, ay, q1, omh, tbh, cc, ix, iy, q7, ex, ey);
+            dp_stages(F, ax, ay, cell_base(ax, ay, lx + 2), q1, omh, tbh, cc, ix, iy, q7, ex, ey);
             float sx, ex2, sy, ey2;
             two_sum(s0.x, ix, sx, ex2);
             two_sum(s0.y, iy, sy, ey2);
