@@ -56,6 +56,7 @@ struct ffb_batch {
 
     // per-map device arrays
     int32_t *d_lx = nullptr, *d_ly = nullptr, *d_region_off = nullptr, *d_ring_map = nullptr;
+    int32_t *d_entry_ring = nullptr;
     int64_t *d_plane_off = nullptr, *d_field_off = nullptr, *d_acc_off = nullptr,
             *d_point_off = nullptr, *d_nvert = nullptr;
     int32_t *d_active = nullptr, *d_round = nullptr, *d_rounds_done = nullptr, *d_order = nullptr,
@@ -108,7 +109,7 @@ void free_batch(ffb_batch *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void *ptrs[] = {b->d_lx, b->d_ly, b->d_region_off, b->d_ring_map, b->d_plane_off,
+    void *ptrs[] = {b->d_lx, b->d_ly, b->d_region_off, b->d_ring_map, b->d_entry_ring, b->d_plane_off,
                     b->d_field_off, b->d_acc_off, b->d_point_off, b->d_nvert, b->d_active,
                     b->d_round, b->d_rounds_done, b->d_order, b->d_stats, b->d_n_active,
                     b->d_status, b->d_max_err, b->d_rows, b->d_cols, b->d_scan_rows,
@@ -136,6 +137,7 @@ batch_view view_of(const ffb_batch *b, const ffb_batch_opts &o)
     v.n_vert = b->d_nvert;
     v.region_off = b->d_region_off;
     v.ring_map = b->d_ring_map;
+    v.entry_ring = b->d_entry_ring;
     v.active = b->d_active;
     v.round = b->d_round;
     v.rounds_done = b->d_rounds_done;
@@ -450,6 +452,9 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) e = upload(&b->d_nvert, nvert);
     if (e == hipSuccess) e = upload(&b->d_region_off, region_off);
     if (e == hipSuccess) e = upload(&b->d_ring_map, ring_map);
+    if (e == hipSuccess) e = alloc(&b->d_entry_ring, g.n_entries > 0 ? g.n_entries : 1);
+    if (e == hipSuccess)
+        e = launch_entry_ring(b->stream, g.ring_offsets, g.n_rings, g.n_entries, b->d_entry_ring);
     if (e == hipSuccess) e = upload(&b->d_order, order);
     if (e == hipSuccess) e = upload(&b->d_rows, rows);
     if (e == hipSuccess) e = upload(&b->d_cols, cols);

@@ -267,7 +267,7 @@ hipError_t launch_diff_setup(ffb_ctx *ctx, diff_ws *w, const diff_ctl &init);
 
 // ---------------------------------------------------------------- batches
 // Device view of a batch of maps, passed by value to the batched kernels.
-// Map m owns grid planes at plane_off[m] ([ly][lx] floats), fields at
+// Map m owns grid planes at plane_off[m] ([ly][lx] doubles), fields at
 // field_off[m] ([(ly+2)][(lx+2)] float4), coverage deltas at acc_off[m]
 // ([ly][lx+1] doubles), points [point_off[m], point_off[m+1]) of which the
 // first n_vert[m] are its vertices, and regions [region_off[m],
@@ -278,6 +278,7 @@ struct batch_view {
     const int64_t *plane_off, *field_off, *acc_off, *point_off, *n_vert;
     const int32_t *region_off;
     const int32_t *ring_map;       // [G] map of each ring
+    const int32_t *entry_ring;     // [E] ring of each ring entry (fixed per batch)
     int32_t *active;               // [M] 1 while the map iterates
     int32_t *round;                // [M] 0-based round index of the next iteration
     int32_t *rounds_done;          // [M] rounds taken when the map stopped
@@ -302,6 +303,9 @@ hipError_t launch_ring_areas(hipStream_t s, const ffb_geometry *g, double *area,
 hipError_t launch_batch_finalize(hipStream_t s, const batch_view &bv, const double *value,
                                  const double *area, double *err, int32_t *n_active,
                                  int32_t *status);
+// Ring of every ring entry, entry_ring[k] = g for off[g] <= k < off[g + 1].
+hipError_t launch_entry_ring(hipStream_t s, const int32_t *off, int32_t G, int64_t E,
+                             int32_t *entry_ring);
 hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                                 const ffb_geometry *g, const double *value, const double *area,
                                 double *w_region, double *rho_pad, double *acc, int64_t acc_total,

@@ -204,15 +204,26 @@ template <typename MapOf>
 __device__ inline bool edge_of(int64_t k, const float2 *__restrict__ xy, int64_t nv,
                                const int32_t *__restrict__ off, const int32_t *__restrict__ vidx,
                                const int32_t *__restrict__ region, int32_t G, int32_t R,
-                               int64_t E, MapOf map_of, int32_t *status, EdgeOf &ed)
+                               int64_t E, MapOf map_of, int32_t *status, EdgeOf &ed,
+                               const int32_t *__restrict__ entry_ring = nullptr)
 {
-    // ring of entry k: largest g with off[g] <= k
-    int32_t lo = 0, hi = G;     // off[lo] <= k < off[hi] if offsets are sane
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= k) lo = mid; else hi = mid;
+    // ring of entry k: from the table if there is one (checked below like
+    // the search's result), else the largest g with off[g] <= k
+    int32_t g;
+    if (entry_ring) {
+        g = entry_ring[k];
+        if (g < 0 || g >= G) {
+            set_status(status, FFB_E_INVALID);
+            return false;
+        }
+    } else {
+        int32_t lo = 0, hi = G;     // off[lo] <= k < off[hi] if offsets are sane
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (off[mid] <= k) lo = mid; else hi = mid;
+        }
+        g = lo;
     }
-    const int32_t g = lo;
     const int64_t b = off[g], e = off[g + 1];
     if (!(b <= k && k < e) || e - b < 3 || e > E) {
         set_status(status, FFB_E_INVALID);
@@ -348,7 +359,8 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
         return true;
     };
     // no early return: every lane of the wave takes part in run_add
-    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, map_of, status, ed))
+    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, map_of, status, ed,
+                         bv.entry_ring))
         edge_deposits(acc, bv.acc_off[m], bv.lx[m], bv.ly[m], w[ed.r], ed.x0, ed.y0, ed.x1,
                       ed.y1, key, va, vb);
     run_add(acc, key, va, vb);
@@ -398,6 +410,21 @@ __global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
         __syncthreads();
     }
     if (threadIdx.x == 0) row[lx] = part[0];
+}
+
+// One lane per ring entry: the ring whose offsets bracket it (rings with
+// offsets out of order leave -1, which the raster reports as malformed).
+__global__ __launch_bounds__(256) void k_entry_ring(const int32_t *__restrict__ off, int32_t G,
+                                                    int64_t E, int32_t *__restrict__ entry_ring)
+{
+    const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+    if (k >= E) return;
+    int32_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    entry_ring[k] = (G > 0 && off[lo] <= k && k < off[lo + 1]) ? lo : -1;
 }
 
 }  // namespace
@@ -453,5 +480,14 @@ hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch
     }
     hipLaunchKernelGGL(kb_raster_scan, dim3(bt.n_scan_rows), dim3(kScanThreads), 0, s, bv,
                        bt.scan_rows, acc, rho_pad, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_entry_ring(hipStream_t s, const int32_t *off, int32_t G, int64_t E,
+                             int32_t *entry_ring)
+{
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_entry_ring, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s, off, G,
+                       E, entry_ring);
     return hipGetLastError();
 }
