@@ -209,7 +209,7 @@ int ffb_flux(ffb_ctx *ctx, const double *rho, float sigma, float *fields, double
  * rho_bar (out, [1] FP64), status (in/out, [1] int32, device): a sticky
  * status word the call sets to FFB_E_NONPOSITIVE if min rho_s <= 0 (the
  * caller clears it); hip_stream: the stream to enqueue on (the current
- * device must be the stream's).  The transform workspace (about 12.7 MB) is
+ * device must be the stream's).  The transform workspace (about 8.4 MB) is
  * a fixed device array of the library, one per device, looked up on the
  * first call on a device; the call allocates nothing.  Calls that overlap
  * on one device (several streams or host threads) race on that array.

@@ -64,15 +64,13 @@ struct ffb_batch {
     double *d_max_err = nullptr;
     // launch tables, rows and columns grouped by grid width class
     int2 *d_rows = nullptr, *d_cols = nullptr, *d_scan_rows = nullptr;
-    int4 *d_tiles_a = nullptr, *d_tiles_b = nullptr;
-    int32_t n_rows = 0, n_cols = 0, n_scan_rows = 0, n_tiles_a = 0, n_tiles_b = 0;
+    int32_t n_rows = 0, n_cols = 0, n_scan_rows = 0;
     int n_classes = 0;
     int32_t class_n[kMaxClasses];                  // grid width of each class
     int32_t row_beg[kMaxClasses + 1], col_beg[kMaxClasses + 1];
     // workspace
     // density grids and transform planes (FP64)
-    double *rho = nullptr, *t1 = nullptr, *t2 = nullptr, *pa = nullptr, *pb = nullptr,
-           *pc = nullptr;
+    double *rho = nullptr, *t1 = nullptr, *pa = nullptr, *pb = nullptr, *pc = nullptr;
     float4 *fields = nullptr;
     double *acc = nullptr, *w_region = nullptr, *rho_pad = nullptr, *rho_bar = nullptr,
            *area = nullptr, *err = nullptr;
@@ -113,7 +111,7 @@ void free_batch(ffb_batch *b)
                     b->d_field_off, b->d_acc_off, b->d_point_off, b->d_nvert, b->d_active,
                     b->d_round, b->d_rounds_done, b->d_order, b->d_stats, b->d_n_active,
                     b->d_status, b->d_max_err, b->d_rows, b->d_cols, b->d_scan_rows,
-                    b->d_tiles_a, b->d_tiles_b, b->rho, b->t1, b->t2, b->pa, b->pb, b->pc,
+                    b->rho, b->t1, b->pa, b->pb, b->pc,
                     b->fields, b->acc, b->w_region, b->rho_pad, b->rho_bar, b->area, b->err,
                     b->st0, b->st1, b->kv0, b->kv1, b->scratch_xy, b->tw1024, b->tq1024};
     for (void *p : ptrs)
@@ -153,13 +151,9 @@ batch_tables tables_of(const ffb_batch *b)
     batch_tables t;
     t.rows = b->d_rows;
     t.cols = b->d_cols;
-    t.tiles_a = b->d_tiles_a;
-    t.tiles_b = b->d_tiles_b;
     t.scan_rows = b->d_scan_rows;
     t.n_rows = b->n_rows;
     t.n_cols = b->n_cols;
-    t.n_tiles_a = b->n_tiles_a;
-    t.n_tiles_b = b->n_tiles_b;
     t.n_scan_rows = b->n_scan_rows;
     return t;
 }
@@ -260,7 +254,7 @@ hipError_t enqueue_step(ffb_batch *b, const ffb_batch_opts &o, float *xy,
                                         b->acc, b->acc_total, b->rho, b->d_status);
     if (e == hipSuccess)
         e = launch_batch_flux(s, bv, bt, plan_of(b, b->fft_threads), b->tw1024, b->tq1024, b->rho,
-                              b->acc, b->t1, b->t2, b->pa, b->pb, b->pc, b->fields, b->rho_bar,
+                              b->acc, b->t1, b->pa, b->pb, b->pc, b->fields, b->rho_bar,
                               b->d_status);
     if (e == hipSuccess)
         e = launch_batch_advect(s, bv, advect_args(b, o, xy, replay_off, replay_h),
@@ -412,7 +406,6 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     });
     // launch tables, rows and columns grouped by width class
     std::vector<int2> rows, cols, scan_rows;
-    std::vector<int4> tiles_a, tiles_b;
     b->n_classes = (int)widths.size();
     for (int c = 0; c < b->n_classes; ++c) {
         b->class_n[c] = widths[c];
@@ -423,22 +416,29 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
             for (int j = 0; j < b->ly[m]; j += 2) rows.push_back(make_int2(m, j));
             for (int i = 0; i < b->lx[m]; i += 2) cols.push_back(make_int2(m, i));
         }
+        // the column pass reads and writes its pair in row-major planes; the
+        // eight pairs of one 128-byte line go to workgroups w, w + 8, ...,
+        // w + 56 of the class's launch, which run on one XCD one after
+        // another (blocks of 64 pairs; a shorter tail keeps its order)
+        const size_t c0 = b->col_beg[c], n = cols.size() - c0;
+        std::vector<int2> blk(64);
+        for (size_t q = 0; q + 64 <= n; q += 64) {
+            for (int w = 0; w < 64; ++w) {
+                const int x = w & 7, t = w >> 3;
+                blk[w] = cols[c0 + q + (size_t)((((t >> 3) << 3) + x) * 8 + (t & 7))];
+            }
+            std::copy(blk.begin(), blk.end(), cols.begin() + (ptrdiff_t)(c0 + q));
+        }
         b->fft_threads[c] = std::min(512, std::max(64, widths[c] / 2));
     }
     b->row_beg[b->n_classes] = (int32_t)rows.size();
     b->col_beg[b->n_classes] = (int32_t)cols.size();
     for (int32_t m = 0; m < M; ++m) {
         for (int j = 0; j < b->ly[m]; ++j) scan_rows.push_back(make_int2(m, j));
-        for (int r = 0; r < b->ly[m]; r += 32)
-            for (int c = 0; c < b->lx[m]; c += 32) tiles_a.push_back(make_int4(m, c, r, 0));
-        for (int r = 0; r < b->lx[m]; r += 32)
-            for (int c = 0; c < b->ly[m]; c += 32) tiles_b.push_back(make_int4(m, c, r, 0));
     }
     b->n_rows = (int32_t)rows.size();
     b->n_cols = (int32_t)cols.size();
     b->n_scan_rows = (int32_t)scan_rows.size();
-    b->n_tiles_a = (int32_t)tiles_a.size();
-    b->n_tiles_b = (int32_t)tiles_b.size();
 
     hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
@@ -459,8 +459,6 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) e = upload(&b->d_rows, rows);
     if (e == hipSuccess) e = upload(&b->d_cols, cols);
     if (e == hipSuccess) e = upload(&b->d_scan_rows, scan_rows);
-    if (e == hipSuccess) e = upload(&b->d_tiles_a, tiles_a);
-    if (e == hipSuccess) e = upload(&b->d_tiles_b, tiles_b);
     if (e == hipSuccess) e = alloc(&b->d_active, M);
     if (e == hipSuccess) e = alloc(&b->d_round, M);
     if (e == hipSuccess) e = alloc(&b->d_rounds_done, M);
@@ -468,7 +466,7 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) e = alloc(&b->d_n_active, 1);
     if (e == hipSuccess) e = alloc(&b->d_status, 1);
     if (e == hipSuccess) e = alloc(&b->d_max_err, M);
-    double **planes[] = {&b->rho, &b->t1, &b->t2, &b->pa, &b->pb, &b->pc};
+    double **planes[] = {&b->rho, &b->t1, &b->pa, &b->pb, &b->pc};
     for (double **pl : planes)
         if (e == hipSuccess) e = alloc(pl, b->plane_total);
     if (e == hipSuccess) e = alloc(&b->fields, b->field_total);
@@ -652,7 +650,7 @@ int ffb_batch_autotune(ffb_batch *b, const ffb_batch_opts *o)
             const batch_fft_plan plan = plan_of(b, threads);
             float ms = time_it(b, [&]() {
                 return launch_batch_flux(b->stream, bv0, tables_of(b), plan, b->tw1024, b->tq1024,
-                                         b->rho, b->acc, b->t1, b->t2, b->pa, b->pb, b->pc,
+                                         b->rho, b->acc, b->t1, b->pa, b->pb, b->pc,
                                          b->fields, b->rho_bar, b->d_status);
             }, 3, &e);
             if (e == hipSuccess && ms < best) {

@@ -147,7 +147,7 @@ hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *val
 // lengths, six [lx*ly] planes and kRedDoubles reduction partials.
 struct flux_ws {
     double2 *tw_x, *tq_x, *tw_y, *tq_y;
-    double *t1, *t2, *t3, *pa, *pb, *pc;
+    double *t1, *pa, *pb, *pc;          // [ly][lx] planes: row DCTs, column-pass outputs
     double *red;
 };
 hipError_t launch_flux_ws(hipStream_t s, int lx, int ly, const flux_ws &w, const double *rho,
@@ -292,9 +292,7 @@ struct batch_view {
 struct batch_tables {
     const int2 *rows;              // (map, j0) for every even row j0 of every map
     const int2 *cols;              // (map, m0) for every even column m0
-    const int4 *tiles_a;           // (map, c0, r0, -) tiles of [ly][lx] -> [lx][ly]
-    const int4 *tiles_b;           // (map, c0, r0, -) tiles of [lx][ly] -> [ly][lx]
-    int32_t n_rows, n_cols, n_tiles_a, n_tiles_b, n_scan_rows;
+    int32_t n_rows, n_cols, n_scan_rows;
     const int2 *scan_rows;         // (map, j) for every row
 };
 
@@ -322,7 +320,7 @@ struct batch_fft_plan {
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const double2 *tw1024,
                              const double2 *tq1024, const double *rho, const double *acc,
-                             double *t1, double *t2, double *pa, double *pb, double *pc,
+                             double *t1, double *pa, double *pb, double *pc,
                              float4 *fields, double *rho_bar, int32_t *status);
 struct batch_advect_args {
     const float4 *fields;
@@ -345,4 +343,32 @@ hipError_t launch_batch_advect(hipStream_t s, const batch_view &bv, const batch_
 __device__ inline void set_status(int32_t *status, int32_t code)
 {
     atomicCAS(status, 0, code);
+}
+
+// Ring of ring entry k: the largest g in [0, G) with off[g] <= k (binary
+// search over off[0..G]; the caller checks off[g] <= k < off[g + 1]).
+// Kernels with one entry per lane first copy off[0..G] to LDS when it fits
+// (kStagedRingOffsets ints): each step of the search is then an LDS read
+// instead of a dependent global load.
+constexpr int kStagedRingOffsets = 4096;
+
+__device__ inline int32_t ring_search(const int32_t *off, int32_t G, int64_t k)
+{
+    int32_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Copies off[0..G] to s_off when it fits; every thread of the workgroup
+// calls it (it passes a barrier).  Returns whether s_off holds the offsets.
+__device__ inline bool stage_ring_offsets(const int32_t *__restrict__ off, int32_t G,
+                                          int32_t *s_off)
+{
+    if (G + 1 > kStagedRingOffsets) return false;
+    for (int i = threadIdx.x; i <= G; i += blockDim.x) s_off[i] = off[i];
+    __syncthreads();
+    return true;
 }

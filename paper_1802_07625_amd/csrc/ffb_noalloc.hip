@@ -2,7 +2,7 @@
 // section 2) for callers that cannot allocate device memory -- code under
 // HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
 //
-// The transform workspace (twiddle tables, six grid planes, reduction
+// The transform workspace (twiddle tables, four grid planes, reduction
 // partials) is one file-scope device array, `scratch`, sized for grids up
 // to kMaxSide x kMaxSide.  Each device holds its own copy; its address is
 // looked up once per device (hipGetSymbolAddress, with that device
@@ -36,8 +36,8 @@ constexpr size_t kOffTqX = kOffTwX + kTwBytes;
 constexpr size_t kOffTwY = kOffTqX + kTqBytes;
 constexpr size_t kOffTqY = kOffTwY + kTwBytes;
 constexpr size_t kOffPlanes = kOffTqY + kTqBytes;
-constexpr size_t kOffRed = kOffPlanes + 6 * kPlaneBytes;
-constexpr size_t kScratchBytes = kOffRed + kRedBytes;   // about 12.7 MB
+constexpr size_t kOffRed = kOffPlanes + 4 * kPlaneBytes;
+constexpr size_t kScratchBytes = kOffRed + kRedBytes;   // about 8.4 MB
 
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -83,15 +83,13 @@ extern "C" int ffb_flux_noalloc(int32_t lx, int32_t ly, const double *rho, float
     w.tq_x = reinterpret_cast<double2 *>(base + kOffTqX);
     w.tw_y = reinterpret_cast<double2 *>(base + kOffTwY);
     w.tq_y = reinterpret_cast<double2 *>(base + kOffTqY);
-    double *pl[6];
-    for (int k = 0; k < 6; ++k)
+    double *pl[4];
+    for (int k = 0; k < 4; ++k)
         pl[k] = reinterpret_cast<double *>(base + kOffPlanes + k * kPlaneBytes);
     w.t1 = pl[0];
-    w.t2 = pl[1];
-    w.t3 = pl[2];
-    w.pa = pl[3];
-    w.pb = pl[4];
-    w.pc = pl[5];
+    w.pa = pl[1];
+    w.pb = pl[2];
+    w.pc = pl[3];
     w.red = reinterpret_cast<double *>(base + kOffRed);
     e = launch_twiddles(s, lx, w.tw_x, w.tq_x);
     if (e == hipSuccess) e = launch_twiddles(s, ly, w.tw_y, w.tq_y);

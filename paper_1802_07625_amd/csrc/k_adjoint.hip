@@ -41,14 +41,21 @@ __global__ __launch_bounds__(kThreads) void k_area_adj(
     int64_t E, const double *__restrict__ lam_area, double *__restrict__ lam_xy,
     int32_t *status)
 {
+    __shared__ int32_t s_off[kStagedRingOffsets];
+    const bool staged = stage_ring_offsets(off, G, s_off);
     const int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x;
     if (k >= E) return;
-    int32_t lo = 0, hi = G;
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= k) lo = mid; else hi = mid;
+    int32_t lo;
+    int64_t b, e;
+    if (staged) {
+        lo = ring_search(s_off, G, k);
+        b = s_off[lo];
+        e = s_off[lo + 1];
+    } else {
+        lo = ring_search(off, G, k);
+        b = off[lo];
+        e = off[lo + 1];
     }
-    const int64_t b = off[lo], e = off[lo + 1];
     if (!(b <= k && k < e) || e - b < 3 || e > E) { set_status(status, FFB_E_INVALID); return; }
     const int32_t r = region[lo];
     const int32_t ic = vidx[k];
@@ -139,16 +146,23 @@ __global__ __launch_bounds__(kThreads) void k_raster_adj(
     const double *__restrict__ suf, int32_t lx, int32_t ly, double *__restrict__ lam_w,
     double *__restrict__ lam_xy, int32_t *status)
 {
+    __shared__ int32_t s_off[kStagedRingOffsets];
+    const bool staged = stage_ring_offsets(off, G, s_off);
     const int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x;
     int32_t r = -1, i0 = 0, i1 = 0;
     double x0 = 0.0, y0 = 0.0, x1 = 0.0, y1 = 0.0;
     if (k < E) {
-        int32_t lo = 0, hi = G;
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (off[mid] <= k) lo = mid; else hi = mid;
+        int32_t lo;
+        int64_t b, e;
+        if (staged) {
+            lo = ring_search(s_off, G, k);
+            b = s_off[lo];
+            e = s_off[lo + 1];
+        } else {
+            lo = ring_search(off, G, k);
+            b = off[lo];
+            e = off[lo + 1];
         }
-        const int64_t b = off[lo], e = off[lo + 1];
         if (!(b <= k && k < e) || e - b < 3 || e > E) {
             set_status(status, FFB_E_INVALID);
         } else {
@@ -391,12 +405,16 @@ __device__ inline void push(float4 *__restrict__ lam, int pitch, float *cw, cons
     if (wx >= R.x0 && wy >= R.y0 && wx + 1 < R.x1 && wy + 1 < R.y1) {
         const int b = wy * kWin + wx;
         const int idx[4] = {b, b + 1, b + kWin, b + kWin + 1};
+        // workgroup-scoped adds: they stay LDS atomics (with the same scope
+        // as the global ones below, the compiler may merge the two branches'
+        // last add into one flat atomic, which every later wait for a field
+        // load then has to wait for as well)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             float *d = cw + 3 * idx[q];
-            atomicAdd(d, ac.g[q].x);
-            atomicAdd(d + 1, ac.g[q].y);
-            atomicAdd(d + 2, ac.g[q].z);
+            __hip_atomic_fetch_add(d, ac.g[q].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(d + 1, ac.g[q].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(d + 2, ac.g[q].z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     } else {
         const int key = ac.cj * pitch + ac.ci;
@@ -484,10 +502,18 @@ __global__ __launch_bounds__(kThreads) void k_adj_jacobian(AdjParams p)
         tile_of(tile, n_pt_tiles, step0, i, false);
         if (i >= p.n) continue;
         const int step1 = min(S, step0 + kChunk);
+        // the tile's recorded states, all loads in flight at once
+        float4 qs[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            qs[u] = step0 + u < step1 ? p.tape[(int64_t)(step0 + u) * p.n + i]
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int k = step0; k < step1; ++k) {
             const double h = p.h[k], t0 = p.tstart[k];
             const float hf = (float)h;
-            const float4 st = p.tape[(int64_t)k * p.n + i];
+            const float4 st = qs[0];
+#pragma unroll
+            for (int u = 0; u + 1 < kChunk; ++u) qs[u] = qs[u + 1];
             float Kx[6], Ky[6];
             float D[6][4];                     // dK_s, row-major 2 x 2
 #pragma unroll
@@ -598,12 +624,26 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
         tile_of(tile, n_pt_tiles, step0, i, false);
         const bool live = i < p.n;
         const int step1 = min(S, step0 + kChunk);
+        // the tile's recorded states and position adjoints, all loads in
+        // flight at once; q[u] belongs to step step1 - 1 - u (last first)
+        float4 qs[kChunk], ql[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const int k = step1 - 1 - u;
+            if (live && k >= step0) {
+                qs[u] = p.tape[(int64_t)k * p.n + i];
+                ql[u] = p.jac[(int64_t)k * p.n + i];
+            } else {
+                qs[u] = ql[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
         // window: the box of the cells of the wavefront's recorded states
         int bx0 = INT32_MAX, by0 = INT32_MAX, bx1 = INT32_MIN, by1 = INT32_MIN;
-        for (int k = step0; k < step1 && live; ++k) {
-            const float4 st = p.tape[(int64_t)k * p.n + i];
-            const int cx = (int)fminf(fmaxf(st.x + 0.5f, 0.f), (float)(p.lx + 1));
-            const int cy = (int)fminf(fmaxf(st.y + 0.5f, 0.f), (float)(p.ly + 1));
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            if (!live || step1 - 1 - u < step0) continue;
+            const int cx = (int)fminf(fmaxf(qs[u].x + 0.5f, 0.f), (float)(p.lx + 1));
+            const int cy = (int)fminf(fmaxf(qs[u].y + 0.5f, 0.f), (float)(p.ly + 1));
             bx0 = min(bx0, cx);
             bx1 = max(bx1, cx);
             by0 = min(by0, cy);
@@ -636,8 +676,12 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
         for (int k = step1 - 1; k >= step0 && live; --k) {
             const double h = p.h[k], t0 = p.tstart[k];
             const float hf = (float)h;
-            const float4 st = p.tape[(int64_t)k * p.n + i];
-            const float4 lam = p.jac[(int64_t)k * p.n + i];
+            const float4 st = qs[0], lam = ql[0];
+#pragma unroll
+            for (int u = 0; u + 1 < kChunk; ++u) {
+                qs[u] = qs[u + 1];
+                ql[u] = ql[u + 1];
+            }
             float omt[6], tb[6];
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
@@ -647,6 +691,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
             }
             Stage L[6];
             float Kx[6], Ky[6];
+            Local o5;                      // the last stage's, reused first below
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
                 float dx = 0.f, dy = 0.f;
@@ -661,6 +706,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
                 local_velocity(cc, omt[s], tb[s], L[s].a, L[s].b, o);
                 Kx[s] = o.kx;
                 Ky[s] = o.ky;
+                if (s == 5) o5 = o;
             }
             float Ybx[6], Yby[6];
 #pragma unroll
@@ -672,9 +718,13 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
                     kby = fmaf(hf * kA[j][s], Yby[j], kby);
                 }
                 const Stage &Ls = L[s];
-                load_cell(p.fields, p.pitch, Ls.cj * p.pitch + Ls.ci, cc);
                 Local o;
-                local_velocity(cc, omt[s], tb[s], Ls.a, Ls.b, o);
+                if (s == 5) {
+                    o = o5;
+                } else {
+                    load_cell(p.fields, p.pitch, Ls.cj * p.pitch + Ls.ci, cc);
+                    local_velocity(cc, omt[s], tb[s], Ls.a, Ls.b, o);
+                }
                 Ybx[s] = Ls.fx ? kbx * o.xa + kby * o.ya : 0.f;
                 Yby[s] = Ls.fy ? kbx * o.xb + kby * o.yb : 0.f;
                 const bool inA = Ls.ci == A.ci && Ls.cj == A.cj;

@@ -6,13 +6,11 @@
 //
 // Pipeline (lx x ly grid, x fastest):
 //   k_dct2_rows   rows j:      T1[j][m]  = sum_i rho[j][i] cos(pi m (i+1/2)/lx)
-//   k_transpose   T1 -> T2[m][j]
-//   k_col_pass    rows m:      S[m][n]   = sum_j T2[m][j] cos(pi n (j+1/2)/ly)
+//   k_col_pass    columns m:   S[n][m]   = sum_j T1[j][m] cos(pi n (j+1/2)/ly)
 //                              rts       = 4 S / ((1+d_m0)(1+d_n0)) * gauss(m, n)
-//                              a[m][j]   = sum_n rts cos(pi n (j+1/2)/ly)
-//                              b[m][j]   = sum_n wx(m,n) rts cos(...)
-//                              c[m][j]   = sum_n wy(m,n) rts sin(pi n (j+1/2)/ly)
-//   k_transpose   a, b, c -> [j][m]
+//                              a[j][m]   = sum_n rts cos(pi n (j+1/2)/ly)
+//                              b[j][m]   = sum_n wx(m,n) rts cos(...)
+//                              c[j][m]   = sum_n wy(m,n) rts sin(pi n (j+1/2)/ly)
 //   k_row_final   rows j:      rho_s = sum_m a cos / (lx ly), J_x = sum_m b sin,
 //                              J_y = sum_m c cos  -> ghosted float4 fields
 // with wx = (ly/pi) m/(m^2 ly^2 + n^2 lx^2), wy = (lx/pi) n/(...).
@@ -292,10 +290,13 @@ __global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ in0,
     transpose_tile(in, out, R, C, blockIdx.x * 32, blockIdx.y * 32, tile);
 }
 
-// Column pass on rows m0, m1 = m0 + 1 of T2 [lx][ly] (precision R; LDS: sa,
-// sb, coef of kMaxN and stw of kMaxN / 2 complex).
+// Column pass on columns m0, m1 = m0 + 1 of T1 [ly][lx] (precision R; LDS:
+// sa, sb, coef of kMaxN and stw of kMaxN / 2 complex).  The pair is read and
+// written in the row-major planes directly, one two-element access per row;
+// the workgroups of the pairs that share a cache line run on one XCD (see
+// col_pair), so the lines are fetched from HBM once.
 template <typename R>
-__device__ __forceinline__ void col_pass_body(const R *__restrict__ t2, int m0, int lx, int ly,
+__device__ __forceinline__ void col_pass_body(const R *__restrict__ t1, int m0, int lx, int ly,
                                               float sigma, const cx<R> *__restrict__ tw,
                                               const cx<R> *__restrict__ tq, int qs,
                                               R *__restrict__ pa, R *__restrict__ pb,
@@ -304,10 +305,11 @@ __device__ __forceinline__ void col_pass_body(const R *__restrict__ t2, int m0, 
 {
     using C = cx<R>;
     const int N = ly;
+    const int64_t cs = lx / 2;                 // row stride in pairs
     load_twiddles(stw, tw, N, qs);
-    const R *ra = t2 + (int64_t)m0 * N, *rb = ra + N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = mkc<C>(ra[i], rb[i]);
-    dct2_pair(sa, sb, coef, N, stw, tq, qs);   // coef[n] = (S[m0][n], S[m1][n])
+    const C *src = reinterpret_cast<const C *>(t1 + m0);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sa[mk_pos(i, N)] = src[i * cs];
+    dct2_pair(sa, sb, coef, N, stw, tq, qs);   // coef[n] = (S[n][m0], S[n][m1])
 
     // normalisation of Eq. 7 and the blur, separable in m and n
     const R PI = R(3.14159265358979323846);
@@ -341,12 +343,8 @@ __device__ __forceinline__ void col_pass_body(const R *__restrict__ t2, int m0, 
     // a: plain DCT-III of the coefficients
     dct3_input(sa, N, tq, [&](int n) { return coef[n]; }, qs);
     C *v = fft_lds(sa, sb, N, stw, true);
-    R *oa0 = pa + (int64_t)m0 * N, *oa1 = oa0 + N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const C y = dct3_output(v, i, N);
-        oa0[i] = y.x;
-        oa1[i] = y.y;
-    }
+    C *oa = reinterpret_cast<C *>(pa + m0);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) oa[i * cs] = dct3_output(v, i, N);
     __syncthreads();
     // b: DCT-III of wx * coefficients
     dct3_input(sa, N, tq, [&](int n) {
@@ -354,12 +352,8 @@ __device__ __forceinline__ void col_pass_body(const R *__restrict__ t2, int m0, 
         return mkc<C>(wx(ma, n) * c.x, wx(mb, n) * c.y);
     }, qs);
     v = fft_lds(sa, sb, N, stw, true);
-    R *ob0 = pb + (int64_t)m0 * N, *ob1 = ob0 + N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const C y = dct3_output(v, i, N);
-        ob0[i] = y.x;
-        ob1[i] = y.y;
-    }
+    C *ob = reinterpret_cast<C *>(pb + m0);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) ob[i * cs] = dct3_output(v, i, N);
     __syncthreads();
     // c: DST-III of wy * coefficients = (-1)^j DCT-III of the reversed sequence
     dct3_input(sa, N, tq, [&](int mm) {
@@ -369,24 +363,35 @@ __device__ __forceinline__ void col_pass_body(const R *__restrict__ t2, int m0, 
         return mkc<C>(wy(ma, n) * c.x, wy(mb, n) * c.y);
     }, qs);
     v = fft_lds(sa, sb, N, stw, true);
-    R *oc0 = pc + (int64_t)m0 * N, *oc1 = oc0 + N;
+    C *oc = reinterpret_cast<C *>(pc + m0);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const C y = dct3_output(v, i, N);
         const R s = (i & 1) ? R(-1) : R(1);
-        oc0[i] = s * y.x;
-        oc1[i] = s * y.y;
+        oc[i * cs] = mkc<C>(s * y.x, s * y.y);
     }
 }
 
-__global__ __launch_bounds__(512) void k_col_pass(const double *__restrict__ t2, int lx, int ly,
+// Column pair of workgroup b out of np pairs (FP64 pairs, 16 bytes): the
+// eight pairs of one 128-byte line go to workgroups b, b + 8, ..., b + 56,
+// which the dispatcher places on the same XCD one after another, so each
+// line of the planes is fetched into that XCD's L2 once.  Any other count
+// keeps the plain order.
+__device__ __forceinline__ int col_pair(int b, int np)
+{
+    if (np % 64) return b;
+    const int x = b & 7, s = b >> 3;
+    return (((s >> 3) << 3) + x) * 8 + (s & 7);
+}
+
+__global__ __launch_bounds__(512) void k_col_pass(const double *__restrict__ t1, int lx, int ly,
                                                   float sigma, const double2 *__restrict__ tw,
                                                   const double2 *__restrict__ tq,
                                                   double *__restrict__ pa, double *__restrict__ pb,
                                                   double *__restrict__ pc)
 {
     __shared__ double2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
-    col_pass_body<double>(t2, 2 * blockIdx.x, lx, ly, sigma, tw, tq, 1, pa, pb, pc, sa, sb, coef,
-                          stw);
+    const int m0 = 2 * col_pair(blockIdx.x, lx / 2);
+    col_pass_body<double>(t1, m0, lx, ly, sigma, tw, tq, 1, pa, pb, pc, sa, sb, coef, stw);
 }
 
 // Row pass on rows j0, j1 = j0 + 1 of a, b, c [ly][lx] (precision R);
@@ -746,25 +751,8 @@ __global__ __launch_bounds__(512) void kb_dct2_rows(batch_view bv, const int2 *_
     dct2_rows_body(in + o, out + o, e.y, N, tw, tq, kMaxN / N, sa, sb, stw);
 }
 
-// blockIdx.y selects the plane pair (in_k -> out_k).
-__global__ __launch_bounds__(256) void kb_transpose(batch_view bv, const int4 *__restrict__ tiles,
-                                                    bool rows_are_y, const double *in0,
-                                                    const double *in1, double *out0, double *out1)
-{
-    __shared__ double tile[32][33];
-    const int4 t = tiles[blockIdx.x];
-    const int m = t.x;
-    if (!bv.active[m]) return;
-    const int R = rows_are_y ? bv.ly[m] : bv.lx[m];
-    const int C = rows_are_y ? bv.lx[m] : bv.ly[m];
-    const int64_t o = bv.plane_off[m];
-    const double *in = (blockIdx.y == 0 ? in0 : in1) + o;
-    double *out = (blockIdx.y == 0 ? out0 : out1) + o;
-    transpose_tile(in, out, R, C, t.y, t.z, tile);
-}
-
 __global__ __launch_bounds__(512) void kb_col_pass(batch_view bv, const int2 *__restrict__ cols,
-                                                   const double *__restrict__ t2,
+                                                   const double *__restrict__ t1,
                                                    const double2 *__restrict__ tw,
                                                    const double2 *__restrict__ tq,
                                                    double *__restrict__ pa, double *__restrict__ pb,
@@ -777,7 +765,7 @@ __global__ __launch_bounds__(512) void kb_col_pass(batch_view bv, const int2 *__
     const int lx = bv.lx[m], ly = bv.ly[m];
     const int64_t o = bv.plane_off[m];
     const float sigma = (float)ldexp(bv.sigma0, -bv.round[m]);
-    col_pass_body(t2 + o, e.y, lx, ly, sigma, tw, tq, kMaxN / ly, pa + o, pb + o, pc + o, sa, sb,
+    col_pass_body(t1 + o, e.y, lx, ly, sigma, tw, tq, kMaxN / ly, pa + o, pb + o, pc + o, sa, sb,
                   coef, stw);
 }
 
@@ -972,14 +960,9 @@ hipError_t launch_flux_ws(hipStream_t s, int lx, int ly, const flux_ws &w, const
                        w.tw_x, w.tq_x, w.red);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, w.red, ly / 2, 1.0 / (double)n,
                        rho_bar, status);
-    hipLaunchKernelGGL(k_transpose<double>, dim3((lx + 31) / 32, (ly + 31) / 32, 1), dim3(256),
-                       0, s, w.t1, w.t1, w.t1, w.t2, w.t2, w.t2, ly, lx);
-    hipLaunchKernelGGL(k_col_pass, dim3(lx / 2), dim3(threads_for(ly)), 0, s, w.t2, lx, ly,
+    hipLaunchKernelGGL(k_col_pass, dim3(lx / 2), dim3(threads_for(ly)), 0, s, w.t1, lx, ly,
                        sigma, w.tw_y, w.tq_y, w.pa, w.pb, w.pc);
-    // [lx][ly] -> [ly][lx]: a, b, c into the free planes t1, t2, t3 (one launch)
-    hipLaunchKernelGGL(k_transpose<double>, dim3((ly + 31) / 32, (lx + 31) / 32, 3), dim3(256),
-                       0, s, w.pa, w.pb, w.pc, w.t1, w.t2, w.t3, lx, ly);
-    hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, w.t1, w.t2, w.t3,
+    hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, w.pa, w.pb, w.pc,
                        lx, ly, w.tw_x, w.tq_x, fields, status);
     return hipGetLastError();
 }
@@ -988,11 +971,15 @@ hipError_t launch_flux(ffb_ctx *ctx, const double *rho, float sigma, float4 *fie
                        double *rho_bar)
 {
     // the context's planes are sized for FP64
-    double *pl[6] = {reinterpret_cast<double *>(ctx->t1), reinterpret_cast<double *>(ctx->t2),
-                     reinterpret_cast<double *>(ctx->t3), reinterpret_cast<double *>(ctx->pa),
-                     reinterpret_cast<double *>(ctx->pb), reinterpret_cast<double *>(ctx->pc)};
-    flux_ws w{ctx->tw64_x, ctx->tq64_x, ctx->tw64_y, ctx->tq64_y, pl[0], pl[1],
-              pl[2],       pl[3],       pl[4],       pl[5],       ctx->red};
+    flux_ws w{ctx->tw64_x,
+              ctx->tq64_x,
+              ctx->tw64_y,
+              ctx->tq64_y,
+              reinterpret_cast<double *>(ctx->t1),
+              reinterpret_cast<double *>(ctx->pa),
+              reinterpret_cast<double *>(ctx->pb),
+              reinterpret_cast<double *>(ctx->pc),
+              ctx->red};
     return launch_flux_ws(ctx->stream, ctx->lx, ctx->ly, w, rho, sigma, fields, rho_bar,
                           ctx->d_status);
 }
@@ -1067,7 +1054,7 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const double2 *tw1024,
                              const double2 *tq1024, const double *rho, const double *acc,
-                             double *t1, double *t2, double *pa, double *pb, double *pc,
+                             double *t1, double *pa, double *pb, double *pc,
                              float4 *fields, double *rho_bar, int32_t *status)
 {
     hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, s, bv, acc, rho_bar, status);
@@ -1077,25 +1064,17 @@ hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_ta
             hipLaunchKernelGGL(kb_dct2_rows, dim3(n), dim3(plan.threads[c]), 0, s, bv,
                                bt.rows + plan.row_beg[c], rho, t1, tw1024, tq1024);
     }
-    // [ly][lx] -> [lx][ly]
-    hipLaunchKernelGGL(kb_transpose, dim3(bt.n_tiles_a, 1), dim3(256), 0, s, bv, bt.tiles_a, true,
-                       t1, t1, t2, t2);
     for (int c = 0; c < plan.n_classes; ++c) {
         const int n = plan.col_beg[c + 1] - plan.col_beg[c];
         if (n > 0)
             hipLaunchKernelGGL(kb_col_pass, dim3(n), dim3(plan.threads[c]), 0, s, bv,
-                               bt.cols + plan.col_beg[c], t2, tw1024, tq1024, pa, pb, pc);
+                               bt.cols + plan.col_beg[c], t1, tw1024, tq1024, pa, pb, pc);
     }
-    // [lx][ly] -> [ly][lx]: a, b into t1, t2 and c into pa (read after the first launch)
-    hipLaunchKernelGGL(kb_transpose, dim3(bt.n_tiles_b, 2), dim3(256), 0, s, bv, bt.tiles_b,
-                       false, pa, pb, t1, t2);
-    hipLaunchKernelGGL(kb_transpose, dim3(bt.n_tiles_b, 1), dim3(256), 0, s, bv, bt.tiles_b,
-                       false, pc, pc, pa, pa);
     for (int c = 0; c < plan.n_classes; ++c) {
         const int n = plan.row_beg[c + 1] - plan.row_beg[c];
         if (n > 0)
             hipLaunchKernelGGL(kb_row_final, dim3(n), dim3(plan.threads[c]), 0, s, bv,
-                               bt.rows + plan.row_beg[c], t1, t2, pa, tw1024, tq1024, fields,
+                               bt.rows + plan.row_beg[c], pa, pb, pc, tw1024, tq1024, fields,
                                status);
     }
     return hipGetLastError();

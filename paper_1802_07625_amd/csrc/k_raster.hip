@@ -205,26 +205,31 @@ __device__ inline bool edge_of(int64_t k, const float2 *__restrict__ xy, int64_t
                                const int32_t *__restrict__ off, const int32_t *__restrict__ vidx,
                                const int32_t *__restrict__ region, int32_t G, int32_t R,
                                int64_t E, MapOf map_of, int32_t *status, EdgeOf &ed,
-                               const int32_t *__restrict__ entry_ring = nullptr)
+                               const int32_t *__restrict__ entry_ring = nullptr,
+                               const int32_t *s_off = nullptr, bool staged = false)
 {
     // ring of entry k: from the table if there is one (checked below like
-    // the search's result), else the largest g with off[g] <= k
+    // the search's result), else the largest g with off[g] <= k, searched in
+    // the LDS copy of the offsets if the workgroup made one
     int32_t g;
+    int64_t b, e;
     if (entry_ring) {
         g = entry_ring[k];
         if (g < 0 || g >= G) {
             set_status(status, FFB_E_INVALID);
             return false;
         }
+        b = off[g];
+        e = off[g + 1];
+    } else if (staged) {
+        g = ring_search(s_off, G, k);
+        b = s_off[g];
+        e = s_off[g + 1];
     } else {
-        int32_t lo = 0, hi = G;     // off[lo] <= k < off[hi] if offsets are sane
-        while (hi - lo > 1) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (off[mid] <= k) lo = mid; else hi = mid;
-        }
-        g = lo;
+        g = ring_search(off, G, k);
+        b = off[g];
+        e = off[g + 1];
     }
-    const int64_t b = off[g], e = off[g + 1];
     if (!(b <= k && k < e) || e - b < 3 || e > E) {
         set_status(status, FFB_E_INVALID);
         return false;
@@ -262,6 +267,8 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
     int32_t R, int64_t E, const double *__restrict__ w, int32_t lx, int32_t ly,
     double *__restrict__ acc, int32_t *status)
 {
+    __shared__ int32_t s_off[kStagedRingOffsets];
+    const bool staged = stage_ring_offsets(off, G, s_off);
     const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
     int64_t key = -1;
     double va = 0.0, vb = 0.0;
@@ -272,7 +279,8 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
         return true;
     };
     // no early return: every lane of the wave takes part in run_add
-    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, one_map, status, ed))
+    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, one_map, status, ed, nullptr,
+                         s_off, staged))
         edge_deposits(acc, 0, lx, ly, w[ed.r], ed.x0, ed.y0, ed.x1, ed.y1, key, va, vb);
     run_add(acc, key, va, vb);
 }
