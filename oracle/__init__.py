@@ -79,6 +79,12 @@ def lib(path: str | None = None):
         L.ffbo_integrate.argtypes = [i32, i32, _d, _d, _d, dbl, i64, _d,
                                      dbl, dbl, dbl, dbl, dbl, dbl, i32,
                                      _d, i32, _i32, _i32, _d, i32]
+        L.ffbo_area_adj.argtypes = [i64, _d, i32, _i32, _i32, _i32, i32, _d, _d]
+        L.ffbo_density_adj.argtypes = [i32, i32, i64, _d, i32, _i32, _i32, _i32, i32, _d, _d,
+                                       _d, _d, _d, _d]
+        L.ffbo_flux_adj.argtypes = [i32, i32, dbl, _d, _d, _d, dbl, _d]
+        L.ffbo_integrate_adj.argtypes = [i32, i32, _d, _d, _d, dbl, i64, _d, _d, i32, _d,
+                                         _d, _d, _d, _d]
         if hasattr(L, "ffbo_inverse"):
             L.ffbo_inverse.argtypes = [i32, i32, _f, i64, _f, _i32, _d]
         if hasattr(L, "ffbo_diff_fields"):
@@ -441,6 +447,119 @@ def fd_gradient(m, density, sigmas, schedules, step=1e-4, points=None):
         lm = rounds(m, dm, sigmas, points, schedules=schedules).loss
         g[r] = (lp - lm) / (2.0 * step)
     return g
+
+
+# ------------------------------------------------- reverse mode (adjoints)
+# Gradients of the K-round area loss with the accepted steps frozen, by the
+# chain rule through each forward step (the C functions ffbo_*_adj, each the
+# transpose of the linearised step).  Not a step of the paper's method: the
+# reference against which a device gradient is compared exactly, where
+# fd_gradient only matches to its truncation error.
+def area_adj(m, lam_area, xy=None) -> np.ndarray:
+    """d(sum_r lam_area_r A_r)/d(vertex coordinates), [V, 2]."""
+    xy = _f64(m.xy if xy is None else xy).reshape(-1, 2)
+    off, vid, reg = _i(m.ring_offsets), _i(m.ring_vidx), _i(m.ring_region)
+    out = np.zeros_like(xy)
+    _check(lib().ffbo_area_adj(xy.shape[0], _p(xy), reg.shape[0], _p(off, _i32), _p(vid, _i32),
+                               _p(reg, _i32), m.n_regions, _p(_f64(lam_area)), _p(out)),
+           "area_adj")
+    return out
+
+
+def density_adj(m, value, area, lam_rho, xy=None, lx=None, ly=None):
+    """Adjoint of density(): for lam_rho [ly, lx], the derivatives of
+    sum_c lam_rho_c rho0_c with respect to value, area and the vertices."""
+    lx = m.lx if lx is None else lx
+    ly = m.ly if ly is None else ly
+    xy = _f64(m.xy if xy is None else xy).reshape(-1, 2)
+    off, vid, reg = _i(m.ring_offsets), _i(m.ring_vidx), _i(m.ring_region)
+    lv, la = np.zeros(m.n_regions), np.zeros(m.n_regions)
+    lxy = np.zeros_like(xy)
+    _check(lib().ffbo_density_adj(lx, ly, xy.shape[0], _p(xy), reg.shape[0], _p(off, _i32),
+                                  _p(vid, _i32), _p(reg, _i32), m.n_regions, _p(_f64(value)),
+                                  _p(_f64(area)), _p(_f64(lam_rho)), _p(lv), _p(la), _p(lxy)),
+           "density_adj")
+    return lv, la, lxy
+
+
+def flux_adj(lam_rs, lam_jx, lam_jy, lam_rb: float, sigma: float) -> np.ndarray:
+    """Adjoint of flux(): lam_rho [ly, lx] from the node adjoints of rho_s,
+    J_x, J_y ([ly, lx] each) and of rho_bar."""
+    lam_rs, lam_jx, lam_jy = _f64(lam_rs), _f64(lam_jx), _f64(lam_jy)
+    ly, lx = lam_rs.shape
+    out = np.zeros((ly, lx))
+    _check(lib().ffbo_flux_adj(lx, ly, float(sigma), _p(lam_rs), _p(lam_jx), _p(lam_jy),
+                               float(lam_rb), _p(out)), "flux_adj")
+    return out
+
+
+def integrate_adj(F: Fields, pts, h, lam_xy):
+    """Adjoint of integrate(F, pts, replay_h=h): from dL/d(end points) the
+    derivatives with respect to the start points and to the fields
+    (rho_s, J_x, J_y at the nodes, and rho_bar)."""
+    pts = _f64(pts).reshape(-1, 2)
+    h = _f64(h)
+    lam = _f64(lam_xy).reshape(-1, 2).copy()
+    rs, jx, jy = _f64(F.rho_s), _f64(F.jx), _f64(F.jy)
+    lrs, ljx, ljy = np.zeros_like(rs), np.zeros_like(rs), np.zeros_like(rs)
+    lrb = np.zeros(1)
+    _check(lib().ffbo_integrate_adj(F.lx, F.ly, _p(rs), _p(jx), _p(jy), F.rho_bar,
+                                    pts.shape[0], _p(pts), _p(h), h.shape[0], _p(lam),
+                                    _p(lrs), _p(ljx), _p(ljy), _p(lrb)), "integrate_adj")
+    return lam, lrs, ljx, ljy, float(lrb[0])
+
+
+def area_loss_adj(value, area):
+    """dL/d(area) and dL/d(value) of area_loss: with e_r = A_r S_v / (v_r S_A) - 1,
+    dL/dA_q = 2 e_q S_v / (v_q S_A) - (S_v / S_A^2) sum_r 2 e_r A_r / v_r and
+    dL/dv_q = (1 / S_A) sum_r 2 e_r A_r / v_r - 2 e_q A_q S_v / (v_q^2 S_A)."""
+    v, a = _f64(value), _f64(area)
+    sv, sa = float(np.sum(v)), float(np.sum(a))
+    e = a * sv / (v * sa) - 1.0
+    t = float(np.sum(2.0 * e * a / v))
+    la = 2.0 * e * sv / (v * sa) - sv / (sa * sa) * t
+    lv = t / sa - 2.0 * e * a * sv / (v * v * sa)
+    return la, lv
+
+
+_density = density        # the parameter of adjoint_gradient shadows the function
+
+
+def adjoint_gradient(m, density, sigmas, schedules, points=None):
+    """Loss and dL/d(density) of rounds(m, density, sigmas, points,
+    schedules=schedules) by reverse mode in FP64: the rounds are run
+    forward once (keeping each round's points, areas and fields), then the
+    adjoints are taken in reverse order.  value = density * (initial areas),
+    and the initial areas do not depend on the densities."""
+    pts = _f64(m.xy if points is None else points).reshape(-1, 2)
+    V = m.n_vertices
+    a0 = region_areas(m, pts[:V])
+    d = _f64(density)
+    value = d * a0
+    saved = []
+    for k, s in enumerate(sigmas):
+        verts = pts[:V]
+        area = region_areas(m, verts)
+        rho, _ = _density(m, value, area, xy=verts)
+        F = flux(rho, s)
+        res = integrate(F, pts, replay_h=schedules[k])
+        saved.append((pts, area, F))
+        pts = res.xy
+    a_end = region_areas(m, pts[:V])
+    loss = area_loss(value, a_end)
+    la, lam_value = area_loss_adj(value, a_end)
+    lam_pts = np.zeros_like(pts)
+    lam_pts[:V] += area_adj(m, la, xy=pts[:V])
+    for k in range(len(sigmas) - 1, -1, -1):
+        pk, area, F = saved[k]
+        lam_pts, lrs, ljx, ljy, lrb = integrate_adj(F, pk, schedules[k], lam_pts)
+        lam_rho = flux_adj(lrs, ljx, ljy, lrb, sigmas[k])
+        lv, lar, lxy = density_adj(m, value, area, lam_rho, xy=pk[:V])
+        lam_value = lam_value + lv
+        lam_pts[:V] += lxy
+        lam_pts[:V] += area_adj(m, lar, xy=pk[:V])
+    return loss, lam_value * a0
+
 
 
 # ------------------------------------------------------------- distortion

@@ -922,3 +922,440 @@ int ffbo_inverse(int32_t lx, int32_t ly, const float *nodes, int64_t nq, const f
     }
     return O_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Reverse mode of one round with the accepted step sizes frozen (the
+ * gradient of a loss of the final areas with respect to the region
+ * statistics).  Not part of the paper's method: written from the forward
+ * definitions above by the chain rule, each function the transpose of the
+ * linearised forward step it is named after.  Every function ADDS to its
+ * output adjoints (lam_*), except ffbo_flux_adj, which writes lam_rho.
+ * ---------------------------------------------------------------------- */
+
+/* Areas: A_r = 1/2 sum_k (x_k y_{k+1} - x_{k+1} y_k) over the region's rings,
+ * so dA/dx_k = (y_{k+1} - y_{k-1}) / 2 and dA/dy_k = (x_{k-1} - x_{k+1}) / 2. */
+int ffbo_area_adj(int64_t nv, const double *xy, int32_t n_rings, const int32_t *ring_offsets,
+                  const int32_t *ring_vidx, const int32_t *ring_region, int32_t n_regions,
+                  const double *lam_area, double *lam_xy)
+{
+    int st = check_geometry(nv, n_rings, ring_offsets, ring_vidx, ring_region, n_regions);
+    if (st) return st;
+    for (int32_t g = 0; g < n_rings; ++g) {
+        const int32_t b = ring_offsets[g], n = ring_offsets[g + 1] - b;
+        const double l = lam_area[ring_region[g]];
+        for (int32_t k = 0; k < n; ++k) {
+            const int64_t p = ring_vidx[b + k];
+            const double *prev = xy + 2 * (int64_t)ring_vidx[b + (k + n - 1) % n];
+            const double *next = xy + 2 * (int64_t)ring_vidx[b + (k + 1) % n];
+            lam_xy[2 * p] += 0.5 * l * (next[1] - prev[1]);
+            lam_xy[2 * p + 1] += 0.5 * l * (prev[0] - next[0]);
+        }
+    }
+    return O_OK;
+}
+
+/* Raster: rho_c = rho_pad + sum_r w_r cov_r(c), w_r = value_r / A_r - rho_pad,
+ * rho_pad = sum(value) / sum(A), cov_r(c) the signed area of cell c inside
+ * the region's rings.  With lam_w_r = sum_c lam_rho_c cov_r(c) (the integral
+ * of the piecewise-constant lam over the region) and
+ * lam_pad = sum_c lam_rho_c - sum_r lam_w_r:
+ *   lam_value_r += lam_w_r / A_r + lam_pad / sum(A),
+ *   lam_area_r  += -lam_w_r value_r / A_r^2 - lam_pad sum(value) / sum(A)^2.
+ * Vertices: moving the end q of an edge p -> q (direction d = q - p, points
+ * p + s d) moves each of its points by s dq, so the integral of lam over the
+ * ring changes by (d_y, -d_x) . dq times the integral over s in [0, 1] of
+ * lam(p + s d) s, and by the same with (1 - s) for the start p.  lam is
+ * constant on the pieces of the edge between grid lines. */
+static int cmp_double(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+int ffbo_density_adj(int32_t lx, int32_t ly, int64_t nv, const double *xy, int32_t n_rings,
+                     const int32_t *ring_offsets, const int32_t *ring_vidx,
+                     const int32_t *ring_region, int32_t n_regions, const double *value,
+                     const double *area, const double *lam_rho, double *lam_value,
+                     double *lam_area, double *lam_xy)
+{
+    if (lx <= 0 || ly <= 0) return O_E_INVALID;
+    int st = check_geometry(nv, n_rings, ring_offsets, ring_vidx, ring_region, n_regions);
+    if (st) return st;
+    for (int64_t k = 0; k < nv; ++k) {
+        double x = xy[2 * k], y = xy[2 * k + 1];
+        if (!isfinite(x) || !isfinite(y)) return O_E_NONFINITE;
+        if (x < 0.0 || x > lx || y < 0.0 || y > ly) return O_E_DOMAIN;
+    }
+    double sa = 0.0, sv = 0.0;
+    for (int32_t r = 0; r < n_regions; ++r) {
+        if (!(value[r] > 0.0) || !(area[r] > 0.0)) return O_E_NONPOSITIVE;
+        sa += area[r];
+        sv += value[r];
+    }
+    const double rho_pad = sv / sa;
+    double *lam_w = (double *)calloc((size_t)n_regions, sizeof(double));
+    if (!lam_w) return O_E_NOMEM;
+
+    /* lam_w_r: the cell areas of the region's rings, clipped as in ffbo_density */
+    int fail = 0;
+    poly_t ring = {0}, t1 = {0}, band = {0}, t2 = {0}, cell = {0};
+    for (int32_t g = 0; g < n_rings && !fail; ++g) {
+        const int32_t b = ring_offsets[g], n = ring_offsets[g + 1] - b;
+        if (poly_reserve(&ring, n)) { fail = 1; break; }
+        double ylo = INFINITY, yhi = -INFINITY;
+        for (int32_t k = 0; k < n; ++k) {
+            ring.x[k] = xy[2 * (int64_t)ring_vidx[b + k]];
+            ring.y[k] = xy[2 * (int64_t)ring_vidx[b + k] + 1];
+            if (ring.y[k] < ylo) ylo = ring.y[k];
+            if (ring.y[k] > yhi) yhi = ring.y[k];
+        }
+        ring.n = n;
+        int32_t j0 = (int32_t)floor(ylo), j1 = (int32_t)ceil(yhi);
+        if (j0 < 0) j0 = 0;
+        if (j1 > ly) j1 = ly;
+        double s = 0.0;
+        for (int32_t j = j0; j < j1 && !fail; ++j) {
+            if (clip_half(&ring, &t1, 1, (double)j, -1.0)) { fail = 1; break; }
+            if (clip_half(&t1, &band, 1, (double)(j + 1), 1.0)) { fail = 1; break; }
+            if (band.n < 3) continue;
+            double xlo = INFINITY, xhi = -INFINITY;
+            for (int32_t k = 0; k < band.n; ++k) {
+                if (band.x[k] < xlo) xlo = band.x[k];
+                if (band.x[k] > xhi) xhi = band.x[k];
+            }
+            int32_t i0 = (int32_t)floor(xlo), i1 = (int32_t)ceil(xhi);
+            if (i0 < 0) i0 = 0;
+            if (i1 > lx) i1 = lx;
+            for (int32_t i = i0; i < i1; ++i) {
+                if (clip_half(&band, &t2, 0, (double)i, -1.0)) { fail = 1; break; }
+                if (clip_half(&t2, &cell, 0, (double)(i + 1), 1.0)) { fail = 1; break; }
+                if (cell.n < 3) continue;
+                s += lam_rho[(int64_t)j * lx + i] * poly_area(&cell, (double)i, (double)j);
+            }
+        }
+        lam_w[ring_region[g]] += s;
+    }
+    free(ring.x); free(ring.y); free(t1.x); free(t1.y); free(band.x); free(band.y);
+    free(t2.x); free(t2.y); free(cell.x); free(cell.y);
+    if (fail) { free(lam_w); return O_E_NOMEM; }
+
+    double lam_pad = 0.0;
+    for (int64_t c = 0; c < (int64_t)lx * ly; ++c) lam_pad += lam_rho[c];
+    for (int32_t r = 0; r < n_regions; ++r) lam_pad -= lam_w[r];
+    for (int32_t r = 0; r < n_regions; ++r) {
+        lam_value[r] += lam_w[r] / area[r] + lam_pad / sa;
+        lam_area[r] += -lam_w[r] * value[r] / (area[r] * area[r]) - lam_pad * sv / (sa * sa);
+    }
+
+    /* vertices: boundary integrals of lam along every edge, weighted by w_r */
+    double *cuts = NULL;
+    int64_t cuts_cap = 0;
+    for (int32_t g = 0; g < n_rings && !fail; ++g) {
+        const int32_t b = ring_offsets[g], n = ring_offsets[g + 1] - b;
+        const int32_t r = ring_region[g];
+        const double w = value[r] / area[r] - rho_pad;
+        for (int32_t k = 0; k < n; ++k) {
+            const int64_t ip = ring_vidx[b + k], iq = ring_vidx[b + (k + 1) % n];
+            const double px = xy[2 * ip], py = xy[2 * ip + 1];
+            const double dx = xy[2 * iq] - px, dy = xy[2 * iq + 1] - py;
+            /* parameters of the crossings with the grid lines, then the ends */
+            const double xa = fmin(px, px + dx), xb = fmax(px, px + dx);
+            const double ya = fmin(py, py + dy), yb = fmax(py, py + dy);
+            const int64_t need = (int64_t)(floor(xb) - ceil(xa) + 1) +
+                                 (int64_t)(floor(yb) - ceil(ya) + 1) + 2;
+            if (need > cuts_cap) {
+                double *nc = (double *)realloc(cuts, sizeof(double) * (size_t)need);
+                if (!nc) { fail = 1; break; }
+                cuts = nc;
+                cuts_cap = need;
+            }
+            int64_t nc = 0;
+            cuts[nc++] = 0.0;
+            cuts[nc++] = 1.0;
+            for (double X = ceil(xa); X <= xb; X += 1.0) {
+                const double s = (X - px) / dx;
+                if (dx != 0.0 && s > 0.0 && s < 1.0) cuts[nc++] = s;
+            }
+            for (double Y = ceil(ya); Y <= yb; Y += 1.0) {
+                const double s = (Y - py) / dy;
+                if (dy != 0.0 && s > 0.0 && s < 1.0) cuts[nc++] = s;
+            }
+            qsort(cuts, (size_t)nc, sizeof(double), cmp_double);
+            double I0 = 0.0, I1 = 0.0;    /* integrals of lam (1 - s) and lam s */
+            for (int64_t q = 0; q + 1 < nc; ++q) {
+                const double s0 = cuts[q], s1 = cuts[q + 1];
+                if (!(s1 > s0)) continue;
+                const double sm = 0.5 * (s0 + s1);
+                int32_t i = (int32_t)floor(px + sm * dx), j = (int32_t)floor(py + sm * dy);
+                if (i < 0) i = 0;
+                if (i > lx - 1) i = lx - 1;
+                if (j < 0) j = 0;
+                if (j > ly - 1) j = ly - 1;
+                const double l = lam_rho[(int64_t)j * lx + i];
+                const double m2 = 0.5 * (s1 * s1 - s0 * s0);
+                I1 += l * m2;
+                I0 += l * ((s1 - s0) - m2);
+            }
+            lam_xy[2 * ip] += w * dy * I0;
+            lam_xy[2 * ip + 1] += -w * dx * I0;
+            lam_xy[2 * iq] += w * dy * I1;
+            lam_xy[2 * iq + 1] += -w * dx * I1;
+        }
+    }
+    free(cuts);
+    free(lam_w);
+    return fail ? O_E_NOMEM : O_OK;
+}
+
+/* Flux series (ffbo_flux) transposed.  The forward is linear in rho:
+ *   S = C_y C_x rho, rts = G o S, A = C_y^T rts, B = C_y^T (W_x o rts),
+ *   C = S_y^T (W_y o rts), rho_s = C_x^T A / N, J_x = S_x^T B, J_y = C_x^T C,
+ *   rho_bar = rts_00 / N,
+ * with C_x[m][i] = cos(pi m (i+1/2)/lx), S_x[m][i] = sin(...), the same in y,
+ * W_x = (ly/pi) m / (m^2 ly^2 + n^2 lx^2) (m > 0), W_y = (lx/pi) n / (...)
+ * (n > 0) and G the Eq. 7 factor times the blur.  Its transpose:
+ *   Abar = C_x lam_rs / N, Bbar = S_x lam_jx, Cbar = C_x lam_jy,
+ *   rtsbar = C_y Abar + W_x o (C_y Bbar) + W_y o (S_y Cbar) (+ lam_rb / N at 00),
+ *   lam_rho = C_x^T C_y^T (G o rtsbar).
+ * Writes lam_rho [ly][lx]. */
+int ffbo_flux_adj(int32_t lx, int32_t ly, double sigma, const double *lam_rs,
+                  const double *lam_jx, const double *lam_jy, double lam_rb, double *lam_rho)
+{
+    if (lx <= 0 || ly <= 0 || !(sigma >= 0.0)) return O_E_INVALID;
+    const int64_t N = (int64_t)lx * ly;
+    double *A = (double *)malloc(sizeof(double) * N);
+    double *B = (double *)malloc(sizeof(double) * N);
+    double *C = (double *)malloc(sizeof(double) * N);
+    double *R = (double *)malloc(sizeof(double) * N);
+    double *T = (double *)malloc(sizeof(double) * N);
+    double *tx = make_table(lx), *ty = make_table(ly);
+    if (!A || !B || !C || !R || !T || !tx || !ty) {
+        free(A); free(B); free(C); free(R); free(T); free(tx); free(ty);
+        return O_E_NOMEM;
+    }
+    const double LX = lx, LY = ly;
+    /* along x: Abar[j][m], Bbar[j][m], Cbar[j][m] */
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t m = 0; m < lx; ++m) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int32_t i = 0; i < lx; ++i) {
+                const int64_t q = (int64_t)j * lx + i;
+                const double cx = tcos(tx, lx, m, i), sx = tsin(tx, lx, m, i);
+                a += lam_rs[q] * cx;
+                b += lam_jx[q] * sx;
+                c += lam_jy[q] * cx;
+            }
+            A[(int64_t)j * lx + m] = a / (double)N;
+            B[(int64_t)j * lx + m] = b;
+            C[(int64_t)j * lx + m] = c;
+        }
+    /* along y: rtsbar[n][m], times G */
+#pragma omp parallel for schedule(static)
+    for (int32_t n = 0; n < ly; ++n)
+        for (int32_t m = 0; m < lx; ++m) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int32_t j = 0; j < ly; ++j) {
+                const int64_t q = (int64_t)j * lx + m;
+                const double cy = tcos(ty, ly, n, j), sy = tsin(ty, ly, n, j);
+                a += A[q] * cy;
+                b += B[q] * cy;
+                c += C[q] * sy;
+            }
+            const double den = (double)m * m * LY * LY + (double)n * n * LX * LX;
+            double rb = a;
+            if (m > 0) rb += (LY / PI) * ((double)m / den) * b;
+            if (n > 0) rb += (LX / PI) * ((double)n / den) * c;
+            if (m == 0 && n == 0) rb += lam_rb / (double)N;
+            const double f = 4.0 / ((m == 0 ? 2.0 : 1.0) * (n == 0 ? 2.0 : 1.0));
+            const double k2 = (double)m * m / (LX * LX) + (double)n * n / (LY * LY);
+            R[(int64_t)n * lx + m] = rb * f * exp(-PI * PI * sigma * sigma * k2 / 2.0);
+        }
+    /* lam_rho = C_x^T C_y^T R: first over n, then over m */
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t m = 0; m < lx; ++m) {
+            double s = 0.0;
+            for (int32_t n = 0; n < ly; ++n) s += R[(int64_t)n * lx + m] * tcos(ty, ly, n, j);
+            T[(int64_t)j * lx + m] = s;
+        }
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < ly; ++j)
+        for (int32_t i = 0; i < lx; ++i) {
+            double s = 0.0;
+            for (int32_t m = 0; m < lx; ++m) s += T[(int64_t)j * lx + m] * tcos(tx, lx, m, i);
+            lam_rho[(int64_t)j * lx + i] = s;
+        }
+    free(A); free(B); free(C); free(R); free(T); free(tx); free(ty);
+    return O_OK;
+}
+
+/* One velocity lookup (velocity_at) and its transpose: given kbar, the
+ * adjoint of the returned v, add to the node field adjoints and return the
+ * adjoint of the position (zero in a clamped coordinate).  With the node
+ * velocities v_n = (s_x J_x, s_y J_y)_c / rt_c, rt_c = (1 - t) rho_s_c +
+ * t rho_bar (ghost nodes mirror an inside node c with signs s_x, s_y) and
+ * the bilinear weights w_n:  dv/dJ_x,c = w_n s_x / rt_c (x component),
+ * dv/drho_s,c = -w_n v_n (1 - t) / rt_c, dv/drho_bar = -w_n v_n t / rt_c. */
+typedef struct { double *rs, *jx, *jy, rb; } field_adj_t;
+
+static void velocity_at_adj(const field_t *F, double t, double qx, double qy, double kbx,
+                            double kby, field_adj_t *G, double *qbx, double *qby)
+{
+    const int inx = qx > 0.0 && qx < F->lx, iny = qy > 0.0 && qy < F->ly;
+    if (qx < 0.0) qx = 0.0;
+    if (qx > F->lx) qx = F->lx;
+    if (qy < 0.0) qy = 0.0;
+    if (qy > F->ly) qy = F->ly;
+    const double u = qx - 0.5, w = qy - 0.5;
+    const double fu = floor(u), fw = floor(w);
+    const int32_t i0 = (int32_t)fu, j0 = (int32_t)fw;
+    const double a = u - fu, b = w - fw;
+    double vx[4], vy[4];
+    const double wt[4] = {(1 - a) * (1 - b), a * (1 - b), (1 - a) * b, a * b};
+    for (int q = 0; q < 4; ++q) {
+        int32_t i = i0 + (q & 1), j = j0 + (q >> 1);
+        double sx = 1.0, sy = 1.0;
+        if (i < 0) { i = 0; sx = -sx; }
+        if (i >= F->lx) { i = F->lx - 1; sx = -sx; }
+        if (j < 0) { j = 0; sy = -sy; }
+        if (j >= F->ly) { j = F->ly - 1; sy = -sy; }
+        const int64_t c = (int64_t)j * F->lx + i;
+        const double rt = (1.0 - t) * F->rho_s[c] + t * F->rho_bar;
+        vx[q] = sx * F->jx[c] / rt;
+        vy[q] = sy * F->jy[c] / rt;
+        const double dot = kbx * vx[q] + kby * vy[q];
+        G->jx[c] += wt[q] * kbx * sx / rt;
+        G->jy[c] += wt[q] * kby * sy / rt;
+        G->rs[c] += -wt[q] * dot * (1.0 - t) / rt;
+        G->rb += -wt[q] * dot * t / rt;
+    }
+    /* dv/dq_x = (1 - b)(v_10 - v_00) + b (v_11 - v_01), dv/dq_y likewise */
+    const double dxx = (1 - b) * (vx[1] - vx[0]) + b * (vx[3] - vx[2]);
+    const double dxy = (1 - b) * (vy[1] - vy[0]) + b * (vy[3] - vy[2]);
+    const double dyx = (1 - a) * (vx[2] - vx[0]) + a * (vx[3] - vx[1]);
+    const double dyy = (1 - a) * (vy[2] - vy[0]) + a * (vy[3] - vy[1]);
+    *qbx = inx ? kbx * dxx + kby * dxy : 0.0;
+    *qby = iny ? kbx * dyx + kby * dyy : 0.0;
+}
+
+/* The integration from t = 0 with the given accepted steps h[0..S) (as
+ * ffbo_integrate replays them: stage s of a step at y evaluates v at
+ * Y_s = y + h sum_{q<s} a_sq k_q and time t + c_s h, the step ends at
+ * y + h sum_s b_s k_s), transposed.  lam_xy [n][2]: in, dL/dy at the end;
+ * out, dL/dy at the start.  The field adjoints lam_rs, lam_jx, lam_jy
+ * ([ly][lx]) and *lam_rb are added to.  The states before every step are
+ * recomputed and kept (n * S * 2 doubles). */
+int ffbo_integrate_adj(int32_t lx, int32_t ly, const double *rho_s, const double *jx,
+                       const double *jy, double rho_bar, int64_t n, const double *xy0,
+                       const double *h, int32_t S, double *lam_xy, double *lam_rs,
+                       double *lam_jx, double *lam_jy, double *lam_rb)
+{
+    if (lx <= 0 || ly <= 0 || n < 0 || S < 0 || !(rho_bar > 0.0)) return O_E_INVALID;
+    const field_t F = {lx, ly, rho_s, jx, jy, rho_bar};
+    double *ys = (double *)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1) * (size_t)(S + 1));
+    double *ts = (double *)malloc(sizeof(double) * (size_t)(S + 1));
+    if (!ys || !ts) { free(ys); free(ts); return O_E_NOMEM; }
+    /* forward: the state before every step and the step start times */
+    memcpy(ys, xy0, sizeof(double) * 2 * (size_t)n);
+    double t = 0.0;
+    for (int32_t s = 0; s < S; ++s) {
+        ts[s] = t;
+        const double *y = ys + 2 * (size_t)n * s;
+        double *y1 = ys + 2 * (size_t)n * (s + 1);
+#pragma omp parallel for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            double kx[6], ky[6];
+            double ex = y[2 * p], ey = y[2 * p + 1];
+            for (int q = 0; q < 6; ++q) {
+                double qx = y[2 * p], qy = y[2 * p + 1];
+                for (int r = 0; r < q; ++r) {
+                    qx += h[s] * DP_A[q][r] * kx[r];
+                    qy += h[s] * DP_A[q][r] * ky[r];
+                }
+                velocity_at(&F, t + DP_C[q] * h[s], qx, qy, &kx[q], &ky[q]);
+            }
+            for (int q = 0; q < 6; ++q) {
+                ex += h[s] * DP_A[6][q] * kx[q];
+                ey += h[s] * DP_A[6][q] * ky[q];
+            }
+            y1[2 * p] = ex;
+            y1[2 * p + 1] = ey;
+        }
+        t = (s == S - 1) ? 1.0 : t + h[s];
+    }
+    /* reverse: per point, the steps last to first; field adjoints are summed
+     * in one buffer per thread and added up at the end */
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    const int64_t NF = (int64_t)lx * ly;
+    double *acc = (double *)calloc((size_t)nt * 3 * (size_t)NF, sizeof(double));
+    double *acc_rb = (double *)calloc((size_t)nt, sizeof(double));
+    if (!acc || !acc_rb) { free(acc); free(acc_rb); free(ys); free(ts); return O_E_NOMEM; }
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        field_adj_t G;
+        G.rs = acc + (size_t)tid * 3 * (size_t)NF;
+        G.jx = G.rs + NF;
+        G.jy = G.jx + NF;
+        G.rb = 0.0;
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            double lx_ = lam_xy[2 * p], ly_ = lam_xy[2 * p + 1];
+            for (int32_t s = S - 1; s >= 0; --s) {
+                const double *y = ys + 2 * (size_t)n * s;
+                const double hs = h[s];
+                double kx[6], ky[6], Qx[6], Qy[6];
+                for (int q = 0; q < 6; ++q) {
+                    double qx = y[2 * p], qy = y[2 * p + 1];
+                    for (int r = 0; r < q; ++r) {
+                        qx += hs * DP_A[q][r] * kx[r];
+                        qy += hs * DP_A[q][r] * ky[r];
+                    }
+                    Qx[q] = qx;
+                    Qy[q] = qy;
+                    velocity_at(&F, ts[s] + DP_C[q] * hs, qx, qy, &kx[q], &ky[q]);
+                }
+                /* kbar_q = h b_q lam' + h sum_{r>q} a_rq Ybar_r, Ybar_q = Jv_q^T kbar_q */
+                double Yx[6], Yy[6];
+                double nx = lx_, ny = ly_;
+                for (int q = 5; q >= 0; --q) {
+                    double kbx = hs * DP_A[6][q] * lx_, kby = hs * DP_A[6][q] * ly_;
+                    for (int r = q + 1; r < 6; ++r) {
+                        kbx += hs * DP_A[r][q] * Yx[r];
+                        kby += hs * DP_A[r][q] * Yy[r];
+                    }
+                    velocity_at_adj(&F, ts[s] + DP_C[q] * hs, Qx[q], Qy[q], kbx, kby, &G,
+                                    &Yx[q], &Yy[q]);
+                    nx += Yx[q];
+                    ny += Yy[q];
+                }
+                lx_ = nx;
+                ly_ = ny;
+            }
+            lam_xy[2 * p] = lx_;
+            lam_xy[2 * p + 1] = ly_;
+        }
+        acc_rb[tid] = G.rb;
+    }
+    for (int k = 0; k < nt; ++k) {
+        const double *a = acc + (size_t)k * 3 * (size_t)NF;
+        for (int64_t c = 0; c < NF; ++c) {
+            lam_rs[c] += a[c];
+            lam_jx[c] += a[NF + c];
+            lam_jy[c] += a[2 * NF + c];
+        }
+        *lam_rb += acc_rb[k];
+    }
+    free(acc);
+    free(acc_rb);
+    free(ys);
+    free(ts);
+    return O_OK;
+}
