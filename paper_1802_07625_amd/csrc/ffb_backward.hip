@@ -374,24 +374,40 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
     if (e == hipSuccess) e = launch_fill_f64(dL_dvalue, R, 0.0, s);
     if (e == hipSuccess) e = launch_area_adj(ctx, &recs[used - 1].g, dL_darea, t->lam_xy);
     bool pending = false;           // an area adjoint from a density record waits
+    bool cleared = false;           // the next density record's accumulators are zero
     for (int64_t k = used - 2; k >= 0 && e == hipSuccess; --k) {
         tape_rec &r = recs[k];
         switch (r.kind) {
-        case 'I':
-            e = launch_fill_f32(reinterpret_cast<float *>(t->lam_f), 4 * nf, 0.f, s);
-            if (e == hipSuccess) e = launch_fill_f64(t->lam_rb, 1, 0.0, s);
+        case 'I': {
+            // one launch zeroes this round's accumulators: the field and
+            // rho_bar adjoints, and those of the density record that follows
+            zero_spans z{};
+            z.p[0] = t->lam_f;
+            z.words[0] = 4 * nf;
+            z.p[1] = t->lam_rb;
+            z.words[1] = 2;
+            z.p[2] = t->lam_area;
+            z.words[2] = 2 * (int64_t)R;
+            z.p[3] = density_adj_total(ctx);
+            z.words[3] = 2;
+            z.p[4] = ctx->lam_w;
+            z.words[4] = 2 * (int64_t)R;
+            e = launch_zero_spans(z, s);
+            cleared = e == hipSuccess;
             if (e == hipSuccess)
                 e = launch_advect_adj(ctx, r.fields, r.rho_bar, &r.at, t->lam_xy, t->lam_f,
                                       t->lam_rb);
             break;
+        }
         case 'F':
             e = launch_flux_adj(ctx, r.sigma, t->lam_f, t->lam_rb, t->lam_rho);
             break;
         case 'D':
-            e = launch_fill_f64(t->lam_area, R, 0.0, s);
+            if (!cleared) e = launch_fill_f64(t->lam_area, R, 0.0, s);
             if (e == hipSuccess)
                 e = launch_density_adj(ctx, &r.g, r.value, r.area, t->lam_rho, dL_dvalue,
-                                       t->lam_area, t->lam_xy);
+                                       t->lam_area, t->lam_xy, cleared);
+            cleared = false;
             pending = true;
             break;
         case 'A':

@@ -136,6 +136,14 @@ hipError_t launch_point_order(ffb_ctx *ctx, const float2 *xy, int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+// Several buffers zeroed by one launch: span q is words[q] 4-byte words at p[q]
+// (unused spans: words 0).
+constexpr int kZeroSpans = 6;
+struct zero_spans {
+    void *p[kZeroSpans];
+    int64_t words[kZeroSpans];
+};
+hipError_t launch_zero_spans(const zero_spans &z, hipStream_t s);
 
 hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                        double *area, double *err, double *max_abs_err);
@@ -184,9 +192,14 @@ hipError_t launch_advect(ffb_ctx *ctx, const float4 *fields, const double *rho_b
 // float4 (J_x, J_y, rho_s, unused); lam_xy is [n][2] FP64.
 hipError_t launch_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *lam_area,
                            double *lam_xy);
+// `cleared`: the caller has already zeroed the context's density-adjoint
+// accumulators (density_adj_scratch) on the stream.
 hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                               const double *area, const float *lam_rho, double *lam_value,
-                              double *lam_area, double *lam_xy);
+                              double *lam_area, double *lam_xy, bool cleared = false);
+// The context's accumulators that launch_density_adj starts from zero: the
+// sum of lam_rho (one double) and the per-region coverage sums (R doubles).
+inline double *density_adj_total(ffb_ctx *ctx) { return ctx->red + 513; }
 hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
                            const double *lam_rho_bar, float *lam_rho);
 hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,

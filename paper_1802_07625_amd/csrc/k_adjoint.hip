@@ -816,17 +816,19 @@ hipError_t launch_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *la
 
 hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                               const double *area, const float *lam_rho, double *lam_value,
-                              double *lam_area, double *lam_xy)
+                              double *lam_area, double *lam_xy, bool cleared)
 {
     hipStream_t s = ctx->stream;
     // w_r and rho_pad of the forward, recomputed from value and area
-    double *pad = ctx->red + 512, *total = ctx->red + 513;
+    double *pad = ctx->red + 512, *total = density_adj_total(ctx);
     hipError_t e = launch_density_weights(ctx, g->n_regions, value, area, pad);
     if (e != hipSuccess) return e;
-    e = launch_fill_f64(total, 1, 0.0, s);
-    if (e != hipSuccess) return e;
-    e = launch_fill_f64(ctx->lam_w, g->n_regions, 0.0, s);
-    if (e != hipSuccess) return e;
+    if (!cleared) {
+        e = launch_fill_f64(total, 1, 0.0, s);
+        if (e != hipSuccess) return e;
+        e = launch_fill_f64(ctx->lam_w, g->n_regions, 0.0, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_row_suffix, dim3(ctx->ly), dim3(kThreads), 0, s, lam_rho, ctx->lx,
                        ctx->acc, total);
     if (g->n_entries > 0) {

@@ -231,6 +231,17 @@ __global__ __launch_bounds__(kFinThreads) void kb_finalize(batch_view bv,
     }
 }
 
+// Zero up to kZeroSpans device spans (4-byte words each) in one launch.
+__global__ __launch_bounds__(256) void k_zero_spans(zero_spans z)
+{
+    for (int q = 0; q < kZeroSpans; ++q) {
+        uint32_t *p = static_cast<uint32_t *>(z.p[q]);
+        const int64_t n = z.words[q];
+        for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+            p[i] = 0u;
+    }
+}
+
 // Number of maps still iterating.
 __global__ __launch_bounds__(256) void kb_count_active(const int32_t *__restrict__ active, int n,
                                                        int32_t *__restrict__ out)
@@ -264,6 +275,16 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s)
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
 {
     return fill<double>(k_fill_f64, p, n, v, s);
+}
+hipError_t launch_zero_spans(const zero_spans &z, hipStream_t s)
+{
+    int64_t most = 0;
+    for (int q = 0; q < kZeroSpans; ++q) most = z.words[q] > most ? z.words[q] : most;
+    if (most == 0) return hipSuccess;
+    int64_t blocks = (most + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_spans, dim3((unsigned)blocks), dim3(256), 0, s, z);
+    return hipGetLastError();
 }
 
 hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *value,

@@ -612,8 +612,10 @@ __global__ __launch_bounds__(512) void k_adj_rows(int lx, const float2 *__restri
     }
 }
 
-// Column pass on rows m0, m0 + 1 of the transposed planes [lx][ly]: the
-// transforms along y, the spectral weights, then the DCT-III along y.
+// Column pass on columns m0, m0 + 1 of the row-pass outputs [ly][lx]
+// (read and written row-major, one 8-byte access per row, as the forward's
+// column pass): the transforms along y, the spectral weights, then the
+// DCT-III along y into out [ly][lx].
 __global__ __launch_bounds__(512) void k_adj_cols(const float *__restrict__ ta,
                                                   const float *__restrict__ tb,
                                                   const float *__restrict__ tc, int lx, int ly,
@@ -624,17 +626,19 @@ __global__ __launch_bounds__(512) void k_adj_cols(const float *__restrict__ ta,
 {
     __shared__ float2 sa[kMaxN], sb[kMaxN], A[kMaxN], B[kMaxN], stw[kMaxN / 2];
     const int N = ly;
+    const int64_t cs = lx / 2;                  // row stride in pairs
     load_twiddles(stw, tw, N);
-    const int m0 = 2 * blockIdx.x;
-    const float *a0 = ta + (int64_t)m0 * N, *a1 = a0 + N;
-    const float *b0 = tb + (int64_t)m0 * N, *b1 = b0 + N;
-    const float *c0 = tc + (int64_t)m0 * N, *c1 = c0 + N;
-    dct2_rows_pair(sa, sb, A, N, stw, tq, [&](int i) { return make_float2(a0[i], a1[i]); });
-    dct2_rows_pair(sa, sb, B, N, stw, tq, [&](int i) { return make_float2(b0[i], b1[i]); });
+    const int m0 = 2 * col_pair(blockIdx.x, lx / 2);
+    const float2 *pa_ = reinterpret_cast<const float2 *>(ta + m0);
+    const float2 *pb_ = reinterpret_cast<const float2 *>(tb + m0);
+    const float2 *pc_ = reinterpret_cast<const float2 *>(tc + m0);
+    dct2_rows_pair(sa, sb, A, N, stw, tq, [&](int i) { return pa_[i * cs]; });
+    dct2_rows_pair(sa, sb, B, N, stw, tq, [&](int i) { return pb_[i * cs]; });
     // C: DST-II along y, kept in the FFT scratch for the combination below
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const float sg = (i & 1) ? -1.f : 1.f;
-        sa[mk_pos(i, N)] = make_float2(sg * c0[i], sg * c1[i]);
+        const float2 c = pc_[i * cs];
+        sa[mk_pos(i, N)] = make_float2(sg * c.x, sg * c.y);
     }
     float2 *Z = fft_lds(sa, sb, N, stw, false);
     float2 *C = (Z == sa) ? sb : sa;
@@ -676,12 +680,8 @@ __global__ __launch_bounds__(512) void k_adj_cols(const float *__restrict__ ta,
     __syncthreads();
     dct3_input(sa, N, tq, [&](int n) { return B[n]; });
     float2 *v = fft_lds(sa, sb, N, stw, true);
-    float *o0 = out + (int64_t)m0 * N, *o1 = o0 + N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const float2 y = dct3_output(v, i, N);
-        o0[i] = y.x;
-        o1[i] = y.y;
-    }
+    float2 *o = reinterpret_cast<float2 *>(out + m0);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) o[i * cs] = dct3_output(v, i, N);
 }
 
 // Final row pass: DCT-III along x of the [ly][lx] plane.
@@ -1038,15 +1038,9 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
                        lam_fields, lx, ly, ctx->pa, ctx->pb, ctx->pc);
     hipLaunchKernelGGL(k_adj_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, lx, ctx->tw_x,
                        ctx->tq_x, ctx->pa, ctx->pb, ctx->pc);
-    // [ly][lx] -> [lx][ly], the three planes in one launch
-    hipLaunchKernelGGL(k_transpose<float>, dim3((lx + 31) / 32, (ly + 31) / 32, 3), dim3(256), 0,
-                       s, ctx->pa, ctx->pb, ctx->pc, ctx->t1, ctx->t2, ctx->t3, ly, lx);
-    hipLaunchKernelGGL(k_adj_cols, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->t1, ctx->t2,
-                       ctx->t3, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->pb);
-    // [lx][ly] -> [ly][lx]
-    hipLaunchKernelGGL(k_transpose<float>, dim3((ly + 31) / 32, (lx + 31) / 32, 1), dim3(256), 0,
-                       s, ctx->pb, ctx->pb, ctx->pb, ctx->pc, ctx->pc, ctx->pc, lx, ly);
-    hipLaunchKernelGGL(k_adj_rows_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->pc, lx,
+    hipLaunchKernelGGL(k_adj_cols, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->pa, ctx->pb,
+                       ctx->pc, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->t1);
+    hipLaunchKernelGGL(k_adj_rows_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->t1, lx,
                        ctx->tw_x, ctx->tq_x, lam_rho);
     return hipGetLastError();
 }
