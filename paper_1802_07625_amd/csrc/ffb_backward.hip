@@ -379,8 +379,9 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
         tape_rec &r = recs[k];
         switch (r.kind) {
         case 'I': {
-            // one launch zeroes this round's accumulators: the field and
-            // rho_bar adjoints, and those of the density record that follows
+            // this round's accumulators (the field and rho_bar adjoints, and
+            // those of the density record that follows) are zeroed by the
+            // integration adjoint's first launch
             zero_spans z{};
             z.p[0] = t->lam_f;
             z.words[0] = 4 * nf;
@@ -392,11 +393,9 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
             z.words[3] = 2;
             z.p[4] = ctx->lam_w;
             z.words[4] = 2 * (int64_t)R;
-            e = launch_zero_spans(z, s);
+            e = launch_advect_adj(ctx, r.fields, r.rho_bar, &r.at, t->lam_xy, t->lam_f,
+                                  t->lam_rb, &z);
             cleared = e == hipSuccess;
-            if (e == hipSuccess)
-                e = launch_advect_adj(ctx, r.fields, r.rho_bar, &r.at, t->lam_xy, t->lam_f,
-                                      t->lam_rb);
             break;
         }
         case 'F':

@@ -202,9 +202,11 @@ hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double 
 inline double *density_adj_total(ffb_ctx *ctx) { return ctx->red + 513; }
 hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
                            const double *lam_rho_bar, float *lam_rho);
+// `clear` (optional): spans zeroed on the stream before any adjoint is added
+// (by the launch that also sums the step start times).
 hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                              const advect_tape *tape, double *lam_xy, float4 *lam_fields,
-                             double *lam_rho_bar);
+                             double *lam_rho_bar, const zero_spans *clear = nullptr);
 
 // ---------------------------------------------------------------- inverse
 // Workspace of the inverse of the piecewise-linear T (grown on demand).

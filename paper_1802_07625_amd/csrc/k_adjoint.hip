@@ -454,9 +454,16 @@ __device__ inline bool adj_ok(const AdjParams &p, int &S)
 }
 
 // Start times of the steps, summed in the order the integration summed them,
-// and the record check.
-__global__ void k_adj_times(AdjParams p)
+// and the record check (block 0, thread 0); every block also takes part in
+// zeroing the spans `z` (accumulators the caller wants cleared first).
+__global__ __launch_bounds__(256) void k_adj_times(AdjParams p, zero_spans z)
 {
+    for (int q = 0; q < kZeroSpans; ++q) {
+        uint32_t *w = static_cast<uint32_t *>(z.p[q]);
+        for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < z.words[q];
+             i += (int64_t)gridDim.x * 256)
+            w[i] = 0u;
+    }
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     const int S = *p.count;
@@ -846,9 +853,9 @@ hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double 
 
 hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
                              const advect_tape *tape, double *lam_xy, float4 *lam_fields,
-                             double *lam_rho_bar)
+                             double *lam_rho_bar, const zero_spans *clear)
 {
-    if (tape->n == 0) return hipSuccess;
+    if (tape->n == 0) return clear ? launch_zero_spans(*clear, ctx->stream) : hipSuccess;
     if (ctx->adj_t_cap < tape->cap || ctx->adj_jac_cap < (int64_t)tape->cap * tape->n)
         return hipErrorInvalidValue;
     AdjParams p;
@@ -875,7 +882,14 @@ hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *r
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(max_tiles, 8 * (int64_t)cus));
-    hipLaunchKernelGGL(k_adj_times, dim3(1), dim3(64), 0, s, p);
+    zero_spans z{};
+    int64_t most = 0;
+    if (clear) {
+        z = *clear;
+        for (int q = 0; q < kZeroSpans; ++q) most = std::max<int64_t>(most, z.words[q]);
+    }
+    const int64_t zb = std::min<int64_t>(4096, std::max<int64_t>(1, (most + 255) / 256));
+    hipLaunchKernelGGL(k_adj_times, dim3((unsigned)zb), dim3(256), 0, s, p, z);
     hipLaunchKernelGGL(k_adj_jacobian, dim3((unsigned)grid), dim3(kThreads), 0, s, p);
     hipLaunchKernelGGL(k_adj_scan, dim3((unsigned)pt_tiles), dim3(kThreads), 0, s, p);
     hipLaunchKernelGGL(k_adj_fields, dim3((unsigned)grid), dim3(kThreads), 0, s, p);

@@ -545,20 +545,15 @@ __device__ void dct2_rows_pair(float2 *sa, float2 *sb, float2 *out, int N, const
     dct2_pair(sa, sb, out, N, stw, tq);
 }
 
-// Transpose of the ghost fill: every ghost entry of lam_fields is added to
-// the node it mirrors, with the parity sign of its component (J_x odd across
-// x edges, J_y odd across y edges, rho_s even).  Writes the node adjoints as
-// planes [ly][lx]: rho_s -> prs, J_x -> pjx, J_y -> pjy.
-__global__ __launch_bounds__(256) void k_adj_fold(const float4 *__restrict__ lam, int lx, int ly,
-                                                  float *__restrict__ prs, float *__restrict__ pjx,
-                                                  float *__restrict__ pjy)
+// Transpose of the ghost fill at node (i, j): the node's own entry of
+// lam_fields plus every ghost entry that mirrors it, with the parity sign of
+// its component (J_x odd across x edges, J_y odd across y edges, rho_s
+// even).  Returns (J_x, J_y, rho_s) adjoints.
+__device__ inline float3 fold_node(const float4 *__restrict__ lam, int lx, int ly, int i, int j)
 {
-    const int64_t c = blockIdx.x * 256ll + threadIdx.x;
-    if (c >= (int64_t)lx * ly) return;
-    const int i = (int)(c % lx), j = (int)(c / lx);
     const int pitch = lx + 2;
     int ii[2] = {i, 0}, jj[2] = {j, 0};
-    float sxs[2] = {1.f, -1.f}, sys[2] = {1.f, -1.f};
+    const float sxs[2] = {1.f, -1.f}, sys[2] = {1.f, -1.f};
     int ni = 1, nj = 1;
     if (i == 0) ii[ni++] = -1;
     else if (i == lx - 1) ii[ni++] = lx;
@@ -572,40 +567,47 @@ __global__ __launch_bounds__(256) void k_adj_fold(const float4 *__restrict__ lam
             ay += sys[q] * v.y;
             ar += v.z;
         }
-    prs[c] = ar;
-    pjx[c] = ax;
-    pjy[c] = ay;
+    return make_float3(ax, ay, ar);
 }
 
-// Row pass along x of the three adjoint planes, in place (each workgroup
-// owns rows j0, j0 + 1): rho_s -> DCT-II, J_x -> DST-II, J_y -> DCT-II.
-__global__ __launch_bounds__(512) void k_adj_rows(int lx, const float2 *__restrict__ tw,
+// Row pass along x of the three node adjoints, folded from the ghosted
+// layout (fold_node) as they are read (each workgroup owns rows j0, j0 + 1):
+// rho_s -> DCT-II into pa, J_x -> DST-II into pb, J_y -> DCT-II into pc
+// ([ly][lx] planes).
+__global__ __launch_bounds__(512) void k_adj_rows(const float4 *__restrict__ lam, int lx, int ly,
+                                                  const float2 *__restrict__ tw,
                                                   const float2 *__restrict__ tq,
                                                   float *__restrict__ pa, float *__restrict__ pb,
                                                   float *__restrict__ pc)
 {
     __shared__ float2 sa[kMaxN], sb[kMaxN], o[kMaxN], stw[kMaxN / 2];
+    __shared__ float3 fo[2][kMaxN];
     const int N = lx;
     load_twiddles(stw, tw, N);
-    const int64_t j0 = 2 * (int64_t)blockIdx.x;
-    float *a0 = pa + j0 * N, *a1 = a0 + N;
-    float *b0 = pb + j0 * N, *b1 = b0 + N;
-    float *c0 = pc + j0 * N, *c1 = c0 + N;
-    dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) { return make_float2(a0[i], a1[i]); });
+    const int j0 = 2 * (int)blockIdx.x;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        fo[0][i] = fold_node(lam, lx, ly, i, j0);
+        fo[1][i] = fold_node(lam, lx, ly, i, j0 + 1);
+    }
+    __syncthreads();
+    float *a0 = pa + (int64_t)j0 * N, *a1 = a0 + N;
+    float *b0 = pb + (int64_t)j0 * N, *b1 = b0 + N;
+    float *c0 = pc + (int64_t)j0 * N, *c1 = c0 + N;
+    dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) { return make_float2(fo[0][i].z, fo[1][i].z); });
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
         a0[m] = o[m].x;
         a1[m] = o[m].y;
     }
     dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) {
         const float sg = (i & 1) ? -1.f : 1.f;
-        return make_float2(sg * b0[i], sg * b1[i]);
+        return make_float2(sg * fo[0][i].x, sg * fo[1][i].x);
     });
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
         const float2 v = m ? o[N - m] : make_float2(0.f, 0.f);
         b0[m] = v.x;
         b1[m] = v.y;
     }
-    dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) { return make_float2(c0[i], c1[i]); });
+    dct2_rows_pair(sa, sb, o, N, stw, tq, [&](int i) { return make_float2(fo[0][i].y, fo[1][i].y); });
     for (int m = threadIdx.x; m < N; m += blockDim.x) {
         c0[m] = o[m].x;
         c1[m] = o[m].y;
@@ -1033,11 +1035,8 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
 {
     hipStream_t s = ctx->stream;
     const int lx = ctx->lx, ly = ctx->ly;
-    const int64_t cells = (int64_t)lx * ly;
-    hipLaunchKernelGGL(k_adj_fold, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s,
-                       lam_fields, lx, ly, ctx->pa, ctx->pb, ctx->pc);
-    hipLaunchKernelGGL(k_adj_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, lx, ctx->tw_x,
-                       ctx->tq_x, ctx->pa, ctx->pb, ctx->pc);
+    hipLaunchKernelGGL(k_adj_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, lam_fields, lx, ly,
+                       ctx->tw_x, ctx->tq_x, ctx->pa, ctx->pb, ctx->pc);
     hipLaunchKernelGGL(k_adj_cols, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->pa, ctx->pb,
                        ctx->pc, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->t1);
     hipLaunchKernelGGL(k_adj_rows_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->t1, lx,
