@@ -374,9 +374,10 @@ int ffb_area_error(ffb_ctx *ctx, const ffb_geometry *g, const double *value, dou
     if (st) return st;
     if (!value || !area || !err || !max_abs_err)
         return fail(ctx, FFB_E_INVALID, "ffb_area_error: NULL output or value%s");
-    st = tape_on_area(ctx, g);
+    float2 *snap = nullptr;
+    st = tape_on_area(ctx, g, &snap);
     if (st) return st;
-    hipError_t e = launch_area(ctx, g, value, area, err, max_abs_err);
+    hipError_t e = launch_area(ctx, g, value, area, err, max_abs_err, snap);
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_area_error launch");
 }
 
@@ -390,9 +391,10 @@ int ffb_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const 
         return fail(ctx, FFB_E_INVALID, "ffb_density: NULL argument%s");
     hipError_t e = ensure_region_capacity(ctx, g->n_regions);
     if (e != hipSuccess) return hip_fail(ctx, e, "ffb_density workspace");
-    st = tape_on_density(ctx, g, value, area);
+    density_snap snap;
+    st = tape_on_density(ctx, g, value, area, &snap);
     if (st) return st;
-    e = launch_density(ctx, g, value, area, rho, rho_pad);
+    e = launch_density(ctx, g, value, area, rho, rho_pad, snap.w ? &snap : nullptr);
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_density launch");
 }
 
@@ -402,9 +404,11 @@ int ffb_flux(ffb_ctx *ctx, const double *rho, float sigma, float *fields, double
     if (!rho || !fields || !rho_bar) return fail(ctx, FFB_E_INVALID, "ffb_flux: NULL argument%s");
     if (!(sigma >= 0.0f) || !isfinite(sigma))
         return fail(ctx, FFB_E_INVALID, "ffb_flux: sigma must be finite and >= 0%s");
-    int st = tape_on_flux(ctx, sigma);
+    flux_snap snap;
+    int st = tape_on_flux(ctx, sigma, reinterpret_cast<const float4 *>(fields), rho_bar, &snap);
     if (st) return st;
-    hipError_t e = launch_flux(ctx, rho, sigma, reinterpret_cast<float4 *>(fields), rho_bar);
+    hipError_t e = launch_flux(ctx, rho, sigma, reinterpret_cast<float4 *>(fields), rho_bar,
+                               snap.fields ? &snap : nullptr);
     return e == hipSuccess ? FFB_OK : hip_fail(ctx, e, "ffb_flux launch");
 }
 

@@ -26,12 +26,17 @@ using namespace ffbi;
 struct tape_rec {
     char kind = 0;                 // 'A'rea, 'D'ensity, 'F'lux, 'I'ntegrate
     ffb_geometry g{};              // A, D: ring arrays referenced; xy -> own copy
-    float2 *xy = nullptr;          // A, D
+    float2 *xy = nullptr;          // A, D: the ring vertices' positions
     double *value = nullptr;       // D
     double *area = nullptr;        // D
+    double *w = nullptr;           // D: the weights w_r of the raster
     float sigma = 0.f;             // F
-    float4 *fields = nullptr;      // I
-    double *rho_bar = nullptr;     // I
+    float4 *fields = nullptr;      // F: the flux outputs; I: a copy if needed
+    double *rho_bar = nullptr;     // F, I (as fields)
+    const float4 *src_fields = nullptr;    // F: the caller's output buffers
+    const double *src_rho_bar = nullptr;
+    const float4 *fields_in = nullptr;     // I: what the integration read
+    const double *rho_bar_in = nullptr;    //    (the flux record's or own copy)
     advect_tape at{};              // I: states, h, count owned by the record
     // allocated sizes (elements), so a later recording can reuse the buffers
     int64_t xy_cap = 0, r_cap = 0, st_cap = 0, h_cap = 0;
@@ -56,7 +61,8 @@ namespace {
 
 void free_rec(tape_rec &r)
 {
-    void *ptrs[] = {r.xy, r.value, r.area, r.fields, r.rho_bar, r.at.states, r.at.h, r.at.count};
+    void *ptrs[] = {r.xy,      r.value, r.area, r.w,         r.fields,
+                    r.rho_bar, r.at.states, r.at.h, r.at.count};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     r = tape_rec{};
@@ -122,43 +128,63 @@ bool tape_sizes(const ffb_tape *t, int64_t *V, int32_t *R)
 
 }  // namespace
 
-int tape_on_area(ffb_ctx *ctx, const ffb_geometry *g)
+int tape_on_area(ffb_ctx *ctx, const ffb_geometry *g, float2 **xy_snap)
 {
+    *xy_snap = nullptr;
     if (!recording(ctx)) return FFB_OK;
     tape_rec &r = next_slot(ctx->tape, 'A');
     r.g = *g;
-    hipError_t e = copy_in(&r.xy, &r.xy_cap, reinterpret_cast<const float2 *>(g->xy),
-                           g->n_vertices, ctx->stream);
+    hipError_t e = ensure(&r.xy, &r.xy_cap, g->n_vertices);
     r.g.xy = reinterpret_cast<const float *>(r.xy);
+    if (e == hipSuccess) *xy_snap = r.xy;     // written by the area kernel
     return commit(ctx, e, "tape (area)");
 }
 
-int tape_on_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const double *area)
+int tape_on_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value, const double *area,
+                    density_snap *snap)
 {
+    *snap = density_snap{};
     if (!recording(ctx)) return FFB_OK;
+    (void)value;
+    (void)area;
     tape_rec &r = next_slot(ctx->tape, 'D');
     r.g = *g;
-    hipError_t e = copy_in(&r.xy, &r.xy_cap, reinterpret_cast<const float2 *>(g->xy),
-                           g->n_vertices, ctx->stream);
+    hipError_t e = ensure(&r.xy, &r.xy_cap, g->n_vertices);
     r.g.xy = reinterpret_cast<const float *>(r.xy);
     if (e == hipSuccess) {
-        int64_t rc = r.r_cap;       // value and area share one capacity
-        e = copy_in(&r.value, &rc, value, g->n_regions, ctx->stream);
+        // value, area and w share one capacity
+        const int64_t R = g->n_regions;
+        int64_t rc = r.r_cap;
+        e = ensure(&r.value, &rc, R);
         if (e == hipSuccess) {
             rc = r.r_cap;
-            e = copy_in(&r.area, &rc, area, g->n_regions, ctx->stream);
+            e = ensure(&r.area, &rc, R);
+        }
+        if (e == hipSuccess) {
+            rc = r.r_cap;
+            e = ensure(&r.w, &rc, R);
         }
         r.r_cap = e == hipSuccess ? rc : 0;
     }
+    if (e == hipSuccess) *snap = density_snap{r.xy, r.value, r.area, r.w};
     return commit(ctx, e, "tape (density)");
 }
 
-int tape_on_flux(ffb_ctx *ctx, float sigma)
+int tape_on_flux(ffb_ctx *ctx, float sigma, const float4 *fields, const double *rho_bar,
+                 flux_snap *snap)
 {
+    *snap = flux_snap{};
     if (!recording(ctx)) return FFB_OK;
     tape_rec &r = next_slot(ctx->tape, 'F');
     r.sigma = sigma;
-    return commit(ctx, hipSuccess, "tape (flux)");
+    const int64_t nf = (int64_t)(ctx->lx + 2) * (ctx->ly + 2);
+    int64_t fcap = r.fields ? nf : 0, one = r.rho_bar ? 1 : 0;
+    hipError_t e = ensure(&r.fields, &fcap, nf);
+    if (e == hipSuccess) e = ensure(&r.rho_bar, &one, 1);
+    r.src_fields = fields;
+    r.src_rho_bar = rho_bar;
+    if (e == hipSuccess) *snap = flux_snap{r.fields, r.rho_bar};
+    return commit(ctx, e, "tape (flux)");
 }
 
 int tape_on_integrate(ffb_ctx *ctx, int64_t n, const float4 *fields, const double *rho_bar,
@@ -173,11 +199,31 @@ int tape_on_integrate(ffb_ctx *ctx, int64_t n, const float4 *fields, const doubl
         return fail(ctx, FFB_E_INVALID, "tape: ffb_integrate recorded before any area or density call%s");
     if (n < V)
         return fail(ctx, FFB_E_INVALID, "tape: ffb_integrate must advect the recorded vertices first%s");
+    // the integration of a round reads the fields and rho_bar that the
+    // round's flux call wrote (the reverse pass assumes it): then the flux
+    // record's copies serve, else the inputs are copied here
+    const float4 *ff = nullptr;
+    const double *fr = nullptr;
+    if (t->used > 0) {
+        const tape_rec &f = t->recs[t->used - 1];
+        if (f.kind == 'F' && f.src_fields == fields && f.src_rho_bar == rho_bar) {
+            ff = f.fields;
+            fr = f.rho_bar;
+        }
+    }
     tape_rec &r = next_slot(t, 'I');
     const int64_t nf = (int64_t)(ctx->lx + 2) * (ctx->ly + 2);
     int64_t fcap = r.fields ? nf : 0, one = r.rho_bar ? 1 : 0, cnt = r.at.count ? 1 : 0;
-    hipError_t e = copy_in(&r.fields, &fcap, fields, nf, ctx->stream);
-    if (e == hipSuccess) e = copy_in(&r.rho_bar, &one, rho_bar, 1, ctx->stream);
+    hipError_t e = hipSuccess;
+    if (ff) {
+        r.fields_in = ff;
+        r.rho_bar_in = fr;
+    } else {
+        e = copy_in(&r.fields, &fcap, fields, nf, ctx->stream);
+        if (e == hipSuccess) e = copy_in(&r.rho_bar, &one, rho_bar, 1, ctx->stream);
+        r.fields_in = r.fields;
+        r.rho_bar_in = r.rho_bar;
+    }
     if (e == hipSuccess) e = ensure(&r.at.states, &r.st_cap, (V > 0 ? V : 1) * (int64_t)t->max_steps);
     if (e == hipSuccess) e = ensure(&r.at.h, &r.h_cap, (int64_t)t->max_steps);
     if (e == hipSuccess) e = ensure(&r.at.count, &cnt, 1);
@@ -370,11 +416,18 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
     if (e == hipSuccess) e = ensure_adjoint_capacity(ctx, t->max_steps, V);
     if (e != hipSuccess) return hip_fail(ctx, e, "ffb_backward workspace");
 
-    e = launch_fill_f64(t->lam_xy, 2 * V, 0.0, s);
-    if (e == hipSuccess) e = launch_fill_f64(dL_dvalue, R, 0.0, s);
+    {
+        zero_spans z{};
+        z.p[0] = t->lam_xy;
+        z.words[0] = 4 * V;
+        z.p[1] = dL_dvalue;
+        z.words[1] = 2 * (int64_t)R;
+        e = launch_zero_spans(z, s);
+    }
     if (e == hipSuccess) e = launch_area_adj(ctx, &recs[used - 1].g, dL_darea, t->lam_xy);
     bool pending = false;           // an area adjoint from a density record waits
     bool cleared = false;           // the next density record's accumulators are zero
+    bool suffixed = false;          // ... and its row suffix sums are computed
     for (int64_t k = used - 2; k >= 0 && e == hipSuccess; --k) {
         tape_rec &r = recs[k];
         switch (r.kind) {
@@ -393,20 +446,26 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
             z.words[3] = 2;
             z.p[4] = ctx->lam_w;
             z.words[4] = 2 * (int64_t)R;
-            e = launch_advect_adj(ctx, r.fields, r.rho_bar, &r.at, t->lam_xy, t->lam_f,
+            e = launch_advect_adj(ctx, r.fields_in, r.rho_bar_in, &r.at, t->lam_xy, t->lam_f,
                                   t->lam_rb, &z);
             cleared = e == hipSuccess;
             break;
         }
         case 'F':
-            e = launch_flux_adj(ctx, r.sigma, t->lam_f, t->lam_rb, t->lam_rho);
+            // with the density accumulators zeroed, the flux adjoint's last
+            // pass also leaves the row suffix sums the density adjoint reads
+            e = launch_flux_adj(ctx, r.sigma, t->lam_f, t->lam_rb, t->lam_rho,
+                                cleared ? ctx->acc : nullptr,
+                                cleared ? density_adj_total(ctx) : nullptr);
+            suffixed = cleared && e == hipSuccess;
             break;
         case 'D':
             if (!cleared) e = launch_fill_f64(t->lam_area, R, 0.0, s);
             if (e == hipSuccess)
                 e = launch_density_adj(ctx, &r.g, r.value, r.area, t->lam_rho, dL_dvalue,
-                                       t->lam_area, t->lam_xy, cleared);
+                                       t->lam_area, t->lam_xy, cleared, suffixed, r.w);
             cleared = false;
+            suffixed = false;
             pending = true;
             break;
         case 'A':

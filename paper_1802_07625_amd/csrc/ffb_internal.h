@@ -109,11 +109,26 @@ void diff_free(ffb_ctx *ctx);
 }  // namespace ffbi
 
 // Context tape (recording for ffb_backward).  Each hook returns FFB_OK when
-// the context is not recording.
-int tape_on_area(ffb_ctx *ctx, const ffb_geometry *g);
+// the context is not recording.  The records' copies of the call's inputs
+// (and of the flux outputs) are written by the call's own kernels into the
+// buffers a hook hands out, so recording adds no launch; a buffer left null
+// means nothing to write.
+//   area:    xy of every ring vertex (the area kernel's reads);
+//   density: xy of every ring vertex, value, area and the weights w_r;
+//   flux:    the fields and rho_bar (what the integration of the round reads).
+struct density_snap {
+    float2 *xy = nullptr;
+    double *value = nullptr, *area = nullptr, *w = nullptr;
+};
+struct flux_snap {
+    float4 *fields = nullptr;
+    double *rho_bar = nullptr;
+};
+int tape_on_area(ffb_ctx *ctx, const ffb_geometry *g, float2 **xy_snap);
 int tape_on_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                    const double *area);
-int tape_on_flux(ffb_ctx *ctx, float sigma);
+                    const double *area, density_snap *snap);
+int tape_on_flux(ffb_ctx *ctx, float sigma, const float4 *fields, const double *rho_bar,
+                 flux_snap *snap);
 // Sets *record and fills *out with the record's buffers when recording.
 int tape_on_integrate(ffb_ctx *ctx, int64_t n, const float4 *fields, const double *rho_bar,
                       struct advect_tape *out, bool *record);
@@ -146,10 +161,13 @@ struct zero_spans {
 hipError_t launch_zero_spans(const zero_spans &z, hipStream_t s);
 
 hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                       double *area, double *err, double *max_abs_err);
+                       double *area, double *err, double *max_abs_err,
+                       float2 *xy_snap = nullptr);
 
+// With `snap`, the weights go to snap->w (and the raster reads them there).
 hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                          const double *area, double *rho, double *rho_pad);
+                          const double *area, double *rho, double *rho_pad,
+                          const density_snap *snap = nullptr);
 
 // Transform workspace of one flux call (FP64): twiddle tables of both
 // lengths, six [lx*ly] planes and kRedDoubles reduction partials.
@@ -159,11 +177,12 @@ struct flux_ws {
     double *red;
 };
 hipError_t launch_flux_ws(hipStream_t s, int lx, int ly, const flux_ws &w, const double *rho,
-                          float sigma, float4 *fields, double *rho_bar, int32_t *status);
+                          float sigma, float4 *fields, double *rho_bar, int32_t *status,
+                          const flux_snap *snap = nullptr);
 // FP64 twiddle tables of length N on the device (tw: N/2 entries, tq: N).
 hipError_t launch_twiddles(hipStream_t s, int N, double2 *tw, double2 *tq);
 hipError_t launch_flux(ffb_ctx *ctx, const double *rho, float sigma, float4 *fields,
-                       double *rho_bar);
+                       double *rho_bar, const flux_snap *snap = nullptr);
 hipError_t launch_pack_fields(ffb_ctx *ctx, const float *jx, const float *jy,
                               const float *rho_s, float4 *fields);
 
@@ -194,14 +213,22 @@ hipError_t launch_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *la
                            double *lam_xy);
 // `cleared`: the caller has already zeroed the context's density-adjoint
 // accumulators (density_adj_scratch) on the stream.
+// `suffixed`: the row suffix sums of lam_rho are in ctx->acc and their total
+// in density_adj_total (from launch_flux_adj; implies `cleared`).  `w`
+// (optional): the forward's weights w_r, else they are recomputed from value
+// and area.
 hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                               const double *area, const float *lam_rho, double *lam_value,
-                              double *lam_area, double *lam_xy, bool cleared = false);
+                              double *lam_area, double *lam_xy, bool cleared = false,
+                              bool suffixed = false, const double *w = nullptr);
 // The context's accumulators that launch_density_adj starts from zero: the
 // sum of lam_rho (one double) and the per-region coverage sums (R doubles).
 inline double *density_adj_total(ffb_ctx *ctx) { return ctx->red + 513; }
+// With `suf` (optional): also the row suffix sums of lam_rho, rows of lx + 1
+// doubles, and their total added to *total (which the caller zeroed).
 hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
-                           const double *lam_rho_bar, float *lam_rho);
+                           const double *lam_rho_bar, float *lam_rho, double *suf = nullptr,
+                           double *total = nullptr);
 // `clear` (optional): spans zeroed on the stream before any adjoint is added
 // (by the launch that also sums the step start times).
 hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,

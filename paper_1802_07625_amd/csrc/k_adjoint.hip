@@ -225,12 +225,30 @@ __global__ __launch_bounds__(kThreads) void k_raster_adj(
             sa = sb; xa = xb; ya = yb;
             if (last) break;
         }
-        const double wr = w[r];
-        // outward normal times length of a counter-clockwise edge: (dy, -dx)
-        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0], wr * dy * I0);
-        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0 + 1], -wr * dx * I0);
-        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1], wr * dy * I1);
-        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1 + 1], -wr * dx * I1);
+    }
+    // outward normal times length of a counter-clockwise edge: (dy, -dx);
+    // the end vertex of lane l's edge is usually the start vertex of lane
+    // l + 1's (consecutive entries of one ring): such pairs are summed in
+    // registers and added with one atomic per coordinate
+    const double wr = r >= 0 ? w[r] : 0.0;
+    double ax = wr * dy * I0, ay = -wr * dx * I0;       // to vertex i0
+    const double bx = wr * dy * I1, by = -wr * dx * I1; // to vertex i1
+    const int32_t v0 = r >= 0 ? i0 : -1, v1 = r >= 0 ? i1 : -2;
+    const int lane = threadIdx.x & 63;
+    const double pbx = __shfl_up(bx, 1, 64), pby = __shfl_up(by, 1, 64);
+    const int32_t pv1 = __shfl_up(v1, 1, 64), nv0 = __shfl_down(v0, 1, 64);
+    if (lane > 0 && pv1 == v0) {
+        ax += pbx;
+        ay += pby;
+    }
+    const bool handed_on = lane < 63 && nv0 == v1;
+    if (r >= 0) {
+        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0], ax);
+        unsafeAtomicAdd(&lam_xy[2 * (int64_t)i0 + 1], ay);
+        if (!handed_on) {
+            unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1], bx);
+            unsafeAtomicAdd(&lam_xy[2 * (int64_t)i1 + 1], by);
+        }
     }
     // region sums of the coverage term
     int32_t rlo = r >= 0 ? r : INT32_MAX, rhi = r;
@@ -823,27 +841,33 @@ hipError_t launch_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *la
 
 hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                               const double *area, const float *lam_rho, double *lam_value,
-                              double *lam_area, double *lam_xy, bool cleared)
+                              double *lam_area, double *lam_xy, bool cleared, bool suffixed,
+                              const double *w)
 {
     hipStream_t s = ctx->stream;
-    // w_r and rho_pad of the forward, recomputed from value and area
-    double *pad = ctx->red + 512, *total = density_adj_total(ctx);
-    hipError_t e = launch_density_weights(ctx, g->n_regions, value, area, pad);
-    if (e != hipSuccess) return e;
+    double *total = density_adj_total(ctx);
+    hipError_t e = hipSuccess;
+    if (!w) {
+        // w_r of the forward, recomputed from value and area
+        e = launch_density_weights(ctx, g->n_regions, value, area, ctx->red + 512);
+        if (e != hipSuccess) return e;
+        w = ctx->w_region;
+    }
     if (!cleared) {
         e = launch_fill_f64(total, 1, 0.0, s);
         if (e != hipSuccess) return e;
         e = launch_fill_f64(ctx->lam_w, g->n_regions, 0.0, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_row_suffix, dim3(ctx->ly), dim3(kThreads), 0, s, lam_rho, ctx->lx,
-                       ctx->acc, total);
+    if (!suffixed)
+        hipLaunchKernelGGL(k_row_suffix, dim3(ctx->ly), dim3(kThreads), 0, s, lam_rho, ctx->lx,
+                           ctx->acc, total);
     if (g->n_entries > 0) {
         const int64_t blocks = (g->n_entries + kThreads - 1) / kThreads;
         hipLaunchKernelGGL(k_raster_adj, dim3((unsigned)blocks), dim3(kThreads), 0, s,
                            reinterpret_cast<const float2 *>(g->xy), g->n_vertices,
                            g->ring_offsets, g->ring_vidx, g->ring_region, g->n_rings,
-                           g->n_regions, g->n_entries, ctx->w_region, lam_rho, ctx->acc, ctx->lx,
+                           g->n_regions, g->n_entries, w, lam_rho, ctx->acc, ctx->lx,
                            ctx->ly, ctx->lam_w, lam_xy, ctx->d_status);
     }
     hipLaunchKernelGGL(k_density_chain, dim3(1), dim3(1024), 0, s, value, area, g->n_regions,

@@ -82,7 +82,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_ring_area(
     const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
     const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t n_regions,
-    int64_t n_entries, double *__restrict__ area, int32_t *status)
+    int64_t n_entries, double *__restrict__ area, int32_t *status, float2 *__restrict__ snap)
 {
     __shared__ double lds[NT / 64 + 1];
     const int32_t g = blockIdx.x;
@@ -100,6 +100,7 @@ __global__ __launch_bounds__(NT) void k_ring_area(
         const int32_t i = vidx[k], j = vidx[k1];
         if (i < 0 || i >= nv || j < 0 || j >= nv) { bad |= 1; continue; }
         const float2 p = xy[i], q = xy[j];
+        if (snap) snap[i] = p;                   // every ring vertex starts one entry
         if (!isfinite(p.x) || !isfinite(p.y)) { bad |= 2; continue; }
         s += (double)p.x * (double)q.y - (double)q.x * (double)p.y;
     }
@@ -112,17 +113,17 @@ __global__ __launch_bounds__(NT) void k_ring_area(
 // One workgroup per ring; long rings (detailed borders) get 1024 lanes so
 // that each lane takes only a few entries.
 hipError_t launch_ring_area_kernel(hipStream_t s, const ffb_geometry *g, double *area,
-                                   int32_t *status)
+                                   int32_t *status, float2 *snap)
 {
     const float2 *xy = reinterpret_cast<const float2 *>(g->xy);
     if (g->n_entries >= (int64_t)2048 * g->n_rings)
         hipLaunchKernelGGL(k_ring_area<1024>, dim3(g->n_rings), dim3(1024), 0, s, xy,
                            g->n_vertices, g->ring_offsets, g->ring_vidx, g->ring_region,
-                           g->n_regions, g->n_entries, area, status);
+                           g->n_regions, g->n_entries, area, status, snap);
     else
         hipLaunchKernelGGL(k_ring_area<kAreaThreads>, dim3(g->n_rings), dim3(kAreaThreads), 0,
                            s, xy, g->n_vertices, g->ring_offsets, g->ring_vidx, g->ring_region,
-                           g->n_regions, g->n_entries, area, status);
+                           g->n_regions, g->n_entries, area, status, snap);
     return hipGetLastError();
 }
 
@@ -288,12 +289,12 @@ hipError_t launch_zero_spans(const zero_spans &z, hipStream_t s)
 }
 
 hipError_t launch_area(const ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                       double *area, double *err, double *max_abs_err)
+                       double *area, double *err, double *max_abs_err, float2 *xy_snap)
 {
     hipError_t e = launch_fill_f64(area, g->n_regions, 0.0, ctx->stream);
     if (e != hipSuccess) return e;
     if (g->n_rings > 0) {
-        e = launch_ring_area_kernel(ctx->stream, g, area, ctx->d_status);
+        e = launch_ring_area_kernel(ctx->stream, g, area, ctx->d_status, xy_snap);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_area_finalize, dim3(1), dim3(kFinThreads), 0, ctx->stream, value,
@@ -305,7 +306,7 @@ hipError_t launch_ring_areas(hipStream_t s, const ffb_geometry *g, double *area,
 {
     hipError_t e = launch_fill_f64(area, g->n_regions, 0.0, s);
     if (e != hipSuccess || g->n_rings == 0) return e;
-    return launch_ring_area_kernel(s, g, area, status);
+    return launch_ring_area_kernel(s, g, area, status, nullptr);
 }
 
 hipError_t launch_batch_finalize(hipStream_t s, const batch_view &bv, const double *value,

@@ -396,8 +396,8 @@ __global__ __launch_bounds__(512) void k_col_pass(const double *__restrict__ t1,
 
 // Row pass on rows j0, j1 = j0 + 1 of a, b, c [ly][lx] (precision R);
 // writes the ghosted FP32 float4 fields (J_x, J_y, rho_s, 0), each value
-// rounded once from R (LDS: sa, sb, rs, jx of kMaxN and stw of kMaxN / 2
-// complex).
+// rounded once from R, to `fields` and, if not null, to `fields2` (LDS: sa,
+// sb, rs, jx of kMaxN and stw of kMaxN / 2 complex).
 template <typename R>
 __device__ __forceinline__ void row_final_body(const R *__restrict__ pa, const R *__restrict__ pb,
                                                const R *__restrict__ pc, int j0, int lx, int ly,
@@ -405,7 +405,7 @@ __device__ __forceinline__ void row_final_body(const R *__restrict__ pa, const R
                                                const cx<R> *__restrict__ tq, int qs,
                                                float4 *__restrict__ fields, int32_t *status,
                                                cx<R> *sa, cx<R> *sb, cx<R> *rs, cx<R> *jx,
-                                               cx<R> *stw)
+                                               cx<R> *stw, float4 *__restrict__ fields2 = nullptr)
 {
     using C = cx<R>;
     const int N = lx;
@@ -444,27 +444,33 @@ __device__ __forceinline__ void row_final_body(const R *__restrict__ pa, const R
         const float4 f0 = make_float4((float)x.x, (float)jy.x, (float)r.x, 0.f);
         const float4 f1 = make_float4((float)x.y, (float)jy.y, (float)r.y, 0.f);
         bad |= !(f0.z > 0.f) || !(f1.z > 0.f);
-        float4 *row0 = fields + (int64_t)(j0 + 1) * P;
-        float4 *row1 = row0 + P;
-        row0[i + 1] = f0;
-        row1[i + 1] = f1;
-        // ghost columns: J_x odd across the x edges
-        if (i == 0 || i == N - 1) {
-            const int gi = (i == 0) ? 0 : N + 1;
-            row0[gi] = make_float4(-f0.x, f0.y, f0.z, 0.f);
-            row1[gi] = make_float4(-f1.x, f1.y, f1.z, 0.f);
-        }
-        // ghost rows: J_y odd across the y edges
-        if (j0 == 0) {
-            float4 *grow = fields;
-            grow[i + 1] = make_float4(f0.x, -f0.y, f0.z, 0.f);
-            if (i == 0 || i == N - 1) grow[(i == 0) ? 0 : N + 1] = make_float4(-f0.x, -f0.y, f0.z, 0.f);
-        }
-        if (j0 + 1 == ly - 1) {
-            float4 *grow = fields + (int64_t)(ly + 1) * P;
-            grow[i + 1] = make_float4(f1.x, -f1.y, f1.z, 0.f);
-            if (i == 0 || i == N - 1) grow[(i == 0) ? 0 : N + 1] = make_float4(-f1.x, -f1.y, f1.z, 0.f);
-        }
+        auto put = [&](float4 *__restrict__ out) {
+            float4 *row0 = out + (int64_t)(j0 + 1) * P;
+            float4 *row1 = row0 + P;
+            row0[i + 1] = f0;
+            row1[i + 1] = f1;
+            // ghost columns: J_x odd across the x edges
+            if (i == 0 || i == N - 1) {
+                const int gi = (i == 0) ? 0 : N + 1;
+                row0[gi] = make_float4(-f0.x, f0.y, f0.z, 0.f);
+                row1[gi] = make_float4(-f1.x, f1.y, f1.z, 0.f);
+            }
+            // ghost rows: J_y odd across the y edges
+            if (j0 == 0) {
+                float4 *grow = out;
+                grow[i + 1] = make_float4(f0.x, -f0.y, f0.z, 0.f);
+                if (i == 0 || i == N - 1)
+                    grow[(i == 0) ? 0 : N + 1] = make_float4(-f0.x, -f0.y, f0.z, 0.f);
+            }
+            if (j0 + 1 == ly - 1) {
+                float4 *grow = out + (int64_t)(ly + 1) * P;
+                grow[i + 1] = make_float4(f1.x, -f1.y, f1.z, 0.f);
+                if (i == 0 || i == N - 1)
+                    grow[(i == 0) ? 0 : N + 1] = make_float4(-f1.x, -f1.y, f1.z, 0.f);
+            }
+        };
+        put(fields);
+        if (fields2) put(fields2);
     }
     if (bad) set_status(status, FFB_E_NONPOSITIVE);
 }
@@ -474,11 +480,12 @@ __global__ __launch_bounds__(512) void k_row_final(const double *__restrict__ pa
                                                    const double *__restrict__ pc, int lx, int ly,
                                                    const double2 *__restrict__ tw,
                                                    const double2 *__restrict__ tq,
-                                                   float4 *__restrict__ fields, int32_t *status)
+                                                   float4 *__restrict__ fields, int32_t *status,
+                                                   float4 *__restrict__ fields2)
 {
     __shared__ double2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
     row_final_body<double>(pa, pb, pc, 2 * blockIdx.x, lx, ly, tw, tq, 1, fields, status, sa, sb,
-                           rs, jx, stw);
+                           rs, jx, stw, fields2);
 }
 
 // Pack caller node arrays into the ghosted layout (same ghost rule).
@@ -507,7 +514,7 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ jx,
 
 __global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ part, int np,
                                                    double scale, double *__restrict__ out,
-                                                   int32_t *status)
+                                                   int32_t *status, double *__restrict__ out2)
 {
     __shared__ double lds[256];
     double s = 0.0;
@@ -521,6 +528,7 @@ __global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ pa
     if (threadIdx.x == 0) {
         const double m = lds[0] * scale;
         *out = m;
+        if (out2) *out2 = m;
         if (!(m > 0.0)) set_status(status, FFB_E_NONPOSITIVE);
     }
 }
@@ -687,24 +695,75 @@ __global__ __launch_bounds__(512) void k_adj_cols(const float *__restrict__ ta,
 }
 
 // Final row pass: DCT-III along x of the [ly][lx] plane.
+// Suffix sums along a pair of rows held in LDS (u[i] = (row j0, row j0 + 1)
+// at column i), in FP64: suf[j][k] = sum_{i >= k} row_j[i] for k in [0, N]
+// (the last is 0), rows of N + 1; the sum of both rows is added to *total.
+// Lanes own contiguous chunks in reverse order (lane 0 the last chunk), so
+// an inclusive scan over the lanes gives each lane the sum to its right.
+__device__ inline void row_pair_suffix(const float2 *u, int N, double *suf, double *total,
+                                       double2 *part)
+{
+    const int T = blockDim.x, t = threadIdx.x;
+    const int chunk = (N + T - 1) / T;
+    const int end = max(0, N - t * chunk), beg = max(0, end - chunk);
+    double sx = 0.0, sy = 0.0;
+    for (int i = beg; i < end; ++i) {
+        sx += u[i].x;
+        sy += u[i].y;
+    }
+    part[t] = make_double2(sx, sy);
+    __syncthreads();
+    for (int o = 1; o < T; o <<= 1) {
+        const double2 a = t >= o ? part[t - o] : make_double2(0.0, 0.0);
+        __syncthreads();
+        part[t].x += a.x;
+        part[t].y += a.y;
+        __syncthreads();
+    }
+    double rx = part[t].x - sx, ry = part[t].y - sy;
+    double *q0 = suf, *q1 = suf + (N + 1);
+    for (int i = end - 1; i >= beg; --i) {
+        rx += u[i].x;
+        ry += u[i].y;
+        q0[i] = rx;
+        q1[i] = ry;
+    }
+    if (t == 0) {
+        q0[N] = 0.0;
+        q1[N] = 0.0;
+        unsafeAtomicAdd(total, part[T - 1].x + part[T - 1].y);
+    }
+}
+
+// With `suf` (optional), also the row suffix sums of lam_rho that the
+// density adjoint's boundary integrals read, and their total added to
+// *total, from the values just stored.
 __global__ __launch_bounds__(512) void k_adj_rows_final(const float *__restrict__ in, int lx,
                                                         const float2 *__restrict__ tw,
                                                         const float2 *__restrict__ tq,
-                                                        float *__restrict__ lam_rho)
+                                                        float *__restrict__ lam_rho,
+                                                        double *__restrict__ suf,
+                                                        double *__restrict__ total)
 {
     __shared__ float2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
+    __shared__ double2 part[512];
     const int N = lx;
     load_twiddles(stw, tw, N);
     const int64_t j0 = 2 * (int64_t)blockIdx.x;
     const float *r0 = in + j0 * N, *r1 = r0 + N;
     dct3_input(sa, N, tq, [&](int m) { return make_float2(r0[m], r1[m]); });
     float2 *v = fft_lds(sa, sb, N, stw, true);
+    float2 *u = v == sa ? sb : sa;               // free after the transform
     float *o0 = lam_rho + j0 * N, *o1 = o0 + N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const float2 y = dct3_output(v, i, N);
         o0[i] = y.x;
         o1[i] = y.y;
+        u[i] = y;
     }
+    if (!suf) return;
+    __syncthreads();
+    row_pair_suffix(u, N, suf + j0 * (N + 1), total, part);
 }
 
 // ------------------------------------------------------------- batched
@@ -954,23 +1013,24 @@ inline int threads_for(int N)
 }  // namespace
 
 hipError_t launch_flux_ws(hipStream_t s, int lx, int ly, const flux_ws &w, const double *rho,
-                          float sigma, float4 *fields, double *rho_bar, int32_t *status)
+                          float sigma, float4 *fields, double *rho_bar, int32_t *status,
+                          const flux_snap *snap)
 {
     const int64_t n = (int64_t)lx * ly;
     // row DCTs, with the FP64 sums of each row pair for the mean density
     hipLaunchKernelGGL(k_dct2_rows, dim3(ly / 2), dim3(threads_for(lx)), 0, s, rho, w.t1, lx,
                        w.tw_x, w.tq_x, w.red);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, w.red, ly / 2, 1.0 / (double)n,
-                       rho_bar, status);
+                       rho_bar, status, snap ? snap->rho_bar : nullptr);
     hipLaunchKernelGGL(k_col_pass, dim3(lx / 2), dim3(threads_for(ly)), 0, s, w.t1, lx, ly,
                        sigma, w.tw_y, w.tq_y, w.pa, w.pb, w.pc);
     hipLaunchKernelGGL(k_row_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, w.pa, w.pb, w.pc,
-                       lx, ly, w.tw_x, w.tq_x, fields, status);
+                       lx, ly, w.tw_x, w.tq_x, fields, status, snap ? snap->fields : nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_flux(ffb_ctx *ctx, const double *rho, float sigma, float4 *fields,
-                       double *rho_bar)
+                       double *rho_bar, const flux_snap *snap)
 {
     // the context's planes are sized for FP64
     flux_ws w{ctx->tw64_x,
@@ -983,7 +1043,7 @@ hipError_t launch_flux(ffb_ctx *ctx, const double *rho, float sigma, float4 *fie
               reinterpret_cast<double *>(ctx->pc),
               ctx->red};
     return launch_flux_ws(ctx->stream, ctx->lx, ctx->ly, w, rho, sigma, fields, rho_bar,
-                          ctx->d_status);
+                          ctx->d_status, snap);
 }
 
 hipError_t launch_twiddles(hipStream_t s, int N, double2 *tw, double2 *tq)
@@ -1031,7 +1091,7 @@ hipError_t launch_diff_fields(ffb_ctx *ctx, diff_ws *w, int slots)
 }
 
 hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
-                           const double *lam_rho_bar, float *lam_rho)
+                           const double *lam_rho_bar, float *lam_rho, double *suf, double *total)
 {
     hipStream_t s = ctx->stream;
     const int lx = ctx->lx, ly = ctx->ly;
@@ -1040,7 +1100,7 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
     hipLaunchKernelGGL(k_adj_cols, dim3(lx / 2), dim3(threads_for(ly)), 0, s, ctx->pa, ctx->pb,
                        ctx->pc, lx, ly, sigma, lam_rho_bar, ctx->tw_y, ctx->tq_y, ctx->t1);
     hipLaunchKernelGGL(k_adj_rows_final, dim3(ly / 2), dim3(threads_for(lx)), 0, s, ctx->t1, lx,
-                       ctx->tw_x, ctx->tq_x, lam_rho);
+                       ctx->tw_x, ctx->tq_x, lam_rho, suf, total);
     return hipGetLastError();
 }
 

@@ -51,9 +51,11 @@ __device__ double block_sum(double v, double *lds)
 }
 
 // rho_pad = sum(value) / sum(area); w_r = value_r / area_r - rho_pad.
+// Optional copies of value and area (snap_v, snap_a).
 __global__ __launch_bounds__(kPrepThreads) void k_density_prep(
     const double *__restrict__ value, const double *__restrict__ area, int32_t R,
-    double *__restrict__ w, double *__restrict__ rho_pad, int32_t *status)
+    double *__restrict__ w, double *__restrict__ rho_pad, int32_t *status,
+    double *__restrict__ snap_v, double *__restrict__ snap_a)
 {
     __shared__ double lds[kPrepThreads / 64 + 1];
     double sa = 0.0, sv = 0.0;
@@ -67,7 +69,14 @@ __global__ __launch_bounds__(kPrepThreads) void k_density_prep(
     sa = block_sum<kPrepThreads>(sa, lds);
     sv = block_sum<kPrepThreads>(sv, lds);
     const double pad = sv / sa;
-    for (int32_t r = threadIdx.x; r < R; r += kPrepThreads) w[r] = value[r] / area[r] - pad;
+    for (int32_t r = threadIdx.x; r < R; r += kPrepThreads) {
+        const double a = area[r], v = value[r];
+        w[r] = v / a - pad;
+        if (snap_v) {
+            snap_v[r] = v;
+            snap_a[r] = a;
+        }
+    }
     if (bad) set_status(status, FFB_E_NONPOSITIVE);
     if (threadIdx.x == 0) *rho_pad = pad;
 }
@@ -196,7 +205,7 @@ __device__ inline void run_add(double *__restrict__ acc, int64_t key, double va,
 // word and return false.  lx and ly come from the caller, or (batches,
 // lx = ly = 0) from the map that owns the ring through `map_of`.
 struct EdgeOf {
-    int32_t g, r;
+    int32_t g, r, i0;
     double x0, y0, x1, y1;
 };
 
@@ -254,6 +263,7 @@ __device__ inline bool edge_of(int64_t k, const float2 *__restrict__ xy, int64_t
     }
     ed.g = g;
     ed.r = r;
+    ed.i0 = i0;
     ed.x0 = p.x;
     ed.y0 = p.y;
     ed.x1 = q.x;
@@ -265,7 +275,7 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
     const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
     const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t G,
     int32_t R, int64_t E, const double *__restrict__ w, int32_t lx, int32_t ly,
-    double *__restrict__ acc, int32_t *status)
+    double *__restrict__ acc, int32_t *status, float2 *__restrict__ snap)
 {
     __shared__ int32_t s_off[kStagedRingOffsets];
     const bool staged = stage_ring_offsets(off, G, s_off);
@@ -280,8 +290,11 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
     };
     // no early return: every lane of the wave takes part in run_add
     if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, one_map, status, ed, nullptr,
-                         s_off, staged))
+                         s_off, staged)) {
+        // optional copy of the edge's start vertex (every ring vertex starts one)
+        if (snap) snap[ed.i0] = make_float2((float)ed.x0, (float)ed.y0);
         edge_deposits(acc, 0, lx, ly, w[ed.r], ed.x0, ed.y0, ed.x1, ed.y1, key, va, vb);
+    }
     run_add(acc, key, va, vb);
 }
 
@@ -441,16 +454,19 @@ hipError_t launch_density_weights(ffb_ctx *ctx, int32_t R, const double *value,
                                   const double *area, double *rho_pad)
 {
     hipLaunchKernelGGL(k_density_prep, dim3(1), dim3(kPrepThreads), 0, ctx->stream, value, area,
-                       R, ctx->w_region, rho_pad, ctx->d_status);
+                       R, ctx->w_region, rho_pad, ctx->d_status, nullptr, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
-                          const double *area, double *rho, double *rho_pad)
+                          const double *area, double *rho, double *rho_pad,
+                          const density_snap *snap)
 {
     hipStream_t s = ctx->stream;
+    double *w = snap ? snap->w : ctx->w_region;
     hipLaunchKernelGGL(k_density_prep, dim3(1), dim3(kPrepThreads), 0, s, value, area,
-                       g->n_regions, ctx->w_region, rho_pad, ctx->d_status);
+                       g->n_regions, w, rho_pad, ctx->d_status, snap ? snap->value : nullptr,
+                       snap ? snap->area : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_fill_f64(ctx->acc, (int64_t)ctx->ly * (ctx->lx + 1), 0.0, s);
@@ -460,8 +476,8 @@ hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *val
         hipLaunchKernelGGL(k_raster_edges, dim3((unsigned)blocks), dim3(kEdgeThreads), 0, s,
                            reinterpret_cast<const float2 *>(g->xy), g->n_vertices,
                            g->ring_offsets, g->ring_vidx, g->ring_region, g->n_rings,
-                           g->n_regions, g->n_entries, ctx->w_region, ctx->lx, ctx->ly,
-                           ctx->acc, ctx->d_status);
+                           g->n_regions, g->n_entries, w, ctx->lx, ctx->ly, ctx->acc,
+                           ctx->d_status, snap ? snap->xy : nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
