@@ -451,10 +451,13 @@ int ffb_batch_destroy(ffb_batch *b);
 const char *ffb_batch_last_error(const ffb_batch *b);
 
 /* Launch shapes: the workgroup size of the transform passes (64, 128, 256
- * or 512; 0 = keep) for every grid-size class and of the integration (256,
- * 512 or 1024; 0 = keep).  Results do not depend on them. */
+ * or 512; 0 = keep) for every transform-length class (the rows of maps
+ * with lx = N and the columns of maps with ly = N) -- a workgroup holds
+ * size / (N / 8) row or column pairs of length N, and at least one -- and of
+ * the integration (256, 512 or 1024; 0 = keep).  Results do not depend on
+ * them. */
 int ffb_batch_set_shapes(ffb_batch *b, int32_t fft_threads, int32_t advect_threads);
-/* (host outs) number of grid-size classes, their widths, transform
+/* (host outs) number of transform-length classes, their lengths N, transform
  * workgroup size per class, integration workgroup size. */
 int ffb_batch_get_shapes(const ffb_batch *b, int32_t *n_classes, int32_t *widths,
                          int32_t *fft_threads, int32_t *advect_threads);

@@ -23,7 +23,7 @@ using namespace ffbi;
 
 namespace {
 
-constexpr int kMaxClasses = kBatchMaxClasses;   // distinct grid widths in one batch
+constexpr int kMaxClasses = kBatchMaxClasses;   // distinct transform lengths in one batch
 constexpr int kFftChoices[] = {64, 128, 256, 512};
 constexpr int kAdvectChoices[] = {256, 512, 1024};
 
@@ -62,11 +62,11 @@ struct ffb_batch {
     int32_t *d_active = nullptr, *d_round = nullptr, *d_rounds_done = nullptr, *d_order = nullptr,
             *d_stats = nullptr, *d_n_active = nullptr, *d_status = nullptr;
     double *d_max_err = nullptr;
-    // launch tables, rows and columns grouped by grid width class
+    // launch tables, rows and columns grouped by transform-length class
     int2 *d_rows = nullptr, *d_cols = nullptr, *d_scan_rows = nullptr;
     int32_t n_rows = 0, n_cols = 0, n_scan_rows = 0;
     int n_classes = 0;
-    int32_t class_n[kMaxClasses];                  // grid width of each class
+    int32_t class_n[kMaxClasses];                  // transform length of each class
     int32_t row_beg[kMaxClasses + 1], col_beg[kMaxClasses + 1];
     // workspace
     // density grids and transform planes (FP64)
@@ -166,7 +166,10 @@ batch_fft_plan plan_of(const ffb_batch *b, const int *threads)
         p.row_beg[c] = b->row_beg[c];
         p.col_beg[c] = b->col_beg[c];
     }
-    for (int c = 0; c < b->n_classes; ++c) p.threads[c] = threads[c];
+    for (int c = 0; c < b->n_classes; ++c) {
+        p.threads[c] = threads[c];
+        p.n[c] = b->class_n[c];
+    }
     return p;
 }
 
@@ -369,7 +372,9 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
         if (d->ring_offsets_map[m + 1] <= d->ring_offsets_map[m] ||
             d->region_offsets[m + 1] <= d->region_offsets[m])
             return FFB_E_INVALID;
-        if (std::find(widths.begin(), widths.end(), lx) == widths.end()) widths.push_back(lx);
+        // transform lengths: the rows of a map have length lx, its columns ly
+        for (int32_t L : {lx, ly})
+            if (std::find(widths.begin(), widths.end(), L) == widths.end()) widths.push_back(L);
     }
     if ((int)widths.size() > kMaxClasses) return FFB_E_INVALID;
     std::sort(widths.begin(), widths.end());
@@ -404,7 +409,8 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return point_off[x + 1] - point_off[x] > point_off[y + 1] - point_off[y];
     });
-    // launch tables, rows and columns grouped by width class
+    // launch tables: the rows of maps with lx = N and the columns of maps
+    // with ly = N form class N
     std::vector<int2> rows, cols, scan_rows;
     b->n_classes = (int)widths.size();
     for (int c = 0; c < b->n_classes; ++c) {
@@ -412,24 +418,15 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
         b->row_beg[c] = (int32_t)rows.size();
         b->col_beg[c] = (int32_t)cols.size();
         for (int32_t m = 0; m < M; ++m) {
-            if (b->lx[m] != widths[c]) continue;
-            for (int j = 0; j < b->ly[m]; j += 2) rows.push_back(make_int2(m, j));
-            for (int i = 0; i < b->lx[m]; i += 2) cols.push_back(make_int2(m, i));
+            if (b->lx[m] == widths[c])
+                for (int j = 0; j < b->ly[m]; j += 2) rows.push_back(make_int2(m, j));
+            if (b->ly[m] == widths[c])
+                for (int i = 0; i < b->lx[m]; i += 2) cols.push_back(make_int2(m, i));
         }
-        // the column pass reads and writes its pair in row-major planes; the
-        // eight pairs of one 128-byte line go to workgroups w, w + 8, ...,
-        // w + 56 of the class's launch, which run on one XCD one after
-        // another (blocks of 64 pairs; a shorter tail keeps its order)
-        const size_t c0 = b->col_beg[c], n = cols.size() - c0;
-        std::vector<int2> blk(64);
-        for (size_t q = 0; q + 64 <= n; q += 64) {
-            for (int w = 0; w < 64; ++w) {
-                const int x = w & 7, t = w >> 3;
-                blk[w] = cols[c0 + q + (size_t)((((t >> 3) << 3) + x) * 8 + (t & 7))];
-            }
-            std::copy(blk.begin(), blk.end(), cols.begin() + (ptrdiff_t)(c0 + q));
-        }
-        b->fft_threads[c] = std::min(512, std::max(64, widths[c] / 2));
+        // the column pass reads and writes consecutive pairs of one map
+        // together (one workgroup takes consecutive entries), so the
+        // entries stay in column order
+        b->fft_threads[c] = 256;
     }
     b->row_beg[b->n_classes] = (int32_t)rows.size();
     b->col_beg[b->n_classes] = (int32_t)cols.size();
@@ -643,7 +640,7 @@ int ffb_batch_autotune(ffb_batch *b, const ffb_batch_opts *o)
         float best = 1e30f;
         int best_t = b->fft_threads[c];
         for (int t : kFftChoices) {
-            if (t > 2 * b->class_n[c] && t != 64) continue;   // more lanes than butterflies
+            if (t < b->class_n[c] / 8) continue;    // runs as N / 8 lanes anyway
             int threads[kMaxClasses];
             std::copy(b->fft_threads, b->fft_threads + b->n_classes, threads);
             threads[c] = t;

@@ -358,6 +358,7 @@ struct batch_fft_plan {
     int n_classes;
     int32_t row_beg[kBatchMaxClasses + 1], col_beg[kBatchMaxClasses + 1];
     int threads[kBatchMaxClasses];
+    int n[kBatchMaxClasses];           // transform length of each class
 };
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const double2 *tw1024,

@@ -20,6 +20,8 @@
 // one as the imaginary part), with the even/odd reordering of Makhoul
 // (1980) turning the real DCT-II/DCT-III into a plain FFT; the DST-III is a
 // DCT-III of the index-reversed coefficients with alternating output signs.
+#include <algorithm>
+
 #include "ffb_internal.h"
 
 namespace {
@@ -328,39 +330,42 @@ __device__ __forceinline__ void col_pass_body(const R *__restrict__ t1, int m0, 
     const R flx = (R)lx, fly = (R)ly;
     const R inv_pi = R(0.318309886183790671537767526745);
     const R ma = (R)m0, mb = (R)(m0 + 1);
-    // wx(m, n) and wy(m, n); zero where the numerator vanishes
-    auto wx = [&](R m, int n) {
-        if (m == R(0)) return R(0);
-        const R den = (m * fly) * (m * fly) + ((R)n * flx) * ((R)n * flx);
-        return fly * inv_pi * m / den;
-    };
-    auto wy = [&](R m, int n) {
-        if (n == 0) return R(0);
-        const R den = (m * fly) * (m * fly) + ((R)n * flx) * ((R)n * flx);
-        return flx * inv_pi * (R)n / den;
-    };
 
     // a: plain DCT-III of the coefficients
     dct3_input(sa, N, tq, [&](int n) { return coef[n]; }, qs);
     C *v = fft_lds(sa, sb, N, stw, true);
     C *oa = reinterpret_cast<C *>(pa + m0);
     for (int i = threadIdx.x; i < N; i += blockDim.x) oa[i * cs] = dct3_output(v, i, N);
+    // b and c weigh the coefficients with
+    //   wx(m, n) = (ly/pi) m / (m^2 ly^2 + n^2 lx^2),  wy(m, n) = (lx/pi) n / (...),
+    // zero where the numerator vanishes: the coefficients are divided by the
+    // common denominator once, in place, and each sum takes its numerator
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const R nl = (R)n * flx;
+        const C c = coef[n];
+        const R da = (ma * fly) * (ma * fly) + nl * nl, db = (mb * fly) * (mb * fly) + nl * nl;
+        // the (m, n) = (0, 0) term has no flux (both numerators vanish)
+        coef[n] = mkc<C>(da > R(0) ? c.x / da : R(0), c.y / db);
+    }
     __syncthreads();
     // b: DCT-III of wx * coefficients
+    const R kxa = fly * inv_pi * ma, kxb = fly * inv_pi * mb;
     dct3_input(sa, N, tq, [&](int n) {
         const C c = coef[n];
-        return mkc<C>(wx(ma, n) * c.x, wx(mb, n) * c.y);
+        return mkc<C>(kxa * c.x, kxb * c.y);
     }, qs);
     v = fft_lds(sa, sb, N, stw, true);
     C *ob = reinterpret_cast<C *>(pb + m0);
     for (int i = threadIdx.x; i < N; i += blockDim.x) ob[i * cs] = dct3_output(v, i, N);
     __syncthreads();
     // c: DST-III of wy * coefficients = (-1)^j DCT-III of the reversed sequence
+    const R ky = flx * inv_pi;
     dct3_input(sa, N, tq, [&](int mm) {
         if (mm == 0) return mkc<C>(R(0), R(0));
         const int n = N - mm;
         const C c = coef[n];
-        return mkc<C>(wy(ma, n) * c.x, wy(mb, n) * c.y);
+        const R k = ky * (R)n;
+        return mkc<C>(k * c.x, k * c.y);
     }, qs);
     v = fft_lds(sa, sb, N, stw, true);
     C *oc = reinterpret_cast<C *>(pc + m0);
@@ -767,10 +772,10 @@ __global__ __launch_bounds__(512) void k_adj_rows_final(const float *__restrict_
 }
 
 // ------------------------------------------------------------- batched
-// Transforms of many maps of different sizes: every workgroup reads its
-// (map, index) from a launch table, offsets its planes, and runs the same
-// bodies as the single-map kernels with the length-1024 twiddle tables read
-// at stride 1024 / N.  Maps that stopped iterating are skipped.
+// Transforms of many maps of different sizes (the grouped kernels below):
+// every group reads its (map, index) from a launch table of its grid-size
+// class, offsets its planes, and reads the length-1024 twiddle tables at
+// stride 1024 / N.  Maps that stopped iterating are skipped.
 
 // Mean density of every active map in FP64 from the row sums the raster
 // scan left in the spare last slot of each accumulation row (fixed order).
@@ -795,57 +800,6 @@ __global__ __launch_bounds__(256) void kb_mean(batch_view bv, const double *__re
         rho_bar[m] = mean;
         if (!(mean > 0.0)) set_status(status, FFB_E_NONPOSITIVE);
     }
-}
-
-__global__ __launch_bounds__(512) void kb_dct2_rows(batch_view bv, const int2 *__restrict__ rows,
-                                                    const double *__restrict__ in,
-                                                    double *__restrict__ out,
-                                                    const double2 *__restrict__ tw,
-                                                    const double2 *__restrict__ tq)
-{
-    __shared__ double2 sa[kMaxN], sb[kMaxN], stw[kMaxN / 2];
-    const int2 e = rows[blockIdx.x];
-    const int m = e.x;
-    if (!bv.active[m]) return;
-    const int N = bv.lx[m];
-    const int64_t o = bv.plane_off[m];
-    dct2_rows_body(in + o, out + o, e.y, N, tw, tq, kMaxN / N, sa, sb, stw);
-}
-
-__global__ __launch_bounds__(512) void kb_col_pass(batch_view bv, const int2 *__restrict__ cols,
-                                                   const double *__restrict__ t1,
-                                                   const double2 *__restrict__ tw,
-                                                   const double2 *__restrict__ tq,
-                                                   double *__restrict__ pa, double *__restrict__ pb,
-                                                   double *__restrict__ pc)
-{
-    __shared__ double2 sa[kMaxN], sb[kMaxN], coef[kMaxN], stw[kMaxN / 2];
-    const int2 e = cols[blockIdx.x];
-    const int m = e.x;
-    if (!bv.active[m]) return;
-    const int lx = bv.lx[m], ly = bv.ly[m];
-    const int64_t o = bv.plane_off[m];
-    const float sigma = (float)ldexp(bv.sigma0, -bv.round[m]);
-    col_pass_body(t1 + o, e.y, lx, ly, sigma, tw, tq, kMaxN / ly, pa + o, pb + o, pc + o, sa, sb,
-                  coef, stw);
-}
-
-__global__ __launch_bounds__(512) void kb_row_final(batch_view bv, const int2 *__restrict__ rows,
-                                                    const double *__restrict__ pa,
-                                                    const double *__restrict__ pb,
-                                                    const double *__restrict__ pc,
-                                                    const double2 *__restrict__ tw,
-                                                    const double2 *__restrict__ tq,
-                                                    float4 *__restrict__ fields, int32_t *status)
-{
-    __shared__ double2 sa[kMaxN], sb[kMaxN], rs[kMaxN], jx[kMaxN], stw[kMaxN / 2];
-    const int2 e = rows[blockIdx.x];
-    const int m = e.x;
-    if (!bv.active[m]) return;
-    const int lx = bv.lx[m], ly = bv.ly[m];
-    const int64_t o = bv.plane_off[m];
-    row_final_body(pa + o, pb + o, pc + o, e.y, lx, ly, tw, tq, kMaxN / lx,
-                   fields + bv.field_off[m], status, sa, sb, rs, jx, stw);
 }
 
 // ------------------------------------------------------- diffusion variant
@@ -1010,6 +964,660 @@ inline int threads_for(int N)
     return t;
 }
 
+// ------------------------------------------------- grouped FP64 transforms
+// The FP64 passes of the single-map and batched flux run many row or column
+// pairs per workgroup: a group of G = N / 8 lanes owns one pair, holds eight
+// complex values per lane in registers and runs the length-N FFT as radix-8
+// Stockham passes (one radix-2 or radix-4 pass first when log2 N is not a
+// multiple of 3), exchanging through its own LDS buffer in place.  A group
+// of at most one wavefront needs no workgroup barrier (its lanes run in
+// lockstep and the LDS serves a wavefront's accesses in order); at N = 1024
+// a group spans two wavefronts and passes workgroup barriers.  The pre- and
+// post-processing of the DCTs keeps each lane's bins in registers, so the
+// only per-group LDS is the FFT buffer, with one spare slot per 16 elements
+// so that the strided writes of the early passes spread over the banks.
+// Workgroups of T lanes (64 to 512, at least G) hold P = T / G groups;
+// their buffers take P * padded(N) = 8 T + T / 2 complex values.
+template <int T> constexpr int grp_lds() { return 8 * T + T / 2; }
+
+__device__ __forceinline__ int px(int i) { return i + (i >> 4); }
+__device__ __forceinline__ int padded(int n) { return n + (n >> 4); }
+
+struct Grp {
+    int N, lgN, G, P, id, lane;
+};
+
+template <int T>
+__device__ __forceinline__ Grp grp_of(int N)
+{
+    Grp g;
+    g.N = N;
+    g.lgN = ilog2(N);
+    g.G = N >> 3;
+    g.P = T / g.G;
+    g.id = threadIdx.x >> (g.lgN - 3);
+    g.lane = threadIdx.x & (g.G - 1);
+    return g;
+}
+
+// Orders the LDS accesses of the group's lanes (uniform over the workgroup).
+__device__ __forceinline__ void gsync(const Grp &g)
+{
+    if (g.G > 64) {
+        __syncthreads();
+        return;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiplication by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 crot(double2 a)
+{
+    return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// Length-4 DFT in place (exponent sign by INV).
+template <bool INV>
+__device__ __forceinline__ void dft4(double2 &c0, double2 &c1, double2 &c2, double2 &c3)
+{
+    const double2 d0 = cadd(c0, c2), d1 = csub(c0, c2), d2 = cadd(c1, c3);
+    const double2 d3 = crot<INV>(csub(c1, c3));
+    c0 = cadd(d0, d2);
+    c1 = cadd(d1, d3);
+    c2 = csub(d0, d2);
+    c3 = csub(d1, d3);
+}
+
+// Length-8 DFT in place: radix 2 over (m, m + 4), the twiddles w8^m, then two
+// length-4 DFTs giving the even and the odd outputs.
+template <bool INV>
+__device__ __forceinline__ void dft8(double2 (&x)[8])
+{
+    const double r = 0.70710678118654752440084436210485;
+    double2 a[4], b[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        a[m] = cadd(x[m], x[m + 4]);
+        b[m] = csub(x[m], x[m + 4]);
+    }
+    // w8 = (1 - i)/sqrt 2 forward, (1 + i)/sqrt 2 inverse
+    if (INV) {
+        b[1] = make_double2(r * (b[1].x - b[1].y), r * (b[1].x + b[1].y));
+        b[3] = make_double2(-r * (b[3].x + b[3].y), r * (b[3].x - b[3].y));
+    } else {
+        b[1] = make_double2(r * (b[1].x + b[1].y), r * (b[1].y - b[1].x));
+        b[3] = make_double2(r * (b[3].y - b[3].x), -r * (b[3].x + b[3].y));
+    }
+    b[2] = crot<INV>(b[2]);
+    dft4<INV>(a[0], a[1], a[2], a[3]);
+    dft4<INV>(b[0], b[1], b[2], b[3]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        x[2 * t] = a[t];
+        x[2 * t + 1] = b[t];
+    }
+}
+
+// Unnormalised length-N FFT of the group's buffer a (padded, natural order
+// in and out), exponent sign by INV.  tw (LDS) = exp(-2 pi i k / N), k < N/2.
+template <bool INV>
+__device__ void fft_grp(double2 *a, const double2 *tw, const Grp &g)
+{
+    const int N = g.N, G = g.G, lane = g.lane;
+    const int r = g.lgN % 3;
+    int lgL = 0;
+    if (r == 1) {
+        // radix 2, sub-length 1: N/2 butterflies, four per lane
+        double2 x[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int bi = lane + u * G;
+            x[2 * u] = a[px(bi)];
+            x[2 * u + 1] = a[px(bi + (N >> 1))];
+        }
+        gsync(g);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int bi = lane + u * G;
+            a[px(2 * bi)] = cadd(x[2 * u], x[2 * u + 1]);
+            a[px(2 * bi + 1)] = csub(x[2 * u], x[2 * u + 1]);
+        }
+        gsync(g);
+        lgL = 1;
+    } else if (r == 2) {
+        // radix 4, sub-length 1: N/4 butterflies, two per lane
+        double2 x[8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int bi = lane + u * G;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) x[4 * u + m] = a[px(bi + m * (N >> 2))];
+        }
+        gsync(g);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int bi = lane + u * G;
+            dft4<INV>(x[4 * u], x[4 * u + 1], x[4 * u + 2], x[4 * u + 3]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[px(4 * bi + t)] = x[4 * u + t];
+        }
+        gsync(g);
+        lgL = 2;
+    }
+    for (; lgL < g.lgN; lgL += 3) {
+        // radix 8 with sub-length Ls: butterfly bi = lane combines the
+        // eight sequences stored N/8 = G apart
+        const int Ls = 1 << lgL;
+        const int j = lane & (Ls - 1), k = lane >> lgL;
+        double2 x[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = a[px(lane + m * G)];
+        if (lgL > 0) {
+            // w^(m j), w = exp(-+2 pi i / (8 Ls)): w^j = tw[e1], e1 = j N / (8 Ls)
+            const int e1 = j << (g.lgN - 3 - lgL);
+            double2 w1 = tw[e1], w2 = tw[2 * e1], w4 = tw[4 * e1];
+            if (INV) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+                w4.y = -w4.y;
+            }
+            const double2 w3 = cmul(w1, w2);
+            x[1] = cmul(x[1], w1);
+            x[2] = cmul(x[2], w2);
+            x[3] = cmul(x[3], w3);
+            x[4] = cmul(x[4], w4);
+            x[5] = cmul(x[5], cmul(w4, w1));
+            x[6] = cmul(x[6], cmul(w4, w2));
+            x[7] = cmul(x[7], cmul(w4, w3));
+        }
+        dft8<INV>(x);
+        gsync(g);
+        const int o = (k << (lgL + 3)) + j;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a[px(o + t * Ls)] = x[t];
+        gsync(g);
+    }
+}
+
+__device__ __forceinline__ void load_tw_grp(double2 *stw, const double2 *__restrict__ tw, int N,
+                                            int qs)
+{
+    for (int k = threadIdx.x; k < (N >> 1); k += blockDim.x) stw[k] = tw[k * qs];
+    __syncthreads();
+}
+
+// Start of a batched grouped pass (length-1024 tables at stride 1024 / N):
+// false if this lane's group has nothing to do and may leave -- a workgroup
+// without live groups leaves before its barriers, a dead group of at most
+// one wavefront after them (it passes no workgroup barrier later); a dead
+// group of a 128-lane pair stays, gated, for the barriers.
+__device__ __forceinline__ bool grp_enter(double2 *stw, const double2 *__restrict__ tw, int N,
+                                          const Grp &g, bool live)
+{
+    if (!__syncthreads_or(live)) return false;
+    load_tw_grp(stw, tw, N, kMaxN / N);
+    return live || g.G > 64;
+}
+
+// DCT-II bin n of the pair from the FFT Z (padded) of its Makhoul-ordered
+// input: (X_a[n], X_b[n]).
+__device__ __forceinline__ double2 grp_dct2_bin(const double2 *Z, int n, int N, double2 q)
+{
+    const double2 zm = Z[px(n)], zc = Z[px((N - n) & (N - 1))];
+    const double2 va = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y - zc.y));
+    const double2 vb = make_double2(0.5 * (zm.y + zc.y), -0.5 * (zm.x - zc.x));
+    return make_double2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
+}
+
+// Inverse-FFT input of a DCT-III pair at index m from the coefficient pairs
+// xm = c[m] and xr = c[N - m] (xr unused for m = 0).
+__device__ __forceinline__ double2 grp_dct3_in(int m, double2 xm, double2 xr, double2 q)
+{
+    if (m) {
+        xm.x *= 0.5;
+        xm.y *= 0.5;
+        xr.x *= 0.5;
+        xr.y *= 0.5;
+    } else {
+        xr = make_double2(0.0, 0.0);
+    }
+    const double cr = q.x, ci = -q.y;         // exp(+i pi m / (2N))
+    const double war = cr * xm.x + ci * xr.x, wai = ci * xm.x - cr * xr.x;
+    const double wbr = cr * xm.y + ci * xr.y, wbi = ci * xm.y - cr * xr.y;
+    return make_double2(war - wbi, wai + wbr);
+}
+
+// 1 / d to full FP64 precision (hardware reciprocal, two Newton steps).
+__device__ __forceinline__ double rcp64(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// DCT-II of rows r0, r0 + 1 of `in` [rows][N] into `out`; with `rowsum`,
+// *rowsum = the FP64 sum of both input rows (fixed order).  `live` false:
+// the group only takes part in the barriers.
+__device__ void grp_dct2_rows(const double *__restrict__ in, double *__restrict__ out, int64_t r0,
+                              const double2 *__restrict__ tq, int qs, double2 *a,
+                              const double2 *stw, double *rowsum, double *part, const Grp &g,
+                              bool live)
+{
+    const int N = g.N;
+    const double *ra = in + r0 * N, *rb = ra + N;
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = g.lane + u * g.G;
+        const double2 v = live ? make_double2(ra[i], rb[i]) : make_double2(0.0, 0.0);
+        s += v.x + v.y;
+        a[px(mk_pos(i, N))] = v;
+    }
+    gsync(g);
+    fft_grp<false>(a, stw, g);
+    double *oa = out + r0 * N, *ob = oa + N;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int n = g.lane + u * g.G;
+        const double2 b = grp_dct2_bin(a, n, N, tq[n * qs]);
+        if (live) {
+            oa[n] = b.x;
+            ob[n] = b.y;
+        }
+    }
+    if (rowsum) {
+        // group sum: within a wavefront by butterflies over the group's
+        // lanes, across the two wavefronts of a 128-lane group through LDS
+        for (int o = 1; o < g.G && o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+        if (g.G > 64) {
+            if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+            __syncthreads();
+            s = part[2 * g.id] + part[2 * g.id + 1];
+        }
+        if (live && g.lane == 0) *rowsum = s;
+    }
+}
+
+// Column pass of a workgroup's P column pairs (entries P b .. P b + P - 1 of
+// the class table, N = ly): the DCT-II along y, the normalisation and blur
+// of Eq. 7, then the three DCT-III / DST-III sums of the flux series into
+// a, b, c.  The pairs are read and written in the row-major planes by the
+// whole workgroup at once: lane t takes pair t mod P of every (T / P)-th
+// row, so consecutive pairs of one map share each access (64 bytes per row
+// at N = 512, a full 128-byte line at N = 256).
+struct ColEntry {
+    const double2 *src;
+    double2 *oa, *ob, *oc;
+    int64_t cs;
+    bool live;
+};
+
+__device__ __forceinline__ void col_load(const ColEntry &e, double2 *buf, int N, int lgP)
+{
+    const int P = 1 << lgP;
+    for (int i = threadIdx.x >> lgP; i < N; i += blockDim.x / P)
+        buf[px(mk_pos(i, N))] = e.live ? e.src[i * e.cs] : make_double2(0.0, 0.0);
+}
+
+template <int WHICH>
+__device__ __forceinline__ void col_store(const ColEntry &e, const double2 *buf, int N, int lgP)
+{
+    const int P = 1 << lgP;
+    if (!e.live) return;
+    double2 *o = WHICH == 0 ? e.oa : (WHICH == 1 ? e.ob : e.oc);
+    for (int i = threadIdx.x >> lgP; i < N; i += blockDim.x / P) {
+        double2 y = buf[px(mk_pos(i, N))];
+        if (WHICH == 2 && (i & 1)) y = make_double2(-y.x, -y.y);   // DST-III sign
+        o[i * e.cs] = y;
+    }
+}
+
+__device__ void grp_col_pass(int m0, int lx, float sigma, const double2 *__restrict__ tq, int qs,
+                             double2 *a, const double2 *stw, const Grp &g, const ColEntry &mine,
+                             double2 *mine_buf, int lgP)
+{
+    const int N = g.N, G = g.G, lane = g.lane;
+    col_load(mine, mine_buf, N, lgP);
+    __syncthreads();
+    fft_grp<false>(a, stw, g);
+
+    // owned bins n = lane + u G: S[n][m0], S[n][m0 + 1], normalised and
+    // blurred; the Gaussian exp(-cgy n^2) by a two-term recurrence in u
+    const double PI = 3.14159265358979323846;
+    const double sg = (double)sigma, flx = (double)lx, fly = (double)N;
+    const double cgx = PI * PI * sg * sg / (2.0 * flx * flx);
+    const double cgy = PI * PI * sg * sg / (2.0 * fly * fly);
+    const double gx0 = exp(-cgx * (double)m0 * (double)m0) * (m0 == 0 ? 2.0 : 4.0);
+    const double gx1 = exp(-cgx * (double)(m0 + 1) * (double)(m0 + 1)) * 4.0;
+    double f = exp(-cgy * (double)lane * (double)lane);
+    double rr = exp(-cgy * ((double)(2 * lane * G) + (double)G * (double)G));
+    const double kap = exp(-2.0 * cgy * (double)G * (double)G);
+    double2 cw[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int n = lane + u * G;
+        const double2 b = grp_dct2_bin(a, n, N, tq[n * qs]);
+        const double gy = n == 0 ? 0.5 * f : f;
+        cw[u] = make_double2(b.x * gx0 * gy, b.y * gx1 * gy);
+        f *= rr;
+        rr *= kap;
+    }
+    gsync(g);
+    // mirror coefficients c[N - n] through the buffer
+    double2 cm[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[px(lane + u * G)] = cw[u];
+    gsync(g);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cm[u] = a[px((N - lane - u * G) & (N - 1))];
+    gsync(g);
+
+    // a: DCT-III of the coefficients
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int n = lane + u * G;
+        a[px(n)] = grp_dct3_in(n, cw[u], cm[u], tq[n * qs]);
+    }
+    gsync(g);
+    fft_grp<true>(a, stw, g);
+    __syncthreads();
+    col_store<0>(mine, mine_buf, N, lgP);
+    __syncthreads();
+
+    // b and c weigh the coefficients with
+    //   wx(m, n) = (ly/pi) m / (m^2 ly^2 + n^2 lx^2),  wy(m, n) = (lx/pi) n / (...),
+    // zero where the numerator vanishes; the coefficients are divided by the
+    // common denominator (at n and at N - n) once
+    const double ma = (double)m0, mb = (double)(m0 + 1);
+    const double inv_pi = 0.318309886183790671537767526745;
+    const double ay = (ma * fly) * (ma * fly), by = (mb * fly) * (mb * fly);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int n = lane + u * G, nr = (N - n) & (N - 1);
+        const double dn = ((double)n * flx) * ((double)n * flx);
+        const double dr = ((double)nr * flx) * ((double)nr * flx);
+        // the (0, 0) term has no flux: both numerators vanish there
+        cw[u] = make_double2(ay + dn > 0.0 ? cw[u].x * rcp64(ay + dn) : 0.0,
+                             cw[u].y * rcp64(by + dn));
+        cm[u] = make_double2(ay + dr > 0.0 ? cm[u].x * rcp64(ay + dr) : 0.0,
+                             cm[u].y * rcp64(by + dr));
+    }
+    const double kxa = fly * inv_pi * ma, kxb = fly * inv_pi * mb;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int n = lane + u * G;
+        a[px(n)] = grp_dct3_in(n, make_double2(kxa * cw[u].x, kxb * cw[u].y),
+                               make_double2(kxa * cm[u].x, kxb * cm[u].y), tq[n * qs]);
+    }
+    gsync(g);
+    fft_grp<true>(a, stw, g);
+    __syncthreads();
+    col_store<1>(mine, mine_buf, N, lgP);
+    __syncthreads();
+    // c: DST-III of wy * coefficients = (-1)^j DCT-III of the reversed
+    // sequence c'[m] = wy(N - m) c[N - m] (c'[0] = 0)
+    const double ky = flx * inv_pi;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int n = lane + u * G;
+        const double kr = n ? ky * (double)(N - n) : 0.0, kn = ky * (double)n;
+        a[px(n)] = grp_dct3_in(n, make_double2(kr * cm[u].x, kr * cm[u].y),
+                               make_double2(kn * cw[u].x, kn * cw[u].y), tq[n * qs]);
+    }
+    gsync(g);
+    fft_grp<true>(a, stw, g);
+    __syncthreads();
+    col_store<2>(mine, mine_buf, N, lgP);
+}
+
+// Row pass on rows j0, j0 + 1 of a, b, c [ly][lx] (N = lx): rho_s, J_x, J_y
+// of the two rows, written as the ghosted FP32 float4 fields to `fields`
+// and, if not null, `fields2`; rho_s and J_x wait in registers, each value
+// rounded once to FP32.
+__device__ void grp_row_final(const double *__restrict__ pa, const double *__restrict__ pb,
+                              const double *__restrict__ pc, int j0, int ly,
+                              const double2 *__restrict__ tq, int qs,
+                              float4 *__restrict__ fields, float4 *__restrict__ fields2,
+                              int32_t *status, double2 *a, const double2 *stw, const Grp &g,
+                              bool live)
+{
+    const int N = g.N, G = g.G, lane = g.lane;
+    const double norm = 1.0 / ((double)N * (double)ly);
+    // each plane's row pair is staged in the buffer (one coalesced read per
+    // element), then every lane takes its elements m and N - m from there
+    auto stage = [&](const double *__restrict__ plane) {
+        const double *r0 = plane + (int64_t)j0 * N, *r1 = r0 + N;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int m = lane + u * G;
+            a[px(m)] = live ? make_double2(r0[m], r1[m]) : make_double2(0.0, 0.0);
+        }
+        gsync(g);
+    };
+    // DCT-III input from the staged pairs; REV: of the index-reversed
+    // sequence c'[m] = c[N - m] (c'[0] = 0), for the DST-III
+    auto dct3_from_stage = [&](bool rev) {
+        double2 xm[8], xr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int m = lane + u * G;
+            const double2 lo = a[px(m)], hi = a[px((N - m) & (N - 1))];
+            xm[u] = rev ? (m ? hi : make_double2(0.0, 0.0)) : lo;
+            xr[u] = rev ? lo : hi;
+        }
+        gsync(g);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int m = lane + u * G;
+            a[px(m)] = grp_dct3_in(m, xm[u], xr[u], tq[m * qs]);
+        }
+        gsync(g);
+    };
+    float2 rs[8], jx[8];
+    // rho_s: DCT-III of a
+    stage(pa);
+    dct3_from_stage(false);
+    fft_grp<true>(a, stw, g);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double2 y = a[px(mk_pos(lane + u * G, N))];
+        rs[u] = make_float2((float)(y.x * norm), (float)(y.y * norm));
+    }
+    gsync(g);
+    // J_x: DST-III of b = (-1)^i DCT-III of b reversed
+    stage(pb);
+    dct3_from_stage(true);
+    fft_grp<true>(a, stw, g);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = lane + u * G;
+        const double2 y = a[px(mk_pos(i, N))];
+        const double s = (i & 1) ? -1.0 : 1.0;
+        jx[u] = make_float2((float)(s * y.x), (float)(s * y.y));
+    }
+    gsync(g);
+    // J_y: DCT-III of c
+    stage(pc);
+    dct3_from_stage(false);
+    fft_grp<true>(a, stw, g);
+    const int P = N + 2;
+    int bad = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = lane + u * G;
+        const double2 y = a[px(mk_pos(i, N))];
+        const float4 f0 = make_float4(jx[u].x, (float)y.x, rs[u].x, 0.f);
+        const float4 f1 = make_float4(jx[u].y, (float)y.y, rs[u].y, 0.f);
+        if (!live) continue;
+        bad |= !(f0.z > 0.f) || !(f1.z > 0.f);
+        auto put = [&](float4 *__restrict__ out) {
+            float4 *row0 = out + (int64_t)(j0 + 1) * P;
+            float4 *row1 = row0 + P;
+            row0[i + 1] = f0;
+            row1[i + 1] = f1;
+            // ghost columns: J_x odd across the x edges
+            if (i == 0 || i == N - 1) {
+                const int gi = (i == 0) ? 0 : N + 1;
+                row0[gi] = make_float4(-f0.x, f0.y, f0.z, 0.f);
+                row1[gi] = make_float4(-f1.x, f1.y, f1.z, 0.f);
+            }
+            // ghost rows: J_y odd across the y edges
+            if (j0 == 0) {
+                out[i + 1] = make_float4(f0.x, -f0.y, f0.z, 0.f);
+                if (i == 0 || i == N - 1)
+                    out[(i == 0) ? 0 : N + 1] = make_float4(-f0.x, -f0.y, f0.z, 0.f);
+            }
+            if (j0 + 1 == ly - 1) {
+                float4 *grow = out + (int64_t)(ly + 1) * P;
+                grow[i + 1] = make_float4(f1.x, -f1.y, f1.z, 0.f);
+                if (i == 0 || i == N - 1)
+                    grow[(i == 0) ? 0 : N + 1] = make_float4(-f1.x, -f1.y, f1.z, 0.f);
+            }
+        };
+        put(fields);
+        if (fields2) put(fields2);
+    }
+    if (bad) set_status(status, FFB_E_NONPOSITIVE);
+}
+
+// Batched kernels: P table entries (map, first row or column of the pair)
+// per workgroup, all of one grid-size class (length N).
+template <int T>
+__global__ __launch_bounds__(T) void kb_dct2_rows_g(batch_view bv,
+                                                              const int2 *__restrict__ rows,
+                                                              int n, int N,
+                                                              const double *__restrict__ in,
+                                                              double *__restrict__ out,
+                                                              const double2 *__restrict__ tw,
+                                                              const double2 *__restrict__ tq)
+{
+    __shared__ double2 buf[grp_lds<T>()], stw[kMaxN / 2];
+    const Grp g = grp_of<T>(N);
+    const int q = blockIdx.x * g.P + g.id;
+    const int2 e = q < n ? rows[q] : make_int2(0, 0);
+    const bool live = q < n && bv.active[e.x];
+    if (!grp_enter(stw, tw, N, g, live)) return;
+    const int64_t o = bv.plane_off[e.x];
+    grp_dct2_rows(in + o, out + o, live ? e.y : 0, tq, kMaxN / N, buf + g.id * padded(N), stw,
+                  nullptr, nullptr, g, live);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void kb_col_pass_g(batch_view bv,
+                                                             const int2 *__restrict__ cols, int n,
+                                                             int N, const double *__restrict__ t1,
+                                                             const double2 *__restrict__ tw,
+                                                             const double2 *__restrict__ tq,
+                                                             double *__restrict__ pa,
+                                                             double *__restrict__ pb,
+                                                             double *__restrict__ pc)
+{
+    __shared__ double2 buf[grp_lds<T>()], stw[kMaxN / 2];
+    const Grp g = grp_of<T>(N);
+    const int lgP = ilog2(g.P);
+    auto entry = [&](int p, int &m0, int &lx, float &sigma) {
+        const int q = blockIdx.x * g.P + p;
+        const int2 e = q < n ? cols[q] : make_int2(0, 0);
+        const int m = e.x;
+        ColEntry c;
+        c.live = q < n && bv.active[m] && bv.ly[m] == N;
+        const int64_t o = bv.plane_off[m];
+        m0 = c.live ? e.y : 0;
+        lx = bv.lx[m];
+        sigma = (float)ldexp(bv.sigma0, -bv.round[m]);
+        c.cs = lx / 2;
+        c.src = reinterpret_cast<const double2 *>(t1 + o + m0);
+        c.oa = reinterpret_cast<double2 *>(pa + o + m0);
+        c.ob = reinterpret_cast<double2 *>(pb + o + m0);
+        c.oc = reinterpret_cast<double2 *>(pc + o + m0);
+        return c;
+    };
+    // this lane's group (transforms) and its pair of the block-wide accesses
+    int m0, lx, m0c, lxc;
+    float sigma, sgc;
+    const ColEntry own = entry(g.id, m0, lx, sigma);
+    const int pc_ = threadIdx.x & (g.P - 1);
+    const ColEntry acc = entry(pc_, m0c, lxc, sgc);
+    // leave only if no pair of the workgroup is live (barriers follow)
+    if (!__syncthreads_or(own.live)) return;
+    load_tw_grp(stw, tw, N, kMaxN / N);
+    grp_col_pass(m0, lx, sigma, tq, kMaxN / N, buf + g.id * padded(N), stw, g, acc,
+                 buf + pc_ * padded(N), lgP);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void kb_row_final_g(
+    batch_view bv, const int2 *__restrict__ rows, int n, int N, const double *__restrict__ pa,
+    const double *__restrict__ pb, const double *__restrict__ pc, const double2 *__restrict__ tw,
+    const double2 *__restrict__ tq, float4 *__restrict__ fields, int32_t *status)
+{
+    __shared__ double2 buf[grp_lds<T>()], stw[kMaxN / 2];
+    const Grp g = grp_of<T>(N);
+    const int q = blockIdx.x * g.P + g.id;
+    const int2 e = q < n ? rows[q] : make_int2(0, 0);
+    const int m = e.x;
+    const bool live = q < n && bv.active[m];
+    if (!grp_enter(stw, tw, N, g, live)) return;
+    const int64_t o = bv.plane_off[m];
+    grp_row_final(pa + o, pb + o, pc + o, live ? e.y : 0, bv.ly[m], tq, kMaxN / N,
+                  fields + bv.field_off[m], nullptr, status, buf + g.id * padded(N), stw, g, live);
+}
+
+// Workgroups of T lanes for a grouped pass over n pairs of length N.
+inline int grp_blocks(int n_pairs, int N, int T)
+{
+    const int P = T / (N / 8);
+    return (n_pairs + P - 1) / P;
+}
+
+// Launches K<T> for a class with the requested workgroup size t (at least
+// one group of N / 8 lanes).
+template <template <int> class K, typename... A>
+hipError_t launch_grp_class(int t, int n, int N, hipStream_t s, A... args)
+{
+    t = std::max(t, N / 8);
+    switch (t) {
+    case 64:
+        return K<64>::go(dim3(grp_blocks(n, N, 64)), s, args...);
+    case 128:
+        return K<128>::go(dim3(grp_blocks(n, N, 128)), s, args...);
+    case 256:
+        return K<256>::go(dim3(grp_blocks(n, N, 256)), s, args...);
+    case 512:
+        return K<512>::go(dim3(grp_blocks(n, N, 512)), s, args...);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+template <int T> struct RowsK {
+    template <typename... A> static hipError_t go(dim3 grid, hipStream_t s, A... a)
+    {
+        hipLaunchKernelGGL(kb_dct2_rows_g<T>, grid, dim3(T), 0, s, a...);
+        return hipGetLastError();
+    }
+};
+template <int T> struct ColsK {
+    template <typename... A> static hipError_t go(dim3 grid, hipStream_t s, A... a)
+    {
+        hipLaunchKernelGGL(kb_col_pass_g<T>, grid, dim3(T), 0, s, a...);
+        return hipGetLastError();
+    }
+};
+template <int T> struct FinalK {
+    template <typename... A> static hipError_t go(dim3 grid, hipStream_t s, A... a)
+    {
+        hipLaunchKernelGGL(kb_row_final_g<T>, grid, dim3(T), 0, s, a...);
+        return hipGetLastError();
+    }
+};
+
 }  // namespace
 
 hipError_t launch_flux_ws(hipStream_t s, int lx, int ly, const flux_ws &w, const double *rho,
@@ -1111,24 +1719,25 @@ hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_ta
                              float4 *fields, double *rho_bar, int32_t *status)
 {
     hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, s, bv, acc, rho_bar, status);
-    for (int c = 0; c < plan.n_classes; ++c) {
-        const int n = plan.row_beg[c + 1] - plan.row_beg[c];
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
+        const int n = plan.row_beg[c + 1] - plan.row_beg[c], N = plan.n[c];
         if (n > 0)
-            hipLaunchKernelGGL(kb_dct2_rows, dim3(n), dim3(plan.threads[c]), 0, s, bv,
-                               bt.rows + plan.row_beg[c], rho, t1, tw1024, tq1024);
+            e = launch_grp_class<RowsK>(plan.threads[c], n, N, s, bv, bt.rows + plan.row_beg[c], n,
+                                        N, rho, t1, tw1024, tq1024);
     }
-    for (int c = 0; c < plan.n_classes; ++c) {
-        const int n = plan.col_beg[c + 1] - plan.col_beg[c];
+    for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
+        const int n = plan.col_beg[c + 1] - plan.col_beg[c], N = plan.n[c];
         if (n > 0)
-            hipLaunchKernelGGL(kb_col_pass, dim3(n), dim3(plan.threads[c]), 0, s, bv,
-                               bt.cols + plan.col_beg[c], t1, tw1024, tq1024, pa, pb, pc);
+            e = launch_grp_class<ColsK>(plan.threads[c], n, N, s, bv, bt.cols + plan.col_beg[c], n,
+                                        N, t1, tw1024, tq1024, pa, pb, pc);
     }
-    for (int c = 0; c < plan.n_classes; ++c) {
-        const int n = plan.row_beg[c + 1] - plan.row_beg[c];
+    for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
+        const int n = plan.row_beg[c + 1] - plan.row_beg[c], N = plan.n[c];
         if (n > 0)
-            hipLaunchKernelGGL(kb_row_final, dim3(n), dim3(plan.threads[c]), 0, s, bv,
-                               bt.rows + plan.row_beg[c], pa, pb, pc, tw1024, tq1024, fields,
-                               status);
+            e = launch_grp_class<FinalK>(plan.threads[c], n, N, s, bv, bt.rows + plan.row_beg[c],
+                                         n, N, pa, pb, pc, tw1024, tq1024, fields, status);
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
