@@ -459,15 +459,20 @@ int ffb_backward(ffb_ctx *ctx, const double *dL_darea, double *dL_dvalue, double
                                 cleared ? density_adj_total(ctx) : nullptr);
             suffixed = cleared && e == hipSuccess;
             break;
-        case 'D':
+        case 'D': {
+            // the area record before it (whose areas the density read) takes
+            // lam_area in the same call
+            const tape_rec *a = k > 0 && recs[k - 1].kind == 'A' ? &recs[k - 1] : nullptr;
             if (!cleared) e = launch_fill_f64(t->lam_area, R, 0.0, s);
             if (e == hipSuccess)
                 e = launch_density_adj(ctx, &r.g, r.value, r.area, t->lam_rho, dL_dvalue,
-                                       t->lam_area, t->lam_xy, cleared, suffixed, r.w);
+                                       t->lam_area, t->lam_xy, cleared, suffixed, r.w,
+                                       a ? &a->g : nullptr);
             cleared = false;
             suffixed = false;
-            pending = true;
+            pending = a == nullptr;
             break;
+        }
         case 'A':
             if (pending) e = launch_area_adj(ctx, &r.g, t->lam_area, t->lam_xy);
             pending = false;

@@ -216,11 +216,14 @@ hipError_t launch_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *la
 // `suffixed`: the row suffix sums of lam_rho are in ctx->acc and their total
 // in density_adj_total (from launch_flux_adj; implies `cleared`).  `w`
 // (optional): the forward's weights w_r, else they are recomputed from value
-// and area.
+// and area.  `area_g` (optional): also the area adjoint of that geometry
+// with the lam_area just formed (lam_area zero before the call when
+// `cleared`), fused into the last launch when the regions are few.
 hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                               const double *area, const float *lam_rho, double *lam_value,
                               double *lam_area, double *lam_xy, bool cleared = false,
-                              bool suffixed = false, const double *w = nullptr);
+                              bool suffixed = false, const double *w = nullptr,
+                              const ffb_geometry *area_g = nullptr);
 // The context's accumulators that launch_density_adj starts from zero: the
 // sum of lam_rho (one double) and the per-region coverage sums (R doubles).
 inline double *density_adj_total(ffb_ctx *ctx) { return ctx->red + 513; }

@@ -298,6 +298,84 @@ __global__ __launch_bounds__(1024) void k_density_chain(
     }
 }
 
+
+// The density chain and the area adjoint that follows it in one launch, for
+// few regions (every workgroup sums the R values itself, in the same order,
+// so all arrive at the same sums): lam_area_r of the density record
+// (starting from zero) is formed where the area adjoint needs it;
+// workgroup 0 also stores lam_value and lam_area.
+constexpr int kChainAreaMaxRegions = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_density_chain_area(
+    const double *__restrict__ value, const double *__restrict__ area, int32_t R,
+    const double *__restrict__ lam_w, const double *__restrict__ lam_total,
+    double *__restrict__ lam_value, double *__restrict__ lam_area,
+    const float2 *__restrict__ xy, int64_t nv, const int32_t *__restrict__ off,
+    const int32_t *__restrict__ vidx, const int32_t *__restrict__ region, int32_t G, int64_t E,
+    double *__restrict__ lam_xy, int32_t *status)
+{
+    __shared__ int32_t s_off[kStagedRingOffsets];
+    __shared__ double part[3][kThreads / 64];
+    double sa = 0.0, sv = 0.0, sw = 0.0;
+    for (int32_t r = threadIdx.x; r < R; r += kThreads) {
+        sa += area[r];
+        sv += value[r];
+        sw += lam_w[r];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sa += __shfl_xor(sa, o, 64);
+        sv += __shfl_xor(sv, o, 64);
+        sw += __shfl_xor(sw, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = sa;
+        part[1][threadIdx.x >> 6] = sv;
+        part[2][threadIdx.x >> 6] = sw;
+    }
+    __syncthreads();
+    double SA = 0.0, SV = 0.0, SW = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+        SA += part[0][w];
+        SV += part[1][w];
+        SW += part[2][w];
+    }
+    const double lam_pad = *lam_total - SW;
+    if (blockIdx.x == 0)
+        for (int32_t r = threadIdx.x; r < R; r += kThreads) {
+            const double a = area[r];
+            lam_value[r] += lam_w[r] / a + lam_pad / SA;
+            lam_area[r] += -lam_w[r] * value[r] / (a * a) - lam_pad * SV / (SA * SA);
+        }
+    const bool staged = stage_ring_offsets(off, G, s_off);
+    const int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (k >= E) return;
+    int32_t lo;
+    int64_t b, e;
+    if (staged) {
+        lo = ring_search(s_off, G, k);
+        b = s_off[lo];
+        e = s_off[lo + 1];
+    } else {
+        lo = ring_search(off, G, k);
+        b = off[lo];
+        e = off[lo + 1];
+    }
+    if (!(b <= k && k < e) || e - b < 3 || e > E) { set_status(status, FFB_E_INVALID); return; }
+    const int32_t r = region[lo];
+    const int32_t ic = vidx[k];
+    const int32_t ip = vidx[(k == b) ? e - 1 : k - 1];
+    const int32_t in = vidx[(k + 1 == e) ? b : k + 1];
+    if (r < 0 || r >= R || ic < 0 || ic >= nv || ip < 0 || ip >= nv || in < 0 || in >= nv) {
+        set_status(status, FFB_E_INVALID);
+        return;
+    }
+    const float2 pp = xy[ip], pn = xy[in];
+    const double a = area[r];
+    const double l = -lam_w[r] * value[r] / (a * a) - lam_pad * SV / (SA * SA);
+    unsafeAtomicAdd(&lam_xy[2 * (int64_t)ic], 0.5 * l * ((double)pn.y - (double)pp.y));
+    unsafeAtomicAdd(&lam_xy[2 * (int64_t)ic + 1], 0.5 * l * ((double)pp.x - (double)pn.x));
+}
+
 // ------------------------------------------------------------ integration
 __constant__ double kC[6] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0};
 __constant__ float kA[6][5] = {
@@ -842,7 +920,7 @@ hipError_t launch_area_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *la
 hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double *value,
                               const double *area, const float *lam_rho, double *lam_value,
                               double *lam_area, double *lam_xy, bool cleared, bool suffixed,
-                              const double *w)
+                              const double *w, const ffb_geometry *area_g)
 {
     hipStream_t s = ctx->stream;
     double *total = density_adj_total(ctx);
@@ -870,9 +948,21 @@ hipError_t launch_density_adj(ffb_ctx *ctx, const ffb_geometry *g, const double 
                            g->n_regions, g->n_entries, w, lam_rho, ctx->acc, ctx->lx,
                            ctx->ly, ctx->lam_w, lam_xy, ctx->d_status);
     }
+    if (area_g && cleared && g->n_regions <= kChainAreaMaxRegions &&
+        area_g->n_regions == g->n_regions && area_g->n_entries > 0) {
+        const int64_t blocks = (area_g->n_entries + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL(k_density_chain_area, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           value, area, g->n_regions, ctx->lam_w, total, lam_value, lam_area,
+                           reinterpret_cast<const float2 *>(area_g->xy), area_g->n_vertices,
+                           area_g->ring_offsets, area_g->ring_vidx, area_g->ring_region,
+                           area_g->n_rings, area_g->n_entries, lam_xy, ctx->d_status);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_density_chain, dim3(1), dim3(1024), 0, s, value, area, g->n_regions,
                        ctx->lam_w, total, lam_value, lam_area);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e == hipSuccess && area_g) e = launch_area_adj(ctx, area_g, lam_area, lam_xy);
+    return e;
 }
 
 hipError_t launch_advect_adj(ffb_ctx *ctx, const float4 *fields, const double *rho_bar,
