@@ -63,14 +63,14 @@ struct ffb_batch {
             *d_stats = nullptr, *d_n_active = nullptr, *d_status = nullptr;
     double *d_max_err = nullptr;
     // launch tables, rows and columns grouped by transform-length class
-    int2 *d_rows = nullptr, *d_cols = nullptr, *d_scan_rows = nullptr;
-    int32_t n_rows = 0, n_cols = 0, n_scan_rows = 0;
+    int2 *d_rows = nullptr, *d_cols = nullptr;
+    int32_t n_rows = 0, n_cols = 0;
     int n_classes = 0;
     int32_t class_n[kMaxClasses];                  // transform length of each class
     int32_t row_beg[kMaxClasses + 1], col_beg[kMaxClasses + 1];
     // workspace
     // density grids and transform planes (FP64)
-    double *rho = nullptr, *t1 = nullptr, *pa = nullptr, *pb = nullptr, *pc = nullptr;
+    double *t1 = nullptr, *pa = nullptr, *pb = nullptr, *pc = nullptr;
     float4 *fields = nullptr;
     double *acc = nullptr, *w_region = nullptr, *rho_pad = nullptr, *rho_bar = nullptr,
            *area = nullptr, *err = nullptr;
@@ -110,8 +110,8 @@ void free_batch(ffb_batch *b)
     void *ptrs[] = {b->d_lx, b->d_ly, b->d_region_off, b->d_ring_map, b->d_entry_ring, b->d_plane_off,
                     b->d_field_off, b->d_acc_off, b->d_point_off, b->d_nvert, b->d_active,
                     b->d_round, b->d_rounds_done, b->d_order, b->d_stats, b->d_n_active,
-                    b->d_status, b->d_max_err, b->d_rows, b->d_cols, b->d_scan_rows,
-                    b->rho, b->t1, b->pa, b->pb, b->pc,
+                    b->d_status, b->d_max_err, b->d_rows, b->d_cols,
+                    b->t1, b->pa, b->pb, b->pc,
                     b->fields, b->acc, b->w_region, b->rho_pad, b->rho_bar, b->area, b->err,
                     b->st0, b->st1, b->kv0, b->kv1, b->scratch_xy, b->tw1024, b->tq1024};
     for (void *p : ptrs)
@@ -151,10 +151,8 @@ batch_tables tables_of(const ffb_batch *b)
     batch_tables t;
     t.rows = b->d_rows;
     t.cols = b->d_cols;
-    t.scan_rows = b->d_scan_rows;
     t.n_rows = b->n_rows;
     t.n_cols = b->n_cols;
-    t.n_scan_rows = b->n_scan_rows;
     return t;
 }
 
@@ -254,9 +252,9 @@ hipError_t enqueue_step(ffb_batch *b, const ffb_batch_opts &o, float *xy,
     const batch_tables bt = tables_of(b);
     ffb_geometry g = geom_of(b, xy);
     hipError_t e = launch_batch_density(s, bv, bt, &g, b->value, b->area, b->w_region, b->rho_pad,
-                                        b->acc, b->acc_total, b->rho, b->d_status);
+                                        b->acc, b->acc_total, b->d_status);
     if (e == hipSuccess)
-        e = launch_batch_flux(s, bv, bt, plan_of(b, b->fft_threads), b->tw1024, b->tq1024, b->rho,
+        e = launch_batch_flux(s, bv, bt, plan_of(b, b->fft_threads), b->tw1024, b->tq1024, b->rho_pad,
                               b->acc, b->t1, b->pa, b->pb, b->pc, b->fields, b->rho_bar,
                               b->d_status);
     if (e == hipSuccess)
@@ -411,7 +409,7 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     });
     // launch tables: the rows of maps with lx = N and the columns of maps
     // with ly = N form class N
-    std::vector<int2> rows, cols, scan_rows;
+    std::vector<int2> rows, cols;
     b->n_classes = (int)widths.size();
     for (int c = 0; c < b->n_classes; ++c) {
         b->class_n[c] = widths[c];
@@ -430,12 +428,8 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     }
     b->row_beg[b->n_classes] = (int32_t)rows.size();
     b->col_beg[b->n_classes] = (int32_t)cols.size();
-    for (int32_t m = 0; m < M; ++m) {
-        for (int j = 0; j < b->ly[m]; ++j) scan_rows.push_back(make_int2(m, j));
-    }
     b->n_rows = (int32_t)rows.size();
     b->n_cols = (int32_t)cols.size();
-    b->n_scan_rows = (int32_t)scan_rows.size();
 
     hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
@@ -455,7 +449,6 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) e = upload(&b->d_order, order);
     if (e == hipSuccess) e = upload(&b->d_rows, rows);
     if (e == hipSuccess) e = upload(&b->d_cols, cols);
-    if (e == hipSuccess) e = upload(&b->d_scan_rows, scan_rows);
     if (e == hipSuccess) e = alloc(&b->d_active, M);
     if (e == hipSuccess) e = alloc(&b->d_round, M);
     if (e == hipSuccess) e = alloc(&b->d_rounds_done, M);
@@ -463,7 +456,7 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) e = alloc(&b->d_n_active, 1);
     if (e == hipSuccess) e = alloc(&b->d_status, 1);
     if (e == hipSuccess) e = alloc(&b->d_max_err, M);
-    double **planes[] = {&b->rho, &b->t1, &b->pa, &b->pb, &b->pc};
+    double **planes[] = {&b->t1, &b->pa, &b->pb, &b->pc};
     for (double **pl : planes)
         if (e == hipSuccess) e = alloc(pl, b->plane_total);
     if (e == hipSuccess) e = alloc(&b->fields, b->field_total);
@@ -634,7 +627,7 @@ int ffb_batch_autotune(ffb_batch *b, const ffb_batch_opts *o)
     if (e == hipSuccess) e = enqueue_reset(b);
     if (e == hipSuccess)
         e = launch_batch_density(b->stream, bv0, tables_of(b), &g, b->value, b->area, b->w_region,
-                                 b->rho_pad, b->acc, b->acc_total, b->rho, b->d_status);
+                                 b->rho_pad, b->acc, b->acc_total, b->d_status);
     // transform passes: one class at a time, the others fixed
     for (int c = 0; c < b->n_classes && e == hipSuccess; ++c) {
         float best = 1e30f;
@@ -647,7 +640,7 @@ int ffb_batch_autotune(ffb_batch *b, const ffb_batch_opts *o)
             const batch_fft_plan plan = plan_of(b, threads);
             float ms = time_it(b, [&]() {
                 return launch_batch_flux(b->stream, bv0, tables_of(b), plan, b->tw1024, b->tq1024,
-                                         b->rho, b->acc, b->t1, b->pa, b->pb, b->pc,
+                                         b->rho_pad, b->acc, b->t1, b->pa, b->pb, b->pc,
                                          b->fields, b->rho_bar, b->d_status);
             }, 3, &e);
             if (e == hipSuccess && ms < best) {

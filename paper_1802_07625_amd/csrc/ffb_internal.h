@@ -337,8 +337,7 @@ struct batch_view {
 struct batch_tables {
     const int2 *rows;              // (map, j0) for every even row j0 of every map
     const int2 *cols;              // (map, m0) for every even column m0
-    int32_t n_rows, n_cols, n_scan_rows;
-    const int2 *scan_rows;         // (map, j) for every row
+    int32_t n_rows, n_cols;
 };
 
 // Batched launchers (k_area.hip, k_raster.hip, k_flux.hip, k_advect.hip).
@@ -349,10 +348,13 @@ hipError_t launch_batch_finalize(hipStream_t s, const batch_view &bv, const doub
 // Ring of every ring entry, entry_ring[k] = g for off[g] <= k < off[g + 1].
 hipError_t launch_entry_ring(hipStream_t s, const int32_t *off, int32_t G, int64_t E,
                              int32_t *entry_ring);
+// Coverage deltas of every active map into acc (rows of lx + 1); the row
+// prefix sums that turn them into densities are the first pass of
+// launch_batch_flux.
 hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                                 const ffb_geometry *g, const double *value, const double *area,
                                 double *w_region, double *rho_pad, double *acc, int64_t acc_total,
-                                double *rho, int32_t *status);
+                                int32_t *status);
 // Row and column tables are sorted by grid width; class c owns entries
 // [row_beg[c], row_beg[c+1]) and [col_beg[c], col_beg[c+1]) and its passes
 // run with threads[c] lanes per workgroup.
@@ -365,7 +367,7 @@ struct batch_fft_plan {
 };
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const double2 *tw1024,
-                             const double2 *tq1024, const double *rho, const double *acc,
+                             const double2 *tq1024, const double *rho_pad, double *acc,
                              double *t1, double *pa, double *pb, double *pc,
                              float4 *fields, double *rho_bar, int32_t *status);
 struct batch_advect_args {

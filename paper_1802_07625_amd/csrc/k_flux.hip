@@ -1245,6 +1245,100 @@ __device__ void grp_dct2_rows(const double *__restrict__ in, double *__restrict_
     }
 }
 
+
+// Densities and row DCT of a row pair in one pass (batched maps): rho[j][i]
+// = rho_pad + the inclusive prefix sum of the coverage deltas acc[j][0..i]
+// (rows of N + 1; the spare slot receives the row's sum of rho, for the
+// mean), in FP64, then the DCT-II of the two density rows into `out`.
+// Lane l of the group holds elements 8 l .. 8 l + 7: a prefix within the
+// lane, an exclusive scan of the lane totals over the group (butterflies
+// within a wavefront, the lower wavefront's total through LDS for a
+// 128-lane group), fixed order throughout.
+__device__ void grp_scan_dct2_rows(double *__restrict__ acc, double pad, double *__restrict__ out,
+                                   int64_t r0, const double2 *__restrict__ tq, int qs, double2 *a,
+                                   const double2 *stw, double *part, const Grp &g, bool live)
+{
+    const int N = g.N, lane = g.lane;
+    double *acc0 = acc + r0 * (N + 1), *acc1 = acc0 + (N + 1);
+    double v0[8], v1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = 8 * lane + u;
+        v0[u] = live ? acc0[i] : 0.0;
+        v1[u] = live ? acc1[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 1; u < 8; ++u) {
+        v0[u] += v0[u - 1];
+        v1[u] += v1[u - 1];
+    }
+    // inclusive scan of the lane totals over the group's lanes
+    const int W = g.G < 64 ? g.G : 64;            // lanes of the group in this wavefront
+    const int wl = threadIdx.x & (W - 1);
+    double s0 = v0[7], s1 = v1[7];
+    for (int o = 1; o < W; o <<= 1) {
+        const double y0 = __shfl_up(s0, o, W), y1 = __shfl_up(s1, o, W);
+        if (wl >= o) {
+            s0 += y0;
+            s1 += y1;
+        }
+    }
+    double e0 = s0 - v0[7], e1 = s1 - v1[7];      // exclusive
+    if (g.G > 64) {
+        // the upper wavefront of the group adds the lower one's total
+        if ((threadIdx.x & 63) == 63) {
+            part[2 * (threadIdx.x >> 6)] = s0;
+            part[2 * (threadIdx.x >> 6) + 1] = s1;
+        }
+        __syncthreads();
+        if (lane >= 64) {
+            const int w = (threadIdx.x >> 6) - 1;
+            e0 += part[2 * w];
+            e1 += part[2 * w + 1];
+        }
+    }
+    double t0 = 0.0, t1 = 0.0;                    // row sums of rho
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = 8 * lane + u;
+        const double r0v = pad + (e0 + v0[u]), r1v = pad + (e1 + v1[u]);
+        t0 += r0v;
+        t1 += r1v;
+        a[px(mk_pos(i, N))] = make_double2(r0v, r1v);
+    }
+    for (int o = 1; o < W; o <<= 1) {
+        t0 += __shfl_xor(t0, o, 64);
+        t1 += __shfl_xor(t1, o, 64);
+    }
+    if (g.G > 64) {
+        __syncthreads();                           // the exclusive totals are read
+        if ((threadIdx.x & 63) == 0) {
+            part[2 * (threadIdx.x >> 6)] = t0;
+            part[2 * (threadIdx.x >> 6) + 1] = t1;
+        }
+        __syncthreads();
+        const int w0 = 2 * g.id;
+        t0 = part[2 * w0] + part[2 * (w0 + 1)];
+        t1 = part[2 * w0 + 1] + part[2 * (w0 + 1) + 1];
+    }
+    if (live && lane == 0) {
+        acc0[N] = t0;
+        acc1[N] = t1;
+    }
+    gsync(g);
+    fft_grp<false>(a, stw, g);
+    double *oa = out + r0 * N, *ob = oa + N;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int n = lane + u * g.G;
+        const double2 b = grp_dct2_bin(a, n, N, tq[n * qs]);
+        if (live) {
+            oa[n] = b.x;
+            ob[n] = b.y;
+        }
+    }
+}
+
 // Column pass of a workgroup's P column pairs (entries P b .. P b + P - 1 of
 // the class table, N = ly): the DCT-II along y, the normalisation and blur
 // of Eq. 7, then the three DCT-III / DST-III sums of the flux series into
@@ -1490,23 +1584,23 @@ __device__ void grp_row_final(const double *__restrict__ pa, const double *__res
 // Batched kernels: P table entries (map, first row or column of the pair)
 // per workgroup, all of one grid-size class (length N).
 template <int T>
-__global__ __launch_bounds__(T) void kb_dct2_rows_g(batch_view bv,
-                                                              const int2 *__restrict__ rows,
-                                                              int n, int N,
-                                                              const double *__restrict__ in,
-                                                              double *__restrict__ out,
-                                                              const double2 *__restrict__ tw,
-                                                              const double2 *__restrict__ tq)
+__global__ __launch_bounds__(T) void kb_scan_dct2_g(batch_view bv, const int2 *__restrict__ rows,
+                                                    int n, int N, double *__restrict__ acc,
+                                                    const double *__restrict__ rho_pad,
+                                                    double *__restrict__ out,
+                                                    const double2 *__restrict__ tw,
+                                                    const double2 *__restrict__ tq)
 {
     __shared__ double2 buf[grp_lds<T>()], stw[kMaxN / 2];
+    __shared__ double part[2 * (T / 64)];
     const Grp g = grp_of<T>(N);
     const int q = blockIdx.x * g.P + g.id;
     const int2 e = q < n ? rows[q] : make_int2(0, 0);
-    const bool live = q < n && bv.active[e.x];
+    const int m = e.x;
+    const bool live = q < n && bv.active[m];
     if (!grp_enter(stw, tw, N, g, live)) return;
-    const int64_t o = bv.plane_off[e.x];
-    grp_dct2_rows(in + o, out + o, live ? e.y : 0, tq, kMaxN / N, buf + g.id * padded(N), stw,
-                  nullptr, nullptr, g, live);
+    grp_scan_dct2_rows(acc + bv.acc_off[m], rho_pad[m], out + bv.plane_off[m], live ? e.y : 0, tq,
+                       kMaxN / N, buf + g.id * padded(N), stw, part, g, live);
 }
 
 template <int T>
@@ -1599,7 +1693,7 @@ hipError_t launch_grp_class(int t, int n, int N, hipStream_t s, A... args)
 template <int T> struct RowsK {
     template <typename... A> static hipError_t go(dim3 grid, hipStream_t s, A... a)
     {
-        hipLaunchKernelGGL(kb_dct2_rows_g<T>, grid, dim3(T), 0, s, a...);
+        hipLaunchKernelGGL(kb_scan_dct2_g<T>, grid, dim3(T), 0, s, a...);
         return hipGetLastError();
     }
 };
@@ -1714,17 +1808,21 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
 
 hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const double2 *tw1024,
-                             const double2 *tq1024, const double *rho, const double *acc,
+                             const double2 *tq1024, const double *rho_pad, double *acc,
                              double *t1, double *pa, double *pb, double *pc,
                              float4 *fields, double *rho_bar, int32_t *status)
 {
-    hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, s, bv, acc, rho_bar, status);
     hipError_t e = hipSuccess;
     for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
         const int n = plan.row_beg[c + 1] - plan.row_beg[c], N = plan.n[c];
         if (n > 0)
             e = launch_grp_class<RowsK>(plan.threads[c], n, N, s, bv, bt.rows + plan.row_beg[c], n,
-                                        N, rho, t1, tw1024, tq1024);
+                                        N, acc, rho_pad, t1, tw1024, tq1024);
+    }
+    // the mean density from the row sums the first pass left
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, s, bv, acc, rho_bar, status);
+        e = hipGetLastError();
     }
     for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
         const int n = plan.col_beg[c + 1] - plan.col_beg[c], N = plan.n[c];

@@ -387,52 +387,6 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
     run_add(acc, key, va, vb);
 }
 
-// Row prefix sums of every active map, one workgroup per (map, row).  The
-// FP64 sum of the row's densities (fixed order: each lane's
-// cells in order, then a tree over the lanes) goes to the row's spare last
-// slot acc[j][lx], which the deposits may have touched but the prefix sum
-// never reads; kb_mean turns the row sums into the map's mean density.
-__global__ __launch_bounds__(kScanThreads) void kb_raster_scan(
-    batch_view bv, const int2 *__restrict__ rows, double *__restrict__ acc,
-    const double *__restrict__ rho_pad, double *__restrict__ rho)
-{
-    __shared__ double part[kScanThreads];
-    const int2 e = rows[blockIdx.x];
-    const int m = e.x, j = e.y;
-    if (!bv.active[m]) return;
-    const int32_t lx = bv.lx[m];
-    double *row = acc + bv.acc_off[m] + (int64_t)j * (lx + 1);
-    const int32_t chunk = (lx + kScanThreads - 1) / kScanThreads;
-    const int32_t beg = threadIdx.x * chunk;
-    const int32_t end = min(beg + chunk, lx);
-    double s = 0.0;
-    for (int32_t i = beg; i < end; ++i) s += row[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < kScanThreads; o <<= 1) {
-        const double v = (threadIdx.x >= (unsigned)o) ? part[threadIdx.x - o] : 0.0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    double run = part[threadIdx.x] - s + rho_pad[m];
-    double *out = rho + bv.plane_off[m] + (int64_t)j * lx;
-    double stored = 0.0;
-    for (int32_t i = beg; i < end; ++i) {
-        run += row[i];
-        out[i] = run;
-        stored += run;
-    }
-    __syncthreads();
-    part[threadIdx.x] = stored;
-    __syncthreads();
-    for (int o = kScanThreads / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) part[threadIdx.x] += part[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) row[lx] = part[0];
-}
-
 // One lane per ring entry: the ring whose offsets bracket it (rings with
 // offsets out of order leave -1, which the raster reports as malformed).
 __global__ __launch_bounds__(256) void k_entry_ring(const int32_t *__restrict__ off, int32_t G,
@@ -489,7 +443,7 @@ hipError_t launch_density(ffb_ctx *ctx, const ffb_geometry *g, const double *val
 hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch_tables &bt,
                                 const ffb_geometry *g, const double *value, const double *area,
                                 double *w_region, double *rho_pad, double *acc, int64_t acc_total,
-                                double *rho, int32_t *status)
+                                int32_t *status)
 {
     hipLaunchKernelGGL(kb_density_prep, dim3(bv.n_maps), dim3(kPrepThreads), 0, s, bv, value,
                        area, w_region, rho_pad, status);
@@ -502,8 +456,7 @@ hipError_t launch_batch_density(hipStream_t s, const batch_view &bv, const batch
                            g->ring_offsets, g->ring_vidx, g->ring_region, g->n_rings,
                            g->n_regions, g->n_entries, w_region, acc, status);
     }
-    hipLaunchKernelGGL(kb_raster_scan, dim3(bt.n_scan_rows), dim3(kScanThreads), 0, s, bv,
-                       bt.scan_rows, acc, rho_pad, rho);
+    (void)bt;                                  // the prefix sums are the flux's first pass
     return hipGetLastError();
 }
 
