@@ -81,21 +81,6 @@ __global__ __launch_bounds__(kPrepThreads) void k_density_prep(
     if (threadIdx.x == 0) *rho_pad = pad;
 }
 
-__device__ inline void deposit(double *__restrict__ acc, int32_t lx, int32_t ly, double wt,
-                               double xa, double ya, double xb, double yb)
-{
-    const double D = ya - yb;
-    if (D == 0.0) return;
-    const double xm = 0.5 * (xa + xb);
-    int32_t k = (int32_t)floor(xm);
-    int32_t j = (int32_t)floor(0.5 * (ya + yb));
-    k = min(max(k, 0), lx - 1);
-    j = min(max(j, 0), ly - 1);
-    double *row = acc + (int64_t)j * (lx + 1);
-    unsafeAtomicAdd(row + k, wt * D * ((double)(k + 1) - xm));
-    unsafeAtomicAdd(row + k + 1, wt * D * (xm - (double)k));
-}
-
 // Number of integer lines strictly between a and b, and the first of them in
 // the direction of travel.
 __device__ inline int32_t lines_between(double a, double b, double *first, double *stepdir)
@@ -115,60 +100,6 @@ __device__ inline int32_t lines_between(double a, double b, double *first, doubl
     *first = 0.0;
     *stepdir = 0.0;
     return 0;
-}
-
-// The deposits of one edge (x0, y0) -> (x1, y1) with weight wt into the
-// accumulation rows at acc + base.  An edge inside one cell (the common
-// case: borders are subdivided far below the cell size) is returned as a
-// keyed pair (acc[key] += va, acc[key + 1] += vb) for run_add; an edge that
-// crosses grid lines deposits its pieces directly.
-__device__ inline void edge_deposits(double *__restrict__ acc, int64_t base, int32_t lx,
-                                     int32_t ly, double wt, double x0, double y0, double x1,
-                                     double y1, int64_t &key, double &va, double &vb)
-{
-    if (y0 == y1) return;                       // horizontal edges add nothing
-    const double dx = x1 - x0, dy = y1 - y0;
-    double fx, sx, fy, sy;
-    const int32_t nx = lines_between(x0, x1, &fx, &sx);
-    const int32_t ny = lines_between(y0, y1, &fy, &sy);
-    if (nx == 0 && ny == 0) {
-        const double D = y0 - y1, xm = 0.5 * (x0 + x1);
-        int32_t k = (int32_t)floor(xm), j = (int32_t)floor(0.5 * (y0 + y1));
-        k = min(max(k, 0), lx - 1);
-        j = min(max(j, 0), ly - 1);
-        key = base + (int64_t)j * (lx + 1) + k;
-        va = wt * D * ((double)(k + 1) - xm);
-        vb = wt * D * (xm - (double)k);
-        return;
-    }
-    double *a = acc + base;
-    int32_t ix = 0, iy = 0;
-    double xa = x0, ya = y0;
-    // merge the crossings with x- and y-lines in order of the edge parameter
-    while (ix < nx || iy < ny) {
-        const double X = fx + sx * ix, Y = fy + sy * iy;
-        const double tx = (ix < nx) ? (X - x0) / dx : 2.0;
-        const double ty = (iy < ny) ? (Y - y0) / dy : 2.0;
-        double xb, yb;
-        if (tx < ty) {
-            xb = X;
-            yb = y0 + tx * dy;
-            ++ix;
-        } else if (ty < tx) {
-            xb = x0 + ty * dx;
-            yb = Y;
-            ++iy;
-        } else {
-            xb = X;
-            yb = Y;
-            ++ix;
-            ++iy;
-        }
-        deposit(a, lx, ly, wt, xa, ya, xb, yb);
-        xa = xb;
-        ya = yb;
-    }
-    deposit(a, lx, ly, wt, xa, ya, x1, y1);
 }
 
 // Lanes of a wave hold consecutive edges of a ring, so runs of lanes deposit
@@ -196,6 +127,69 @@ __device__ inline void run_add(double *__restrict__ acc, int64_t key, double va,
     if (key >= 0 && (lane == 63 || next != key)) {
         unsafeAtomicAdd(acc + key, va);
         unsafeAtomicAdd(acc + key + 1, vb);
+    }
+}
+
+// The pieces of the wave's edges (one edge per lane, `have` false for none)
+// one piece per lane and round: the pieces are cut at the grid lines in
+// order of the edge parameter, each becomes a keyed pair of deltas for its
+// cell, and run_add merges the lanes' pairs of each round (consecutive edges
+// of a ring mostly have their k-th pieces in the same cells).  Every lane of
+// the wave runs the same number of rounds (the wave's largest piece count).
+__device__ inline void edge_pieces(double *__restrict__ acc, int64_t base, int32_t lx, int32_t ly,
+                                   double wt, double x0, double y0, double x1, double y1,
+                                   bool have)
+{
+    have = have && y0 != y1;                    // horizontal edges add nothing
+    const double dx = x1 - x0, dy = y1 - y0;
+    double fx = 0.0, sx = 0.0, fy = 0.0, sy = 0.0;
+    const int32_t nx = have ? lines_between(x0, x1, &fx, &sx) : 0;
+    const int32_t ny = have ? lines_between(y0, y1, &fy, &sy) : 0;
+    int32_t ix = 0, iy = 0;
+    double xa = x0, ya = y0;
+    bool done = !have;
+    while (__any(!done)) {
+        int64_t key = -1;
+        double va = 0.0, vb = 0.0;
+        if (!done) {
+            double xb, yb;
+            if (ix < nx || iy < ny) {
+                const double X = fx + sx * ix, Y = fy + sy * iy;
+                const double tx = (ix < nx) ? (X - x0) / dx : 2.0;
+                const double ty = (iy < ny) ? (Y - y0) / dy : 2.0;
+                if (tx < ty) {
+                    xb = X;
+                    yb = y0 + tx * dy;
+                    ++ix;
+                } else if (ty < tx) {
+                    xb = x0 + ty * dx;
+                    yb = Y;
+                    ++iy;
+                } else {
+                    xb = X;
+                    yb = Y;
+                    ++ix;
+                    ++iy;
+                }
+            } else {
+                xb = x1;
+                yb = y1;
+                done = true;
+            }
+            const double D = ya - yb;
+            if (D != 0.0) {
+                const double xm = 0.5 * (xa + xb);
+                int32_t k = (int32_t)floor(xm), j = (int32_t)floor(0.5 * (ya + yb));
+                k = min(max(k, 0), lx - 1);
+                j = min(max(j, 0), ly - 1);
+                key = base + (int64_t)j * (lx + 1) + k;
+                va = wt * D * ((double)(k + 1) - xm);
+                vb = wt * D * (xm - (double)k);
+            }
+            xa = xb;
+            ya = yb;
+        }
+        run_add(acc, key, va, vb);
     }
 }
 
@@ -280,22 +274,18 @@ __global__ __launch_bounds__(kEdgeThreads) void k_raster_edges(
     __shared__ int32_t s_off[kStagedRingOffsets];
     const bool staged = stage_ring_offsets(off, G, s_off);
     const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
-    int64_t key = -1;
-    double va = 0.0, vb = 0.0;
-    EdgeOf ed;
+    EdgeOf ed{};
     auto one_map = [&](int32_t, int32_t &mx, int32_t &my) {
         mx = lx;
         my = ly;
         return true;
     };
-    // no early return: every lane of the wave takes part in run_add
-    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, one_map, status, ed, nullptr,
-                         s_off, staged)) {
-        // optional copy of the edge's start vertex (every ring vertex starts one)
-        if (snap) snap[ed.i0] = make_float2((float)ed.x0, (float)ed.y0);
-        edge_deposits(acc, 0, lx, ly, w[ed.r], ed.x0, ed.y0, ed.x1, ed.y1, key, va, vb);
-    }
-    run_add(acc, key, va, vb);
+    // no early return: every lane of the wave takes part in the merged adds
+    const bool have = k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, one_map, status,
+                                       ed, nullptr, s_off, staged);
+    // optional copy of the edge's start vertex (every ring vertex starts one)
+    if (have && snap) snap[ed.i0] = make_float2((float)ed.x0, (float)ed.y0);
+    edge_pieces(acc, 0, lx, ly, have ? w[ed.r] : 0.0, ed.x0, ed.y0, ed.x1, ed.y1, have);
 }
 
 // rho[j][i] = rho_pad + inclusive prefix sum of acc[j][0..i] (FP64, stored
@@ -363,9 +353,7 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
     int64_t E, const double *__restrict__ w, double *__restrict__ acc, int32_t *status)
 {
     const int64_t k = blockIdx.x * (int64_t)kEdgeThreads + threadIdx.x;
-    int64_t key = -1;
-    double va = 0.0, vb = 0.0;
-    EdgeOf ed;
+    EdgeOf ed{};
     int32_t m = -1;
     // the map of the ring; rings of maps that have stopped deposit nothing
     auto map_of = [&](int32_t g, int32_t &mx, int32_t &my) {
@@ -379,12 +367,11 @@ __global__ __launch_bounds__(kEdgeThreads) void kb_raster_edges(
         my = bv.ly[m];
         return true;
     };
-    // no early return: every lane of the wave takes part in run_add
-    if (k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, map_of, status, ed,
-                         bv.entry_ring))
-        edge_deposits(acc, bv.acc_off[m], bv.lx[m], bv.ly[m], w[ed.r], ed.x0, ed.y0, ed.x1,
-                      ed.y1, key, va, vb);
-    run_add(acc, key, va, vb);
+    // no early return: every lane of the wave takes part in the merged adds
+    const bool have = k < E && edge_of(k, xy, nv, off, vidx, region, G, R, E, map_of, status,
+                                       ed, bv.entry_ring);
+    edge_pieces(acc, have ? bv.acc_off[m] : 0, have ? bv.lx[m] : 1, have ? bv.ly[m] : 1,
+                have ? w[ed.r] : 0.0, ed.x0, ed.y0, ed.x1, ed.y1, have);
 }
 
 // One lane per ring entry: the ring whose offsets bracket it (rings with
