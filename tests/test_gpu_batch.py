@@ -145,3 +145,46 @@ def test_batch_rejects_bad_descriptions():
     with pytest.raises(ffb.FFBError):
         b2 = ffb.Batch([m])
         b2.set_shapes(96, 0)
+
+
+# Maps whose transform lengths reach every group shape of the batched
+# transforms: rows and columns of length 8, 16, 32 and 64 (groups of 1 to 8
+# lanes, several groups per wavefront) and 1024 (a group of two wavefronts,
+# with the cross-wavefront scan and barriers).
+EXTREME = [
+    dict(L=8, ly=16, n_seeds=3, seed=41, density="lognormal", inner=(1.0, 7.0),
+         inner_y=(2.0, 14.0), target_vertices=80),
+    dict(L=32, ly=64, n_seeds=6, seed=42, density="lognormal", inner=(4.0, 28.0),
+         inner_y=(8.0, 56.0), target_vertices=600),
+    dict(L=1024, ly=16, n_seeds=8, seed=43, density="lognormal", inner=(100.0, 924.0),
+         inner_y=(2.0, 14.0), target_vertices=3000),
+    dict(L=64, ly=1024, n_seeds=8, seed=44, density="lognormal", inner=(8.0, 56.0),
+         inner_y=(100.0, 924.0), target_vertices=3000),
+]
+
+
+@pytest.mark.parametrize("fft_threads", [64, 512])
+def test_round0_replayed_matches_oracle_at_every_transform_length(fft_threads):
+    from synth.voronoi import make_map
+    maps = [make_map(name=f"x{k}", **kw) for k, kw in enumerate(EXTREME)]
+    refs = [oracle.iterate(m, m.value, m.xy.astype(np.float64), m.n_vertices, 4.0) for m in maps]
+    offs = np.cumsum([0] + [len(r.h) for r in refs]).astype(np.int32)
+    steps = np.concatenate([r.h for r in refs])
+    b = ffb.Batch(maps)
+    b.set_shapes(fft_threads, 0)
+    print(f"[batch] extreme sizes shapes={b.shapes()}", flush=True)
+    assert sorted(b.shapes()["widths"]) == [8, 16, 32, 64, 1024]
+    replay = (torch.as_tensor(offs, device="cuda"), dev_f64(steps))
+    b.step(ffb.BatchOpts(use_graph=False), replay=replay)
+    rounds, mx, stats, area = b.results()
+    area = to_np(area)
+    for k, (m, r) in enumerate(zip(maps, refs)):
+        assert stats[k, 0] == len(r.h) and stats[k, 3] == 0, (k, stats[k])
+        p = to_np(b.map_points(k)).astype(np.float64)
+        dx = np.abs(p - r.points).max()
+        a = area[b.region_offsets[k]:b.region_offsets[k + 1]]
+        print(f"[batch] {m.lx}x{m.ly} V={m.n_vertices} steps={len(r.h)} max|dx|={dx:.3e}",
+              flush=True)
+        assert dx < 1e-4
+        bound = area_bound(m, r.points[:m.n_vertices], dx) + 1e-12 * np.abs(r.area_after)
+        assert np.all(np.abs(a - r.area_after) <= bound)
