@@ -1382,44 +1382,73 @@ __device__ void grp_col_pass(int m0, int lx, float sigma, const double2 *__restr
     __syncthreads();
     fft_grp<false>(a, stw, g);
 
-    // owned bins n = lane + u G: S[n][m0], S[n][m0 + 1], normalised and
-    // blurred; the Gaussian exp(-cgy n^2) by a two-term recurrence in u
+    // Lane l owns the index pairs (n1, n2) = (s, N - s) of the slots
+    // s = l + u G, u < 4 (slot 0: the self-paired 0 and N/2): the DCT-II
+    // bins of both come from the same two FFT values, and the DCT-III inputs
+    // of both from the same two coefficients, so the coefficients stay in
+    // the lane's registers and no lane reads another's.
     const double PI = 3.14159265358979323846;
     const double sg = (double)sigma, flx = (double)lx, fly = (double)N;
     const double cgx = PI * PI * sg * sg / (2.0 * flx * flx);
     const double cgy = PI * PI * sg * sg / (2.0 * fly * fly);
     const double gx0 = exp(-cgx * (double)m0 * (double)m0) * (m0 == 0 ? 2.0 : 4.0);
     const double gx1 = exp(-cgx * (double)(m0 + 1) * (double)(m0 + 1)) * 4.0;
-    double f = exp(-cgy * (double)lane * (double)lane);
-    double rr = exp(-cgy * ((double)(2 * lane * G) + (double)G * (double)G));
+    // Gaussians exp(-cgy n^2) of n1 = l + u G (u up) and of N - l - u G
+    // (u down, so that both recurrences multiply by factors <= 1)
     const double kap = exp(-2.0 * cgy * (double)G * (double)G);
-    double2 cw[8];
+    double f1 = exp(-cgy * (double)lane * (double)lane);
+    double r1 = exp(-cgy * ((double)(2 * lane * G) + (double)G * (double)G));
+    const double nb = (double)(N - lane - 3 * G);
+    double f2 = exp(-cgy * nb * nb);
+    double r2 = exp(-cgy * (2.0 * nb * (double)G + (double)G * (double)G));
+    double g1[4], g2[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int n = lane + u * G;
-        const double2 b = grp_dct2_bin(a, n, N, tq[n * qs]);
-        const double gy = n == 0 ? 0.5 * f : f;
-        cw[u] = make_double2(b.x * gx0 * gy, b.y * gx1 * gy);
-        f *= rr;
-        rr *= kap;
+    for (int u = 0; u < 4; ++u) {
+        g1[u] = f1;
+        f1 *= r1;
+        r1 *= kap;
     }
-    gsync(g);
-    // mirror coefficients c[N - n] through the buffer
-    double2 cm[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[px(lane + u * G)] = cw[u];
-    gsync(g);
+    for (int u = 3; u >= 0; --u) {
+        g2[u] = f2;
+        f2 *= r2;
+        r2 *= kap;
+    }
+    if (lane == 0) g2[0] = exp(-cgy * 0.25 * fly * fly);        // n2 = N/2
+    auto bin = [&](double2 zm, double2 zc, int n) {
+        const double2 q = tq[n * qs];
+        const double2 va = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y - zc.y));
+        const double2 vb = make_double2(0.5 * (zm.y + zc.y), -0.5 * (zm.x - zc.x));
+        return make_double2(q.x * va.x - q.y * va.y, q.x * vb.x - q.y * vb.y);
+    };
+    double2 c1[4], c2[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) cm[u] = a[px((N - lane - u * G) & (N - 1))];
-    gsync(g);
+    for (int u = 0; u < 4; ++u) {
+        const int sl = lane + u * G, n1 = sl, n2 = sl ? N - sl : N >> 1;
+        const double2 A = a[px(n1)], B = a[px(n2)];
+        const double2 b1 = bin(A, sl ? B : A, n1), b2 = bin(B, sl ? A : B, n2);
+        const double y1 = n1 == 0 ? 0.5 * g1[u] : g1[u];
+        c1[u] = make_double2(b1.x * gx0 * y1, b1.y * gx1 * y1);
+        c2[u] = make_double2(b2.x * gx0 * g2[u], b2.y * gx1 * g2[u]);
+    }
+    // DCT-III inputs of both indices of every slot; K1, K2 map a slot's two
+    // coefficients to the inputs' (xm, xr) pairs
+    auto put_inputs = [&](auto K1, auto K2) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sl = lane + u * G, n1 = sl, n2 = sl ? N - sl : N >> 1;
+            double2 xm1, xr1, xm2, xr2;
+            K1(u, sl, xm1, xr1);
+            K2(u, sl, xm2, xr2);
+            a[px(n1)] = grp_dct3_in(n1, xm1, xr1, tq[n1 * qs]);
+            a[px(n2)] = grp_dct3_in(n2, xm2, xr2, tq[n2 * qs]);
+        }
+        gsync(g);
+    };
 
     // a: DCT-III of the coefficients
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int n = lane + u * G;
-        a[px(n)] = grp_dct3_in(n, cw[u], cm[u], tq[n * qs]);
-    }
-    gsync(g);
+    put_inputs([&](int u, int sl, double2 &xm, double2 &xr) { xm = c1[u]; xr = sl ? c2[u] : c1[u]; },
+               [&](int u, int sl, double2 &xm, double2 &xr) { xm = c2[u]; xr = sl ? c1[u] : c2[u]; });
     fft_grp<true>(a, stw, g);
     __syncthreads();
     col_store<0>(mine, mine_buf, N, lgP);
@@ -1428,29 +1457,26 @@ __device__ void grp_col_pass(int m0, int lx, float sigma, const double2 *__restr
     // b and c weigh the coefficients with
     //   wx(m, n) = (ly/pi) m / (m^2 ly^2 + n^2 lx^2),  wy(m, n) = (lx/pi) n / (...),
     // zero where the numerator vanishes; the coefficients are divided by the
-    // common denominator (at n and at N - n) once
+    // common denominator once
     const double ma = (double)m0, mb = (double)(m0 + 1);
     const double inv_pi = 0.318309886183790671537767526745;
     const double ay = (ma * fly) * (ma * fly), by = (mb * fly) * (mb * fly);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int n = lane + u * G, nr = (N - n) & (N - 1);
+    auto divide = [&](double2 c, int n) {
         const double dn = ((double)n * flx) * ((double)n * flx);
-        const double dr = ((double)nr * flx) * ((double)nr * flx);
         // the (0, 0) term has no flux: both numerators vanish there
-        cw[u] = make_double2(ay + dn > 0.0 ? cw[u].x * rcp64(ay + dn) : 0.0,
-                             cw[u].y * rcp64(by + dn));
-        cm[u] = make_double2(ay + dr > 0.0 ? cm[u].x * rcp64(ay + dr) : 0.0,
-                             cm[u].y * rcp64(by + dr));
+        return make_double2(ay + dn > 0.0 ? c.x * rcp64(ay + dn) : 0.0, c.y * rcp64(by + dn));
+    };
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int sl = lane + u * G, n1 = sl, n2 = sl ? N - sl : N >> 1;
+        c1[u] = divide(c1[u], n1);
+        c2[u] = divide(c2[u], n2);
     }
     const double kxa = fly * inv_pi * ma, kxb = fly * inv_pi * mb;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int n = lane + u * G;
-        a[px(n)] = grp_dct3_in(n, make_double2(kxa * cw[u].x, kxb * cw[u].y),
-                               make_double2(kxa * cm[u].x, kxb * cm[u].y), tq[n * qs]);
-    }
-    gsync(g);
+    auto wxc = [&](double2 c) { return make_double2(kxa * c.x, kxb * c.y); };
+    put_inputs(
+        [&](int u, int sl, double2 &xm, double2 &xr) { xm = wxc(c1[u]); xr = wxc(sl ? c2[u] : c1[u]); },
+        [&](int u, int sl, double2 &xm, double2 &xr) { xm = wxc(c2[u]); xr = wxc(sl ? c1[u] : c2[u]); });
     fft_grp<true>(a, stw, g);
     __syncthreads();
     col_store<1>(mine, mine_buf, N, lgP);
@@ -1458,14 +1484,21 @@ __device__ void grp_col_pass(int m0, int lx, float sigma, const double2 *__restr
     // c: DST-III of wy * coefficients = (-1)^j DCT-III of the reversed
     // sequence c'[m] = wy(N - m) c[N - m] (c'[0] = 0)
     const double ky = flx * inv_pi;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int n = lane + u * G;
-        const double kr = n ? ky * (double)(N - n) : 0.0, kn = ky * (double)n;
-        a[px(n)] = grp_dct3_in(n, make_double2(kr * cm[u].x, kr * cm[u].y),
-                               make_double2(kn * cw[u].x, kn * cw[u].y), tq[n * qs]);
-    }
-    gsync(g);
+    auto wyc = [&](double2 c, int n) {
+        const double k = ky * (double)n;
+        return make_double2(k * c.x, k * c.y);
+    };
+    put_inputs(
+        [&](int u, int sl, double2 &xm, double2 &xr) {
+            // index n1 = s: c'[s] = wy(N - s) c[N - s], c'[N - s] = wy(s) c[s]
+            xm = sl ? wyc(c2[u], N - sl) : make_double2(0.0, 0.0);
+            xr = wyc(c1[u], sl);
+        },
+        [&](int u, int sl, double2 &xm, double2 &xr) {
+            // index n2 = N - s: c'[N - s] = wy(s) c[s]; slot 0: n2 = N/2
+            xm = sl ? wyc(c1[u], sl) : wyc(c2[u], N >> 1);
+            xr = sl ? wyc(c2[u], N - sl) : wyc(c2[u], N >> 1);
+        });
     fft_grp<true>(a, stw, g);
     __syncthreads();
     col_store<2>(mine, mine_buf, N, lgP);
@@ -1495,22 +1528,22 @@ __device__ void grp_row_final(const double *__restrict__ pa, const double *__res
         }
         gsync(g);
     };
-    // DCT-III input from the staged pairs; REV: of the index-reversed
-    // sequence c'[m] = c[N - m] (c'[0] = 0), for the DST-III
+    // DCT-III input from the staged pairs, in place: lane l takes the index
+    // pairs (s, N - s) for the slots s = l + u G, u < 4 (slot 0: the
+    // self-paired indices 0 and N/2), so it reads and writes only its own
+    // elements.  REV: of the index-reversed sequence c'[m] = c[N - m]
+    // (c'[0] = 0), for the DST-III.
     auto dct3_from_stage = [&](bool rev) {
-        double2 xm[8], xr[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int m = lane + u * G;
-            const double2 lo = a[px(m)], hi = a[px((N - m) & (N - 1))];
-            xm[u] = rev ? (m ? hi : make_double2(0.0, 0.0)) : lo;
-            xr[u] = rev ? lo : hi;
-        }
-        gsync(g);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int m = lane + u * G;
-            a[px(m)] = grp_dct3_in(m, xm[u], xr[u], tq[m * qs]);
+        for (int u = 0; u < 4; ++u) {
+            const int sl = lane + u * G;
+            const int m1 = sl, m2 = sl ? N - sl : N >> 1;
+            const double2 A = a[px(m1)], B = a[px(m2)];
+            const double2 h1 = sl ? B : A, h2 = sl ? A : B;      // partners' values
+            a[px(m1)] = rev ? grp_dct3_in(m1, m1 ? h1 : make_double2(0.0, 0.0), A, tq[m1 * qs])
+                            : grp_dct3_in(m1, A, h1, tq[m1 * qs]);
+            a[px(m2)] = rev ? grp_dct3_in(m2, h2, B, tq[m2 * qs])
+                            : grp_dct3_in(m2, B, h2, tq[m2 * qs]);
         }
         gsync(g);
     };
