@@ -965,17 +965,20 @@ inline int threads_for(int N)
 }
 
 // ------------------------------------------------- grouped FP64 transforms
-// The FP64 passes of the single-map and batched flux run many row or column
-// pairs per workgroup: a group of G = N / 8 lanes owns one pair, holds eight
+// The FP64 passes of the batched flux run many row or column pairs per
+// workgroup: a group of G = N / 8 lanes owns one pair, holds eight
 // complex values per lane in registers and runs the length-N FFT as radix-8
 // Stockham passes (one radix-2 or radix-4 pass first when log2 N is not a
 // multiple of 3), exchanging through its own LDS buffer in place.  A group
 // of at most one wavefront needs no workgroup barrier (its lanes run in
 // lockstep and the LDS serves a wavefront's accesses in order); at N = 1024
 // a group spans two wavefronts and passes workgroup barriers.  The pre- and
-// post-processing of the DCTs keeps each lane's bins in registers, so the
-// only per-group LDS is the FFT buffer, with one spare slot per 16 elements
-// so that the strided writes of the early passes spread over the banks.
+// post-processing of the DCTs keeps each lane's bins in registers (a lane
+// owns the index pairs (s, N - s)), so the only per-group LDS is the FFT
+// buffer, with one spare slot per 16 elements so that the strided writes of
+// the early passes spread over the banks.  (A single grid has too few pairs
+// to fill the chip this way; the single-map flux keeps one pair per
+// workgroup.)
 // Workgroups of T lanes (64 to 512, at least G) hold P = T / G groups;
 // their buffers take P * padded(N) = 8 T + T / 2 complex values.
 template <int T> constexpr int grp_lds() { return 8 * T + T / 2; }
@@ -1201,50 +1204,6 @@ __device__ __forceinline__ double rcp64(double d)
     e = fma(-d, r, 1.0);
     return fma(r, e, r);
 }
-
-// DCT-II of rows r0, r0 + 1 of `in` [rows][N] into `out`; with `rowsum`,
-// *rowsum = the FP64 sum of both input rows (fixed order).  `live` false:
-// the group only takes part in the barriers.
-__device__ void grp_dct2_rows(const double *__restrict__ in, double *__restrict__ out, int64_t r0,
-                              const double2 *__restrict__ tq, int qs, double2 *a,
-                              const double2 *stw, double *rowsum, double *part, const Grp &g,
-                              bool live)
-{
-    const int N = g.N;
-    const double *ra = in + r0 * N, *rb = ra + N;
-    double s = 0.0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int i = g.lane + u * g.G;
-        const double2 v = live ? make_double2(ra[i], rb[i]) : make_double2(0.0, 0.0);
-        s += v.x + v.y;
-        a[px(mk_pos(i, N))] = v;
-    }
-    gsync(g);
-    fft_grp<false>(a, stw, g);
-    double *oa = out + r0 * N, *ob = oa + N;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int n = g.lane + u * g.G;
-        const double2 b = grp_dct2_bin(a, n, N, tq[n * qs]);
-        if (live) {
-            oa[n] = b.x;
-            ob[n] = b.y;
-        }
-    }
-    if (rowsum) {
-        // group sum: within a wavefront by butterflies over the group's
-        // lanes, across the two wavefronts of a 128-lane group through LDS
-        for (int o = 1; o < g.G && o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
-        if (g.G > 64) {
-            if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-            __syncthreads();
-            s = part[2 * g.id] + part[2 * g.id + 1];
-        }
-        if (live && g.lane == 0) *rowsum = s;
-    }
-}
-
 
 // Densities and row DCT of a row pair in one pass (batched maps): rho[j][i]
 // = rho_pad + the inclusive prefix sum of the coverage deltas acc[j][0..i]
