@@ -370,9 +370,14 @@ int ffb_integrate_adj(ffb_ctx *ctx, const float *fields, const double *rho_bar,
  * (its device buffers are reused in stream order, so no wait is needed) and
  * starts recording: every later ffb_area_error,
  * ffb_density, ffb_flux and ffb_integrate call appends what its adjoint
- * needs to the context (device copies of its vertices, values, areas,
- * fields and rho_bar, made on the stream, so callers may reuse those
- * buffers; the geometry's ring arrays are referenced and must stay alive).
+ * needs to the context (device copies of the ring vertices' positions,
+ * values, areas, the density weights, fields and rho_bar, written on the
+ * stream by the call's own kernels, so callers may reuse those buffers; the
+ * geometry's ring arrays are referenced and must stay alive).  The reverse
+ * pass differentiates each integration through the flux call before it:
+ * when ffb_integrate reads the buffers that flux call wrote, the flux's
+ * record serves (the fields as the flux produced them); other buffers are
+ * copied when ffb_integrate is called.
  * ffb_integrate records the state of the first V points (the recorded
  * geometry's vertices, which must come first in its xy) before each
  * accepted step, for at most max_steps steps per call.  Memory per round:
