@@ -523,3 +523,40 @@ def test_backward_matches_oracle_golden_c5_full_size(with_grid):
     assert err_ad < 1e-4, err_ad
     # scale invariance at full size
     assert abs(np.dot(m.density, g)) < 1e-3 * np.sum(np.abs(m.density * g))
+
+
+def test_integration_of_copied_fields_records_the_same_gradient():
+    """While recording, an integration that reads the fields and mean density
+    the flux call before it wrote uses the flux record's copy; one that reads
+    other buffers with the same values is copied when called.  Both records
+    hold the same values, so the forwards agree bit for bit and the
+    gradients to the order in which the reverse pass's atomic adds land
+    (≈ 1e-8 of the largest entry)."""
+    m = synth.workload("c1_L64")
+    a0 = oracle.region_areas(m)
+    value = dev_f64(m.density * a0)
+    g_area = dev_f64(np.linspace(-1.0, 1.0, m.n_regions))
+    out = []
+    for copy in (False, True):
+        ctx = new_ctx(m.lx, max_points=m.n_vertices)
+        pts = dev_f32(m.xy).reshape(-1, 2)
+        geom = ffb.Geometry.from_map(m, pts)
+        print(f"[adj] copied fields={copy}", flush=True)
+        ctx.tape_begin(64)
+        area, _, _ = ctx.area_error(geom, value)
+        for sigma in SIGMAS[:2]:
+            rho, _ = ctx.density(geom, value, area)
+            fields, rb = ctx.flux(rho, sigma)
+            if copy:
+                fields, rb = fields.clone(), rb.clone()
+            ctx.integrate(fields, rb, pts, h_cap=0)
+            area, _, _ = ctx.area_error(geom, value)
+        ctx.tape_end()
+        dval, _ = ctx.backward(g_area)
+        assert ctx.sync(check=False) == 0
+        out.append((to_np(area).copy(), to_np(dval).copy()))
+        ctx.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    scale = np.abs(out[0][1]).max()
+    assert scale > 0
+    assert np.abs(out[0][1] - out[1][1]).max() <= 1e-6 * scale
