@@ -247,4 +247,28 @@ __device__ inline float wave_max(float v)
     return v;
 }
 
+// Maximum over the 64 lanes of a wave by data-parallel-primitive moves
+// (register-to-register, no LDS round trip): shifts within each row of 16
+// lanes leave every row's maximum in its lane 15, two row broadcasts carry
+// them to lane 63.  Lanes a move has no source for read 0, the identity of
+// an unsigned maximum.  Returns the maximum in every lane (read from lane 63).
+__device__ inline uint32_t wave_max_bits(uint32_t v)
+{
+    const auto step = [](uint32_t x, uint32_t y) { return x > y ? x : y; };
+    v = step(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = step(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = step(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = step(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = step(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = step(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// The same for non-negative FP32 values (+inf included), whose bit patterns
+// order as the values do.
+__device__ inline float wave_max_bits_f(float v)
+{
+    return __uint_as_float(wave_max_bits(__float_as_uint(v)));
+}
+
 }  // namespace

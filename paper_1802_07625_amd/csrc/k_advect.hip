@@ -125,7 +125,8 @@ __device__ inline Slots slots_of(int b, int nb, int n)
 // Grid-wide maximum of the workgroups' values for attempt n; it doubles as
 // the grid barrier of the attempt.  Each workgroup stores one tagged 64-bit
 // slot; wave 0 of every workgroup then scans all slots of the attempt's bank
-// (one relaxed load per lane per 64 workgroups) until every tag is current.
+// (one relaxed load per lane per 64 workgroups, the loads of one scan issued
+// together, four at a time) until every tag is current.
 // No read-modify-write atomic and no cache-maintaining fence is involved, so
 // the cost does not grow with contention on one address.  Banks alternate
 // by attempt parity: a workgroup can only overwrite a bank two attempts
@@ -149,19 +150,24 @@ __device__ bool grid_max(uint64_t *sync, int n, float m, int32_t *status, float 
         for (;;) {
             bool done = true;
             uint32_t v = 0;
-            for (int r = lane; r < nb; r += 64) {
-                const uint64_t w = __hip_atomic_load(&bank[r], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                if ((uint32_t)(w >> 32) != tag) done = false;
-                const uint32_t x = (uint32_t)w;
-                v = v > x ? v : x;
-            }
-            if (__all(done)) {
-                for (int o = 32; o > 0; o >>= 1) {
-                    const uint32_t x = __shfl_xor(v, o, 64);
+            for (int r0 = lane; r0 < nb; r0 += 4 * 64) {
+                uint64_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    // past the last slot a lane reads the last one again
+                    const int r = r0 + 64 * j < nb ? r0 + 64 * j : nb - 1;
+                    w[j] = __hip_atomic_load(&bank[r], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if ((uint32_t)(w[j] >> 32) != tag) done = false;
+                    const uint32_t x = (uint32_t)w[j];
                     v = v > x ? v : x;
                 }
-                mx = v;
+            }
+            if (__all(done)) {
+                mx = wave_max_bits(v);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_advect(Params p)
             if (MODE != kLdsRecompute) kvn[i] = make_float2(q7.x * rhf, q7.y * rhf);
         }
         // workgroup max, then the grid-wide max (one barrier per attempt)
-        emax = wave_max(emax);
+        emax = wave_max_bits_f(emax);
         if ((threadIdx.x & 63) == 0) s_err[threadIdx.x >> 6] = emax;
         __syncthreads();
         float m = s_err[0];
