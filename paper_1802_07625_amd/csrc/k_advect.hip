@@ -189,10 +189,10 @@ __device__ bool grid_max(uint64_t *sync, int n, float m, int32_t *status, float 
         }
     }
     __syncthreads();
+    // res and ok are written again only after the next attempt's workgroup
+    // barrier, which every wave reaches after reading them here
     out = res;
-    const bool r = ok != 0;
-    __syncthreads();
-    return r;
+    return ok != 0;
 }
 
 // Where a point's state lives during one launch.
@@ -435,7 +435,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args a,
                                                 int32_t *status)
 {
-    __shared__ float s_err[NT / 64];
+    __shared__ float s_err[2][NT / 64];
     const int m = a.order[blockIdx.x];
     if (!bv.active[m]) return;
     if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
@@ -511,13 +511,16 @@ __global__ __launch_bounds__(NT) void kb_advect(batch_view bv, batch_advect_args
             emax = fmaxf(emax, e);
             kvn[k] = make_float2(q7.x * rhf, q7.y * rhf);
         }
-        emax = wave_max(emax);
-        if ((threadIdx.x & 63) == 0) s_err[threadIdx.x >> 6] = emax;
+        // the banks alternate by attempt parity: a bank is written again two
+        // attempts later, after a barrier every wave passes once it has read
+        // this attempt's maxima, so one barrier per attempt suffices
+        float *se = s_err[attempt & 1];
+        emax = wave_max_bits_f(emax);
+        if ((threadIdx.x & 63) == 0) se[threadIdx.x >> 6] = emax;
         __syncthreads();
-        float gmax = s_err[0];
+        float gmax = se[0];
 #pragma unroll
-        for (int w = 1; w < NT / 64; ++w) gmax = fmaxf(gmax, s_err[w]);
-        __syncthreads();
+        for (int w = 1; w < NT / 64; ++w) gmax = fmaxf(gmax, se[w]);
         const double err = (double)gmax;
         ++attempt;
         if (!(err < __builtin_huge_val())) {
