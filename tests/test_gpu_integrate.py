@@ -91,6 +91,47 @@ def test_adaptive_run_outcome(name):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_step_control_sees_every_point(mode):
+    """300 k copies of one point P and, at index k, one point H in a steeper
+    part of the flow.  Copies of P have the same error estimates, so the
+    adaptive schedule must be that of the two-point set {P, H}, bit for bit,
+    wherever H sits in the array (any lane, wavefront, workgroup or XCD
+    share): the error maximum taken per wavefront, per workgroup and over
+    the grid covers every point.  P alone takes another schedule, so a
+    maximum that missed H would show."""
+    from gpu_util import new_ctx, pack_oracle_fields
+    L = 64
+    rho = np.ones((L, L))
+    rho[28:36, 28:36] = 4.0
+    F = oracle.flux(rho, 1.0)
+    P = np.array([8.3, 9.1], dtype=np.float32)
+    H = np.array([27.5, 31.2], dtype=np.float32)
+
+    def run(pts):
+        ctx = new_ctx(L, L, pts.shape[0], mode=mode)
+        fields, rb, _ = pack_oracle_fields(ctx, F)
+        return _gpu_integrate(ctx, fields, rb, pts)
+
+    _, sp, hp, cp = run(P[None, :])
+    x2, s2, h2, c2 = run(np.stack([P, H]))
+    assert cp == 0 and c2 == 0
+    assert hp.shape != h2.shape or not np.array_equal(hp, h2)
+    n = 300_000
+    for k in (0, 63, 81, 1023, 1029, 70_000, 150_001, n - 1):
+        pts = np.tile(P, (n, 1))
+        pts[k] = H
+        x, s, h, c = run(pts)
+        assert c == 0
+        assert (s["accepted"], s["rejected"]) == (s2["accepted"], s2["rejected"]), k
+        np.testing.assert_array_equal(h, h2)
+        np.testing.assert_array_equal(x[k], x2[1])
+        np.testing.assert_array_equal(x[k - 1], x2[0])
+    print(f"[integrate] mode={mode} P alone {sp['accepted']}/{sp['rejected']}, "
+          f"with H {s2['accepted']}/{s2['rejected']}: reproduced with H at 8 positions "
+          f"among {n} points", flush=True)
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_replay_equals_adaptive_bitwise(mode):
     """Rejected attempts (forced by a large first step) leave no trace: the
     adaptive run equals a replay of its accepted steps bit for bit."""
