@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # from FETCH_SIZE and WRITE_SIZE counter runs calibrated on a copy of known
 # size, for the kernel source with this sha256 prefix; reported only while the
 # source is unchanged.
-ADVECT_TRAFFIC = {"bytes_per_attempt": 2.2803e+10 / 267,
-                  "valu_wave_insts_per_attempt": 2.9660e+09 / 267,
-                  "workload": "c3_L1024", "source_sha256": "5e0435dec4713d41"}
+ADVECT_TRAFFIC = {"bytes_per_attempt": 2.2811e+10 / 267,
+                  "valu_wave_insts_per_attempt": 2.9315e+09 / 267,
+                  "workload": "c3_L1024", "source_sha256": "258649db088c6f02"}
 # non-packed FP32 issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
