@@ -46,6 +46,8 @@ hipError_t alloc(T **d, int64_t n)
 struct ffb_batch {
     hipStream_t user_stream = nullptr, stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // the transform classes' streams (cs.s[0] = stream) and their events
+    class_streams cs{};
     std::string last_error;
     int32_t M = 0;
     std::vector<int32_t> lx, ly;
@@ -119,6 +121,11 @@ void free_batch(ffb_batch *b)
     if (b->h_n_active) (void)hipHostFree(b->h_n_active);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->cs.fork) (void)hipEventDestroy(b->cs.fork);
+    for (int c = 1; c < kMaxClasses; ++c) {
+        if (b->cs.join[c]) (void)hipEventDestroy(b->cs.join[c]);
+        if (b->cs.s[c]) (void)hipStreamDestroy(b->cs.s[c]);
+    }
     if (b->stream) (void)hipStreamDestroy(b->stream);
 }
 
@@ -254,7 +261,7 @@ hipError_t enqueue_step(ffb_batch *b, const ffb_batch_opts &o, float *xy,
     hipError_t e = launch_batch_density(s, bv, bt, &g, b->value, b->area, b->w_region, b->rho_pad,
                                         b->acc, b->acc_total, b->d_status);
     if (e == hipSuccess)
-        e = launch_batch_flux(s, bv, bt, plan_of(b, b->fft_threads), b->tw1024, b->tq1024, b->rho_pad,
+        e = launch_batch_flux(b->cs, bv, bt, plan_of(b, b->fft_threads), b->tw1024, b->tq1024, b->rho_pad,
                               b->acc, b->t1, b->pa, b->pb, b->pc, b->fields, b->rho_bar,
                               b->d_status);
     if (e == hipSuccess)
@@ -434,6 +441,15 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    // one stream per transform class beyond the first (default priority)
+    b->cs.n = b->n_classes;
+    b->cs.s[0] = b->stream;
+    if (e == hipSuccess && b->cs.n > 1)
+        e = hipEventCreateWithFlags(&b->cs.fork, hipEventDisableTiming);
+    for (int c = 1; c < b->cs.n && e == hipSuccess; ++c) {
+        e = hipStreamCreateWithFlags(&b->cs.s[c], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->cs.join[c], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = upload(&b->d_lx, b->lx);
     if (e == hipSuccess) e = upload(&b->d_ly, b->ly);
     if (e == hipSuccess) e = upload(&b->d_plane_off, plane_off);
@@ -639,7 +655,7 @@ int ffb_batch_autotune(ffb_batch *b, const ffb_batch_opts *o)
             threads[c] = t;
             const batch_fft_plan plan = plan_of(b, threads);
             float ms = time_it(b, [&]() {
-                return launch_batch_flux(b->stream, bv0, tables_of(b), plan, b->tw1024, b->tq1024,
+                return launch_batch_flux(b->cs, bv0, tables_of(b), plan, b->tw1024, b->tq1024,
                                          b->rho_pad, b->acc, b->t1, b->pa, b->pb, b->pc,
                                          b->fields, b->rho_bar, b->d_status);
             }, 3, &e);

@@ -365,7 +365,17 @@ struct batch_fft_plan {
     int threads[kBatchMaxClasses];
     int n[kBatchMaxClasses];           // transform length of each class
 };
-hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
+// Streams of a batch's transform classes: class c's passes run on s[c] (s[0]
+// is the batch stream, on which every pass starts and ends: an event fork
+// before and a join after each pass, so that a graph captured from s[0]
+// holds the classes' launches as parallel branches).  n <= 1: s[0] only.
+struct class_streams {
+    int n;
+    hipStream_t s[kBatchMaxClasses];
+    hipEvent_t fork;
+    hipEvent_t join[kBatchMaxClasses];
+};
+hipError_t launch_batch_flux(const class_streams &cs, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const double2 *tw1024,
                              const double2 *tq1024, const double *rho_pad, double *acc,
                              double *t1, double *pa, double *pb, double *pc,

@@ -1798,36 +1798,62 @@ hipError_t launch_flux_adj(ffb_ctx *ctx, float sigma, const float4 *lam_fields,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_flux(hipStream_t s, const batch_view &bv, const batch_tables &bt,
+// Fork the class streams off s[0] / join them back.
+static hipError_t class_fork(const class_streams &cs)
+{
+    if (cs.n <= 1) return hipSuccess;
+    hipError_t e = hipEventRecord(cs.fork, cs.s[0]);
+    for (int c = 1; c < cs.n && e == hipSuccess; ++c) e = hipStreamWaitEvent(cs.s[c], cs.fork, 0);
+    return e;
+}
+
+static hipError_t class_join(const class_streams &cs)
+{
+    hipError_t e = hipSuccess;
+    for (int c = 1; c < cs.n && e == hipSuccess; ++c) {
+        e = hipEventRecord(cs.join[c], cs.s[c]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs.s[0], cs.join[c], 0);
+    }
+    return e;
+}
+
+hipError_t launch_batch_flux(const class_streams &cs, const batch_view &bv, const batch_tables &bt,
                              const batch_fft_plan &plan, const double2 *tw1024,
                              const double2 *tq1024, const double *rho_pad, double *acc,
                              double *t1, double *pa, double *pb, double *pc,
                              float4 *fields, double *rho_bar, int32_t *status)
 {
-    hipError_t e = hipSuccess;
+    const auto on = [&](int c) { return cs.s[c < cs.n ? c : 0]; };
+    hipError_t e = class_fork(cs);
     for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
         const int n = plan.row_beg[c + 1] - plan.row_beg[c], N = plan.n[c];
         if (n > 0)
-            e = launch_grp_class<RowsK>(plan.threads[c], n, N, s, bv, bt.rows + plan.row_beg[c], n,
-                                        N, acc, rho_pad, t1, tw1024, tq1024);
+            e = launch_grp_class<RowsK>(plan.threads[c], n, N, on(c), bv, bt.rows + plan.row_beg[c],
+                                        n, N, acc, rho_pad, t1, tw1024, tq1024);
     }
+    if (e == hipSuccess) e = class_join(cs);
     // the mean density from the row sums the first pass left
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, s, bv, acc, rho_bar, status);
+        hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, cs.s[0], bv, acc, rho_bar,
+                           status);
         e = hipGetLastError();
     }
+    if (e == hipSuccess) e = class_fork(cs);
     for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
         const int n = plan.col_beg[c + 1] - plan.col_beg[c], N = plan.n[c];
         if (n > 0)
-            e = launch_grp_class<ColsK>(plan.threads[c], n, N, s, bv, bt.cols + plan.col_beg[c], n,
-                                        N, t1, tw1024, tq1024, pa, pb, pc);
+            e = launch_grp_class<ColsK>(plan.threads[c], n, N, on(c), bv, bt.cols + plan.col_beg[c],
+                                        n, N, t1, tw1024, tq1024, pa, pb, pc);
     }
+    if (e == hipSuccess) e = class_join(cs);
+    if (e == hipSuccess) e = class_fork(cs);
     for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
         const int n = plan.row_beg[c + 1] - plan.row_beg[c], N = plan.n[c];
         if (n > 0)
-            e = launch_grp_class<FinalK>(plan.threads[c], n, N, s, bv, bt.rows + plan.row_beg[c],
+            e = launch_grp_class<FinalK>(plan.threads[c], n, N, on(c), bv, bt.rows + plan.row_beg[c],
                                          n, N, pa, pb, pc, tw1024, tq1024, fields, status);
     }
+    if (e == hipSuccess) e = class_join(cs);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
