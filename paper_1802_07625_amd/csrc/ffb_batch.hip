@@ -443,6 +443,8 @@ int ffb_batch_create(ffb_batch **out, const ffb_batch_desc *d, void *hip_stream)
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
     // one stream per transform class beyond the first (default priority)
     b->cs.n = b->n_classes;
+    b->cs.own = true;
+    for (int32_t m = 0; m < b->M; ++m) b->cs.own = b->cs.own && b->lx[m] == b->ly[m];
     b->cs.s[0] = b->stream;
     if (e == hipSuccess && b->cs.n > 1)
         e = hipEventCreateWithFlags(&b->cs.fork, hipEventDisableTiming);

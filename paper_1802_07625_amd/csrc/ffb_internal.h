@@ -365,12 +365,16 @@ struct batch_fft_plan {
     int threads[kBatchMaxClasses];
     int n[kBatchMaxClasses];           // transform length of each class
 };
-// Streams of a batch's transform classes: class c's passes run on s[c] (s[0]
-// is the batch stream, on which every pass starts and ends: an event fork
-// before and a join after each pass, so that a graph captured from s[0]
-// holds the classes' launches as parallel branches).  n <= 1: s[0] only.
+// Streams of a batch's transform classes: class c's passes run on s[c]; s[0]
+// is the batch stream, on which the transforms start and end (an event fork
+// before and a join after, so that a graph captured from s[0] holds the
+// classes' launches as parallel branches).  With `own` (every map square,
+// so a class's passes read only its own maps' earlier passes) each class
+// runs its passes back to back; otherwise the classes are joined after
+// every pass.  n <= 1: s[0] only.
 struct class_streams {
     int n;
+    bool own;
     hipStream_t s[kBatchMaxClasses];
     hipEvent_t fork;
     hipEvent_t join[kBatchMaxClasses];

@@ -1831,22 +1831,27 @@ hipError_t launch_batch_flux(const class_streams &cs, const batch_view &bv, cons
             e = launch_grp_class<RowsK>(plan.threads[c], n, N, on(c), bv, bt.rows + plan.row_beg[c],
                                         n, N, acc, rho_pad, t1, tw1024, tq1024);
     }
-    if (e == hipSuccess) e = class_join(cs);
+    // with every map square, each class runs its three passes back to back
+    // (its column and row passes read only its own maps' earlier passes) and
+    // the mean density, which reads the first pass of every class and is
+    // read by none of the passes, follows the final join; otherwise the
+    // classes are joined after every pass
+    if (e == hipSuccess && !cs.own) e = class_join(cs);
     // the mean density from the row sums the first pass left
-    if (e == hipSuccess) {
+    if (e == hipSuccess && !cs.own) {
         hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, cs.s[0], bv, acc, rho_bar,
                            status);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = class_fork(cs);
+    if (e == hipSuccess && !cs.own) e = class_fork(cs);
     for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
         const int n = plan.col_beg[c + 1] - plan.col_beg[c], N = plan.n[c];
         if (n > 0)
             e = launch_grp_class<ColsK>(plan.threads[c], n, N, on(c), bv, bt.cols + plan.col_beg[c],
                                         n, N, t1, tw1024, tq1024, pa, pb, pc);
     }
-    if (e == hipSuccess) e = class_join(cs);
-    if (e == hipSuccess) e = class_fork(cs);
+    if (e == hipSuccess && !cs.own) e = class_join(cs);
+    if (e == hipSuccess && !cs.own) e = class_fork(cs);
     for (int c = 0; c < plan.n_classes && e == hipSuccess; ++c) {
         const int n = plan.row_beg[c + 1] - plan.row_beg[c], N = plan.n[c];
         if (n > 0)
@@ -1854,6 +1859,11 @@ hipError_t launch_batch_flux(const class_streams &cs, const batch_view &bv, cons
                                          n, N, pa, pb, pc, tw1024, tq1024, fields, status);
     }
     if (e == hipSuccess) e = class_join(cs);
+    if (e == hipSuccess && cs.own) {
+        hipLaunchKernelGGL(kb_mean, dim3(bv.n_maps), dim3(256), 0, cs.s[0], bv, acc, rho_bar,
+                           status);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
