@@ -574,17 +574,28 @@ __global__ __launch_bounds__(256) void k_adj_times(AdjParams p, zero_spans z)
     }
 }
 
-// Work tiles: kChunk consecutive steps of kThreads consecutive points.
+// Work tiles: `chunk` consecutive steps of kThreads consecutive points.
 // `spread` deals the tile's points to the wavefronts round-robin, so that
 // the lanes of one wavefront hold every (kThreads/64)-th vertex of a chain:
 // fewer lanes of one atomic instruction then share a grid node.
-__device__ inline void tile_of(int tile, int n_pt_tiles, int &step0, int &i, bool spread)
+__device__ inline void tile_of(int tile, int n_pt_tiles, int chunk, int &step0, int &i,
+                               bool spread)
 {
     const int st = tile / n_pt_tiles;
-    step0 = st * kChunk;
+    step0 = st * chunk;
     const int t = (int)threadIdx.x;
     const int r = spread ? (t & 63) * (kThreads / 64) + (t >> 6) : t;
     i = (tile - st * n_pt_tiles) * kThreads + r;
+}
+
+// Steps per tile: kChunk, halved while a record of few steps would give
+// fewer tiles than a quarter of the grid's workgroups (at most two of them
+// are resident per CU), so that short rounds still spread over the chip.
+__device__ inline int chunk_for(int S, int n_pt_tiles)
+{
+    int c = kChunk;
+    while (c > 1 && (int64_t)((S + c - 1) / c) * n_pt_tiles < (int64_t)gridDim.x / 4) c >>= 1;
+    return c;
 }
 
 // The six stages of step k of a point: lookups, velocities K_s and their
@@ -597,14 +608,15 @@ __global__ __launch_bounds__(kThreads) void k_adj_jacobian(AdjParams p)
     if (!adj_ok(p, S)) return;
     const double rho_bar = *p.rho_bar;
     const int n_pt_tiles = (p.n + kThreads - 1) / kThreads;
-    const int n_tiles = ((S + kChunk - 1) / kChunk) * n_pt_tiles;
+    const int chunk = chunk_for(S, n_pt_tiles);
+    const int n_tiles = ((S + chunk - 1) / chunk) * n_pt_tiles;
     Cell cc;
     cc.key = -1;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         int step0, i;
-        tile_of(tile, n_pt_tiles, step0, i, false);
+        tile_of(tile, n_pt_tiles, chunk, step0, i, false);
         if (i >= p.n) continue;
-        const int step1 = min(S, step0 + kChunk);
+        const int step1 = min(S, step0 + chunk);
         // the tile's recorded states, all loads in flight at once
         float4 qs[kChunk];
 #pragma unroll
@@ -714,7 +726,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
     if (!adj_ok(p, S)) return;
     const double rho_bar = *p.rho_bar;
     const int n_pt_tiles = (p.n + kThreads - 1) / kThreads;
-    const int n_tiles = ((S + kChunk - 1) / kChunk) * n_pt_tiles;
+    const int chunk = chunk_for(S, n_pt_tiles);
+    const int n_tiles = ((S + chunk - 1) / chunk) * n_pt_tiles;
     const int lane = threadIdx.x & 63;
     float *wwin = win + (threadIdx.x >> 6) * kWaveFloats;      // this wavefront's copies
     float *cw = wwin + (lane % kCopies) * kWinFloats;           // this lane's copy
@@ -724,9 +737,9 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
     for (int k = lane; k < kWaveFloats; k += 64) wwin[k] = 0.f;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         int step0, i;
-        tile_of(tile, n_pt_tiles, step0, i, false);
+        tile_of(tile, n_pt_tiles, chunk, step0, i, false);
         const bool live = i < p.n;
-        const int step1 = min(S, step0 + kChunk);
+        const int step1 = min(S, step0 + chunk);
         // the tile's recorded states and position adjoints, all loads in
         // flight at once; q[u] belongs to step step1 - 1 - u (last first)
         float4 qs[kChunk], ql[kChunk];
