@@ -772,11 +772,22 @@ __global__ __launch_bounds__(kThreads) void k_adj_fields(AdjParams p)
             by1 = max(by1, __shfl_xor(by1, o, 64));
         }
         if (bx0 > bx1 || by0 > by1) bx0 = bx1 = by0 = by1 = 0;
+        // a box too wide for the window (the wavefront's points lie on two
+        // rings, or far apart on one) centres the window on the cell of
+        // lane 32, which lies with the larger part of a wavefront split in
+        // two, instead of on the box's middle, which may lie between them
+        int ax = -1, ay = -1;
+        if (live && step1 > step0) {
+            ax = (int)fminf(fmaxf(qs[0].x + 0.5f, 0.f), (float)(p.lx + 1));
+            ay = (int)fminf(fmaxf(qs[0].y + 0.5f, 0.f), (float)(p.ly + 1));
+        }
+        ax = __shfl(ax, 32, 64);
+        ay = __shfl(ay, 32, 64);
         Region R;
         R.wx0 = bx0 - 1;
         R.wy0 = by0 - 1;
-        if (bx1 - bx0 + 3 > kWin) R.wx0 = (bx0 + bx1) / 2 - kWin / 2;
-        if (by1 - by0 + 3 > kWin) R.wy0 = (by0 + by1) / 2 - kWin / 2;
+        if (bx1 - bx0 + 3 > kWin) R.wx0 = (ax >= 0 ? ax : (bx0 + bx1) / 2) - kWin / 2;
+        if (by1 - by0 + 3 > kWin) R.wy0 = (ay >= 0 ? ay : (by0 + by1) / 2) - kWin / 2;
         R.wx0 = max(0, min(R.wx0, p.lx + 2 - kWin));
         R.wy0 = max(0, min(R.wy0, p.ly + 2 - kWin));
         R.x0 = 0;
